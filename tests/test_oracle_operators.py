@@ -1,0 +1,125 @@
+"""Pins of the oracle's spatial and all-at-once operators (not GPU).
+
+Each check compares the oracle against something other than itself: an
+independent textbook construction, a closed form of Appendix A, a dense
+eigensolver, or a direct solve of the sequential chain of Section 1.
+"""
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import operators as ops
+from oracle.alloc import paper_operator_kappa
+from synth import lognormal_kappa, random_block_vector, first_block_rhs
+
+
+def _tridiag(n, periodic=False):
+    T = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tolil()
+    if periodic:
+        T[0, n - 1] -= 1
+        T[n - 1, 0] -= 1
+    return T.tocsr()
+
+
+@pytest.mark.parametrize("dim,nx,ny", [(1, 9, 1), (2, 7, 5)])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+def test_constant_kappa_is_identity_plus_scaled_laplacian(dim, nx, ny, bc):
+    """Constant kappa must give I + kappa(-Delta_h) built as a Kronecker sum of 1D
+    second-difference matrices (the paper's operator of Section 5)."""
+    kap = 3.7
+    per = bc == "periodic"
+    if dim == 1:
+        L = _tridiag(nx, per)
+    else:
+        L = sp.kron(sp.identity(ny), _tridiag(nx, per)) + sp.kron(_tridiag(ny, per), sp.identity(nx))
+    ref = sp.identity(nx * ny) + kap * L
+    A = ops.build_A(dim, nx, ny, kap, bc)
+    assert abs(A - ref).max() < 1e-13
+
+
+def test_dirichlet_spectrum_appendix_a():
+    nx, ny, kap = 8, 6, 12.5
+    A = ops.build_A(2, nx, ny, kap).toarray()
+    ev = np.linalg.eigvalsh(A)
+    ref = np.sort(ops.dirichlet_eigs(2, nx, ny, kap).ravel())
+    assert np.max(np.abs(ev - ref)) < 1e-11 * ref.max()
+
+
+def test_sine_eigenvectors_appendix_a():
+    n, kap = 11, 4.0
+    A = ops.build_A(1, n, 1, kap)
+    mu = ops.dirichlet_eigs_1d(n, kap)
+    for j in range(1, n + 1):
+        v = ops.sine_vector(n, j)
+        assert abs(np.linalg.norm(v) - 1) < 1e-13
+        assert np.linalg.norm(A @ v - mu[j - 1] * v) < 1e-12 * mu[j - 1]
+    # 2D eigenvectors are tensor products V_i (x) V_j
+    A2 = ops.build_A(2, n, n, kap)
+    mu2 = ops.dirichlet_eigs(2, n, n, kap)
+    v = np.kron(ops.sine_vector(n, 3), ops.sine_vector(n, 7))
+    assert np.linalg.norm(A2 @ v - mu2[2, 6] * v) < 1e-12 * mu2.max()
+
+
+def test_periodic_spectrum():
+    nx, ny, kap = 6, 5, 2.0
+    A = ops.build_A(2, nx, ny, kap, "periodic").toarray()
+    ev = np.linalg.eigvalsh(A)
+    assert np.max(np.abs(ev - np.sort(ops.periodic_eigs(2, nx, ny, kap).ravel()))) < 1e-12
+
+
+def test_paper_operator_statements():
+    """Appendix A: mu_min > 1; for large n_x mu_max ~ 1 + 8 nu/h^2 and mu_min ~ 1 + 2 nu pi^2."""
+    ell = 10
+    for nx in (50, 100, 500):
+        kap = paper_operator_kappa(nx, ell)
+        lo, hi = ops.constant_interval(2, nx, nx, kap)
+        nu = 0.04 / (2 * ell - 4)
+        assert lo > 1.0
+        assert abs(hi - (1 + 8 * kap)) / hi < 2e-3 * (100 / nx) ** 2 + 1e-12
+        assert abs(lo - (1 + 2 * nu * np.pi ** 2)) < 1e-2
+    # n_x = 100, l = 10: nu/h^2 = 0.04/16 * 101^2
+    assert abs(paper_operator_kappa(100, 10) - 25.5025) < 1e-12
+
+
+@pytest.mark.parametrize("dim,nx,ny", [(1, 40, 1), (2, 12, 9)])
+def test_variable_interval_encloses_spectrum(dim, nx, ny):
+    kap = lognormal_kappa(nx, ny, 5.0, 3.0, 1.0, seed=3)
+    lo, hi = ops.spectral_interval(dim, nx, ny, kap)
+    ev = np.linalg.eigvalsh(ops.build_A(dim, nx, ny, kap).toarray())
+    assert lo <= ev.min() + 1e-12 and ev.max() <= hi + 1e-9
+    assert lo >= 1.0
+
+
+def test_apply_calA_matches_explicit_matrix():
+    nx, ny, ell = 6, 5, 4
+    kap = lognormal_kappa(nx, ny, 2.0, 2.0, 0.7, seed=1)
+    A = ops.build_A(2, nx, ny, kap)
+    x = random_block_vector(nx * ny, ell, seed=5)
+    calA = ops.build_calA(A, ell)
+    assert np.linalg.norm(calA @ x - ops.apply_calA(A, x, ell)) < 1e-13 * np.linalg.norm(calA @ x)
+    # explicit block structure of eq. (1)
+    D = calA.toarray()
+    n = nx * ny
+    assert np.allclose(D[n:2 * n, 0:n], -np.eye(n))
+    assert np.allclose(D[0:n, n:2 * n], 0.0)
+    assert np.allclose(D[2 * n:3 * n, 2 * n:3 * n], A.toarray())
+
+
+@pytest.mark.parametrize("ell", [2, 4, 7])
+def test_all_at_once_equals_sequential(ell):
+    """Section 1: solving the all-at-once system is the chain A x_1 = b_1, A x_{k+1} = x_k."""
+    nx, ny = 9, 7
+    kap = lognormal_kappa(nx, ny, 3.0, 2.0, 1.0, seed=2)
+    A = ops.build_A(2, nx, ny, kap)
+    b = first_block_rhs(nx * ny, ell, seed=0)
+    x_seq = ops.sequential_solve(A, b, ell)
+    x_dir = spla.spsolve(ops.build_calA(A, ell).tocsc(), b)
+    assert np.linalg.norm(x_seq - x_dir) < 1e-13 * np.linalg.norm(x_dir)
+    # the chain by hand for the first two blocks
+    n = nx * ny
+    x1 = np.linalg.solve(A.toarray(), b[:n])
+    x2 = np.linalg.solve(A.toarray(), x1)
+    assert np.allclose(x_seq[:n], x1, rtol=1e-13, atol=1e-15)
+    assert np.allclose(x_seq[n:2 * n], x2, rtol=1e-13, atol=1e-15)
