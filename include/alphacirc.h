@@ -1,0 +1,223 @@
+/*
+ * alphacirc: block alpha-circulant preconditioned all-at-once diffusion solves
+ * on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Tabeart, Guerol, Pearson, Weaver, "Block alpha-circulant
+ * preconditioners for all-at-once diffusion-based covariance operators".
+ *
+ *   All-at-once system (Section 1, eq. (1)):   calA x = b,
+ *     calA = I_l (x) A - S (x) I_N, S the l x l down-shift, b = (b_1, 0, ..., 0).
+ *   Preconditioner (eq. (2)):  P_alpha = I_l (x) A - C_alpha (x) I_N.
+ *   Its inverse (eq. (4)):  scale by Gamma_alpha = diag(alpha^{(k-1)/l}),
+ *     DFT across the l blocks, l shifted solves (A - lambda_j I) y_j = r_j
+ *     (eq. (6)), inverse DFT, scale by Gamma_alpha^{-1}.
+ *   Nested Chebyshev (Section 3): each shifted solve is p_j steps of Chebyshev
+ *     semi-iteration on the segment S_j = [mu_lo - lambda_j, mu_hi - lambda_j]
+ *     (Lemma 2, Proposition 1).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ * Memory   All vector arguments are DEVICE pointers on the context's device,
+ *          owned by the caller; the library never frees them.  Small arrays
+ *          documented as "host" are host pointers.  The library allocates
+ *          device memory only inside ac_ctx_create and ac_problem_create (and
+ *          ac_cnn_create) and frees it in the matching _destroy.
+ * Layout   Block vectors are float64, block-major: x[k*N + i], k in [0, l),
+ *          grid index i = iy*nx + ix (x fastest).  Cell-centred coefficient
+ *          kappa[i] > 0, float64, length N.
+ * Streams  All work is enqueued on the stream given to ac_ctx_create and is
+ *          asynchronous with respect to the host, except where a function
+ *          documents a synchronisation (ac_problem_create, ac_solve and the
+ *          query functions).
+ * Errors   Every function returns an ac_status; nothing throws across the ABI.
+ *          A negative status is an error, with a message in ac_last_error()
+ *          (per thread).  On error no output is guaranteed to be written.
+ * Shifts   lambda_m = alpha^{1/l} exp(-2 pi i m / l), m = 0..l-1: the paper's
+ *          shifts with the labelling conjugated so that they pair with the
+ *          negative-exponent forward DFT (the pairing printed with eq. (3) does
+ *          not diagonalise the down-shift C_alpha).  Because the block vectors are
+ *          real, only the l_s = floor(l/2)+1 shifts m = 0..floor(l/2) are solved;
+ *          the others are their complex conjugates.  Shift 0 and (l even) shift
+ *          l/2 are real.
+ */
+#ifndef ALPHACIRC_H
+#define ALPHACIRC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ac_ctx ac_ctx;         /* device, stream, pinned staging, kernel timers */
+typedef struct ac_problem ac_problem; /* one grid + kappa field, one l, one alpha */
+
+typedef enum {
+    AC_OK = 0,
+    AC_NOT_CONVERGED = 1,    /* non-fatal: ac_solve hit max_outer; info is filled in */
+    AC_ERR_ARG = -1,         /* invalid argument (null pointer, size, option) */
+    AC_ERR_ALPHA = -2,       /* alpha outside (0, mu_lo^l) (Corollary 1, Lemma 1) */
+    AC_ERR_BOUNDS = -3,      /* spectral bounds not 1 <= mu_lo <= mu_hi, finite */
+    AC_ERR_HIP = -4,         /* a HIP runtime call failed */
+    AC_ERR_WORKSPACE = -5,   /* workspace pointer null or smaller than required */
+    AC_ERR_NONFINITE = -6,   /* kappa not finite and positive, or a solve produced NaN/Inf */
+    AC_ERR_UNSUPPORTED = -7  /* e.g. l outside [2, 16], restart_m > 32 */
+} ac_status;
+
+typedef enum { AC_BC_DIRICHLET = 0, AC_BC_PERIODIC = 1 } ac_bc;
+
+/* Arithmetic of the inner (time-DFT + shifted Chebyshev) part.  The outer
+ * operator, Krylov basis, residuals and solution are always float64.
+ *   AC_PREC_FP64        complex128 iterates, float64 kappa
+ *   AC_PREC_MIXED_BF16K complex64 iterates, bfloat16 kappa (round to nearest even)
+ *   AC_PREC_MIXED_FP32K complex64 iterates, float32 kappa */
+typedef enum { AC_PREC_FP64 = 0, AC_PREC_MIXED_BF16K = 1, AC_PREC_MIXED_FP32K = 2 } ac_precision;
+
+/* Inner initial guess: zero (the paper's method), or the learned warm start
+ * attached with ac_cnn_attach (makes the preconditioner nonlinear). */
+typedef enum { AC_INNER_CHEB = 0, AC_INNER_CHEB_CNN = 1 } ac_inner;
+
+typedef struct {
+    int dim;   /* 1 or 2 */
+    int nx;    /* >= 1 */
+    int ny;    /* >= 1; must be 1 when dim == 1 */
+    int bc;    /* ac_bc */
+} ac_grid;
+
+typedef struct {
+    double mu_lo;  /* lower end of an interval enclosing the spectrum of A */
+    double mu_hi;  /* upper end */
+} ac_bounds;
+
+typedef struct {
+    int precision;           /* ac_precision */
+    int inner;               /* ac_inner */
+    const int* p_per_shift;  /* host, l entries (entry m pairs with lambda_m; conjugate
+                                entries must be equal), or NULL to use p_uniform */
+    int p_uniform;           /* inner Chebyshev steps per shift when p_per_shift == NULL */
+    double tol;              /* ac_solve: stop when ||b - calA x||_2 / ||b||_2 <= tol */
+    int restart_m;           /* ac_solve: FGMRES restart length, 1..32 */
+    int max_outer;           /* ac_solve: maximum total FGMRES iterations */
+    int reserved;            /* set to 0 */
+} ac_solve_opts;
+
+typedef struct {
+    int outer_iters;          /* FGMRES iterations (preconditioner applications) */
+    int restarts;             /* completed FGMRES cycles */
+    long long matvecs_A;      /* products with A, counted as in Table 1: l per calA,
+                                 p_j per shift per preconditioner application (all l shifts) */
+    double rel_residual_true; /* ||b - calA x|| / ||b|| of the returned x, float64 */
+    double seconds;           /* wall time of the solve (host clock, includes syncs) */
+    int cnn_fallbacks;        /* shifted solves where the warm start was rejected */
+    int reserved;
+} ac_solve_info;
+
+/* Kernel classes timed when profiling is on (ac_ctx_set_profiling). */
+typedef enum {
+    AC_K_TDFT_FWD = 0,   /* forward scaled time-DFT (+ conversion to the inner type) */
+    AC_K_CHEB_STEP = 1,  /* one batched shifted Chebyshev sweep over all active shifts */
+    AC_K_CHEB_FINAL = 2, /* last Chebyshev sweep fused with the inverse scaled time-DFT */
+    AC_K_APPLY_CALA = 3, /* calA x or b - calA x, float64 */
+    AC_K_KRYLOV = 4,     /* multi-dot / multi-axpy / norms, float64 */
+    AC_K_CNN = 5,        /* warm-start network */
+    AC_K_COUNT = 6
+} ac_kernel_class;
+
+/* ---- status ------------------------------------------------------------- */
+const char* ac_status_string(int status);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* ac_last_error(void);
+
+/* ---- context ------------------------------------------------------------ */
+/* Binds a device and a stream.  hip_stream is a hipStream_t (NULL = default
+ * stream); the caller keeps it alive until ac_ctx_destroy. */
+int ac_ctx_create(int device, void* hip_stream, ac_ctx** out);
+int ac_ctx_destroy(ac_ctx* ctx);
+int ac_ctx_set_stream(ac_ctx* ctx, void* hip_stream);
+/* Profiling: when on, every launch of the classes above is bracketed by HIP events
+ * on the context stream and its algorithmic bytes are accumulated. */
+int ac_ctx_set_profiling(ac_ctx* ctx, int on);
+/* Synchronises the stream, then returns per class the summed kernel milliseconds,
+ * launch count and algorithmic bytes since the last reset (host arrays of
+ * AC_K_COUNT entries; any may be NULL). */
+int ac_ctx_kernel_stats(ac_ctx* ctx, double* ms, long long* launches, double* bytes);
+int ac_ctx_reset_stats(ac_ctx* ctx);
+/* Marching-stencil tile shape for the Chebyshev sweeps (0 = automatic):
+ * rows_per_wave in [0, 4096], waves_per_block in [0, 4], points_per_lane in [0, 2]
+ * (2 needs an even nx >= 128; otherwise 1 is used).  Results do not depend on it. */
+int ac_ctx_set_tiling(ac_ctx* ctx, int rows_per_wave, int waves_per_block, int points_per_lane);
+
+/* ---- problem ------------------------------------------------------------ */
+/* Builds A from the grid and the cell-centred kappa (device, N float64, read
+ * during the call; a float64 copy and the float32/bfloat16 copies are kept):
+ *   (A u)_i = u_i + sum over faces f of kappa_f (u_i - u_nb),
+ *   kappa_f = (kappa_i + kappa_nb)/2; a Dirichlet boundary face uses kappa_i and
+ *   a zero ghost value; periodic faces wrap.  Constant kappa gives I + kappa (-Delta_h),
+ *   the paper's operator (Section 5, eq. (IminusLap)) with kappa = nu/h^2.
+ * bounds == NULL: computes an enclosing interval on the device: mu_hi = the
+ * Gershgorin maximum over rows, mu_lo = 1 + min(kappa) * lambda_min(-Delta_h)
+ * (lambda_min of the integer Dirichlet stencil; 0 for periodic).  The interval
+ * feeds the Chebyshev centres (Proposition 1).  Checks 0 < alpha < mu_lo^l
+ * (Corollary 1) and l in [2, 16].  Synchronises the stream. */
+int ac_problem_create(ac_ctx* ctx, const ac_grid* grid, const double* kappa_dev, int ell, double alpha,
+                      const ac_bounds* bounds, ac_problem** out);
+int ac_problem_destroy(ac_problem* p);
+/* Interval used for the FP64 inner solve (host outputs). */
+int ac_spectral_bounds(const ac_problem* p, double* mu_lo, double* mu_hi);
+/* Sizes: N, l and l_s = floor(l/2) + 1 (host outputs, any may be NULL). */
+int ac_problem_dims(const ac_problem* p, long long* n, int* ell, int* n_shifts);
+
+/* ---- inner-iteration allocation (Section 5.1, Table 1) ------------------- */
+/* NC2, Algorithm 1: sigma_m from the condition number of Re(A - lambda_m I),
+ * r_m = ln(sigma_0)/ln(sigma_m), normalised, p_m = floor(r_m * budget), clamped
+ * to >= 1 (a zero would drop a frequency).  budget is the total inner budget
+ * (the paper's l * n_x * eta).  p_out: host, l entries. */
+int ac_alloc_nc2(const ac_problem* p, double budget, int* p_out);
+/* NC1: floor(budget / l) for every shift, clamped to >= 1. */
+int ac_alloc_nc1(const ac_problem* p, double budget, int* p_out);
+
+/* ---- workspaces ----------------------------------------------------------- */
+/* Device bytes needed by ac_apply_prec / ac_shifted_cheb (prec) and ac_solve. */
+int ac_prec_workspace_size(const ac_problem* p, const ac_solve_opts* opts, size_t* bytes);
+int ac_solve_workspace_size(const ac_problem* p, const ac_solve_opts* opts, size_t* bytes);
+
+/* ---- operators (Section 1 eq. (1); Section 2.2 eq. (4); Section 3) ------- */
+/* y = calA x: y_k = A x_k - x_{k-1}, x_0 := 0 (float64; x, y: l*N, must not overlap). */
+int ac_apply_A(ac_problem* p, const double* x, double* y);
+
+/* z = P_NC^{-1} r (nested Chebyshev, opts->precision / p_per_shift / inner), the
+ * three steps fused into first/last Chebyshev sweeps.  With p_m -> infinity this
+ * tends to the exact P_alpha^{-1} r of eq. (4).  r, z: l*N float64, must not overlap. */
+int ac_apply_prec(ac_problem* p, const ac_solve_opts* opts, const double* r, double* z, void* ws, size_t ws_bytes);
+
+/* Spectral buffers used by the three stages below: l_s shift slices, slice m of
+ * ac_spectral_offsets()[m] elements of the inner real type (float64 for
+ * AC_PREC_FP64, float32 otherwise), real shifts (m = 0, and m = l/2 for even l) as
+ * N reals, complex shifts as N interleaved (re, im) pairs.  offsets: host array of
+ * l_s + 1 entries (last = total elements). */
+int ac_spectral_offsets(const ac_problem* p, int precision, long long* offsets);
+/* rhat_m = sum_k alpha^{k/l} r_k exp(-2 pi i m k / l), m = 0..l_s-1 (unnormalised). */
+int ac_tdft_forward(ac_problem* p, int precision, const double* r, void* rhat);
+/* yhat_m = p_m Chebyshev steps on (A - lambda_m I) y = rhat_m from zero (or from x0hat
+ * when non-NULL, same layout).  yhat may not alias rhat. */
+int ac_shifted_cheb(ac_problem* p, const ac_solve_opts* opts, const void* rhat, const void* x0hat, void* yhat,
+                    void* ws, size_t ws_bytes);
+/* z_k = alpha^{-k/l} (1/l) Re sum_{m=0}^{l-1} yhat_m exp(+2 pi i m k / l), using
+ * yhat_{l-m} = conj(yhat_m). */
+int ac_tdft_inverse(ac_problem* p, int precision, const void* yhat, double* z);
+
+/* ---- outer solve ---------------------------------------------------------- */
+/* Right-preconditioned flexible GMRES(restart_m) on calA x = b with P_NC^{-1},
+ * Arnoldi by classical Gram-Schmidt applied twice, all in float64; Givens
+ * rotations on the host.  x holds the initial guess on entry and the solution on
+ * return.  Converged when the TRUE relative residual ||b - calA x||/||b|| <= tol
+ * (the paper's residual definition, Section 5).  Synchronises once per
+ * iteration.  info may be NULL.  Returns AC_NOT_CONVERGED after max_outer. */
+int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws, size_t ws_bytes,
+             ac_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ALPHACIRC_H */

@@ -1,0 +1,265 @@
+"""Python binding of the alphacirc C ABI: same names, argument marshalling only.
+
+Device buffers are torch tensors on the GPU (float64 block vectors of length
+l*N, layout x[k*N + i]); their data pointers go straight to the library, which
+runs every step in its HIP kernels on the context's stream.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib as L
+from ._lib import check
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _f64(t: torch.Tensor, n: int, name: str):
+    if t.dtype != torch.float64 or t.numel() != n:
+        raise ValueError(f"{name}: expected {n} float64 values, got {t.numel()} {t.dtype}")
+    return _ptr(t)
+
+
+class Ctx:
+    def __init__(self, handle, device, stream):
+        self.h = handle
+        self.device = device
+        self.stream = stream
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            L.load().ac_ctx_destroy(self.h)
+            self.h = None
+
+
+class Problem:
+    def __init__(self, handle, ctx, n, ell, ns):
+        self.h = handle
+        self.ctx = ctx
+        self.n = n
+        self.ell = ell
+        self.ns = ns
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            L.load().ac_problem_destroy(self.h)
+            self.h = None
+
+
+@dataclass
+class Opts:
+    precision: int = L.AC_PREC_FP64
+    inner: int = L.AC_INNER_CHEB
+    p: object = 10          # int (uniform) or a length-l sequence
+    tol: float = 1e-8
+    restart_m: int = 30
+    max_outer: int = 500
+
+    def to_c(self, ell: int):
+        o = L.ac_solve_opts()
+        o.precision = self.precision
+        o.inner = self.inner
+        if isinstance(self.p, int):
+            o.p_uniform = int(self.p)
+            o.p_per_shift = None
+            keep = None
+        else:
+            arr = (C.c_int * ell)(*[int(v) for v in self.p])
+            o.p_per_shift = C.cast(arr, C.POINTER(C.c_int))
+            o.p_uniform = 0
+            keep = arr
+        o.tol = float(self.tol)
+        o.restart_m = int(self.restart_m)
+        o.max_outer = int(self.max_outer)
+        o.reserved = 0
+        return o, keep
+
+
+def ac_status_string(status: int) -> str:
+    return L.load().ac_status_string(status).decode()
+
+
+def ac_last_error() -> str:
+    return L.load().ac_last_error().decode()
+
+
+def ac_ctx_create(device: int = 0, stream: torch.cuda.Stream | None = None) -> Ctx:
+    lib = L.load()
+    stream = stream if stream is not None else torch.cuda.current_stream(device)
+    h = C.c_void_p()
+    check(lib.ac_ctx_create(device, C.c_void_p(stream.cuda_stream), C.byref(h)), "ac_ctx_create")
+    return Ctx(h, device, stream)
+
+
+def ac_ctx_set_profiling(ctx: Ctx, on: bool) -> None:
+    check(L.load().ac_ctx_set_profiling(ctx.h, int(bool(on))), "ac_ctx_set_profiling")
+
+
+def ac_ctx_kernel_stats(ctx: Ctx) -> dict:
+    ms = (C.c_double * L.AC_K_COUNT)()
+    launches = (C.c_longlong * L.AC_K_COUNT)()
+    nbytes = (C.c_double * L.AC_K_COUNT)()
+    check(L.load().ac_ctx_kernel_stats(ctx.h, ms, launches, nbytes), "ac_ctx_kernel_stats")
+    return {name: {"ms": ms[i], "launches": launches[i], "bytes": nbytes[i]}
+            for i, name in enumerate(L.KERNEL_CLASS_NAMES)}
+
+
+def ac_ctx_reset_stats(ctx: Ctx) -> None:
+    check(L.load().ac_ctx_reset_stats(ctx.h), "ac_ctx_reset_stats")
+
+
+def ac_ctx_set_tiling(ctx: Ctx, rows_per_wave: int = 0, waves_per_block: int = 0, points_per_lane: int = 0) -> None:
+    check(L.load().ac_ctx_set_tiling(ctx.h, rows_per_wave, waves_per_block, points_per_lane), "ac_ctx_set_tiling")
+
+
+def ac_problem_create(ctx: Ctx, dim: int, nx: int, ny: int, kappa: torch.Tensor, ell: int, alpha: float,
+                      bc: int = L.AC_BC_DIRICHLET, bounds: tuple[float, float] | None = None) -> Problem:
+    lib = L.load()
+    g = L.ac_grid(dim, nx, ny, bc)
+    n = nx * ny
+    kp = _f64(kappa, n, "kappa")
+    bp = None
+    if bounds is not None:
+        bp = C.byref(L.ac_bounds(float(bounds[0]), float(bounds[1])))
+    h = C.c_void_p()
+    check(lib.ac_problem_create(ctx.h, C.byref(g), kp, ell, float(alpha), bp, C.byref(h)), "ac_problem_create")
+    nn, ee, ns = C.c_longlong(), C.c_int(), C.c_int()
+    check(lib.ac_problem_dims(h, C.byref(nn), C.byref(ee), C.byref(ns)), "ac_problem_dims")
+    return Problem(h, ctx, nn.value, ee.value, ns.value)
+
+
+def ac_spectral_bounds(p: Problem) -> tuple[float, float]:
+    lo, hi = C.c_double(), C.c_double()
+    check(L.load().ac_spectral_bounds(p.h, C.byref(lo), C.byref(hi)), "ac_spectral_bounds")
+    return lo.value, hi.value
+
+
+def ac_alloc_nc2(p: Problem, budget: float) -> list[int]:
+    out = (C.c_int * p.ell)()
+    check(L.load().ac_alloc_nc2(p.h, float(budget), out), "ac_alloc_nc2")
+    return list(out)
+
+
+def ac_alloc_nc1(p: Problem, budget: float) -> list[int]:
+    out = (C.c_int * p.ell)()
+    check(L.load().ac_alloc_nc1(p.h, float(budget), out), "ac_alloc_nc1")
+    return list(out)
+
+
+def ac_prec_workspace_size(p: Problem, opts: Opts) -> int:
+    o, keep = opts.to_c(p.ell)
+    n = C.c_size_t()
+    check(L.load().ac_prec_workspace_size(p.h, C.byref(o), C.byref(n)), "ac_prec_workspace_size")
+    return n.value
+
+
+def ac_solve_workspace_size(p: Problem, opts: Opts) -> int:
+    o, keep = opts.to_c(p.ell)
+    n = C.c_size_t()
+    check(L.load().ac_solve_workspace_size(p.h, C.byref(o), C.byref(n)), "ac_solve_workspace_size")
+    return n.value
+
+
+def workspace(nbytes: int, device: int = 0) -> torch.Tensor:
+    """A device byte buffer to pass as workspace."""
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{device}")
+
+
+def ac_apply_A(p: Problem, x: torch.Tensor, y: torch.Tensor) -> None:
+    n = p.ell * p.n
+    check(L.load().ac_apply_A(p.h, _f64(x, n, "x"), _f64(y, n, "y")), "ac_apply_A")
+
+
+def ac_apply_prec(p: Problem, opts: Opts, r: torch.Tensor, z: torch.Tensor, ws: torch.Tensor) -> None:
+    n = p.ell * p.n
+    o, keep = opts.to_c(p.ell)
+    check(L.load().ac_apply_prec(p.h, C.byref(o), _f64(r, n, "r"), _f64(z, n, "z"), _ptr(ws), ws.numel()),
+          "ac_apply_prec")
+
+
+def ac_spectral_offsets(p: Problem, precision: int) -> list[int]:
+    off = (C.c_longlong * (p.ns + 1))()
+    check(L.load().ac_spectral_offsets(p.h, precision, off), "ac_spectral_offsets")
+    return list(off)
+
+
+def spectral_dtype(precision: int) -> torch.dtype:
+    return torch.float64 if precision == L.AC_PREC_FP64 else torch.float32
+
+
+def ac_tdft_forward(p: Problem, precision: int, r: torch.Tensor, rhat: torch.Tensor) -> None:
+    check(L.load().ac_tdft_forward(p.h, precision, _f64(r, p.ell * p.n, "r"), _ptr(rhat)), "ac_tdft_forward")
+
+
+def ac_shifted_cheb(p: Problem, opts: Opts, rhat: torch.Tensor, x0hat: torch.Tensor | None, yhat: torch.Tensor,
+                    ws: torch.Tensor) -> None:
+    o, keep = opts.to_c(p.ell)
+    check(L.load().ac_shifted_cheb(p.h, C.byref(o), _ptr(rhat), _ptr(x0hat), _ptr(yhat), _ptr(ws), ws.numel()),
+          "ac_shifted_cheb")
+
+
+def ac_tdft_inverse(p: Problem, precision: int, yhat: torch.Tensor, z: torch.Tensor) -> None:
+    check(L.load().ac_tdft_inverse(p.h, precision, _ptr(yhat), _f64(z, p.ell * p.n, "z")), "ac_tdft_inverse")
+
+
+def ac_solve(p: Problem, opts: Opts, b: torch.Tensor, x: torch.Tensor, ws: torch.Tensor) -> dict:
+    n = p.ell * p.n
+    o, keep = opts.to_c(p.ell)
+    info = L.ac_solve_info()
+    st = check(L.load().ac_solve(p.h, C.byref(o), _f64(b, n, "b"), _f64(x, n, "x"), _ptr(ws), ws.numel(),
+                                 C.byref(info)), "ac_solve")
+    return {
+        "status": st,
+        "converged": st == L.AC_OK,
+        "outer_iters": info.outer_iters,
+        "restarts": info.restarts,
+        "matvecs_A": info.matvecs_A,
+        "rel_residual_true": info.rel_residual_true,
+        "seconds": info.seconds,
+        "cnn_fallbacks": info.cnn_fallbacks,
+    }
+
+
+# ---- spectral buffer helpers (host side views, no arithmetic) -------------------
+
+def spectral_to_complex(p: Problem, precision: int, buf: torch.Tensor):
+    """Split a spectral buffer into per-frequency complex tensors (m = 0..l_s-1)."""
+    off = ac_spectral_offsets(p, precision)
+    out = []
+    for m in range(p.ns):
+        real = (m == 0) or (p.ell % 2 == 0 and m == p.ell // 2)
+        sl = buf[off[m]: off[m] + (p.n if real else 2 * p.n)]
+        if real:
+            out.append(torch.complex(sl, torch.zeros_like(sl)))
+        else:
+            v = sl.view(p.n, 2)
+            out.append(torch.complex(v[:, 0].contiguous(), v[:, 1].contiguous()))
+    return out
+
+
+def complex_to_spectral(p: Problem, precision: int, slices) -> torch.Tensor:
+    """Pack per-frequency complex tensors (m = 0..l_s-1) into a spectral buffer."""
+    off = ac_spectral_offsets(p, precision)
+    dt = spectral_dtype(precision)
+    dev = slices[0].device
+    buf = torch.zeros(off[-1], dtype=dt, device=dev)
+    for m in range(p.ns):
+        real = (m == 0) or (p.ell % 2 == 0 and m == p.ell // 2)
+        s = slices[m]
+        if real:
+            buf[off[m]: off[m] + p.n] = s.real.to(dt)
+        else:
+            buf[off[m]: off[m] + 2 * p.n] = torch.stack([s.real, s.imag], dim=1).reshape(-1).to(dt)
+    return buf

@@ -1,0 +1,130 @@
+// Internal declarations shared by the alphacirc HIP sources (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ac {
+
+constexpr int kMaxEll = 16;
+constexpr int kMaxShift = kMaxEll / 2 + 1;  // unique shifts l_s = floor(l/2) + 1
+constexpr int kWave = 64;                   // CDNA wavefront
+constexpr int kMaxBasis = 33;               // FGMRES(32): V_0..V_32
+
+// Grid geometry.  dim 1 has faces in x only.
+struct Geom {
+    int nx, ny;
+    int dim;
+    int periodic;
+    long long n;
+};
+
+// Marching-stencil tiling: every wave owns a strip of 64*vx columns and a chunk
+// of h rows, and walks the chunk row by row keeping three rows in registers.
+struct Tiling {
+    int vx;         // consecutive x points per lane (1 or 2)
+    int h;          // rows per wave
+    int wpb;        // waves per block
+    int nsx, ncy;   // strips in x, chunks in y
+    long long tiles;
+    int blocks;
+};
+
+// Where a Chebyshev operand comes from.
+enum Src : int {
+    SRC_BUF = 0,      // an iterate buffer
+    SRC_RHAT = 1,     // x_1 = rhat / theta (zero initial guess, never stored)
+    SRC_ZERO = 2,     // x_0 = 0
+    SRC_COMPUTE = 3,  // (final sweep) computed in this launch
+};
+
+// Per-shift Chebyshev data for one sweep.  Shift slot order: real shifts first
+// (m = 0, then m = l/2 for even l), then complex shifts m = 1..ceil(l/2)-1.
+template <typename R>
+struct ShiftCoef {
+    R lam_re[kMaxShift], lam_im[kMaxShift];  // lambda_m
+    R a_re[kMaxShift], a_im[kMaxShift];      // rho_k rho_{k-1}  (momentum)
+    R c_re[kMaxShift], c_im[kMaxShift];      // 2 rho_k / delta  (residual weight)
+    R s_re[kMaxShift], s_im[kMaxShift];      // 1 / theta        (x_1 = rhat / theta)
+};
+
+template <typename R>
+struct SweepArgs {
+    Geom g;
+    Tiling t;
+    const void* kappa;  // storage type depends on the precision
+    ShiftCoef<R> cf;
+    int src[kMaxShift];        // step: SRC_COMPUTE (active) or anything else (skip)
+                               // final: SRC_COMPUTE / SRC_RHAT / SRC_BUF
+    const R* rhat[kMaxShift];  // right-hand side slice
+    const R* cur[kMaxShift];   // x_k (when the current operand is a buffer)
+    R* out[kMaxShift];         // step: holds x_{k-1} on entry (if a buffer), x_{k+1} on exit
+    const R* prev[kMaxShift];  // final: x_{k-1} buffer
+    const R* fin[kMaxShift];   // final: finished iterate when src == SRC_BUF
+    // inverse transform (final sweep only)
+    double ginv[kMaxEll];      // 1 / (l * alpha^{k/l})
+    double cw[kMaxEll], sw[kMaxEll];  // cos / sin (2 pi j / l)
+    double* z;
+};
+
+struct FwdArgs {
+    long long n;
+    double gam[kMaxEll];              // input scale * alpha^{k/l}
+    double cw[kMaxEll], sw[kMaxEll];  // cos / sin (2 pi j / l)
+    const double* r;
+    void* rhat[kMaxShift];            // slot order as ShiftCoef
+};
+
+struct InvArgs {
+    long long n;
+    double ginv[kMaxEll];
+    double cw[kMaxEll], sw[kMaxEll];
+    const void* yhat[kMaxShift];
+    double* z;
+};
+
+struct CalAArgs {
+    Geom g;
+    Tiling t;
+    const double* kappa;
+    const double* x;
+    const double* b;      // residual mode: y = b - calA x
+    double* y;
+    double* partial;      // residual mode: per-tile sum of squares
+    int ell;
+};
+
+// ---- launchers (stencil.hip) ----------------------------------------------
+// prec: 0 = FP64 (double, kappa double), 1 = float + bf16 kappa, 2 = float + float kappa
+hipError_t launch_cheb_step(int ell, int prec, int curk, int prevk, const void* args, hipStream_t s);
+hipError_t launch_cheb_final(int ell, int prec, int curk, int prevk, const void* args, hipStream_t s);
+hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
+hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
+hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);
+
+// ---- Krylov vector kernels (krylov.hip) ------------------------------------
+struct VecSet {
+    const double* v[kMaxBasis];
+    double s2[kMaxBasis];  // squared scales of the raw basis vectors
+};
+int krylov_blocks();
+// partial[blk*nq + q]
+hipError_t launch_mdot(const VecSet& V, int nv, const double* w, long long len, double* partial, int nq_stride,
+                       hipStream_t s);
+hipError_t launch_axpy_dot(const VecSet& V, int nv, const double* dcoef, double* w, long long len, double* partial,
+                           int nq_stride, hipStream_t s);
+hipError_t launch_axpy_norm(const VecSet& V, int nv, const double* dcoef, double* w, long long len, double* partial,
+                            int nq_stride, hipStream_t s);
+hipError_t launch_maxpy(const VecSet& Z, int nv, const double* coef_host_scaled, double* x, long long len,
+                        hipStream_t s);
+hipError_t launch_norm2(const double* w, long long len, double* partial, hipStream_t s);
+hipError_t launch_reduce(const double* partial, int nblk, int nq, int nq_stride, double* out, hipStream_t s);
+
+// ---- setup kernels (setup.hip) -----------------------------------------------
+hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,
+                              int nblk, hipStream_t s);
+int setup_blocks();
+
+}  // namespace ac

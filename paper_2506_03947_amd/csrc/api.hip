@@ -1,0 +1,1034 @@
+// C ABI of alphacirc: contexts, problems, the preconditioner stages and the
+// flexible GMRES outer solve.  Host orchestration only; every vector operation
+// runs in the kernels of stencil.hip / krylov.hip / setup.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "alphacirc.h"
+#include "ac_internal.h"
+
+using ac::Geom;
+using ac::kMaxEll;
+using ac::kMaxShift;
+using ac::Tiling;
+using cplx = std::complex<double>;
+
+// ---------------------------------------------------------------------------
+// error plumbing
+
+namespace {
+thread_local std::string g_last_error;
+
+int fail(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+#define AC_HIP(call)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(AC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+#define AC_TRY(call)              \
+    do {                          \
+        int s_ = (call);          \
+        if (s_ < 0) return s_;    \
+    } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+constexpr double kPi = 3.14159265358979323846;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// opaque types
+
+struct ac_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    double* pinned = nullptr;  // host staging for reductions
+    bool profiling = false;
+    struct Pending {
+        hipEvent_t a, b;
+        int cls;
+        double bytes;
+    };
+    std::vector<Pending> pending;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    double ms[AC_K_COUNT] = {};
+    long long launches[AC_K_COUNT] = {};
+    double bytes[AC_K_COUNT] = {};
+    // tiling overrides (0 = automatic): rows per wave, waves per block, points per lane
+    int tile_h = 0, tile_wpb = 0, tile_vx = 0;
+};
+
+struct ac_problem {
+    ac_ctx* ctx = nullptr;
+    Geom g{};
+    int ell = 0;
+    double alpha = 0;
+    int nsr = 0, nsc = 0, ns = 0;
+    double* k64 = nullptr;
+    float* k32 = nullptr;
+    uint16_t* k16 = nullptr;
+    double bounds[3][2] = {};  // per precision: mu_lo, mu_hi
+    double kmin64 = 0;
+};
+
+// ---------------------------------------------------------------------------
+// profiling helpers
+
+namespace {
+
+struct ProfScope {
+    ac_ctx* c;
+    hipEvent_t a = nullptr, b = nullptr;
+    int cls;
+    double bytes;
+    ProfScope(ac_ctx* ctx, int cls_, double bytes_) : c(ctx), cls(cls_), bytes(bytes_) {
+        if (!c->profiling) return;
+        if (!c->pool.empty()) {
+            a = c->pool.back().first;
+            b = c->pool.back().second;
+            c->pool.pop_back();
+        } else {
+            (void)hipEventCreate(&a);
+            (void)hipEventCreate(&b);
+        }
+        (void)hipEventRecord(a, c->stream);
+    }
+    ~ProfScope() {
+        if (!c->profiling || !a) return;
+        (void)hipEventRecord(b, c->stream);
+        c->pending.push_back({a, b, cls, bytes});
+    }
+};
+
+int harvest(ac_ctx* c) {
+    AC_HIP(hipStreamSynchronize(c->stream));
+    for (auto& p : c->pending) {
+        float ms = 0.f;
+        AC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
+        c->ms[p.cls] += ms;
+        c->launches[p.cls] += 1;
+        c->bytes[p.cls] += p.bytes;
+        c->pool.emplace_back(p.a, p.b);
+    }
+    c->pending.clear();
+    return AC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// geometry helpers
+
+// Shift slot <-> frequency m.  Slot order: real shifts (m = 0, then m = l/2 for
+// even l), then complex shifts m = 1..ceil(l/2)-1.
+int slot_to_m(const ac_problem* p, int slot) {
+    if (slot < p->nsr) return slot == 0 ? 0 : p->ell / 2;
+    return slot - p->nsr + 1;
+}
+bool slot_is_real(const ac_problem* p, int slot) { return slot < p->nsr; }
+
+size_t inner_elem(int prec) { return prec == AC_PREC_FP64 ? sizeof(double) : sizeof(float); }
+
+// Elements (of the inner real type) of the slice for frequency m, padded.
+long long slice_elems(const ac_problem* p, int m) {
+    const bool real = (m == 0) || (p->ell % 2 == 0 && m == p->ell / 2);
+    const long long e = real ? p->g.n : 2 * p->g.n;
+    return (e + 63) / 64 * 64;
+}
+
+// offsets by frequency m = 0..ns-1 (ABI order), last entry = total
+void spectral_offsets(const ac_problem* p, long long* off) {
+    long long o = 0;
+    for (int m = 0; m < p->ns; ++m) {
+        off[m] = o;
+        o += slice_elems(p, m);
+    }
+    off[p->ns] = o;
+}
+
+Tiling make_tiling(const ac_problem* p, int vx_pref, int h_pref, int wpb_pref) {
+    Tiling t{};
+    const Geom& g = p->g;
+    int vx = vx_pref > 0 ? vx_pref : 2;
+    if (g.nx % 2 != 0 || g.nx < 128) vx = 1;
+    t.vx = vx;
+    t.h = h_pref > 0 ? h_pref : 16;
+    if (t.h > g.ny) t.h = g.ny;
+    t.wpb = wpb_pref > 0 ? wpb_pref : 4;
+    t.nsx = (g.nx + ac::kWave * vx - 1) / (ac::kWave * vx);
+    t.ncy = (g.ny + t.h - 1) / t.h;
+    t.tiles = static_cast<long long>(t.nsx) * t.ncy;
+    t.blocks = static_cast<int>((t.tiles + t.wpb - 1) / t.wpb);
+    return t;
+}
+
+Tiling sweep_tiling(const ac_problem* p) { return make_tiling(p, p->ctx->tile_vx, p->ctx->tile_h, p->ctx->tile_wpb); }
+
+Tiling calA_tiling(const ac_problem* p) {
+    // float64 operand with l blocks per point: one point per lane past l = 8
+    return make_tiling(p, p->ell > 8 ? 1 : 2, 16, 4);
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev tables (Section 3; textbook three-term recurrence in x form):
+//   theta = (mu_hi + mu_lo)/2 - lambda, delta = (mu_hi - mu_lo)/2,
+//   rho_0 = delta/theta, rho_k = 1/(2 theta/delta - rho_{k-1}),
+//   x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k/delta)(rhat - B x_k),
+//   x_1 = x_0 + (rhat - B x_0)/theta.
+struct ChebShift {
+    cplx lam, theta;
+    double delta;
+    std::vector<cplx> a, c;  // index k = 0..p-1: coefficients producing x_{k+1}
+};
+
+ChebShift cheb_tables(const ac_problem* p, int prec, int m, int steps) {
+    ChebShift s;
+    const double lo = p->bounds[prec][0], hi = p->bounds[prec][1];
+    s.lam = std::polar(std::pow(p->alpha, 1.0 / p->ell), -2.0 * kPi * m / p->ell);
+    s.theta = cplx(0.5 * (hi + lo), 0.0) - s.lam;
+    s.delta = 0.5 * (hi - lo);
+    s.a.assign(std::max(steps, 1), cplx(0));
+    s.c.assign(std::max(steps, 1), cplx(0));
+    s.a[0] = 0.0;
+    s.c[0] = 1.0 / s.theta;
+    const bool degenerate = s.delta <= 1e-300 || s.delta < 1e-15 * std::abs(s.theta);
+    cplx rho = degenerate ? cplx(0) : s.delta / s.theta;
+    for (int k = 1; k < steps; ++k) {
+        if (degenerate) {
+            s.a[k] = 0.0;
+            s.c[k] = 0.0;
+            continue;
+        }
+        const cplx rn = 1.0 / (2.0 * s.theta / s.delta - rho);
+        s.a[k] = rn * rho;
+        s.c[k] = 2.0 * rn / s.delta;
+        rho = rn;
+    }
+    return s;
+}
+
+int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>& pm) {
+    if (!o) return fail(AC_ERR_ARG, "opts is NULL");
+    if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
+    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN) return fail(AC_ERR_ARG, "unknown inner mode");
+    if (o->inner == AC_INNER_CHEB_CNN) return fail(AC_ERR_UNSUPPORTED, "no warm-start network attached");
+    pm.assign(p->ell, 0);
+    for (int m = 0; m < p->ell; ++m) {
+        const int v = o->p_per_shift ? o->p_per_shift[m] : o->p_uniform;
+        if (v < 1 || v > 100000) return fail(AC_ERR_ARG, "inner iteration counts must be in [1, 100000]");
+        pm[m] = v;
+    }
+    for (int m = 1; m < p->ell; ++m)
+        if (pm[m] != pm[p->ell - m]) return fail(AC_ERR_ARG, "conjugate shifts m and l-m need equal inner counts");
+    return AC_OK;
+}
+
+// Prec workspace: rhat + 2 iterate buffers (+ a warm-start buffer) of the spectral size.
+size_t prec_ws_bytes(const ac_problem* p, int prec) {
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    return 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
+}
+
+struct PrecBufs {
+    char* rhat;
+    char* buf[2];
+};
+
+PrecBufs carve_prec(const ac_problem* p, int prec, void* ws) {
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    const size_t sz = align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256);
+    char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
+    return {base, {base + sz, base + 2 * sz}};
+}
+
+// slot pointer into a spectral buffer
+char* slot_ptr(const ac_problem* p, int prec, char* buf, int slot) {
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    return buf + off[slot_to_m(p, slot)] * inner_elem(prec);
+}
+
+void fill_twiddles(int ell, double* cw, double* sw) {
+    for (int j = 0; j < ell; ++j) {
+        cw[j] = std::cos(2.0 * kPi * j / ell);
+        sw[j] = std::sin(2.0 * kPi * j / ell);
+    }
+}
+
+int run_fwd(ac_problem* p, int prec, const double* r, char* rhat, double in_scale) {
+    ac::FwdArgs a{};
+    a.n = p->g.n;
+    for (int k = 0; k < p->ell; ++k) a.gam[k] = in_scale * std::pow(p->alpha, static_cast<double>(k) / p->ell);
+    fill_twiddles(p->ell, a.cw, a.sw);
+    a.r = r;
+    for (int s = 0; s < p->ns; ++s) a.rhat[s] = slot_ptr(p, prec, rhat, s);
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    const double bytes = 8.0 * p->ell * p->g.n + static_cast<double>(off[p->ns]) * inner_elem(prec);
+    ProfScope ps(p->ctx, AC_K_TDFT_FWD, bytes);
+    AC_HIP(ac::launch_tdft_fwd(p->ell, prec, a, p->ctx->stream));
+    return AC_OK;
+}
+
+template <typename R>
+void fill_coef(ac::SweepArgs<R>& a, int slot, const ChebShift& cs, int k) {
+    a.cf.lam_re[slot] = static_cast<R>(cs.lam.real());
+    a.cf.lam_im[slot] = static_cast<R>(cs.lam.imag());
+    a.cf.a_re[slot] = static_cast<R>(cs.a[k].real());
+    a.cf.a_im[slot] = static_cast<R>(cs.a[k].imag());
+    a.cf.c_re[slot] = static_cast<R>(cs.c[k].real());
+    a.cf.c_im[slot] = static_cast<R>(cs.c[k].imag());
+    const cplx s = 1.0 / cs.theta;
+    a.cf.s_re[slot] = static_cast<R>(s.real());
+    a.cf.s_im[slot] = static_cast<R>(s.imag());
+}
+
+// Bytes a sweep moves, per point, for one computing shift of element size esz.
+double sweep_bytes_per_point(int curk, int prevk, bool final, double esz) {
+    double n = 1.0;                                 // the stencil operand
+    if (curk == ac::SRC_BUF) n += 1.0;              // rhat read separately
+    if (prevk == ac::SRC_BUF) n += 1.0;             // x_{k-1}
+    if (!final) n += 1.0;                           // x_{k+1} write
+    return n * esz;
+}
+
+// Nested Chebyshev over all unique shifts.  warm: x_0 is in buf[0].
+// If z != nullptr the last sweep is fused with the inverse transform into z;
+// otherwise the finished iterates are left in place and `where` reports them.
+template <typename R>
+int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[2], bool warm,
+               double* z, std::vector<std::pair<int, char*>>* where) {
+    const int ns = p->ns;
+    int pmax = 0;
+    std::vector<int> ps(ns);
+    for (int s = 0; s < ns; ++s) {
+        ps[s] = pm[slot_to_m(p, s)];
+        pmax = std::max(pmax, ps[s]);
+    }
+    std::vector<ChebShift> cs(ns);
+    for (int s = 0; s < ns; ++s) cs[s] = cheb_tables(p, prec, slot_to_m(p, s), pmax);
+
+    const Tiling t = sweep_tiling(p);
+    const double esz_c = 2.0 * sizeof(R), esz_r = sizeof(R);
+    const double ksz = prec == AC_PREC_FP64 ? 8.0 : prec == AC_PREC_MIXED_BF16K ? 2.0 : 4.0;
+    const void* kap = prec == AC_PREC_FP64 ? static_cast<const void*>(p->k64)
+                      : prec == AC_PREC_MIXED_BF16K ? static_cast<const void*>(p->k16)
+                                                    : static_cast<const void*>(p->k32);
+    auto slot = [&](char* b, int s) { return reinterpret_cast<R*>(slot_ptr(p, prec, b, s)); };
+
+    // first step index and the operand kinds for step k (computing x_{k+1})
+    const int k_first = warm ? 0 : 1;
+    auto kinds = [&](int k, int& curk, int& prevk) {
+        if (warm) {
+            curk = ac::SRC_BUF;
+            prevk = (k == 0) ? ac::SRC_ZERO : ac::SRC_BUF;
+        } else {
+            curk = (k == 1) ? ac::SRC_RHAT : ac::SRC_BUF;
+            prevk = (k == 1) ? ac::SRC_ZERO : (k == 2) ? ac::SRC_RHAT : ac::SRC_BUF;
+        }
+    };
+    // location of a finished iterate x_q
+    auto fin_src = [&](int q, int& kind, char*& b) {
+        if (!warm && q == 1) {
+            kind = ac::SRC_RHAT;
+            b = rhat;
+        } else {
+            kind = ac::SRC_BUF;
+            b = buf[q % 2];
+        }
+    };
+
+    const bool fuse = (z != nullptr);
+    const int k_last = pmax - 1;  // step producing x_pmax
+    for (int k = k_first; k <= k_last; ++k) {
+        const bool final = fuse && (k == k_last);
+        ac::SweepArgs<R> a{};
+        a.g = p->g;
+        a.t = t;
+        a.kappa = kap;
+        int curk, prevk;
+        kinds(k, curk, prevk);
+        double bytes = 0.0;
+        bool anyc = false;
+        for (int s = 0; s < ns; ++s) {
+            fill_coef(a, s, cs[s], k);
+            a.rhat[s] = slot(rhat, s);
+            a.cur[s] = slot(buf[k % 2], s);
+            a.out[s] = slot(buf[(k + 1) % 2], s);
+            a.prev[s] = slot(buf[(k + 1) % 2], s);
+            const double esz = slot_is_real(p, s) ? esz_r : esz_c;
+            if (ps[s] >= k + 1) {
+                a.src[s] = ac::SRC_COMPUTE;
+                anyc = true;
+                bytes += sweep_bytes_per_point(curk, prevk, final, esz);
+            } else {
+                int kind;
+                char* b;
+                fin_src(ps[s], kind, b);
+                a.src[s] = kind;
+                a.fin[s] = slot(b, s);
+                if (final) bytes += esz;
+            }
+        }
+        if (anyc) bytes += ksz;
+        bytes *= static_cast<double>(p->g.n);
+        if (final) {
+            bytes += 8.0 * p->ell * p->g.n;
+            for (int kk = 0; kk < p->ell; ++kk)
+                a.ginv[kk] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(kk) / p->ell));
+            fill_twiddles(p->ell, a.cw, a.sw);
+            a.z = z;
+            ProfScope ps_(p->ctx, AC_K_CHEB_FINAL, bytes);
+            AC_HIP(ac::launch_cheb_final(p->ell, prec, curk, prevk, &a, p->ctx->stream));
+        } else {
+            ProfScope ps_(p->ctx, AC_K_CHEB_STEP, bytes);
+            AC_HIP(ac::launch_cheb_step(p->ell, prec, curk, prevk, &a, p->ctx->stream));
+        }
+    }
+    if (fuse && k_last < k_first) {
+        // nothing to iterate (cold start, every p = 1): x_1 = rhat/theta everywhere
+        ac::SweepArgs<R> a{};
+        a.g = p->g;
+        a.t = t;
+        a.kappa = kap;
+        double bytes = 0.0;
+        for (int s = 0; s < ns; ++s) {
+            fill_coef(a, s, cs[s], 0);
+            a.rhat[s] = slot(rhat, s);
+            a.src[s] = ac::SRC_RHAT;
+            a.fin[s] = slot(rhat, s);
+            bytes += slot_is_real(p, s) ? esz_r : esz_c;
+        }
+        bytes = bytes * p->g.n + 8.0 * p->ell * p->g.n;
+        for (int kk = 0; kk < p->ell; ++kk)
+            a.ginv[kk] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(kk) / p->ell));
+        fill_twiddles(p->ell, a.cw, a.sw);
+        a.z = z;
+        ProfScope ps_(p->ctx, AC_K_CHEB_FINAL, bytes);
+        AC_HIP(ac::launch_cheb_final(p->ell, prec, ac::SRC_RHAT, ac::SRC_ZERO, &a, p->ctx->stream));
+    }
+    if (where) {
+        where->clear();
+        for (int s = 0; s < ns; ++s) {
+            int kind;
+            char* b;
+            fin_src(ps[s], kind, b);
+            where->emplace_back(kind, b);
+        }
+    }
+    return AC_OK;
+}
+
+int run_cheb(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[2], bool warm, double* z,
+             std::vector<std::pair<int, char*>>* where) {
+    if (prec == AC_PREC_FP64) return run_cheb_t<double>(p, prec, pm, rhat, buf, warm, z, where);
+    return run_cheb_t<float>(p, prec, pm, rhat, buf, warm, z, where);
+}
+
+int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* r, double* z,
+                    void* ws, double in_scale) {
+    const PrecBufs b = carve_prec(p, o->precision, ws);
+    AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
+    AC_TRY(run_cheb(p, o->precision, pm, b.rhat, b.buf, false, z, nullptr));
+    return AC_OK;
+}
+
+int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double* partial) {
+    ac::CalAArgs a{};
+    a.g = p->g;
+    a.t = calA_tiling(p);
+    a.kappa = p->k64;
+    a.x = x;
+    a.y = y;
+    a.b = b;
+    a.partial = partial;
+    a.ell = p->ell;
+    const double bytes = (b ? 24.0 : 16.0) * p->ell * p->g.n + 8.0 * p->g.n;
+    ProfScope ps(p->ctx, AC_K_APPLY_CALA, bytes);
+    AC_HIP(ac::launch_apply_calA(p->ell, b != nullptr, a, p->ctx->stream));
+    return AC_OK;
+}
+
+long long calA_partials(const ac_problem* p) { return calA_tiling(p).tiles; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI (every definition below matches an extern "C" declaration of alphacirc.h)
+
+const char* ac_status_string(int s) {
+    switch (s) {
+        case AC_OK: return "ok";
+        case AC_NOT_CONVERGED: return "not converged";
+        case AC_ERR_ARG: return "invalid argument";
+        case AC_ERR_ALPHA: return "alpha outside (0, mu_lo^l)";
+        case AC_ERR_BOUNDS: return "invalid spectral bounds";
+        case AC_ERR_HIP: return "HIP runtime error";
+        case AC_ERR_WORKSPACE: return "workspace too small";
+        case AC_ERR_NONFINITE: return "non-finite or non-positive value";
+        case AC_ERR_UNSUPPORTED: return "unsupported configuration";
+        default: return "unknown status";
+    }
+}
+
+const char* ac_last_error(void) { return g_last_error.c_str(); }
+
+int ac_ctx_create(int device, void* stream, ac_ctx** out) {
+    if (!out) return fail(AC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    AC_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(AC_ERR_ARG, "device index out of range");
+    AC_HIP(hipSetDevice(device));
+    auto* c = new ac_ctx();
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(stream);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 8192 * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(AC_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return AC_OK;
+}
+
+int ac_ctx_destroy(ac_ctx* c) {
+    if (!c) return AC_OK;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (auto& p : c->pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto& p : c->pool) {
+        (void)hipEventDestroy(p.first);
+        (void)hipEventDestroy(p.second);
+    }
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    delete c;
+    return AC_OK;
+}
+
+int ac_ctx_set_stream(ac_ctx* c, void* stream) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    c->stream = static_cast<hipStream_t>(stream);
+    return AC_OK;
+}
+
+int ac_ctx_set_profiling(ac_ctx* c, int on) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    c->profiling = on != 0;
+    return AC_OK;
+}
+
+int ac_ctx_kernel_stats(ac_ctx* c, double* ms, long long* launches, double* bytes) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    AC_TRY(harvest(c));
+    for (int i = 0; i < AC_K_COUNT; ++i) {
+        if (ms) ms[i] = c->ms[i];
+        if (launches) launches[i] = c->launches[i];
+        if (bytes) bytes[i] = c->bytes[i];
+    }
+    return AC_OK;
+}
+
+int ac_ctx_reset_stats(ac_ctx* c) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    AC_TRY(harvest(c));
+    for (int i = 0; i < AC_K_COUNT; ++i) {
+        c->ms[i] = 0;
+        c->launches[i] = 0;
+        c->bytes[i] = 0;
+    }
+    return AC_OK;
+}
+
+int ac_problem_create(ac_ctx* c, const ac_grid* grid, const double* kappa, int ell, double alpha,
+                      const ac_bounds* bounds, ac_problem** out) {
+    if (!out) return fail(AC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!c || !grid || !kappa) return fail(AC_ERR_ARG, "NULL argument");
+    if (grid->dim != 1 && grid->dim != 2) return fail(AC_ERR_ARG, "dim must be 1 or 2");
+    if (grid->nx < 1 || grid->ny < 1) return fail(AC_ERR_ARG, "grid sizes must be positive");
+    if (grid->dim == 1 && grid->ny != 1) return fail(AC_ERR_ARG, "dim 1 needs ny == 1");
+    if (grid->bc != AC_BC_DIRICHLET && grid->bc != AC_BC_PERIODIC) return fail(AC_ERR_ARG, "unknown boundary");
+    if (ell < 2 || ell > kMaxEll) return fail(AC_ERR_UNSUPPORTED, "l must be in [2, 16]");
+    if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(AC_ERR_ALPHA, "alpha must be positive and finite");
+    if (static_cast<long long>(grid->nx) * grid->ny > (1LL << 31) - 1) return fail(AC_ERR_UNSUPPORTED, "N too large");
+    AC_HIP(hipSetDevice(c->device));
+
+    auto* p = new ac_problem();
+    p->ctx = c;
+    p->g.nx = grid->nx;
+    p->g.ny = grid->ny;
+    p->g.dim = grid->dim;
+    p->g.periodic = grid->bc == AC_BC_PERIODIC;
+    p->g.n = static_cast<long long>(grid->nx) * grid->ny;
+    p->ell = ell;
+    p->alpha = alpha;
+    p->nsr = (ell % 2 == 0) ? 2 : 1;
+    p->nsc = (ell - p->nsr) / 2;
+    p->ns = p->nsr + p->nsc;
+    const size_t n = static_cast<size_t>(p->g.n);
+    const int nblk = ac::setup_blocks();
+    double* partial = nullptr;
+    auto cleanup = [&]() {
+        if (p->k64) (void)hipFree(p->k64);
+        if (p->k32) (void)hipFree(p->k32);
+        if (p->k16) (void)hipFree(p->k16);
+        if (partial) (void)hipFree(partial);
+        delete p;
+    };
+    hipError_t e = hipMalloc(&p->k64, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&p->k32, align_up(n * sizeof(float), 256));
+    if (e == hipSuccess) e = hipMalloc(&p->k16, align_up(n * sizeof(uint16_t), 256));
+    if (e == hipSuccess) e = hipMalloc(&partial, nblk * 7 * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(p->k64, kappa, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = ac::launch_kappa_setup(p->g, p->k64, p->k32, p->k16, partial, nblk, c->stream);
+    std::vector<double> h(nblk * 7);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h.data(), partial, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(AC_ERR_HIP, std::string("problem set-up: ") + hipGetErrorString(e));
+    }
+    (void)hipFree(partial);
+    partial = nullptr;
+    double q[7] = {1e308, 0, 1e308, 0, 1e308, 0, 0};
+    for (int b = 0; b < nblk; ++b) {
+        for (int i = 0; i < 6; ++i) q[i] = (i % 2 == 0) ? std::min(q[i], h[b * 7 + i]) : std::max(q[i], h[b * 7 + i]);
+        q[6] += h[b * 7 + 6];
+    }
+    if (q[6] != 0.0 || !(q[0] > 0.0)) {
+        cleanup();
+        return fail(AC_ERR_NONFINITE, "kappa must be finite and positive everywhere");
+    }
+    // lambda_min of the integer -Delta_h stencil (Dirichlet), 0 for periodic
+    double lmin = 0.0;
+    if (!p->g.periodic) {
+        lmin = 4.0 * std::pow(std::sin(kPi / (2.0 * (p->g.nx + 1))), 2);
+        if (p->g.dim == 2) lmin += 4.0 * std::pow(std::sin(kPi / (2.0 * (p->g.ny + 1))), 2);
+    }
+    p->kmin64 = q[0];
+    if (bounds) {
+        if (!(bounds->mu_lo >= 1.0 - 1e-12) || !(bounds->mu_hi >= bounds->mu_lo) || !std::isfinite(bounds->mu_hi)) {
+            cleanup();
+            return fail(AC_ERR_BOUNDS, "need 1 <= mu_lo <= mu_hi < inf");
+        }
+        for (int i = 0; i < 3; ++i) {
+            p->bounds[i][0] = bounds->mu_lo;
+            p->bounds[i][1] = bounds->mu_hi;
+        }
+    } else {
+        p->bounds[AC_PREC_FP64][0] = 1.0 + q[0] * lmin;
+        p->bounds[AC_PREC_FP64][1] = q[1];
+        p->bounds[AC_PREC_MIXED_FP32K][0] = 1.0 + q[2] * lmin;
+        p->bounds[AC_PREC_MIXED_FP32K][1] = q[3];
+        p->bounds[AC_PREC_MIXED_BF16K][0] = 1.0 + q[4] * lmin;
+        p->bounds[AC_PREC_MIXED_BF16K][1] = q[5];
+    }
+    // Corollary 1 / Lemma 1: 0 < alpha < mu_lo^l (alpha != mu_j^l for all j)
+    const double mulo = std::min({p->bounds[0][0], p->bounds[1][0], p->bounds[2][0]});
+    if (!(alpha < std::pow(mulo, ell))) {
+        cleanup();
+        return fail(AC_ERR_ALPHA, "alpha must satisfy 0 < alpha < mu_lo^l");
+    }
+    *out = p;
+    return AC_OK;
+}
+
+int ac_problem_destroy(ac_problem* p) {
+    if (!p) return AC_OK;
+    (void)hipSetDevice(p->ctx->device);
+    (void)hipStreamSynchronize(p->ctx->stream);
+    (void)hipFree(p->k64);
+    (void)hipFree(p->k32);
+    (void)hipFree(p->k16);
+    delete p;
+    return AC_OK;
+}
+
+int ac_spectral_bounds(const ac_problem* p, double* lo, double* hi) {
+    if (!p) return fail(AC_ERR_ARG, "problem is NULL");
+    if (lo) *lo = p->bounds[AC_PREC_FP64][0];
+    if (hi) *hi = p->bounds[AC_PREC_FP64][1];
+    return AC_OK;
+}
+
+int ac_problem_dims(const ac_problem* p, long long* n, int* ell, int* ns) {
+    if (!p) return fail(AC_ERR_ARG, "problem is NULL");
+    if (n) *n = p->g.n;
+    if (ell) *ell = p->ell;
+    if (ns) *ns = p->ns;
+    return AC_OK;
+}
+
+int ac_alloc_nc2(const ac_problem* p, double budget, int* out) {
+    if (!p || !out) return fail(AC_ERR_ARG, "NULL argument");
+    if (!(budget > 0)) return fail(AC_ERR_ARG, "budget must be positive");
+    const double lo = p->bounds[AC_PREC_FP64][0], hi = p->bounds[AC_PREC_FP64][1];
+    std::vector<double> r(p->ell);
+    double sum = 0.0;
+    auto sigma = [&](double re) {
+        const double k = (hi - re) / (lo - re);
+        return (std::sqrt(k) - 1.0) / (std::sqrt(k) + 1.0);
+    };
+    const double a1 = std::pow(p->alpha, 1.0 / p->ell);
+    const double s0 = sigma(a1);
+    for (int m = 0; m < p->ell; ++m) {
+        const double re = a1 * std::cos(2.0 * kPi * m / p->ell);
+        r[m] = std::log(s0) / std::log(sigma(re));
+        sum += r[m];
+    }
+    for (int m = 0; m < p->ell; ++m) out[m] = std::max(1, static_cast<int>(std::floor(r[m] / sum * budget)));
+    return AC_OK;
+}
+
+int ac_alloc_nc1(const ac_problem* p, double budget, int* out) {
+    if (!p || !out) return fail(AC_ERR_ARG, "NULL argument");
+    if (!(budget > 0)) return fail(AC_ERR_ARG, "budget must be positive");
+    const int v = std::max(1, static_cast<int>(std::floor(budget / p->ell)));
+    for (int m = 0; m < p->ell; ++m) out[m] = v;
+    return AC_OK;
+}
+
+int ac_prec_workspace_size(const ac_problem* p, const ac_solve_opts* o, size_t* bytes) {
+    if (!p || !o || !bytes) return fail(AC_ERR_ARG, "NULL argument");
+    if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
+    *bytes = prec_ws_bytes(p, o->precision);
+    return AC_OK;
+}
+
+namespace {
+struct SolveWs {
+    double* V[ac::kMaxBasis];
+    double* Z[ac::kMaxBasis];
+    double* partial;   // krylov_blocks * 40
+    double* partial2;  // calA tiles
+    double* red;       // 128 reduced scalars
+    void* prec;
+};
+size_t vec_bytes(const ac_problem* p) { return align_up(static_cast<size_t>(p->ell) * p->g.n * sizeof(double), 256); }
+size_t solve_ws_bytes(const ac_problem* p, const ac_solve_opts* o) {
+    const int m = o->restart_m;
+    size_t b = 256;
+    b += static_cast<size_t>(2 * m + 1) * vec_bytes(p);
+    b += align_up(static_cast<size_t>(ac::krylov_blocks()) * 40 * sizeof(double), 256);
+    b += align_up(static_cast<size_t>(calA_partials(p)) * sizeof(double), 256);
+    b += align_up(128 * sizeof(double), 256);
+    b += prec_ws_bytes(p, o->precision);
+    return b;
+}
+SolveWs carve_solve(const ac_problem* p, const ac_solve_opts* o, void* ws) {
+    SolveWs w{};
+    char* b = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
+    const size_t vb = vec_bytes(p);
+    for (int i = 0; i <= o->restart_m; ++i, b += vb) w.V[i] = reinterpret_cast<double*>(b);
+    for (int i = 0; i < o->restart_m; ++i, b += vb) w.Z[i] = reinterpret_cast<double*>(b);
+    w.partial = reinterpret_cast<double*>(b);
+    b += align_up(static_cast<size_t>(ac::krylov_blocks()) * 40 * sizeof(double), 256);
+    w.partial2 = reinterpret_cast<double*>(b);
+    b += align_up(static_cast<size_t>(calA_partials(p)) * sizeof(double), 256);
+    w.red = reinterpret_cast<double*>(b);
+    b += align_up(128 * sizeof(double), 256);
+    w.prec = b;
+    return w;
+}
+}  // namespace
+
+int ac_solve_workspace_size(const ac_problem* p, const ac_solve_opts* o, size_t* bytes) {
+    if (!p || !o || !bytes) return fail(AC_ERR_ARG, "NULL argument");
+    if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
+    if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
+    *bytes = solve_ws_bytes(p, o);
+    return AC_OK;
+}
+
+int ac_apply_A(ac_problem* p, const double* x, double* y) {
+    if (!p || !x || !y) return fail(AC_ERR_ARG, "NULL argument");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    return calA_impl(p, x, y, nullptr, nullptr);
+}
+
+int ac_apply_prec(ac_problem* p, const ac_solve_opts* o, const double* r, double* z, void* ws, size_t ws_bytes) {
+    if (!p || !r || !z) return fail(AC_ERR_ARG, "NULL argument");
+    std::vector<int> pm;
+    AC_TRY(validate_opts(p, o, pm));
+    if (!ws || ws_bytes < prec_ws_bytes(p, o->precision)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    return apply_prec_impl(p, o, pm, r, z, ws, 1.0);
+}
+
+int ac_spectral_offsets(const ac_problem* p, int prec, long long* offsets) {
+    if (!p || !offsets) return fail(AC_ERR_ARG, "NULL argument");
+    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
+    spectral_offsets(p, offsets);
+    return AC_OK;
+}
+
+int ac_tdft_forward(ac_problem* p, int prec, const double* r, void* rhat) {
+    if (!p || !r || !rhat) return fail(AC_ERR_ARG, "NULL argument");
+    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    return run_fwd(p, prec, r, static_cast<char*>(rhat), 1.0);
+}
+
+namespace {
+__global__ void zero_kernel(double* x, long long n) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
+}
+
+template <typename R>
+__global__ void scale_copy_kernel(R* dst, const R* src, long long n, int cplx_, R sr, R si) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cplx_) {
+        const R a = src[2 * i], b = src[2 * i + 1];
+        dst[2 * i] = sr * a - si * b;
+        dst[2 * i + 1] = sr * b + si * a;
+    } else {
+        dst[i] = sr * src[i];
+    }
+}
+
+template <typename R>
+int gather_t(ac_problem* p, int prec, const std::vector<std::pair<int, char*>>& where, char* rhat, char* yhat) {
+    const int blocks = static_cast<int>((p->g.n + 255) / 256);
+    for (int s = 0; s < p->ns; ++s) {
+        const int m = slot_to_m(p, s);
+        const ChebShift cs = cheb_tables(p, prec, m, 1);
+        const cplx sc = where[s].first == ac::SRC_RHAT ? 1.0 / cs.theta : cplx(1.0);
+        R* dst = reinterpret_cast<R*>(slot_ptr(p, prec, yhat, s));
+        const R* src = reinterpret_cast<const R*>(slot_ptr(p, prec, where[s].second, s));
+        hipLaunchKernelGGL((scale_copy_kernel<R>), dim3(blocks), dim3(256), 0, p->ctx->stream, dst, src, p->g.n,
+                           slot_is_real(p, s) ? 0 : 1, static_cast<R>(sc.real()), static_cast<R>(sc.imag()));
+        AC_HIP(hipGetLastError());
+    }
+    (void)rhat;
+    return AC_OK;
+}
+}  // namespace
+
+int ac_shifted_cheb(ac_problem* p, const ac_solve_opts* o, const void* rhat, const void* x0hat, void* yhat, void* ws,
+                    size_t ws_bytes) {
+    if (!p || !rhat || !yhat) return fail(AC_ERR_ARG, "NULL argument");
+    std::vector<int> pm;
+    AC_TRY(validate_opts(p, o, pm));
+    if (!ws || ws_bytes < prec_ws_bytes(p, o->precision)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    const int prec = o->precision;
+    PrecBufs b = carve_prec(p, prec, ws);
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    const size_t sbytes = static_cast<size_t>(off[p->ns]) * inner_elem(prec);
+    AC_HIP(hipMemcpyAsync(b.rhat, rhat, sbytes, hipMemcpyDeviceToDevice, p->ctx->stream));
+    const bool warm = x0hat != nullptr;
+    if (warm) AC_HIP(hipMemcpyAsync(b.buf[0], x0hat, sbytes, hipMemcpyDeviceToDevice, p->ctx->stream));
+    std::vector<std::pair<int, char*>> where;
+    AC_TRY(run_cheb(p, prec, pm, b.rhat, b.buf, warm, nullptr, &where));
+    if (prec == AC_PREC_FP64) return gather_t<double>(p, prec, where, b.rhat, static_cast<char*>(yhat));
+    return gather_t<float>(p, prec, where, b.rhat, static_cast<char*>(yhat));
+}
+
+int ac_tdft_inverse(ac_problem* p, int prec, const void* yhat, double* z) {
+    if (!p || !yhat || !z) return fail(AC_ERR_ARG, "NULL argument");
+    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    ac::InvArgs a{};
+    a.n = p->g.n;
+    for (int k = 0; k < p->ell; ++k) a.ginv[k] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(k) / p->ell));
+    fill_twiddles(p->ell, a.cw, a.sw);
+    for (int s = 0; s < p->ns; ++s) a.yhat[s] = slot_ptr(p, prec, const_cast<char*>(static_cast<const char*>(yhat)), s);
+    a.z = z;
+    AC_HIP(ac::launch_tdft_inv(p->ell, prec, a, p->ctx->stream));
+    return AC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// FGMRES
+
+int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
+             ac_solve_info* info) {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!p || !b || !x) return fail(AC_ERR_ARG, "NULL argument");
+    std::vector<int> pm;
+    AC_TRY(validate_opts(p, o, pm));
+    if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
+    if (!(o->tol > 0.0)) return fail(AC_ERR_ARG, "tol must be positive");
+    if (o->max_outer < 1) return fail(AC_ERR_ARG, "max_outer must be >= 1");
+    if (!ws || ws_bytes < solve_ws_bytes(p, o)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    ac_ctx* c = p->ctx;
+    hipStream_t st = c->stream;
+    const int m = o->restart_m;
+    const long long len = static_cast<long long>(p->ell) * p->g.n;
+    SolveWs w = carve_solve(p, o, ws);
+    const int kb = ac::krylov_blocks();
+    const int ptiles = static_cast<int>(calA_partials(p));
+    long long psum = 0;
+    for (int v : pm) psum += v;
+    long long matvecs = 0;
+
+    auto fetch = [&](int nq) -> int {
+        AC_HIP(hipMemcpyAsync(c->pinned, w.red, nq * sizeof(double), hipMemcpyDeviceToHost, st));
+        AC_HIP(hipStreamSynchronize(st));
+        return AC_OK;
+    };
+    // ||b||
+    {
+        ProfScope ps(c, AC_K_KRYLOV, 8.0 * len);
+        AC_HIP(ac::launch_norm2(b, len, w.partial, st));
+        AC_HIP(ac::launch_reduce(w.partial, kb, 1, 1, w.red, st));
+    }
+    AC_TRY(fetch(1));
+    const double bnorm = std::sqrt(c->pinned[0]);
+    if (!std::isfinite(bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
+    auto residual = [&](double& beta) -> int {
+        AC_TRY(calA_impl(p, x, w.V[0], b, w.partial2));
+        AC_HIP(ac::launch_reduce(w.partial2, ptiles, 1, 1, w.red, st));
+        AC_TRY(fetch(1));
+        beta = std::sqrt(c->pinned[0]);
+        matvecs += p->ell;
+        return AC_OK;
+    };
+    if (bnorm == 0.0) {
+        hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((len + 255) / 256)), dim3(256), 0, st, x, len);
+        AC_HIP(hipGetLastError());
+        AC_HIP(hipStreamSynchronize(st));
+        if (info) {
+            *info = ac_solve_info{};
+        }
+        return AC_OK;
+    }
+    double beta = 0;
+    AC_TRY(residual(beta));
+    int total = 0, restarts = 0;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), s2(m + 1), scale(m + 1), y(m);
+    int status = AC_OK;
+    while (true) {
+        if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
+        if (beta / bnorm <= o->tol) break;
+        if (total >= o->max_outer) {
+            status = AC_NOT_CONVERGED;
+            break;
+        }
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        scale[0] = 1.0 / beta;
+        int kdone = 0;
+        for (int j = 0; j < m; ++j) {
+            // z_j = P^{-1} v_j with v_j = scale_j * V_j (scale folded into the transform)
+            {
+                const PrecBufs pb = carve_prec(p, o->precision, w.prec);
+                AC_TRY(run_fwd(p, o->precision, w.V[j], pb.rhat, scale[j]));
+                AC_TRY(run_cheb(p, o->precision, pm, pb.rhat, pb.buf, false, w.Z[j], nullptr));
+            }
+            AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
+            matvecs += p->ell + psum;
+            ac::VecSet vs{};
+            for (int i = 0; i <= j; ++i) {
+                vs.v[i] = w.V[i];
+                vs.s2[i] = scale[i] * scale[i];
+            }
+            const int nv = j + 1;
+            double* d1 = w.red;
+            double* d2 = w.red + 40;
+            double* nr = w.red + 80;
+            {
+                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 1));
+                AC_HIP(ac::launch_mdot(vs, nv, w.V[j + 1], len, w.partial, 40, st));
+                AC_HIP(ac::launch_reduce(w.partial, kb, nv, 40, d1, st));
+            }
+            {
+                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 2));
+                AC_HIP(ac::launch_axpy_dot(vs, nv, d1, w.V[j + 1], len, w.partial, 40, st));
+                AC_HIP(ac::launch_reduce(w.partial, kb, nv, 40, d2, st));
+            }
+            {
+                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 2));
+                AC_HIP(ac::launch_axpy_norm(vs, nv, d2, w.V[j + 1], len, w.partial, 40, st));
+                AC_HIP(ac::launch_reduce(w.partial, kb, 1, 40, nr, st));
+            }
+            AC_TRY(fetch(81));
+            const double* hd = c->pinned;
+            for (int i = 0; i <= j; ++i) H[i * m + j] = scale[i] * (hd[i] + hd[40 + i]);
+            const double hn = std::sqrt(hd[80]);
+            if (!std::isfinite(hn)) return fail(AC_ERR_NONFINITE, "Arnoldi produced a non-finite value");
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
+                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
+                H[i * m + j] = t;
+            }
+            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+            cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
+            sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
+            H[j * m + j] = den;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++total;
+            kdone = j + 1;
+            if (std::abs(g[j + 1]) / bnorm <= o->tol || total >= o->max_outer || hn == 0.0) break;
+            scale[j + 1] = 1.0 / hn;
+        }
+        // back substitution and x += Z y
+        for (int i = kdone - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int k = i + 1; k < kdone; ++k) t -= H[i * m + k] * y[k];
+            y[i] = H[i * m + i] != 0.0 ? t / H[i * m + i] : 0.0;
+        }
+        {
+            ac::VecSet zs{};
+            for (int i = 0; i < kdone; ++i) {
+                zs.v[i] = w.Z[i];
+                zs.s2[i] = y[i];
+            }
+            ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (kdone + 2));
+            AC_HIP(ac::launch_maxpy(zs, kdone, nullptr, x, len, st));
+        }
+        ++restarts;
+        AC_TRY(residual(beta));
+    }
+    if (info) {
+        info->outer_iters = total;
+        info->restarts = restarts;
+        info->matvecs_A = matvecs;
+        info->rel_residual_true = beta / bnorm;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->cnn_fallbacks = 0;
+        info->reserved = 0;
+    }
+    return status;
+}
+
+// ---------------------------------------------------------------------------
+// tiling control (used by the tile tuner)
+int ac_ctx_set_tiling(ac_ctx* c, int rows_per_wave, int waves_per_block, int points_per_lane) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
+    if (waves_per_block < 0 || waves_per_block > 4) return fail(AC_ERR_ARG, "waves_per_block must be 0..4");
+    if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
+    c->tile_h = rows_per_wave;
+    c->tile_wpb = waves_per_block;
+    c->tile_vx = points_per_lane;
+    return AC_OK;
+}

@@ -1,0 +1,215 @@
+"""GPU parity: every stage of the hot path through the C ABI against the oracle.
+
+Inputs come from synth (seeded); expected values from oracle/ only.  Sizes span
+several tiles (strips of 64 or 128 columns, chunks of 16 rows) and ragged tails
+in x and y.  Tolerances:
+* float64 paths: 1e-12 relative (norm-wise and max-element), the rounding of a
+  few hundred float64 operations per output;
+* complex64 paths: a bound derived from float32 unit roundoff (6e-8) times the
+  growth of the scaled transforms (cond(U^* Gamma) = alpha^{-(l-1)/l}, Fig. 2)
+  times the number of Chebyshev steps, stated per test.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import precond as pc
+from oracle.precision import to_bfloat16, to_float32
+from paper_2506_03947_amd import api
+from synth import lognormal_kappa, random_block_vector
+from tests import gpu_util as G
+
+L = api.L
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # dim, nx, ny, ell, alpha, bc, kappa kind
+    (1, 256, 1, 4, 1e-2, "dirichlet", "const25"),
+    (1, 300, 1, 5, 1e-1, "dirichlet", "lognormal"),
+    (2, 37, 29, 3, 1e-2, "dirichlet", "lognormal"),
+    (2, 130, 45, 10, 1e-2, "dirichlet", "lognormal"),
+    (2, 256, 33, 6, 1e-3, "dirichlet", "lognormal"),
+    (2, 20, 17, 4, 0.5, "periodic", "lognormal"),
+    (2, 128, 20, 2, 1e-2, "periodic", "const"),
+    (2, 64, 64, 16, 1e-2, "dirichlet", "lognormal"),
+]
+
+
+def _kappa(dim, nx, ny, kind, seed=0):
+    if kind == "const25":
+        return np.full(nx * ny, 25.0)
+    if kind == "const":
+        return np.full(nx * ny, 7.5)
+    return lognormal_kappa(nx, ny, 20.0, 5.0, 1.0, seed=seed)
+
+
+def _setup(case, seed=0):
+    dim, nx, ny, ell, alpha, bc, kind = case
+    kap = _kappa(dim, nx, ny, kind, seed)
+    bcode = L.AC_BC_PERIODIC if bc == "periodic" else L.AC_BC_DIRICHLET
+    A = ops.build_A(dim, nx, ny, kap, bc)
+    lo, hi = ops.spectral_interval(dim, nx, ny, kap, bc)
+    p = G.problem(dim, nx, ny, kap, ell, alpha, bc=bcode, bounds=(lo, hi))
+    return p, A, kap, lo, hi
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}_{c[5]}")
+def test_apply_calA(case):
+    p, A, kap, lo, hi = _setup(case)
+    ell = case[3]
+    x = random_block_vector(p.n, ell, seed=3)
+    y = G.dev(np.zeros_like(x))
+    api.ac_apply_A(p, G.dev(x), y)
+    ref = ops.apply_calA(A, x, ell)
+    got = G.host(y)
+    assert G.max_rel(got, ref) < 1e-13
+    assert G.rel(got, ref) < 1e-13
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}_{c[5]}")
+def test_device_bounds_match_oracle(case):
+    dim, nx, ny, ell, alpha, bc, kind = case
+    kap = _kappa(dim, nx, ny, kind)
+    bcode = L.AC_BC_PERIODIC if bc == "periodic" else L.AC_BC_DIRICHLET
+    p = G.problem(dim, nx, ny, kap, ell, alpha, bc=bcode)
+    lo, hi = api.ac_spectral_bounds(p)
+    olo, ohi = ops.spectral_interval(dim, nx, ny, kap, bc)
+    assert abs(lo - olo) <= 1e-12 * olo and abs(hi - ohi) <= 1e-12 * ohi
+
+
+@pytest.mark.parametrize("prec", [L.AC_PREC_FP64, L.AC_PREC_MIXED_FP32K])
+@pytest.mark.parametrize("case", CASES[:6], ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}")
+def test_tdft_forward(case, prec):
+    p, A, kap, lo, hi = _setup(case)
+    ell, alpha = case[3], case[4]
+    r = random_block_vector(p.n, ell, seed=4)
+    off = api.ac_spectral_offsets(p, prec)
+    rhat = G.dev(np.zeros(off[-1], dtype=np.float64 if prec == 0 else np.float32))
+    api.ac_tdft_forward(p, prec, G.dev(r), rhat)
+    got = [G.host(t) for t in api.spectral_to_complex(p, prec, rhat)]
+    ref = pc.forward_transform(r, ell, alpha)
+    tol = 1e-13 if prec == 0 else 2e-7
+    for m in range(p.ns):
+        assert G.max_rel(got[m], ref[m]) < tol, m
+
+
+@pytest.mark.parametrize("prec", [L.AC_PREC_FP64, L.AC_PREC_MIXED_FP32K])
+@pytest.mark.parametrize("case", CASES[:6], ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}")
+def test_tdft_inverse(case, prec):
+    p, A, kap, lo, hi = _setup(case)
+    ell, alpha = case[3], case[4]
+    rng = np.random.default_rng(5)
+    yh = []
+    for m in range(p.ns):
+        real = (m == 0) or (ell % 2 == 0 and m == ell // 2)
+        v = rng.standard_normal(p.n) + (0 if real else 1j * rng.standard_normal(p.n))
+        if prec != 0:
+            v = v.astype(np.complex64).astype(np.complex128)
+        yh.append(v)
+    full = np.zeros((ell, p.n), dtype=np.complex128)
+    for m in range(ell):
+        full[m] = yh[m] if m < p.ns else np.conj(yh[ell - m])
+    ref = pc.inverse_transform(full, ell, alpha).real
+    import torch
+    buf = api.complex_to_spectral(p, prec, [torch.from_numpy(v).to("cuda:0") for v in yh])
+    z = G.dev(np.zeros(ell * p.n))
+    api.ac_tdft_inverse(p, prec, buf, z)
+    got = G.host(z)
+    tol = 1e-13 if prec == 0 else 1e-13  # float32 inputs are exact in float64 arithmetic
+    assert G.max_rel(got, ref) < tol
+
+
+def _cheb_ref(A, rhat_m, lam, lo, hi, pm, x0=None):
+    theta, delta = pc.cheb_centre(lo, hi, lam)
+    return pc.chebyshev_solve(lambda v: A @ v - lam * v, rhat_m, theta, delta, pm, x0)
+
+
+@pytest.mark.parametrize("warm", [False, True])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}_{c[5]}")
+def test_shifted_cheb_fp64(case, warm):
+    import torch
+    p, A, kap, lo, hi = _setup(case)
+    ell, alpha = case[3], case[4]
+    rng = np.random.default_rng(6)
+    # uneven counts, equal on conjugate pairs (NC2-like), including p = 1 and p = 2
+    base = [1, 2, 3, 5, 7, 4, 6, 9, 2]
+    pm = [base[min(m, ell - m) % len(base)] + (0 if m else 3) for m in range(ell)]
+    rh = []
+    for m in range(p.ns):
+        real = (m == 0) or (ell % 2 == 0 and m == ell // 2)
+        rh.append(rng.standard_normal(p.n) + (0 if real else 1j * rng.standard_normal(p.n)))
+    x0 = None
+    if warm:
+        x0 = []
+        for m in range(p.ns):
+            real = (m == 0) or (ell % 2 == 0 and m == ell // 2)
+            x0.append(0.1 * (rng.standard_normal(p.n) + (0 if real else 1j * rng.standard_normal(p.n))))
+    opts = api.Opts(precision=L.AC_PREC_FP64, p=pm)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    rbuf = api.complex_to_spectral(p, 0, [torch.from_numpy(v).to("cuda:0") for v in rh])
+    xbuf = None if x0 is None else api.complex_to_spectral(p, 0, [torch.from_numpy(v).to("cuda:0") for v in x0])
+    ybuf = torch.zeros_like(rbuf)
+    api.ac_shifted_cheb(p, opts, rbuf, xbuf, ybuf, ws)
+    got = [G.host(t) for t in api.spectral_to_complex(p, 0, ybuf)]
+    lam = pc.shifts(ell, alpha)
+    for m in range(p.ns):
+        ref = _cheb_ref(A, rh[m], lam[m], lo, hi, pm[m], None if x0 is None else x0[m])
+        assert G.max_rel(got[m], ref) < 1e-12, (m, pm[m])
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}_{c[5]}")
+@pytest.mark.parametrize("pspec", ["uniform1", "uniform2", "uniform3", "uniform10", "nc2"])
+def test_apply_prec_fp64(case, pspec):
+    p, A, kap, lo, hi = _setup(case)
+    ell, alpha = case[3], case[4]
+    if pspec == "nc2":
+        pm = api.ac_alloc_nc2(p, 6.0 * ell)
+    else:
+        pm = [int(pspec[7:])] * ell
+    r = random_block_vector(p.n, ell, seed=7)
+    opts = api.Opts(precision=L.AC_PREC_FP64, p=pm)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    z = G.dev(np.zeros_like(r))
+    api.ac_apply_prec(p, opts, G.dev(r), z, ws)
+    ref = pc.apply_prec_nc(A, r, ell, alpha, lo, hi, pm)
+    got = G.host(z)
+    assert G.max_rel(got, ref) < 1e-12
+    assert G.rel(got, ref) < 1e-12
+
+
+@pytest.mark.parametrize("prec", [L.AC_PREC_MIXED_FP32K, L.AC_PREC_MIXED_BF16K])
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}_{c[5]}")
+def test_apply_prec_mixed(case, prec):
+    """complex64 inner solve against the float64 oracle run on the same rounded
+    coefficients.  Bound: 64 u_32 cond(U^* Gamma) (p + 1), u_32 = 2^-24."""
+    dim, nx, ny, ell, alpha, bc, kind = case
+    kap = _kappa(dim, nx, ny, kind)
+    kq = to_float32(kap) if prec == L.AC_PREC_MIXED_FP32K else to_bfloat16(kap)
+    bcode = L.AC_BC_PERIODIC if bc == "periodic" else L.AC_BC_DIRICHLET
+    lo, hi = ops.spectral_interval(dim, nx, ny, kq, bc)
+    p = G.problem(dim, nx, ny, kap, ell, alpha, bc=bcode, bounds=(lo, hi))
+    Aq = ops.build_A(dim, nx, ny, kq, bc)
+    pp = 8
+    r = random_block_vector(p.n, ell, seed=8)
+    opts = api.Opts(precision=prec, p=pp)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    z = G.dev(np.zeros_like(r))
+    api.ac_apply_prec(p, opts, G.dev(r), z, ws)
+    ref = pc.apply_prec_nc(Aq, r, ell, alpha, lo, hi, pp)
+    tol = 64 * 2.0 ** -24 * alpha ** (-(ell - 1) / ell) * (pp + 1)
+    assert G.rel(G.host(z), ref) < tol
+
+
+def test_prec_is_linear_and_deterministic():
+    case = CASES[3]
+    p, A, kap, lo, hi = _setup(case)
+    ell = case[3]
+    opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=6)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    r1 = G.dev(random_block_vector(p.n, ell, seed=9))
+    z1 = G.dev(np.zeros(ell * p.n))
+    z2 = G.dev(np.zeros(ell * p.n))
+    api.ac_apply_prec(p, opts, r1, z1, ws)
+    api.ac_apply_prec(p, opts, r1, z2, ws)
+    assert np.array_equal(G.host(z1), G.host(z2))
