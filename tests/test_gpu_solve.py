@@ -1,0 +1,194 @@
+"""GPU end-to-end solves and error handling through the C ABI.
+
+The all-at-once solution is unique (block lower-triangular calA with SPD blocks),
+so every converged solve is compared with the oracle's sequential direct solve
+(Section 1).  Error bound: ||x - x*|| / ||x*|| <= cond(calA) * tol; float64 solves
+stop at 1e-12 and must match to 1e-10, mixed-precision solves stop at 1e-10 and
+must match to 1e-6.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import operators as ops
+from oracle import precond as pc
+from oracle.alloc import alg1_allocation, nc1_allocation
+from oracle.krylov import fgmres
+from oracle.precision import to_bfloat16
+from paper_2506_03947_amd import api
+from synth import first_block_rhs, lognormal_kappa, random_block_vector
+from tests import gpu_util as G
+
+L = api.L
+pytestmark = pytest.mark.gpu
+
+
+def _solve(p, b, precision, pp, tol, m=30, max_outer=2000):
+    opts = api.Opts(precision=precision, p=pp, tol=tol, restart_m=m, max_outer=max_outer)
+    ws = api.workspace(api.ac_solve_workspace_size(p, opts))
+    x = G.dev(np.zeros_like(b))
+    info = api.ac_solve(p, opts, G.dev(b), x, ws)
+    return G.host(x), info
+
+
+def test_config1_fp64_cheb20():
+    """1D, N = 256, kappa = 25, l = 4, alpha = 1e-2, b_1 ~ N(0,1) seed 0, Chebyshev-20, float64."""
+    n, ell, alpha = 256, 4, 1e-2
+    kap = np.full(n, 25.0)
+    A = ops.build_A(1, n, 1, kap)
+    lo, hi = ops.spectral_interval(1, n, 1, kap)
+    b = first_block_rhs(n, ell, seed=0)
+    p = G.problem(1, n, 1, kap, ell, alpha)
+    x, info = _solve(p, b, L.AC_PREC_FP64, 20, 1e-12)
+    x_seq = ops.sequential_solve(A, b, ell)
+    assert info["converged"] and info["rel_residual_true"] <= 1e-12
+    assert G.rel(x, x_seq) < 1e-10
+    # same preconditioned Krylov method on the CPU: iteration counts agree
+    xo, io = fgmres(lambda v: ops.apply_calA(A, v, ell), b,
+                    lambda r: pc.apply_prec_nc(A, r, ell, alpha, lo, hi, 20), tol=1e-12, m=30)
+    assert abs(info["outer_iters"] - io["iterations"]) <= 1
+
+
+@pytest.mark.parametrize("alpha", [1e-1, 1e-2, 1e-3])
+@pytest.mark.parametrize("precision", [L.AC_PREC_FP64, L.AC_PREC_MIXED_BF16K, L.AC_PREC_MIXED_FP32K])
+def test_2d_lognormal_solve(alpha, precision):
+    nx, ny, ell = 160, 96, 10
+    kap = lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=0)
+    A = ops.build_A(2, nx, ny, kap)
+    b = first_block_rhs(nx * ny, ell, seed=0)
+    p = G.problem(2, nx, ny, kap, ell, alpha)
+    tol = 1e-12 if precision == L.AC_PREC_FP64 else 1e-10
+    x, info = _solve(p, b, precision, 10, tol)
+    x_seq = ops.sequential_solve(A, b, ell)
+    assert info["converged"], info
+    assert G.rel(x, x_seq) < (1e-10 if precision == L.AC_PREC_FP64 else 1e-6)
+
+
+def test_restart_and_nc2_counts():
+    nx, ny, ell, alpha = 64, 48, 6, 1e-2
+    kap = lognormal_kappa(nx, ny, 10.0, 5.0, 0.5, seed=4)
+    A = ops.build_A(2, nx, ny, kap)
+    lo, hi = ops.spectral_interval(2, nx, ny, kap)
+    p = G.problem(2, nx, ny, kap, ell, alpha, bounds=(lo, hi))
+    budget = 48.0
+    assert list(api.ac_alloc_nc2(p, budget)) == list(alg1_allocation(ell, budget, lo, hi, alpha))
+    assert list(api.ac_alloc_nc1(p, budget)) == list(nc1_allocation(ell, budget))
+    pm = api.ac_alloc_nc2(p, budget)
+    b = first_block_rhs(nx * ny, ell, seed=1)
+    x, info = _solve(p, b, L.AC_PREC_FP64, pm, 1e-12, m=4)
+    assert info["restarts"] > 1 and info["converged"]
+    assert G.rel(x, ops.sequential_solve(A, b, ell)) < 1e-10
+    # matvec accounting (Table 1): l per calA product, sum of p over all l shifts per P^-1
+    it = info["outer_iters"]
+    assert info["matvecs_A"] == it * (ell + sum(pm)) + info["restarts"] * ell + ell
+
+
+def test_medium_config_mixed_matches_oracle():
+    """512 x 512, kappa0 = 50 exp(g), l = 10, alpha = 1e-2: complex64 + bfloat16 inner,
+    float64 FGMRES, against the sequential float64 solution."""
+    nx = ny = 512
+    ell, alpha = 10, 1e-2
+    kap = lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=0)
+    A = ops.build_A(2, nx, ny, kap)
+    b = first_block_rhs(nx * ny, ell, seed=0)
+    p = G.problem(2, nx, ny, kap, ell, alpha)
+    x, info = _solve(p, b, L.AC_PREC_MIXED_BF16K, 10, 1e-10)
+    assert info["converged"]
+    assert G.rel(x, ops.sequential_solve(A, b, ell)) < 1e-6
+
+
+def test_large_grid_apply_calA_full_compare():
+    nx = ny = 2048
+    ell = 10
+    kap = lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=0)
+    A = ops.build_A(2, nx, ny, kap)
+    xin = random_block_vector(nx * ny, ell, seed=1)
+    p = G.problem(2, nx, ny, kap, ell, 1e-2)
+    y = G.dev(np.zeros_like(xin))
+    api.ac_apply_A(p, G.dev(xin), y)
+    ref = ops.apply_calA(A, xin, ell)
+    assert G.max_rel(G.host(y), ref) < 1e-13
+
+
+def test_large_grid_prec_fp64_closed_form():
+    """Constant kappa at 2048^2: P_NC^{-1} (p = 10) against the modewise Chebyshev
+    polynomial multiplier through the spatial sine transform (Appendix A, Prop. 1)."""
+    nx = ny = 2048
+    ell, alpha, kap, pp = 10, 1e-2, 50.0, 10
+    lo, hi = ops.constant_interval(2, nx, ny, kap)
+    p = G.problem(2, nx, ny, kap, ell, alpha, bounds=(lo, hi))
+    r = random_block_vector(nx * ny, ell, seed=2)
+    opts = api.Opts(precision=L.AC_PREC_FP64, p=pp)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    z = G.dev(np.zeros_like(r))
+    api.ac_apply_prec(p, opts, G.dev(r), z, ws)
+    ref = pc.apply_prec_closed_form(2, nx, ny, kap, r, ell, alpha, pp, lo, hi)
+    assert G.rel(G.host(z), ref) < 1e-11
+
+
+def test_large_grid_prec_mixed_sampled():
+    """Log-normal kappa at 2048^2, the bench's launch shape: complex64 + bfloat16 P_NC^{-1}
+    (p = 3) against the float64 oracle on the rounded coefficients."""
+    nx = ny = 2048
+    ell, alpha, pp = 10, 1e-2, 3
+    kap = lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=0)
+    kq = to_bfloat16(kap)
+    lo, hi = ops.spectral_interval(2, nx, ny, kq)
+    p = G.problem(2, nx, ny, kap, ell, alpha)
+    r = random_block_vector(nx * ny, ell, seed=3)
+    opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=pp)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    z = G.dev(np.zeros_like(r))
+    api.ac_apply_prec(p, opts, G.dev(r), z, ws)
+    ref = pc.apply_prec_nc(ops.build_A(2, nx, ny, kq), r, ell, alpha, lo, hi, pp)
+    assert G.rel(G.host(z), ref) < 64 * 2.0 ** -24 * alpha ** (-(ell - 1) / ell) * (pp + 1)
+
+
+# ---- error handling (all detected on the host before any kernel runs) -----------------
+
+def test_errors():
+    n = 64
+    kap = np.full(n, 5.0)
+    with pytest.raises(api.L.AlphacircError) as e:
+        G.problem(1, n, 1, kap, 4, 50.0)  # alpha >= mu_lo^l
+    assert e.value.status == L.AC_ERR_ALPHA
+    with pytest.raises(api.L.AlphacircError) as e:
+        G.problem(1, n, 1, kap, 17, 1e-2)
+    assert e.value.status == L.AC_ERR_UNSUPPORTED
+    bad = kap.copy()
+    bad[3] = -1.0
+    with pytest.raises(api.L.AlphacircError) as e:
+        G.problem(1, n, 1, bad, 4, 1e-2)
+    assert e.value.status == L.AC_ERR_NONFINITE
+    bad[3] = np.nan
+    with pytest.raises(api.L.AlphacircError) as e:
+        G.problem(1, n, 1, bad, 4, 1e-2)
+    assert e.value.status == L.AC_ERR_NONFINITE
+    with pytest.raises(api.L.AlphacircError) as e:
+        G.problem(1, n, 1, kap, 4, 1e-2, bounds=(0.5, 10.0))
+    assert e.value.status == L.AC_ERR_BOUNDS
+    p = G.problem(1, n, 1, kap, 4, 1e-2)
+    r = G.dev(np.ones(4 * n))
+    z = G.dev(np.zeros(4 * n))
+    small = api.workspace(16)
+    with pytest.raises(api.L.AlphacircError) as e:
+        api.ac_apply_prec(p, api.Opts(p=3), r, z, small)
+    assert e.value.status == L.AC_ERR_WORKSPACE
+    ws = api.workspace(api.ac_prec_workspace_size(p, api.Opts(p=3)))
+    with pytest.raises(api.L.AlphacircError) as e:
+        api.ac_apply_prec(p, api.Opts(p=[3, 2, 3, 4]), r, z, ws)  # conjugate pair 1/3 differs
+    assert e.value.status == L.AC_ERR_ARG
+    with pytest.raises(api.L.AlphacircError) as e:
+        api.ac_apply_prec(p, api.Opts(p=0), r, z, ws)
+    assert e.value.status == L.AC_ERR_ARG
+    # not converged: a non-fatal status with the info filled in
+    b = first_block_rhs(n, 4, seed=0)
+    opts = api.Opts(precision=L.AC_PREC_FP64, p=1, tol=1e-14, restart_m=2, max_outer=3)
+    sws = api.workspace(api.ac_solve_workspace_size(p, opts))
+    x = G.dev(np.zeros(4 * n))
+    info = api.ac_solve(p, opts, G.dev(b), x, sws)
+    assert info["status"] == L.AC_NOT_CONVERGED and info["outer_iters"] == 3
+    # zero right-hand side gives x = 0 immediately
+    x = G.dev(np.ones(4 * n))
+    info = api.ac_solve(p, opts, G.dev(np.zeros(4 * n)), x, sws)
+    assert info["converged"] and not G.host(x).any()
