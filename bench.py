@@ -185,6 +185,7 @@ def main():
         "outer_iters": info_mixed["outer_iters"],
         "rel_residual_true": info_mixed["rel_residual_true"],
         "matvecs_A": info_mixed["matvecs_A"],
+        "orth_loss": info_mixed["orth_loss"],
         "shifted_stencil_GBps": achieved,
         "shifted_stencil_pct_hbm_peak": 100 * achieved / HBM_PEAK_GBS,
         "fp64": out_fp64,

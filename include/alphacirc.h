@@ -111,6 +111,7 @@ typedef struct {
     double seconds;           /* wall time of the solve (host clock, includes syncs) */
     int cnn_fallbacks;        /* shifted solves where the warm start was rejected */
     int reserved;
+    double orth_loss;         /* max |q_i . q_k|, i != k, over the Krylov bases built */
 } ac_solve_info;
 
 /* Kernel classes timed when profiling is on (ac_ctx_set_profiling). */
@@ -209,7 +210,8 @@ int ac_tdft_inverse(ac_problem* p, int precision, const void* yhat, double* z);
 
 /* ---- outer solve ---------------------------------------------------------- */
 /* Right-preconditioned flexible GMRES(restart_m) on calA x = b with P_NC^{-1},
- * Arnoldi by classical Gram-Schmidt applied twice, all in float64; Givens
+ * Arnoldi by modified Gram-Schmidt in inverse compact WY form (two sweeps over
+ * the basis per step), all in float64; Givens
  * rotations on the host.  x holds the initial guess on entry and the solution on
  * return.  Converged when the TRUE relative residual ||b - calA x||/||b|| <= tol
  * (the paper's residual definition, Section 5).  Synchronises once per

@@ -72,6 +72,7 @@ class ac_solve_info(C.Structure):
         ("seconds", C.c_double),
         ("cnn_fallbacks", C.c_int),
         ("reserved", C.c_int),
+        ("orth_loss", C.c_double),
     ]
 
 

@@ -39,9 +39,9 @@ class Ctx:
         self.stream = stream
 
     def __del__(self):
-        if getattr(self, "h", None):
-            L.load().ac_ctx_destroy(self.h)
-            self.h = None
+        if getattr(self, "h", None) and L is not None and L._lib is not None:
+            L._lib.ac_ctx_destroy(self.h)
+        self.h = None
 
 
 class Problem:
@@ -53,9 +53,9 @@ class Problem:
         self.ns = ns
 
     def __del__(self):
-        if getattr(self, "h", None):
-            L.load().ac_problem_destroy(self.h)
-            self.h = None
+        if getattr(self, "h", None) and L is not None and L._lib is not None:
+            L._lib.ac_problem_destroy(self.h)
+        self.h = None
 
 
 @dataclass
@@ -229,6 +229,7 @@ def ac_solve(p: Problem, opts: Opts, b: torch.Tensor, x: torch.Tensor, ws: torch
         "rel_residual_true": info.rel_residual_true,
         "seconds": info.seconds,
         "cnn_fallbacks": info.cnn_fallbacks,
+        "orth_loss": info.orth_loss,
     }
 
 

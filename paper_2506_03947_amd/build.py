@@ -48,10 +48,18 @@ PER_ELL = "stencil_ell.hip"   # compiled once per number of time blocks
 ELLS = range(2, 17)
 
 
-def compile_one(job, debug: bool) -> str:
+def _newest_dep(src: str) -> float:
+    deps = [src] + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".h")]
+    deps.append(os.path.join(INCLUDE, "alphacirc.h"))
+    return max(os.path.getmtime(d) for d in deps)
+
+
+def compile_one(job, debug: bool, incremental: bool = False) -> str:
     src, ell = job
     tag = os.path.basename(src) + ("" if ell is None else f".l{ell}")
     obj = os.path.join(BUILD, tag + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _newest_dep(src):
+        return obj
     cmd = [hipcc(), "-c", src, "-o", obj] + common_flags(debug)
     if ell is not None:
         cmd.append(f"-DAC_ELL={ell}")
@@ -61,7 +69,9 @@ def compile_one(job, debug: bool) -> str:
     return obj
 
 
-def build(jobs: int | None = None, debug: bool = False, verbose: bool = True) -> str:
+def build(jobs: int | None = None, debug: bool = False, verbose: bool = True, incremental: bool = False) -> str:
+    """Compile and link.  incremental=True reuses objects newer than their sources
+    and every header (a development shortcut); the default recompiles everything."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
     work = []
@@ -74,7 +84,7 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = True) ->
     work.sort(key=lambda j: 0 if j[1] is not None else 1)
     jobs = jobs or max(1, min(len(work), os.cpu_count() or 2))
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(lambda j: compile_one(j, debug), work))
+        objs = list(ex.map(lambda j: compile_one(j, debug, incremental), work))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-shared", "-o", tmp] + objs + ["--offload-arch=gfx950", "-fPIC"]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -90,9 +100,10 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--jobs", type=int, default=None)
     ap.add_argument("--debug", action="store_true")
+    ap.add_argument("--incremental", action="store_true")
     a = ap.parse_args()
     try:
-        build(a.jobs, a.debug)
+        build(a.jobs, a.debug, incremental=a.incremental)
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

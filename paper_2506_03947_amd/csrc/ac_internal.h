@@ -56,15 +56,18 @@ struct SweepArgs {
     Tiling t;
     const void* kappa;  // storage type depends on the precision
     ShiftCoef<R> cf;
-    int src[kMaxShift];        // step: SRC_COMPUTE (active) or anything else (skip)
-                               // final: SRC_COMPUTE / SRC_RHAT / SRC_BUF
-    const R* rhat[kMaxShift];  // right-hand side slice
-    const R* cur[kMaxShift];   // x_k (when the current operand is a buffer)
-    R* out[kMaxShift];         // step: holds x_{k-1} on entry (if a buffer), x_{k+1} on exit
-    const R* prev[kMaxShift];  // final: x_{k-1} buffer
-    const R* fin[kMaxShift];   // final: finished iterate when src == SRC_BUF
+    int src[kMaxShift];        // SRC_COMPUTE, or (final sweep) SRC_RHAT / SRC_BUF for finished shifts
+    int fbuf[kMaxShift];       // final sweep, SRC_BUF: finished iterate in buf0 (0) or buf1 (1)
+    unsigned soff[kMaxShift];  // slot offset (elements of R) inside every spectral buffer
+    int prevk;                 // kind of x_{k-1}: SRC_ZERO / SRC_RHAT / SRC_BUF
+    const R* rhat;             // spectral buffers (identical layouts)
+    const R* cur;              // x_k
+    R* out;                    // step: holds x_{k-1} on entry (if a buffer), x_{k+1} on exit
+    const R* prev;             // final: x_{k-1}
+    const R* buf0;
+    const R* buf1;
     // inverse transform (final sweep only)
-    double ginv[kMaxEll];      // 1 / (l * alpha^{k/l})
+    double ginv[kMaxEll];             // 1 / (l * alpha^{k/l})
     double cw[kMaxEll], sw[kMaxEll];  // cos / sin (2 pi j / l)
     double* z;
 };
@@ -98,8 +101,10 @@ struct CalAArgs {
 
 // ---- launchers (stencil.hip) ----------------------------------------------
 // prec: 0 = FP64 (double, kappa double), 1 = float + bf16 kappa, 2 = float + float kappa
-hipError_t launch_cheb_step(int ell, int prec, int curk, int prevk, const void* args, hipStream_t s);
-hipError_t launch_cheb_final(int ell, int prec, int curk, int prevk, const void* args, hipStream_t s);
+// curk selects the stencil operand (SRC_RHAT: x_1 = rhat/theta, else a buffer);
+// the kind of x_{k-1} travels in SweepArgs::prevk.
+hipError_t launch_cheb_step(int ell, int prec, int curk, const void* args, hipStream_t s);
+hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipStream_t s);
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);
@@ -110,11 +115,15 @@ struct VecSet {
     double s2[kMaxBasis];  // squared scales of the raw basis vectors
 };
 int krylov_blocks();
-// partial[blk*nq + q]
-hipError_t launch_mdot(const VecSet& V, int nv, const double* w, long long len, double* partial, int nq_stride,
-                       hipStream_t s);
-hipError_t launch_axpy_dot(const VecSet& V, int nv, const double* dcoef, double* w, long long len, double* partial,
-                           int nq_stride, hipStream_t s);
+// Partial sums go to partial[blk*nq_stride + q].
+// mdot: q < nv: V_q . w, q = nv: w . w; with_last: q = nv+1+i (i < nv-1): V_i . V_{nv-1}
+hipError_t launch_mdot(const VecSet& V, int nv, bool with_last, const double* w, long long len, double* partial,
+                       int nq_stride, hipStream_t s);
+// Same outputs for a basis with a fixed stride, vectors split over the waves of a block.
+hipError_t launch_mdot_strided(const double* v0, long long vstride, int nv, bool with_last, const double* w,
+                               long long len, double* partial, int nq_stride, hipStream_t s);
+// axpy_norm: w -= sum_q c_q V_q with c_q = s2_q dcoef_q (dcoef on the device) or
+// c_q = s2_q (dcoef == nullptr); q = 0: ||w||^2 after the update
 hipError_t launch_axpy_norm(const VecSet& V, int nv, const double* dcoef, double* w, long long len, double* partial,
                             int nq_stride, hipStream_t s);
 hipError_t launch_maxpy(const VecSet& Z, int nv, const double* coef_host_scaled, double* x, long long len,

@@ -163,7 +163,7 @@ Tiling make_tiling(const ac_problem* p, int vx_pref, int h_pref, int wpb_pref) {
     Tiling t{};
     const Geom& g = p->g;
     int vx = vx_pref > 0 ? vx_pref : 2;
-    if (g.nx % 2 != 0 || g.nx < 128) vx = 1;
+    if (g.nx % 2 != 0 || g.nx < 128 || g.periodic) vx = 1;  // periodic sweeps use one point per lane
     t.vx = vx;
     t.h = h_pref > 0 ? h_pref : 16;
     if (t.h > g.ny) t.h = g.ny;
@@ -329,7 +329,6 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     const void* kap = prec == AC_PREC_FP64 ? static_cast<const void*>(p->k64)
                       : prec == AC_PREC_MIXED_BF16K ? static_cast<const void*>(p->k16)
                                                     : static_cast<const void*>(p->k32);
-    auto slot = [&](char* b, int s) { return reinterpret_cast<R*>(slot_ptr(p, prec, b, s)); };
 
     // first step index and the operand kinds for step k (computing x_{k+1})
     const int k_first = warm ? 0 : 1;
@@ -355,22 +354,37 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
 
     const bool fuse = (z != nullptr);
     const int k_last = pmax - 1;  // step producing x_pmax
-    for (int k = k_first; k <= k_last; ++k) {
-        const bool final = fuse && (k == k_last);
-        ac::SweepArgs<R> a{};
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    auto base_args = [&](ac::SweepArgs<R>& a) {
         a.g = p->g;
         a.t = t;
         a.kappa = kap;
+        a.rhat = reinterpret_cast<const R*>(rhat);
+        a.buf0 = reinterpret_cast<const R*>(buf[0]);
+        a.buf1 = reinterpret_cast<const R*>(buf[1]);
+        for (int s = 0; s < ns; ++s) a.soff[s] = static_cast<unsigned>(off[slot_to_m(p, s)]);
+    };
+    auto fill_final = [&](ac::SweepArgs<R>& a) {
+        for (int kk = 0; kk < p->ell; ++kk)
+            a.ginv[kk] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(kk) / p->ell));
+        fill_twiddles(p->ell, a.cw, a.sw);
+        a.z = z;
+    };
+    for (int k = k_first; k <= k_last; ++k) {
+        const bool final = fuse && (k == k_last);
+        ac::SweepArgs<R> a{};
+        base_args(a);
         int curk, prevk;
         kinds(k, curk, prevk);
+        a.prevk = prevk;
+        a.cur = reinterpret_cast<const R*>(buf[k % 2]);
+        a.out = reinterpret_cast<R*>(buf[(k + 1) % 2]);
+        a.prev = reinterpret_cast<const R*>(buf[(k + 1) % 2]);
         double bytes = 0.0;
         bool anyc = false;
         for (int s = 0; s < ns; ++s) {
             fill_coef(a, s, cs[s], k);
-            a.rhat[s] = slot(rhat, s);
-            a.cur[s] = slot(buf[k % 2], s);
-            a.out[s] = slot(buf[(k + 1) % 2], s);
-            a.prev[s] = slot(buf[(k + 1) % 2], s);
             const double esz = slot_is_real(p, s) ? esz_r : esz_c;
             if (ps[s] >= k + 1) {
                 a.src[s] = ac::SRC_COMPUTE;
@@ -381,7 +395,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 char* b;
                 fin_src(ps[s], kind, b);
                 a.src[s] = kind;
-                a.fin[s] = slot(b, s);
+                a.fbuf[s] = (b == buf[1]) ? 1 : 0;
                 if (final) bytes += esz;
             }
         }
@@ -389,38 +403,29 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         bytes *= static_cast<double>(p->g.n);
         if (final) {
             bytes += 8.0 * p->ell * p->g.n;
-            for (int kk = 0; kk < p->ell; ++kk)
-                a.ginv[kk] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(kk) / p->ell));
-            fill_twiddles(p->ell, a.cw, a.sw);
-            a.z = z;
+            fill_final(a);
             ProfScope ps_(p->ctx, AC_K_CHEB_FINAL, bytes);
-            AC_HIP(ac::launch_cheb_final(p->ell, prec, curk, prevk, &a, p->ctx->stream));
+            AC_HIP(ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream));
         } else {
             ProfScope ps_(p->ctx, AC_K_CHEB_STEP, bytes);
-            AC_HIP(ac::launch_cheb_step(p->ell, prec, curk, prevk, &a, p->ctx->stream));
+            AC_HIP(ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream));
         }
     }
     if (fuse && k_last < k_first) {
         // nothing to iterate (cold start, every p = 1): x_1 = rhat/theta everywhere
         ac::SweepArgs<R> a{};
-        a.g = p->g;
-        a.t = t;
-        a.kappa = kap;
+        base_args(a);
+        a.prevk = ac::SRC_ZERO;
         double bytes = 0.0;
         for (int s = 0; s < ns; ++s) {
             fill_coef(a, s, cs[s], 0);
-            a.rhat[s] = slot(rhat, s);
             a.src[s] = ac::SRC_RHAT;
-            a.fin[s] = slot(rhat, s);
             bytes += slot_is_real(p, s) ? esz_r : esz_c;
         }
         bytes = bytes * p->g.n + 8.0 * p->ell * p->g.n;
-        for (int kk = 0; kk < p->ell; ++kk)
-            a.ginv[kk] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(kk) / p->ell));
-        fill_twiddles(p->ell, a.cw, a.sw);
-        a.z = z;
+        fill_final(a);
         ProfScope ps_(p->ctx, AC_K_CHEB_FINAL, bytes);
-        AC_HIP(ac::launch_cheb_final(p->ell, prec, ac::SRC_RHAT, ac::SRC_ZERO, &a, p->ctx->stream));
+        AC_HIP(ac::launch_cheb_final(p->ell, prec, ac::SRC_BUF, &a, p->ctx->stream));
     }
     if (where) {
         where->clear();
@@ -719,7 +724,7 @@ namespace {
 struct SolveWs {
     double* V[ac::kMaxBasis];
     double* Z[ac::kMaxBasis];
-    double* partial;   // krylov_blocks * 40
+    double* partial;   // krylov_blocks * 72
     double* partial2;  // calA tiles
     double* red;       // 128 reduced scalars
     void* prec;
@@ -729,7 +734,7 @@ size_t solve_ws_bytes(const ac_problem* p, const ac_solve_opts* o) {
     const int m = o->restart_m;
     size_t b = 256;
     b += static_cast<size_t>(2 * m + 1) * vec_bytes(p);
-    b += align_up(static_cast<size_t>(ac::krylov_blocks()) * 40 * sizeof(double), 256);
+    b += align_up(static_cast<size_t>(ac::krylov_blocks()) * 72 * sizeof(double), 256);
     b += align_up(static_cast<size_t>(calA_partials(p)) * sizeof(double), 256);
     b += align_up(128 * sizeof(double), 256);
     b += prec_ws_bytes(p, o->precision);
@@ -742,7 +747,7 @@ SolveWs carve_solve(const ac_problem* p, const ac_solve_opts* o, void* ws) {
     for (int i = 0; i <= o->restart_m; ++i, b += vb) w.V[i] = reinterpret_cast<double*>(b);
     for (int i = 0; i < o->restart_m; ++i, b += vb) w.Z[i] = reinterpret_cast<double*>(b);
     w.partial = reinterpret_cast<double*>(b);
-    b += align_up(static_cast<size_t>(ac::krylov_blocks()) * 40 * sizeof(double), 256);
+    b += align_up(static_cast<size_t>(ac::krylov_blocks()) * 72 * sizeof(double), 256);
     w.partial2 = reinterpret_cast<double*>(b);
     b += align_up(static_cast<size_t>(calA_partials(p)) * sizeof(double), 256);
     w.red = reinterpret_cast<double*>(b);
@@ -920,7 +925,8 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
     double beta = 0;
     AC_TRY(residual(beta));
     int total = 0, restarts = 0;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), s2(m + 1), scale(m + 1), y(m);
+    double orth_loss = 0.0;
+    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), scale(m + 1), y(m), Lg(m * m), hcol(m + 1);
     int status = AC_OK;
     while (true) {
         if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
@@ -944,33 +950,41 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
             AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
             matvecs += p->ell + psum;
             ac::VecSet vs{};
-            for (int i = 0; i <= j; ++i) {
-                vs.v[i] = w.V[i];
-                vs.s2[i] = scale[i] * scale[i];
-            }
+            for (int i = 0; i <= j; ++i) vs.v[i] = w.V[i];
             const int nv = j + 1;
-            double* d1 = w.red;
-            double* d2 = w.red + 40;
-            double* nr = w.red + 80;
+            // Modified Gram-Schmidt in inverse compact WY form (one reduction per step):
+            // the projector (I - q_j q_j^T)...(I - q_0 q_0^T) equals I - Q (I + L)^{-1} Q^T with
+            // L the strictly lower part of Q^T Q.  One sweep gives r = Q^T w and the new row
+            // of L (dots of the newest basis vector with the older ones); the host solves
+            // (I + L) h = r; a second sweep forms w - Q h and its norm.
             {
                 ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 1));
-                AC_HIP(ac::launch_mdot(vs, nv, w.V[j + 1], len, w.partial, 40, st));
-                AC_HIP(ac::launch_reduce(w.partial, kb, nv, 40, d1, st));
+                AC_HIP(ac::launch_mdot_strided(w.V[0], static_cast<long long>(vec_bytes(p) / sizeof(double)), nv,
+                                               j >= 1, w.V[j + 1], len, w.partial, 72, st));
+                AC_HIP(ac::launch_reduce(w.partial, kb, j >= 1 ? 2 * nv : nv + 1, 72, w.red, st));
+            }
+            AC_TRY(fetch(2 * nv + 1));
+            {
+                const double* hd = c->pinned;
+                for (int i = 0; i < j; ++i) {
+                    Lg[j * m + i] = scale[i] * scale[j] * hd[nv + 1 + i];
+                    orth_loss = std::max(orth_loss, std::abs(Lg[j * m + i]));
+                }
+                for (int i = 0; i <= j; ++i) {
+                    double hi = scale[i] * hd[i];
+                    for (int k = 0; k < i; ++k) hi -= Lg[i * m + k] * hcol[k];
+                    hcol[i] = hi;
+                    H[i * m + j] = hi;
+                    vs.s2[i] = scale[i] * hi;  // coefficient of the raw basis vector
+                }
             }
             {
                 ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 2));
-                AC_HIP(ac::launch_axpy_dot(vs, nv, d1, w.V[j + 1], len, w.partial, 40, st));
-                AC_HIP(ac::launch_reduce(w.partial, kb, nv, 40, d2, st));
+                AC_HIP(ac::launch_axpy_norm(vs, nv, nullptr, w.V[j + 1], len, w.partial, 72, st));
+                AC_HIP(ac::launch_reduce(w.partial, kb, 1, 72, w.red, st));
             }
-            {
-                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 2));
-                AC_HIP(ac::launch_axpy_norm(vs, nv, d2, w.V[j + 1], len, w.partial, 40, st));
-                AC_HIP(ac::launch_reduce(w.partial, kb, 1, 40, nr, st));
-            }
-            AC_TRY(fetch(81));
-            const double* hd = c->pinned;
-            for (int i = 0; i <= j; ++i) H[i * m + j] = scale[i] * (hd[i] + hd[40 + i]);
-            const double hn = std::sqrt(hd[80]);
+            AC_TRY(fetch(1));
+            const double hn = std::sqrt(c->pinned[0]);
             if (!std::isfinite(hn)) return fail(AC_ERR_NONFINITE, "Arnoldi produced a non-finite value");
             H[(j + 1) * m + j] = hn;
             for (int i = 0; i < j; ++i) {
@@ -1016,6 +1030,7 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         info->cnn_fallbacks = 0;
         info->reserved = 0;
+        info->orth_loss = orth_loss;
     }
     return status;
 }

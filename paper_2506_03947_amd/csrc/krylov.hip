@@ -1,11 +1,13 @@
-// Float64 Krylov vector kernels for the outer FGMRES: fused multi-dot,
-// multi-axpy with dot or norm, and a deterministic two-stage reduction.
+// Float64 Krylov vector kernels for the outer FGMRES: fused multi-dot (with the
+// norm of the target), multi-axpy with the norm of the result, and a
+// deterministic two-stage reduction.
 //
-// Classical Gram-Schmidt applied twice costs three passes over the basis:
-//   (1) d1 = V^T w,  (2) w -= V (s2 .* d1) and d2 = V^T w,  (3) w -= V (s2 .* d2) and ||w||^2,
-// where the basis vectors are stored unnormalised and s2_i is the square of their
-// scale (so no pass is spent normalising).  Each thread keeps the basis values of
-// its two elements in registers between the axpy and the following dot.
+// One Gram-Schmidt step costs two sweeps over the basis:
+//   (1) d = V^T w, ||w||^2 and (optionally) e = V^T v_last, the dots of the newest
+//       basis vector with the older ones (free: v_last is read anyway),
+//   (2) w -= V c and ||w||^2 with host-computed coefficients c,
+// where the basis vectors are stored unnormalised (the host keeps their scales,
+// so no sweep is spent normalising).
 #include <hip/hip_runtime.h>
 
 #include "ac_internal.h"
@@ -38,9 +40,10 @@ __device__ __forceinline__ void store2(double* p, long long e, long long len, D2
     }
 }
 
-// Block-wide sums of NQ per-thread values; thread q < nq writes partial[q].
+// Block-wide sums of NQ per-thread values; thread q < nq writes partial[q] from
+// accumulator src(q) = q, except that q == remap_from reads accumulator NQ-1.
 template <int NQ>
-__device__ __forceinline__ void block_sums(double (&acc)[NQ], int nq, double* partial) {
+__device__ __forceinline__ void block_sums(double (&acc)[NQ], int nq, double* partial, int remap_from = -1) {
     __shared__ double red[kThreads / kWave][NQ];
     const int lane = threadIdx.x & (kWave - 1);
     const int wid = threadIdx.x >> 6;
@@ -53,65 +56,159 @@ __device__ __forceinline__ void block_sums(double (&acc)[NQ], int nq, double* pa
     }
     __syncthreads();
     if (threadIdx.x < nq) {
+        const int src = (static_cast<int>(threadIdx.x) == remap_from) ? NQ - 1 : threadIdx.x;
         double s = 0.0;
 #pragma unroll
-        for (int w = 0; w < kThreads / kWave; ++w) s += red[w][threadIdx.x];
+        for (int w = 0; w < kThreads / kWave; ++w) s += red[w][src];
         partial[threadIdx.x] = s;
     }
 }
 
-template <int NVB>
+// Block sums for mdot: out[q] for q < nv from acc[q], out[nv] from acc[NVB], and
+// (TWO) out[nv + 1 + q] for q < nv - 1 from acc[NVB + 1 + q].
+template <int NQ, int NVB, bool TWO>
+__device__ __forceinline__ void block_sums_mdot(double (&acc)[NQ], int nv, double* partial) {
+    __shared__ double red[kThreads / kWave][NQ];
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double v = acc[q];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_down(v, off, kWave);
+        if (lane == 0) red[wid][q] = v;
+    }
+    __syncthreads();
+    const int nout = TWO ? 2 * nv : nv + 1;
+    const int t = threadIdx.x;
+    if (t < nout) {
+        const int src = (t < nv) ? t : (t == nv ? NVB : NVB + 1 + (t - nv - 1));
+        double s = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / kWave; ++w) s += red[w][src];
+        partial[t] = s;
+    }
+}
+
+// partial[q], q < nv: V_q . w;  partial[nv]: w . w;
+// TWO: partial[nv + 1 + q], q < nv - 1: V_q . V_{nv-1}
+template <int NVB, bool TWO>
 __global__ __launch_bounds__(kThreads) void mdot_kernel(const VecSet V, int nv, const double* __restrict__ w,
                                                         long long len, double* partial, int stride) {
-    double acc[NVB];
+    constexpr int NQ = TWO ? 2 * NVB + 1 : NVB + 1;
+    double acc[NQ];
 #pragma unroll
-    for (int i = 0; i < NVB; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
+    if (TWO) {
+        // one element per thread per step keeps the two accumulator sets in registers
+        const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
+        const double* __restrict__ vl = V.v[nv - 1];
+        for (long long e = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; e < len; e += step) {
+            const double wv = w[e];
+            const double lv = vl[e];
+            acc[NVB] += wv * wv;
+#pragma unroll
+            for (int i = 0; i < NVB; ++i) {
+                if (i < nv) {
+                    const double v = V.v[i][e];
+                    acc[i] += v * wv;
+                    if (TWO && i < NVB) acc[(NVB + 1 + i) % NQ] += v * lv;
+                }
+            }
+        }
+    } else {
+        const long long step = 2LL * gridDim.x * blockDim.x;
+        for (long long e = 2LL * (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x); e < len;
+             e += step) {
+            const D2 wv = load2(w, e, len);
+            acc[NVB] += wv.x * wv.x + wv.y * wv.y;
+#pragma unroll
+            for (int i = 0; i < NVB; ++i) {
+                if (i < nv) {
+                    const D2 v = load2(V.v[i], e, len);
+                    acc[i] += v.x * wv.x + v.y * wv.y;
+                }
+            }
+        }
+    }
+    block_sums_mdot<NQ, NVB, TWO>(acc, nv, partial + static_cast<long long>(blockIdx.x) * stride);
+}
+
+// Vector-parallel multi-dot for a basis stored with a fixed stride (V_i = V_0 + i*vstride):
+// the waves of a block walk the same element chunk, wave g owning basis vectors
+// [g*G, g*G + G), so each thread keeps at most 2G accumulators; the shared operands
+// w (and v_last) are re-read by the four waves from L1/L2, not from HBM.
+// Outputs as mdot_kernel: q < nv: V_q . w;  nv: w . w;  (TWO) nv + 1 + q: V_q . V_{nv-1}.
+template <int G, bool TWO>
+__global__ __launch_bounds__(kThreads) void mdot_vp_kernel(const double* __restrict__ v0, long long vstride, int nv,
+                                                           const double* __restrict__ w, long long len,
+                                                           double* partial, int stride) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int i0 = wid * G;
+    double acc[G], acc2[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) acc[g] = acc2[g] = 0.0;
+    double nrm = 0.0;
+    const double* __restrict__ vl = v0 + static_cast<long long>(nv - 1) * vstride;
+    const long long step = 2LL * kWave * gridDim.x;
+    for (long long e = 2LL * (static_cast<long long>(blockIdx.x) * kWave + lane); e < len; e += step) {
+        const D2 wv = load2(w, e, len);
+        D2 lv{0.0, 0.0};
+        if (TWO) lv = load2(vl, e, len);
+        if (wid == 0) nrm += wv.x * wv.x + wv.y * wv.y;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (i0 + g < nv) {
+                const D2 v = load2(v0 + static_cast<long long>(i0 + g) * vstride, e, len);
+                acc[g] += v.x * wv.x + v.y * wv.y;
+                if (TWO) acc2[g] += v.x * lv.x + v.y * lv.y;
+            }
+        }
+    }
+    double* out = partial + static_cast<long long>(blockIdx.x) * stride;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        double a = acc[g], b = acc2[g];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) {
+            a += __shfl_down(a, off, kWave);
+            if (TWO) b += __shfl_down(b, off, kWave);
+        }
+        if (lane == 0 && i0 + g < nv) out[i0 + g] = a;
+        if (TWO && lane == 0 && i0 + g < nv - 1) out[nv + 1 + i0 + g] = b;
+    }
+    if (wid == 0) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) nrm += __shfl_down(nrm, off, kWave);
+        if (lane == 0) out[nv] = nrm;
+    }
+}
+
+// w -= sum_i c_i V_i with c_i = s2_i dcoef_i (dcoef on the device) or c_i = s2_i
+// (dcoef == nullptr);  partial[0] = ||w||^2 afterwards
+template <int NVB>
+__global__ __launch_bounds__(kThreads) void axpy_norm_kernel(const VecSet V, int nv, const double* __restrict__ dcoef,
+                                                             double* w, long long len, double* partial, int stride) {
+    double coef[NVB];
+#pragma unroll
+    for (int i = 0; i < NVB; ++i) coef[i] = (i < nv) ? (dcoef ? V.s2[i] * dcoef[i] : V.s2[i]) : 0.0;
+    double acc[1] = {0.0};
     const long long step = 2LL * gridDim.x * blockDim.x;
     for (long long e = 2LL * (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x); e < len; e += step) {
-        const D2 wv = load2(w, e, len);
+        D2 wv = load2(w, e, len);
 #pragma unroll
         for (int i = 0; i < NVB; ++i) {
             if (i < nv) {
                 const D2 v = load2(V.v[i], e, len);
-                acc[i] += v.x * wv.x + v.y * wv.y;
-            }
-        }
-    }
-    block_sums<NVB>(acc, nv, partial + static_cast<long long>(blockIdx.x) * stride);
-}
-
-template <int NVB, bool DOT>
-__global__ __launch_bounds__(kThreads) void axpy_kernel(const VecSet V, int nv, const double* __restrict__ dcoef,
-                                                        double* w, long long len, double* partial, int stride) {
-    double coef[NVB];
-#pragma unroll
-    for (int i = 0; i < NVB; ++i) coef[i] = (i < nv) ? V.s2[i] * dcoef[i] : 0.0;
-    constexpr int NQ = DOT ? NVB : 1;
-    double acc[NQ];
-#pragma unroll
-    for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
-    const long long step = 2LL * gridDim.x * blockDim.x;
-    for (long long e = 2LL * (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x); e < len; e += step) {
-        D2 wv = load2(w, e, len);
-        D2 vv[NVB];
-#pragma unroll
-        for (int i = 0; i < NVB; ++i) {
-            if (i < nv) {
-                vv[i] = load2(V.v[i], e, len);
-                wv.x -= coef[i] * vv[i].x;
-                wv.y -= coef[i] * vv[i].y;
+                wv.x -= coef[i] * v.x;
+                wv.y -= coef[i] * v.y;
             }
         }
         store2(w, e, len, wv);
-        if (DOT) {
-#pragma unroll
-            for (int i = 0; i < NVB; ++i)
-                if (i < nv) acc[i < NQ ? i : 0] += vv[i].x * wv.x + vv[i].y * wv.y;
-        } else {
-            acc[0] += wv.x * wv.x + wv.y * wv.y;
-        }
+        acc[0] += wv.x * wv.x + wv.y * wv.y;
     }
-    block_sums<NQ>(acc, DOT ? nv : 1, partial + static_cast<long long>(blockIdx.x) * stride);
+    block_sums<1>(acc, 1, partial + static_cast<long long>(blockIdx.x) * stride);
 }
 
 template <int NVB>
@@ -157,27 +254,36 @@ int bucket(int nv) { return nv <= 4 ? 4 : nv <= 8 ? 8 : nv <= 16 ? 16 : 32; }
 
 int krylov_blocks() { return kBlocks; }
 
-hipError_t launch_mdot(const VecSet& V, int nv, const double* w, long long len, double* partial, int stride,
-                       hipStream_t s) {
+hipError_t launch_mdot(const VecSet& V, int nv, bool with_last, const double* w, long long len, double* partial,
+                       int stride, hipStream_t s) {
     if (nv < 1 || nv > 32) return hipErrorInvalidValue;
+    const dim3 g(kBlocks), b(kThreads);
+#define AC_MD(NB)                                                                                   \
+    if (with_last) hipLaunchKernelGGL((mdot_kernel<NB, true>), g, b, 0, s, V, nv, w, len, partial, stride); \
+    else hipLaunchKernelGGL((mdot_kernel<NB, false>), g, b, 0, s, V, nv, w, len, partial, stride);
     switch (bucket(nv)) {
-        case 4: hipLaunchKernelGGL(mdot_kernel<4>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, w, len, partial, stride); break;
-        case 8: hipLaunchKernelGGL(mdot_kernel<8>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, w, len, partial, stride); break;
-        case 16: hipLaunchKernelGGL(mdot_kernel<16>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, w, len, partial, stride); break;
-        default: hipLaunchKernelGGL(mdot_kernel<32>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, w, len, partial, stride); break;
+        case 4: AC_MD(4) break;
+        case 8: AC_MD(8) break;
+        case 16: AC_MD(16) break;
+        default: AC_MD(32) break;
     }
+#undef AC_MD
     return hipGetLastError();
 }
 
-hipError_t launch_axpy_dot(const VecSet& V, int nv, const double* dcoef, double* w, long long len, double* partial,
-                           int stride, hipStream_t s) {
+hipError_t launch_mdot_strided(const double* v0, long long vstride, int nv, bool with_last, const double* w,
+                               long long len, double* partial, int stride, hipStream_t s) {
     if (nv < 1 || nv > 32) return hipErrorInvalidValue;
-    switch (bucket(nv)) {
-        case 4: hipLaunchKernelGGL((axpy_kernel<4, true>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
-        case 8: hipLaunchKernelGGL((axpy_kernel<8, true>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
-        case 16: hipLaunchKernelGGL((axpy_kernel<16, true>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
-        default: hipLaunchKernelGGL((axpy_kernel<32, true>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
-    }
+    const int per_wave = (nv + kThreads / kWave - 1) / (kThreads / kWave);
+    const dim3 g(kBlocks), b(kThreads);
+#define AC_MV(GG)                                                                                             \
+    if (with_last) hipLaunchKernelGGL((mdot_vp_kernel<GG, true>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride); \
+    else hipLaunchKernelGGL((mdot_vp_kernel<GG, false>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
+    if (per_wave <= 1) { AC_MV(1) }
+    else if (per_wave <= 2) { AC_MV(2) }
+    else if (per_wave <= 4) { AC_MV(4) }
+    else { AC_MV(8) }
+#undef AC_MV
     return hipGetLastError();
 }
 
@@ -185,10 +291,10 @@ hipError_t launch_axpy_norm(const VecSet& V, int nv, const double* dcoef, double
                             int stride, hipStream_t s) {
     if (nv < 1 || nv > 32) return hipErrorInvalidValue;
     switch (bucket(nv)) {
-        case 4: hipLaunchKernelGGL((axpy_kernel<4, false>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
-        case 8: hipLaunchKernelGGL((axpy_kernel<8, false>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
-        case 16: hipLaunchKernelGGL((axpy_kernel<16, false>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
-        default: hipLaunchKernelGGL((axpy_kernel<32, false>), dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
+        case 4: hipLaunchKernelGGL(axpy_norm_kernel<4>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
+        case 8: hipLaunchKernelGGL(axpy_norm_kernel<8>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
+        case 16: hipLaunchKernelGGL(axpy_norm_kernel<16>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
+        default: hipLaunchKernelGGL(axpy_norm_kernel<32>, dim3(kBlocks), dim3(kThreads), 0, s, V, nv, dcoef, w, len, partial, stride); break;
     }
     return hipGetLastError();
 }

@@ -7,8 +7,7 @@
 namespace ac {
 
 #define AC_DECL(L)                                                                                       \
-    hipError_t sweep_ell_##L(bool final, int prec, int vx, int curk, int prevk, const void* args,         \
-                             hipStream_t s);                                                             \
+    hipError_t sweep_ell_##L(bool final, int prec, int vx, int curk, const void* args, hipStream_t s);    \
     hipError_t fwd_ell_##L(int prec, const FwdArgs& a, hipStream_t s);                                    \
     hipError_t inv_ell_##L(int prec, const InvArgs& a, hipStream_t s);                                    \
     hipError_t calA_ell_##L(bool resid, const CalAArgs& a, hipStream_t s);
@@ -41,16 +40,16 @@ static int sweep_vx(int prec, const void* args) {
                      : static_cast<const SweepArgs<float>*>(args)->t.vx;
 }
 
-hipError_t launch_cheb_step(int ell, int prec, int curk, int prevk, const void* args, hipStream_t s) {
+hipError_t launch_cheb_step(int ell, int prec, int curk, const void* args, hipStream_t s) {
     const int vx = sweep_vx(prec, args);
-#define AC_X(L) sweep_ell_##L(false, prec, vx, curk, prevk, args, s)
+#define AC_X(L) sweep_ell_##L(false, prec, vx, curk, args, s)
     AC_SWITCH(AC_X)
 #undef AC_X
 }
 
-hipError_t launch_cheb_final(int ell, int prec, int curk, int prevk, const void* args, hipStream_t s) {
+hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipStream_t s) {
     const int vx = sweep_vx(prec, args);
-#define AC_X(L) sweep_ell_##L(true, prec, vx, curk, prevk, args, s)
+#define AC_X(L) sweep_ell_##L(true, prec, vx, curk, args, s)
     AC_SWITCH(AC_X)
 #undef AC_X
 }

@@ -10,36 +10,32 @@
 namespace ac {
 namespace {
 
-template <typename R, typename KS, int ELL, int VX, int CURK, int PREVK, bool FINAL>
+template <typename R, typename KS, int VX, bool CUR_RHAT, bool FINAL, bool PER>
 hipError_t launch_sweep_t(const SweepArgs<R>& a, hipStream_t s) {
-    hipLaunchKernelGGL((cheb_sweep_kernel<R, KS, ELL, VX, CURK, PREVK, FINAL>), dim3(a.t.blocks),
+    hipLaunchKernelGGL((cheb_sweep_kernel<R, KS, AC_ELL, VX, CUR_RHAT, FINAL, PER>), dim3(a.t.blocks),
                        dim3(a.t.wpb * kWave), 0, s, a);
     return hipGetLastError();
 }
 
 template <typename R, typename KS, bool FINAL>
-hipError_t sweep_by_kind(int vx, int curk, int prevk, const void* args, hipStream_t s) {
+hipError_t sweep_by_kind(int vx, int curk, const void* args, hipStream_t s) {
     const SweepArgs<R>& a = *static_cast<const SweepArgs<R>*>(args);
-#define AC_SW(V, C, P) \
-    if (vx == V && curk == C && prevk == P) return launch_sweep_t<R, KS, AC_ELL, V, C, P, FINAL>(a, s);
-    AC_SW(1, SRC_RHAT, SRC_ZERO)
-    AC_SW(1, SRC_BUF, SRC_RHAT)
-    AC_SW(1, SRC_BUF, SRC_BUF)
-    AC_SW(1, SRC_BUF, SRC_ZERO)
-    AC_SW(2, SRC_RHAT, SRC_ZERO)
-    AC_SW(2, SRC_BUF, SRC_RHAT)
-    AC_SW(2, SRC_BUF, SRC_BUF)
-    AC_SW(2, SRC_BUF, SRC_ZERO)
-#undef AC_SW
-    return hipErrorInvalidValue;
+    const bool rh = (curk == SRC_RHAT);
+    if (a.g.periodic) {
+        if (vx != 1) return hipErrorInvalidValue;
+        return rh ? launch_sweep_t<R, KS, 1, true, FINAL, true>(a, s) : launch_sweep_t<R, KS, 1, false, FINAL, true>(a, s);
+    }
+    if (vx == 2)
+        return rh ? launch_sweep_t<R, KS, 2, true, FINAL, false>(a, s) : launch_sweep_t<R, KS, 2, false, FINAL, false>(a, s);
+    return rh ? launch_sweep_t<R, KS, 1, true, FINAL, false>(a, s) : launch_sweep_t<R, KS, 1, false, FINAL, false>(a, s);
 }
 
 template <bool FINAL>
-hipError_t sweep_by_prec(int prec, int vx, int curk, int prevk, const void* args, hipStream_t s) {
+hipError_t sweep_by_prec(int prec, int vx, int curk, const void* args, hipStream_t s) {
     switch (prec) {
-        case 0: return sweep_by_kind<double, double, FINAL>(vx, curk, prevk, args, s);
-        case 1: return sweep_by_kind<float, uint16_t, FINAL>(vx, curk, prevk, args, s);
-        case 2: return sweep_by_kind<float, float, FINAL>(vx, curk, prevk, args, s);
+        case 0: return sweep_by_kind<double, double, FINAL>(vx, curk, args, s);
+        case 1: return sweep_by_kind<float, uint16_t, FINAL>(vx, curk, args, s);
+        case 2: return sweep_by_kind<float, float, FINAL>(vx, curk, args, s);
         default: return hipErrorInvalidValue;
     }
 }
@@ -49,10 +45,8 @@ hipError_t sweep_by_prec(int prec, int vx, int curk, int prevk, const void* args
 #define AC_CAT2(a, b) a##b
 #define AC_CAT(a, b) AC_CAT2(a, b)
 
-hipError_t AC_CAT(sweep_ell_, AC_ELL)(bool final, int prec, int vx, int curk, int prevk, const void* args,
-                                      hipStream_t s) {
-    return final ? sweep_by_prec<true>(prec, vx, curk, prevk, args, s)
-                 : sweep_by_prec<false>(prec, vx, curk, prevk, args, s);
+hipError_t AC_CAT(sweep_ell_, AC_ELL)(bool final, int prec, int vx, int curk, const void* args, hipStream_t s) {
+    return final ? sweep_by_prec<true>(prec, vx, curk, args, s) : sweep_by_prec<false>(prec, vx, curk, args, s);
 }
 
 hipError_t AC_CAT(fwd_ell_, AC_ELL)(int prec, const FwdArgs& a, hipStream_t s) {

@@ -16,6 +16,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "ac_internal.h"
 
 namespace ac {
@@ -207,15 +209,20 @@ __device__ __forceinline__ Faces<K> faces(const Geom& g, int px, int py, K kc, K
 // Batched shifted Chebyshev sweep.
 //
 // For every shift slot with src == SRC_COMPUTE:
-//   x_{k+1} = x_k + a (x_k - x_{k-1}) + c (rhat - (A - lambda) x_k)
-// The stencil operand x_k is either a buffer (CURK == SRC_BUF) or s * rhat
-// (CURK == SRC_RHAT, s = 1/theta: the first iterate from a zero guess).
-// x_{k-1} is a buffer (read in place from `out`, or from `prev` in the final
-// sweep), s * rhat, or zero.  FINAL fuses the inverse scaled time-DFT: the new
-// iterates (and the finished iterates of shifts that stopped earlier) are
-// combined in registers into the l float64 blocks of z.
+//   x_{k+1} = x_k + a (x_k - x_{k-1}) + c (rhat - (A - lambda) x_k).
+// CUR_RHAT: the stencil operand is x_1 = s * rhat (s = 1/theta, zero initial
+// guess, never stored); the window then holds rhat itself and the scale is
+// applied after the (linear) stencil.  x_{k-1} is a buffer, s * rhat or zero
+// (runtime kind, uniform).  FINAL fuses the inverse scaled time-DFT: the new
+// iterates and the finished iterates of shifts that stopped earlier are combined
+// in registers into the l float64 blocks of z.
+//
+// Per row, every load of every shift is issued before the first arithmetic
+// instruction that needs one of them (loads complete in order, so each shift
+// only waits for its own operands), and all addresses are 32-bit offsets from a
+// few uniform base pointers.
 
-template <typename R, typename KS, int ELL, int VX, int CURK, int PREVK, bool FINAL>
+template <typename R, typename KS, int ELL, int VX, bool CUR_RHAT, bool FINAL, bool PER>
 __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
     constexpr int NSR = (ELL % 2 == 0) ? 2 : 1;
     constexpr int NSC = (ELL - NSR) / 2;
@@ -225,14 +232,14 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
 
     const long long tile = tile_of_wave(a.t);
     if (tile < 0) return;
-    const Geom& g = a.g;
+    const int nx = a.g.nx, ny = a.g.ny;
     const int lane = threadIdx.x & (kWave - 1);
     const int sx = static_cast<int>(tile % a.t.nsx);
     const int cy = static_cast<int>(tile / a.t.nsx);
     const int x0 = sx * kWave * VX;
     const int y0 = cy * a.t.h;
-    const int y1 = min(y0 + a.t.h, g.ny);
-    const KS* kap = static_cast<const KS*>(a.kappa);
+    const int y1 = min(y0 + a.t.h, ny);
+    const KS* __restrict__ kap = static_cast<const KS*>(a.kappa);
 
     bool comp[NS];
     bool any = false;
@@ -241,133 +248,163 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
         comp[s] = (a.src[s] == SRC_COMPUTE);
         any = any || comp[s];
     }
+    const R* __restrict__ wbase = CUR_RHAT ? a.rhat : a.cur;  // stencil operand buffer
 
-    // three-row windows: p = y-1, c = y, n = y+1
-    K kp[VX], kc[VX], kn[VX], khc, khn, kdummy;
-    R rp[NSR][VX], rc[NSR][VX], rn[NSR][VX], rhc[NSR], rhn[NSR];
-    R cpr[NSCA][VX], cpi[NSCA][VX], ccr[NSCA][VX], cci[NSCA][VX], cnr[NSCA][VX], cni[NSCA][VX];
-    R chcr[NSCA], chci[NSCA], chnr[NSCA], chni[NSCA];
+    // per-lane columns
+    const int xb = x0 + lane * VX;
+    const bool lane_ok = PER || (xb < nx);
+    const int xl = PER ? (xb % nx) : xb;
+    const bool hl = (lane == 0 || lane == kWave - 1);  // lanes that fetch the strip halo
+    int hx = -1;
+    if (hl) {
+        hx = (lane == 0) ? x0 - 1 : x0 + kWave * VX;
+        if (PER) hx = ((hx % nx) + nx) % nx;
+    }
+    const bool hok = hl && hx >= 0 && hx < nx;
 
-    auto load_window_row = [&](int y, K (&kk)[VX], K& kh, R (&rr)[NSR][VX], R (&rh)[NSR], R (&qr)[NSCA][VX],
-                               R (&qi)[NSCA][VX], R (&qhr)[NSCA], R (&qhi)[NSCA]) {
-        if (any) load_real_row<K, VX, KS>(kap, g, y, x0, lane, kk, kh);
+    // three-row windows of the stencil operand (raw rhat when CUR_RHAT)
+    K kw[3][VX], kh[3];
+    R wr[3][NSR][VX], wrh[3][NSR];
+    R wc[3][NSCA][2 * VX], wch[3][NSCA][2];
+
+    auto load_row = [&](auto W_, int y) {
+        constexpr int W = decltype(W_)::value;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) kw[W][v] = K(0);
+        kh[W] = K(0);
+#pragma unroll
+        for (int s = 0; s < NSR; ++s) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) wr[W][s][v] = R(0);
+            wrh[W][s] = R(0);
+        }
+#pragma unroll
+        for (int c = 0; c < NSCA; ++c) {
+#pragma unroll
+            for (int v = 0; v < 2 * VX; ++v) wc[W][c][v] = R(0);
+            wch[W][c][0] = wch[W][c][1] = R(0);
+        }
+        int yy = y;
+        if (PER) yy = (y < 0) ? y + ny : (y >= ny ? y - ny : y);
+        if (!PER && (y < 0 || y >= ny)) return;  // Dirichlet ghost row: zeros
+        const unsigned rowp = static_cast<unsigned>(yy) * static_cast<unsigned>(nx);
+        const unsigned pt = rowp + static_cast<unsigned>(xl);
+        const unsigned hp = rowp + static_cast<unsigned>(hx);
+        if (any) {
+            if (lane_ok) {
+                if constexpr (sizeof(KS) == sizeof(K)) {
+                    ldv<K, VX>(reinterpret_cast<const K*>(kap) + pt, kw[W]);
+                } else {
+                    kloadv<VX>(kap, pt, kw[W]);
+                }
+            }
+            if (hok) kh[W] = static_cast<K>(kload(kap, hp));
+        }
 #pragma unroll
         for (int s = 0; s < NSR; ++s) {
             if (comp[s]) {
-                const R* src = (CURK == SRC_RHAT) ? a.rhat[s] : a.cur[s];
-                load_real_row<R, VX, R>(src, g, y, x0, lane, rr[s], rh[s]);
-                if (CURK == SRC_RHAT) {
+                const R* b = wbase + a.soff[s];
+                if (lane_ok) ldv<R, VX>(b + pt, wr[W][s]);
+                if (hok) wrh[W][s] = b[hp];
+            }
+        }
 #pragma unroll
-                    for (int v = 0; v < VX; ++v) rr[s][v] *= a.cf.s_re[s];
-                    rh[s] *= a.cf.s_re[s];
+        for (int c = 0; c < NSC; ++c) {
+            if (comp[NSR + c]) {
+                const R* b = wbase + a.soff[NSR + c];
+                if (lane_ok) ldv<R, 2 * VX>(b + 2u * pt, wc[W][c]);
+                if (hok) {
+                    wch[W][c][0] = b[2u * hp];
+                    wch[W][c][1] = b[2u * hp + 1u];
                 }
+            }
+        }
+    };
+
+    // centre-row operands: rhat (unless CUR_RHAT), x_{k-1}, or (FINAL) finished iterates
+    R hr[NSR][VX], hc[NSCA][2 * VX];  // rhat centre
+    R pr[NSR][VX], pc[NSCA][2 * VX];  // x_{k-1} centre, or finished iterate
+    const int prevk = a.prevk;
+    const R* __restrict__ pbase = FINAL ? a.prev : a.out;
+
+    auto load_centre = [&](int y) {
+        const unsigned pt = static_cast<unsigned>(y) * static_cast<unsigned>(nx) + static_cast<unsigned>(xb);
+        const bool ok = (xb < nx);
+#pragma unroll
+        for (int s = 0; s < NSR; ++s) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) hr[s][v] = pr[s][v] = R(0);
+            const unsigned o = a.soff[s] + pt;
+            if (comp[s]) {
+                if (!CUR_RHAT && ok) ldv<R, VX>(a.rhat + o, hr[s]);
+                if (prevk == SRC_BUF && ok) ldv<R, VX>(pbase + o, pr[s]);
+                if (prevk == SRC_RHAT && ok) ldv<R, VX>(a.rhat + o, pr[s]);
+            } else if (FINAL && ok) {
+                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : (a.fbuf[s] ? a.buf1 : a.buf0);
+                ldv<R, VX>(f + o, pr[s]);
             }
         }
 #pragma unroll
         for (int c = 0; c < NSC; ++c) {
             const int s = NSR + c;
+#pragma unroll
+            for (int v = 0; v < 2 * VX; ++v) hc[c][v] = pc[c][v] = R(0);
+            const unsigned o = a.soff[s] + 2u * pt;
             if (comp[s]) {
-                const R* src = (CURK == SRC_RHAT) ? a.rhat[s] : a.cur[s];
-                const R sr = (CURK == SRC_RHAT) ? a.cf.s_re[s] : R(1);
-                const R si = (CURK == SRC_RHAT) ? a.cf.s_im[s] : R(0);
-                load_cplx_row<R, VX>(src, g, y, x0, lane, sr, si, qr[c], qi[c], qhr[c], qhi[c]);
+                if (!CUR_RHAT && ok) ldv<R, 2 * VX>(a.rhat + o, hc[c]);
+                if (prevk == SRC_BUF && ok) ldv<R, 2 * VX>(pbase + o, pc[c]);
+                if (prevk == SRC_RHAT && ok) ldv<R, 2 * VX>(a.rhat + o, pc[c]);
+            } else if (FINAL && ok) {
+                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : (a.fbuf[s] ? a.buf1 : a.buf0);
+                ldv<R, 2 * VX>(f + o, pc[c]);
             }
         }
     };
 
-    {
-        R dr[NSR], dcr[NSCA], dci[NSCA];
-        load_window_row(y0 - 1, kp, kdummy, rp, dr, cpr, cpi, dcr, dci);
-        load_window_row(y0, kc, khc, rc, rhc, ccr, cci, chcr, chci);
-    }
+    auto compute_row = [&](auto P_, auto C_, auto N_, int y) {
+        constexpr int P = decltype(P_)::value, C = decltype(C_)::value, N = decltype(N_)::value;
+        const unsigned pt = static_cast<unsigned>(y) * static_cast<unsigned>(nx) + static_cast<unsigned>(xb);
+        const bool store_ok = (xb < nx);
 
-    for (int y = y0; y < y1; ++y) {
-        load_window_row(y + 1, kn, khn, rn, rhn, cnr, cni, chnr, chni);
-
-        const long long rowoff = static_cast<long long>(y) * g.nx;
-        const int xb = x0 + lane * VX;
-        const bool store_ok = (xb < g.nx);
-
-        // kappa neighbours in x
-        const K kwv = shfl_up1(kc[VX - 1]);
-        const K kev = shfl_dn1(kc[0]);
+        // face coefficients, shared by all shifts
+        const K kwv = shfl_up1(kw[C][VX - 1]);
+        const K kev = shfl_dn1(kw[C][0]);
         Faces<K> fc[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            const K kw = (v > 0) ? kc[v - 1] : (lane == 0 ? khc : kwv);
-            const K ke = (v < VX - 1) ? kc[v + 1] : (lane == kWave - 1 ? khc : kev);
-            fc[v] = faces<K>(g, xb + v, y, kc[v], kw, ke, kp[v], kn[v]);
+            const K kwest = (v > 0) ? kw[C][v - 1] : (lane == 0 ? kh[C] : kwv);
+            const K keast = (v < VX - 1) ? kw[C][v + 1] : (lane == kWave - 1 ? kh[C] : kev);
+            fc[v] = faces<K>(a.g, xb + v, y, kw[C][v], kwest, keast, kw[P][v], kw[N][v]);
         }
 
-        // final-sweep accumulators: yhat per slot
-        R yr_real[NSR][VX];
-        R yc_re[NSCA][VX], yc_im[NSCA][VX];
+        R yr[NSR][VX];
+        R yc[NSCA][2 * VX];
 
         // ---- real shifts
 #pragma unroll
         for (int s = 0; s < NSR; ++s) {
             if (comp[s]) {
-                const R wv = shfl_up1(rc[s][VX - 1]);
-                const R ev = shfl_dn1(rc[s][0]);
-                R rh[VX], xp[VX];
-                if (CURK == SRC_RHAT) {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) rh[v] = rc[s][v] / a.cf.s_re[s];
-                } else if (store_ok) {
-                    ldv<R, VX>(a.rhat[s] + rowoff + xb, rh);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) rh[v] = R(0);
-                }
-                if (PREVK == SRC_BUF) {
-                    const R* pb = FINAL ? a.prev[s] : a.out[s];
-                    if (store_ok) {
-                        ldv<R, VX>(pb + rowoff + xb, xp);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < VX; ++v) xp[v] = R(0);
-                    }
-                } else if (PREVK == SRC_RHAT) {
-                    R t[VX];
-                    if (store_ok) {
-                        ldv<R, VX>(a.rhat[s] + rowoff + xb, t);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < VX; ++v) t[v] = R(0);
-                    }
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) xp[v] = a.cf.s_re[s] * t[v];
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) xp[v] = R(0);
-                }
-                R xo[VX];
+                const R sc = CUR_RHAT ? a.cf.s_re[s] : R(1);
+                const R wv = shfl_up1(wr[C][s][VX - 1]);
+                const R ev = shfl_dn1(wr[C][s][0]);
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    const R xw = (v > 0) ? rc[s][v - 1] : (lane == 0 ? rhc[s] : wv);
-                    const R xe = (v < VX - 1) ? rc[s][v + 1] : (lane == kWave - 1 ? rhc[s] : ev);
-                    const R xc = rc[s][v];
-                    R bx = (fc[v].diag - a.cf.lam_re[s]) * xc;
-                    bx -= fc[v].w * xw + fc[v].e * xe + fc[v].s * rp[s][v] + fc[v].n * rn[s][v];
-                    xo[v] = xc + a.cf.a_re[s] * (xc - xp[v]) + a.cf.c_re[s] * (rh[v] - bx);
+                    const R uw = (v > 0) ? wr[C][s][v - 1] : (lane == 0 ? wrh[C][s] : wv);
+                    const R ue = (v < VX - 1) ? wr[C][s][v + 1] : (lane == kWave - 1 ? wrh[C][s] : ev);
+                    const R uc = wr[C][s][v];
+                    R bu = (fc[v].diag - a.cf.lam_re[s]) * uc;
+                    bu -= fc[v].w * uw + fc[v].e * ue + fc[v].s * wr[P][s][v] + fc[v].n * wr[N][s][v];
+                    const R xc = sc * uc;
+                    const R bx = sc * bu;
+                    const R rh = CUR_RHAT ? uc : hr[s][v];
+                    const R xp = (prevk == SRC_RHAT) ? a.cf.s_re[s] * pr[s][v] : pr[s][v];
+                    yr[s][v] = xc + a.cf.a_re[s] * (xc - xp) + a.cf.c_re[s] * (rh - bx);
                 }
-                if (FINAL) {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) yr_real[s][v] = xo[v];
-                } else if (store_ok) {
-                    stv<R, VX>(a.out[s] + rowoff + xb, xo);
-                }
+                if (!FINAL && store_ok) stv<R, VX>(a.out + a.soff[s] + pt, yr[s]);
             } else if (FINAL) {
-                R t[VX];
-                if (store_ok) {
-                    ldv<R, VX>((a.src[s] == SRC_RHAT ? a.rhat[s] : a.fin[s]) + rowoff + xb, t);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) t[v] = R(0);
-                }
                 const R sc = (a.src[s] == SRC_RHAT) ? a.cf.s_re[s] : R(1);
 #pragma unroll
-                for (int v = 0; v < VX; ++v) yr_real[s][v] = sc * t[v];
+                for (int v = 0; v < VX; ++v) yr[s][v] = sc * pr[s][v];
             }
         }
 
@@ -376,116 +413,52 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
         for (int c = 0; c < NSC; ++c) {
             const int s = NSR + c;
             if (comp[s]) {
-                const R wr = shfl_up1(ccr[c][VX - 1]);
-                const R wi = shfl_up1(cci[c][VX - 1]);
-                const R er = shfl_dn1(ccr[c][0]);
-                const R ei = shfl_dn1(cci[c][0]);
-                R rhr[VX], rhi[VX], xpr[VX], xpi[VX];
-                if (CURK == SRC_RHAT) {
-                    // window holds s*rhat; recover rhat = window / s
-                    const R sr = a.cf.s_re[s], si = a.cf.s_im[s];
-                    const R inv = R(1) / (sr * sr + si * si);
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        rhr[v] = (ccr[c][v] * sr + cci[c][v] * si) * inv;
-                        rhi[v] = (cci[c][v] * sr - ccr[c][v] * si) * inv;
-                    }
-                } else {
-                    R t[2 * VX];
-                    if (store_ok) {
-                        ldv<R, 2 * VX>(a.rhat[s] + 2 * (rowoff + xb), t);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < 2 * VX; ++v) t[v] = R(0);
-                    }
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        rhr[v] = t[2 * v];
-                        rhi[v] = t[2 * v + 1];
-                    }
-                }
-                if (PREVK == SRC_BUF) {
-                    const R* pb = FINAL ? a.prev[s] : a.out[s];
-                    R t[2 * VX];
-                    if (store_ok) {
-                        ldv<R, 2 * VX>(pb + 2 * (rowoff + xb), t);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < 2 * VX; ++v) t[v] = R(0);
-                    }
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        xpr[v] = t[2 * v];
-                        xpi[v] = t[2 * v + 1];
-                    }
-                } else if (PREVK == SRC_RHAT) {
-                    R t[2 * VX];
-                    if (store_ok) {
-                        ldv<R, 2 * VX>(a.rhat[s] + 2 * (rowoff + xb), t);
-                    } else {
-#pragma unroll
-                        for (int v = 0; v < 2 * VX; ++v) t[v] = R(0);
-                    }
-                    const R sr = a.cf.s_re[s], si = a.cf.s_im[s];
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        xpr[v] = sr * t[2 * v] - si * t[2 * v + 1];
-                        xpi[v] = sr * t[2 * v + 1] + si * t[2 * v];
-                    }
-                } else {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) xpr[v] = xpi[v] = R(0);
-                }
+                const R sr = CUR_RHAT ? a.cf.s_re[s] : R(1);
+                const R si = CUR_RHAT ? a.cf.s_im[s] : R(0);
+                const R wre = shfl_up1(wc[C][c][2 * VX - 2]);
+                const R wim = shfl_up1(wc[C][c][2 * VX - 1]);
+                const R ere = shfl_dn1(wc[C][c][0]);
+                const R eim = shfl_dn1(wc[C][c][1]);
                 const R lr = a.cf.lam_re[s], li = a.cf.lam_im[s];
                 const R ar = a.cf.a_re[s], ai = a.cf.a_im[s];
                 const R cr = a.cf.c_re[s], ci = a.cf.c_im[s];
-                R xor_[VX], xoi[VX];
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    const R xwr = (v > 0) ? ccr[c][v - 1] : (lane == 0 ? chcr[c] : wr);
-                    const R xwi = (v > 0) ? cci[c][v - 1] : (lane == 0 ? chci[c] : wi);
-                    const R xer = (v < VX - 1) ? ccr[c][v + 1] : (lane == kWave - 1 ? chcr[c] : er);
-                    const R xei = (v < VX - 1) ? cci[c][v + 1] : (lane == kWave - 1 ? chci[c] : ei);
-                    const R xr = ccr[c][v], xi = cci[c][v];
+                    const R uwr = (v > 0) ? wc[C][c][2 * v - 2] : (lane == 0 ? wch[C][c][0] : wre);
+                    const R uwi = (v > 0) ? wc[C][c][2 * v - 1] : (lane == 0 ? wch[C][c][1] : wim);
+                    const R uer = (v < VX - 1) ? wc[C][c][2 * v + 2] : (lane == kWave - 1 ? wch[C][c][0] : ere);
+                    const R uei = (v < VX - 1) ? wc[C][c][2 * v + 3] : (lane == kWave - 1 ? wch[C][c][1] : eim);
+                    const R ucr = wc[C][c][2 * v], uci = wc[C][c][2 * v + 1];
                     const R dl = fc[v].diag - lr;
-                    R bxr = dl * xr + li * xi;
-                    R bxi = dl * xi - li * xr;
-                    bxr -= fc[v].w * xwr + fc[v].e * xer + fc[v].s * cpr[c][v] + fc[v].n * cnr[c][v];
-                    bxi -= fc[v].w * xwi + fc[v].e * xei + fc[v].s * cpi[c][v] + fc[v].n * cni[c][v];
-                    const R dr = xr - xpr[v], di = xi - xpi[v];
-                    const R qr = rhr[v] - bxr, qi = rhi[v] - bxi;
-                    xor_[v] = xr + (ar * dr - ai * di) + (cr * qr - ci * qi);
-                    xoi[v] = xi + (ar * di + ai * dr) + (cr * qi + ci * qr);
-                }
-                if (FINAL) {
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        yc_re[c][v] = xor_[v];
-                        yc_im[c][v] = xoi[v];
+                    R bur = dl * ucr + li * uci;
+                    R bui = dl * uci - li * ucr;
+                    bur -= fc[v].w * uwr + fc[v].e * uer + fc[v].s * wc[P][c][2 * v] + fc[v].n * wc[N][c][2 * v];
+                    bui -= fc[v].w * uwi + fc[v].e * uei + fc[v].s * wc[P][c][2 * v + 1] +
+                           fc[v].n * wc[N][c][2 * v + 1];
+                    // x = s u, B x = s (B u)
+                    const R xr = sr * ucr - si * uci, xi = sr * uci + si * ucr;
+                    const R bxr = sr * bur - si * bui, bxi = sr * bui + si * bur;
+                    const R rhr = CUR_RHAT ? ucr : hc[c][2 * v];
+                    const R rhi = CUR_RHAT ? uci : hc[c][2 * v + 1];
+                    R xpr = pc[c][2 * v], xpi = pc[c][2 * v + 1];
+                    if (prevk == SRC_RHAT) {
+                        const R t = a.cf.s_re[s] * xpr - a.cf.s_im[s] * xpi;
+                        xpi = a.cf.s_re[s] * xpi + a.cf.s_im[s] * xpr;
+                        xpr = t;
                     }
-                } else if (store_ok) {
-                    R t[2 * VX];
-#pragma unroll
-                    for (int v = 0; v < VX; ++v) {
-                        t[2 * v] = xor_[v];
-                        t[2 * v + 1] = xoi[v];
-                    }
-                    stv<R, 2 * VX>(a.out[s] + 2 * (rowoff + xb), t);
+                    const R dr = xr - xpr, di = xi - xpi;
+                    const R qr = rhr - bxr, qi = rhi - bxi;
+                    yc[c][2 * v] = xr + (ar * dr - ai * di) + (cr * qr - ci * qi);
+                    yc[c][2 * v + 1] = xi + (ar * di + ai * dr) + (cr * qi + ci * qr);
                 }
+                if (!FINAL && store_ok) stv<R, 2 * VX>(a.out + a.soff[s] + 2u * pt, yc[c]);
             } else if (FINAL) {
-                R t[2 * VX];
-                if (store_ok) {
-                    ldv<R, 2 * VX>((a.src[s] == SRC_RHAT ? a.rhat[s] : a.fin[s]) + 2 * (rowoff + xb), t);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < 2 * VX; ++v) t[v] = R(0);
-                }
-                const bool sc = (a.src[s] == SRC_RHAT);
-                const R sr = sc ? a.cf.s_re[s] : R(1), si = sc ? a.cf.s_im[s] : R(0);
+                const bool rs = (a.src[s] == SRC_RHAT);
+                const R sr = rs ? a.cf.s_re[s] : R(1), si = rs ? a.cf.s_im[s] : R(0);
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    yc_re[c][v] = sr * t[2 * v] - si * t[2 * v + 1];
-                    yc_im[c][v] = sr * t[2 * v + 1] + si * t[2 * v];
+                    yc[c][2 * v] = sr * pc[c][2 * v] - si * pc[c][2 * v + 1];
+                    yc[c][2 * v + 1] = sr * pc[c][2 * v + 1] + si * pc[c][2 * v];
                 }
             }
         }
@@ -499,48 +472,42 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
                 double zk[VX];
 #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    double acc = static_cast<double>(yr_real[0][v]);
-                    if (NSR == 2) acc += ((k & 1) ? -1.0 : 1.0) * static_cast<double>(yr_real[NSR - 1][v]);
+                    double acc = static_cast<double>(yr[0][v]);
+                    if (NSR == 2) acc += ((k & 1) ? -1.0 : 1.0) * static_cast<double>(yr[NSR - 1][v]);
                     double sum = 0.0;
 #pragma unroll
                     for (int c = 0; c < NSC; ++c) {
                         const int j = ((c + 1) * k) % ELL;
-                        sum += static_cast<double>(yc_re[c][v]) * a.cw[j] - static_cast<double>(yc_im[c][v]) * a.sw[j];
+                        sum += static_cast<double>(yc[c][2 * v]) * a.cw[j] -
+                               static_cast<double>(yc[c][2 * v + 1]) * a.sw[j];
                     }
                     zk[v] = a.ginv[k] * (acc + 2.0 * sum);
                 }
-                stv<double, VX>(a.z + static_cast<long long>(k) * g.n + rowoff + xb, zk);
+                stv<double, VX>(a.z + static_cast<size_t>(k) * static_cast<size_t>(a.g.n) + pt, zk);
             }
         }
+    };
 
-        // rotate windows
-#pragma unroll
-        for (int v = 0; v < VX; ++v) {
-            kp[v] = kc[v];
-            kc[v] = kn[v];
-        }
-        khc = khn;
-#pragma unroll
-        for (int s = 0; s < NSR; ++s) {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                rp[s][v] = rc[s][v];
-                rc[s][v] = rn[s][v];
-            }
-            rhc[s] = rhn[s];
-        }
-#pragma unroll
-        for (int c = 0; c < NSC; ++c) {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                cpr[c][v] = ccr[c][v];
-                cpi[c][v] = cci[c][v];
-                ccr[c][v] = cnr[c][v];
-                cci[c][v] = cni[c][v];
-            }
-            chcr[c] = chnr[c];
-            chci[c] = chni[c];
-        }
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    load_row(I0{}, y0 - 1);
+    load_row(I1{}, y0);
+    // rows rotate through the three window slots: (p, c, n) = (0,1,2), (1,2,0), (2,0,1)
+    int y = y0;
+    while (y < y1) {
+        load_row(I2{}, y + 1);
+        load_centre(y);
+        compute_row(I0{}, I1{}, I2{}, y);
+        if (++y >= y1) break;
+        load_row(I0{}, y + 1);
+        load_centre(y);
+        compute_row(I1{}, I2{}, I0{}, y);
+        if (++y >= y1) break;
+        load_row(I1{}, y + 1);
+        load_centre(y);
+        compute_row(I2{}, I0{}, I1{}, y);
+        ++y;
     }
 }
 
