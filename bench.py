@@ -2,7 +2,7 @@
 mixed precision against float64 inner solves, with the shifted-stencil roofline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium]
-                    [--p 10] [--no-cpu-baseline]
+                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels]
 
 One step = one FGMRES(30) solve of calA x = b (b = (b_1, 0, ..., 0)) from x = 0
 on resident device inputs, preconditioned by the nested-Chebyshev block
@@ -10,7 +10,7 @@ alpha-circulant preconditioner.  Prints ONE JSON line.
 
 Workloads (synthetic, seeded):
 * large  (default): 2048 x 2048 grid, kappa = 50 exp(g), g a Gaussian random
-  field (std 1, correlation length 10 cells), l = 10, alpha = 1e-2, p = 10 inner
+  field (std 1, correlation length 10 cells), l = 10, alpha = 1e-2, p = 20 inner
   steps per shift, complex64 inner with bfloat16 kappa, float64 outer.
 * medium: the same on 512 x 512.
 """
@@ -42,17 +42,67 @@ def parse():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
-    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--p", type=int, default=20)
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels"],
+                    help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
+                         "(the launch set used for hardware-counter runs)")
     return ap.parse_args()
+
+
+def kernels_only(a, api, prob, ell, n):
+    """A few P_NC^{-1} applications in the solve's precision and launch shape, then a
+    plain device copy of known size (reference for the FETCH_SIZE/WRITE_SIZE scale)."""
+    import torch
+    L = api.L
+    dev = torch.device("cuda:0")
+    r = torch.randn(ell * n, dtype=torch.float64, device=dev)
+    z = torch.empty_like(r)
+    opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=a.p)
+    ws = api.workspace(api.ac_prec_workspace_size(prob, opts))
+    ctx = prob.ctx
+    api.ac_apply_prec(prob, opts, r, z, ws)
+    api.ac_ctx_set_profiling(ctx, True)
+    api.ac_ctx_reset_stats(ctx)
+    for _ in range(max(a.steps, 1)):
+        api.ac_apply_prec(prob, opts, r, z, ws)
+    st = api.ac_ctx_kernel_stats(ctx)["cheb_step"]
+    api.ac_ctx_set_profiling(ctx, False)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)  # 512 MiB
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    avg_ms = st["ms"] / st["launches"]
+    per = st["bytes"] / st["launches"]
+    print(json.dumps({"mode": "kernels", "cheb_step_avg_ms": avg_ms, "cheb_step_bytes_per_launch": per,
+                      "cheb_step_GBps": per / avg_ms / 1e6, "launches": st["launches"],
+                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def measured_traffic(a):
+    """HBM bytes per launch of the steady-state sweep from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE record (scaled by a copy of known size), or None when the
+    record does not cover this workload or the kernel source changed since."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "cheb_sweep_2048x2048_l10_traffic.json")
+    if a.workload != "large" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, "paper_2506_03947_amd", "csrc", "stencil_kernels.h"), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"] or a.p < 4:
+        return None
+    # steady-state launches per application: k = 2..p-2, the k = 2 one reads x_1 = rhat/theta
+    v = rec["variants"]
+    n = a.p - 3
+    return ((n - 1) * v["steady_prev_buffer"]["bytes"] + v["steady_prev_rhat"]["bytes"]) / n
 
 
 def cpu_baseline(w, kappa, b, p, gpu_outer_iters):
@@ -106,6 +156,9 @@ def main():
     ctx = api.ac_ctx_create(0)
     prob = api.ac_problem_create(ctx, 2, nx, ny, kd, ell, alpha)
     mu_lo, mu_hi = api.ac_spectral_bounds(prob)
+    if a.mode == "kernels":
+        kernels_only(a, api, prob, ell, n)
+        return
 
     def run(precision, steps, warmup, profile):
         opts = api.Opts(precision=precision, p=a.p, tol=a.tol, restart_m=a.restart, max_outer=3000)
@@ -150,9 +203,9 @@ def main():
     avg_ms = st["ms"] / max(st["launches"], 1)
     bytes_per_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"kernel": "cheb_sweep_kernel (batched shifted Chebyshev step, all unique shifts)",
+    roofline = {"kernel": "cheb_sweep_kernel (steady-state batched shifted Chebyshev sweep, all unique shifts)",
                 "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(a),
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
                 "launches": st["launches"]}
 

@@ -117,12 +117,13 @@ typedef struct {
 /* Kernel classes timed when profiling is on (ac_ctx_set_profiling). */
 typedef enum {
     AC_K_TDFT_FWD = 0,   /* forward scaled time-DFT (+ conversion to the inner type) */
-    AC_K_CHEB_STEP = 1,  /* one batched shifted Chebyshev sweep over all active shifts */
+    AC_K_CHEB_STEP = 1,  /* one steady-state batched shifted Chebyshev sweep, all active shifts */
     AC_K_CHEB_FINAL = 2, /* last Chebyshev sweep fused with the inverse scaled time-DFT */
     AC_K_APPLY_CALA = 3, /* calA x or b - calA x, float64 */
     AC_K_KRYLOV = 4,     /* multi-dot / multi-axpy / norms, float64 */
     AC_K_CNN = 5,        /* warm-start network */
-    AC_K_COUNT = 6
+    AC_K_CHEB_FIRST = 6, /* the first sweep from a zero guess (x_2 from x_1 = rhat/theta) */
+    AC_K_COUNT = 7
 } ac_kernel_class;
 
 /* ---- status ------------------------------------------------------------- */

@@ -38,8 +38,9 @@ AC_K_CHEB_FINAL = 2
 AC_K_APPLY_CALA = 3
 AC_K_KRYLOV = 4
 AC_K_CNN = 5
-AC_K_COUNT = 6
-KERNEL_CLASS_NAMES = ["tdft_fwd", "cheb_step", "cheb_final", "apply_calA", "krylov", "cnn"]
+AC_K_CHEB_FIRST = 6
+AC_K_COUNT = 7
+KERNEL_CLASS_NAMES = ["tdft_fwd", "cheb_step", "cheb_final", "apply_calA", "krylov", "cnn", "cheb_first"]
 
 
 class ac_grid(C.Structure):

@@ -9,6 +9,7 @@
 #include <complex>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -63,6 +64,7 @@ struct ac_ctx {
         hipEvent_t a, b;
         int cls;
         double bytes;
+        int launches;
     };
     std::vector<Pending> pending;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
@@ -96,6 +98,7 @@ struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     int cls;
     double bytes;
+    int launches = 1;
     ProfScope(ac_ctx* ctx, int cls_, double bytes_) : c(ctx), cls(cls_), bytes(bytes_) {
         if (!c->profiling) return;
         if (!c->pool.empty()) {
@@ -111,7 +114,7 @@ struct ProfScope {
     ~ProfScope() {
         if (!c->profiling || !a) return;
         (void)hipEventRecord(b, c->stream);
-        c->pending.push_back({a, b, cls, bytes});
+        c->pending.push_back({a, b, cls, bytes, launches});
     }
 };
 
@@ -121,7 +124,7 @@ int harvest(ac_ctx* c) {
         float ms = 0.f;
         AC_HIP(hipEventElapsedTime(&ms, p.a, p.b));
         c->ms[p.cls] += ms;
-        c->launches[p.cls] += 1;
+        c->launches[p.cls] += p.launches;
         c->bytes[p.cls] += p.bytes;
         c->pool.emplace_back(p.a, p.b);
     }
@@ -371,6 +374,8 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         fill_twiddles(p->ell, a.cw, a.sw);
         a.z = z;
     };
+    // consecutive steady-state sweeps share one event pair (no per-launch event cost)
+    std::unique_ptr<ProfScope> steady;
     for (int k = k_first; k <= k_last; ++k) {
         const bool final = fuse && (k == k_last);
         ac::SweepArgs<R> a{};
@@ -406,10 +411,19 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             fill_final(a);
             ProfScope ps_(p->ctx, AC_K_CHEB_FINAL, bytes);
             AC_HIP(ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream));
+        } else if (curk == ac::SRC_RHAT) {
+            ProfScope ps_(p->ctx, AC_K_CHEB_FIRST, bytes);
+            AC_HIP(ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream));
         } else {
-            ProfScope ps_(p->ctx, AC_K_CHEB_STEP, bytes);
+            if (!steady) {
+                steady = std::make_unique<ProfScope>(p->ctx, AC_K_CHEB_STEP, 0.0);
+                steady->launches = 0;
+            }
+            steady->bytes += bytes;
+            steady->launches += 1;
             AC_HIP(ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream));
         }
+        if (steady && (k + 1 > k_last || (fuse && k + 1 == k_last))) steady.reset();
     }
     if (fuse && k_last < k_first) {
         // nothing to iterate (cold start, every p = 1): x_1 = rhat/theta everywhere

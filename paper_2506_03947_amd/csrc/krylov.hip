@@ -22,10 +22,15 @@ struct alignas(16) D2 {
     double x, y;
 };
 
+// Krylov vectors are far larger than the caches between two uses: stream them.
+typedef double D2v __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ D2 load2(const double* p, long long e, long long len) {
     D2 r;
     if (e + 1 < len) {
-        r = *reinterpret_cast<const D2*>(p + e);
+        const D2v t = __builtin_nontemporal_load(reinterpret_cast<const D2v*>(p + e));
+        r.x = t[0];
+        r.y = t[1];
     } else {
         r.x = p[e];
         r.y = 0.0;
@@ -34,7 +39,10 @@ __device__ __forceinline__ D2 load2(const double* p, long long e, long long len)
 }
 __device__ __forceinline__ void store2(double* p, long long e, long long len, D2 v) {
     if (e + 1 < len) {
-        *reinterpret_cast<D2*>(p + e) = v;
+        D2v t;
+        t[0] = v.x;
+        t[1] = v.y;
+        __builtin_nontemporal_store(t, reinterpret_cast<D2v*>(p + e));
     } else {
         p[e] = v.x;
     }

@@ -46,6 +46,56 @@ __device__ __forceinline__ void stv(T* p, const T (&in)[V]) {
     *reinterpret_cast<Vec<T, V>*>(p) = t;
 }
 
+// Non-temporal variants for operands touched once per sweep (clang ext vectors).
+template <typename T, int V>
+using ExtVec = T __attribute__((ext_vector_type(V)));
+
+template <typename T, int V>
+__device__ __forceinline__ void ldv_nt(const T* p, T (&out)[V]) {
+    if constexpr (V == 1) {
+        out[0] = __builtin_nontemporal_load(p);
+    } else {
+        const ExtVec<T, V> t = __builtin_nontemporal_load(reinterpret_cast<const ExtVec<T, V>*>(p));
+#pragma unroll
+        for (int i = 0; i < V; ++i) out[i] = t[i];
+    }
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void stv_nt(T* p, const T (&in)[V]) {
+    if constexpr (V == 1) {
+        __builtin_nontemporal_store(in[0], p);
+    } else {
+        ExtVec<T, V> t;
+#pragma unroll
+        for (int i = 0; i < V; ++i) t[i] = in[i];
+        __builtin_nontemporal_store(t, reinterpret_cast<ExtVec<T, V>*>(p));
+    }
+}
+
+// 1: the centre operands (rhat, x_{k-1}) and the new iterate, each touched once per
+// sweep, use non-temporal loads/stores (measured +20 % on 2048^2, l = 10, complex64);
+// 2: the stencil window as well (slower: the chunk halo rows are then refetched).
+#ifndef AC_SWEEP_NT
+#define AC_SWEEP_NT 1
+#endif
+template <typename T, int V>
+__device__ __forceinline__ void ldc(const T* p, T (&out)[V]) {
+    if constexpr (AC_SWEEP_NT != 0) ldv_nt<T, V>(p, out);
+    else ldv<T, V>(p, out);
+}
+// stencil-window operand (read once per sweep apart from the chunk halo rows)
+template <typename T, int V>
+__device__ __forceinline__ void ldw(const T* p, T (&out)[V]) {
+    if constexpr (AC_SWEEP_NT >= 2) ldv_nt<T, V>(p, out);
+    else ldv<T, V>(p, out);
+}
+template <typename T, int V>
+__device__ __forceinline__ void stc(T* p, const T (&in)[V]) {
+    if constexpr (AC_SWEEP_NT != 0) stv_nt<T, V>(p, in);
+    else stv<T, V>(p, in);
+}
+
 // kappa storage -> compute type
 __device__ __forceinline__ float kload(const uint16_t* p, long long i) {
     return __uint_as_float(static_cast<uint32_t>(p[i]) << 16);
@@ -304,7 +354,7 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
         for (int s = 0; s < NSR; ++s) {
             if (comp[s]) {
                 const R* b = wbase + a.soff[s];
-                if (lane_ok) ldv<R, VX>(b + pt, wr[W][s]);
+                if (lane_ok) ldw<R, VX>(b + pt, wr[W][s]);
                 if (hok) wrh[W][s] = b[hp];
             }
         }
@@ -312,7 +362,7 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
         for (int c = 0; c < NSC; ++c) {
             if (comp[NSR + c]) {
                 const R* b = wbase + a.soff[NSR + c];
-                if (lane_ok) ldv<R, 2 * VX>(b + 2u * pt, wc[W][c]);
+                if (lane_ok) ldw<R, 2 * VX>(b + 2u * pt, wc[W][c]);
                 if (hok) {
                     wch[W][c][0] = b[2u * hp];
                     wch[W][c][1] = b[2u * hp + 1u];
@@ -336,12 +386,12 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
             for (int v = 0; v < VX; ++v) hr[s][v] = pr[s][v] = R(0);
             const unsigned o = a.soff[s] + pt;
             if (comp[s]) {
-                if (!CUR_RHAT && ok) ldv<R, VX>(a.rhat + o, hr[s]);
-                if (prevk == SRC_BUF && ok) ldv<R, VX>(pbase + o, pr[s]);
-                if (prevk == SRC_RHAT && ok) ldv<R, VX>(a.rhat + o, pr[s]);
+                if (!CUR_RHAT && ok) ldc<R, VX>(a.rhat + o, hr[s]);
+                if (prevk == SRC_BUF && ok) ldc<R, VX>(pbase + o, pr[s]);
+                if (prevk == SRC_RHAT && ok) ldc<R, VX>(a.rhat + o, pr[s]);
             } else if (FINAL && ok) {
                 const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : (a.fbuf[s] ? a.buf1 : a.buf0);
-                ldv<R, VX>(f + o, pr[s]);
+                ldc<R, VX>(f + o, pr[s]);
             }
         }
 #pragma unroll
@@ -351,12 +401,12 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
             for (int v = 0; v < 2 * VX; ++v) hc[c][v] = pc[c][v] = R(0);
             const unsigned o = a.soff[s] + 2u * pt;
             if (comp[s]) {
-                if (!CUR_RHAT && ok) ldv<R, 2 * VX>(a.rhat + o, hc[c]);
-                if (prevk == SRC_BUF && ok) ldv<R, 2 * VX>(pbase + o, pc[c]);
-                if (prevk == SRC_RHAT && ok) ldv<R, 2 * VX>(a.rhat + o, pc[c]);
+                if (!CUR_RHAT && ok) ldc<R, 2 * VX>(a.rhat + o, hc[c]);
+                if (prevk == SRC_BUF && ok) ldc<R, 2 * VX>(pbase + o, pc[c]);
+                if (prevk == SRC_RHAT && ok) ldc<R, 2 * VX>(a.rhat + o, pc[c]);
             } else if (FINAL && ok) {
                 const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : (a.fbuf[s] ? a.buf1 : a.buf0);
-                ldv<R, 2 * VX>(f + o, pc[c]);
+                ldc<R, 2 * VX>(f + o, pc[c]);
             }
         }
     };
@@ -400,7 +450,7 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
                     const R xp = (prevk == SRC_RHAT) ? a.cf.s_re[s] * pr[s][v] : pr[s][v];
                     yr[s][v] = xc + a.cf.a_re[s] * (xc - xp) + a.cf.c_re[s] * (rh - bx);
                 }
-                if (!FINAL && store_ok) stv<R, VX>(a.out + a.soff[s] + pt, yr[s]);
+                if (!FINAL && store_ok) stc<R, VX>(a.out + a.soff[s] + pt, yr[s]);
             } else if (FINAL) {
                 const R sc = (a.src[s] == SRC_RHAT) ? a.cf.s_re[s] : R(1);
 #pragma unroll
@@ -451,7 +501,7 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
                     yc[c][2 * v] = xr + (ar * dr - ai * di) + (cr * qr - ci * qi);
                     yc[c][2 * v + 1] = xi + (ar * di + ai * dr) + (cr * qi + ci * qr);
                 }
-                if (!FINAL && store_ok) stv<R, 2 * VX>(a.out + a.soff[s] + 2u * pt, yc[c]);
+                if (!FINAL && store_ok) stc<R, 2 * VX>(a.out + a.soff[s] + 2u * pt, yc[c]);
             } else if (FINAL) {
                 const bool rs = (a.src[s] == SRC_RHAT);
                 const R sr = rs ? a.cf.s_re[s] : R(1), si = rs ? a.cf.s_im[s] : R(0);
