@@ -220,6 +220,48 @@ int ac_tdft_inverse(ac_problem* p, int precision, const void* yhat, double* z);
 int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws, size_t ws_bytes,
              ac_solve_info* info);
 
+/* ---- learned warm start (not part of the paper's method) ----------------------
+ * A three-layer 3x3 convolutional network (5 -> 16 -> 16 -> 2 channels, ReLU after
+ * the first two layers, zero padding), bfloat16 weights/activations with float32
+ * accumulation on the matrix cores, gives the initial guess of each shifted inner
+ * solve; the Chebyshev steps then correct it (AC_INNER_CHEB_CNN).  Inputs per shift
+ * m and grid point: Re rhat_m / s_m, Im rhat_m / s_m, Re lambda_m, Im lambda_m,
+ * (ln kappa - c0) / c1 with s_m = RMS(rhat_m); outputs Re x0_m / s_m, Im x0_m / s_m.
+ * A guess with ||rhat_m - (A - lambda_m) x0_m|| >= ||rhat_m|| is replaced by zero
+ * (counted in ac_solve_info.cnn_fallbacks).
+ * Parameter vector (float, host): [W1, b1, W2, b2, W3, b3], each W as [tap = 3 ky + kx]
+ * [out 16][in 16] and each b as [16]; entries beyond 5 inputs (layer 1) and 2 outputs
+ * (layer 3) are held at zero.
+ * Tensors are NHWC with 16 channels: x bf16 bits [B][H][W][16] (uint16), targets and
+ * outputs float [B][H][W][2]. */
+typedef struct ac_cnn ac_cnn;
+int ac_cnn_param_count(void);
+int ac_cnn_create(ac_ctx* ctx, ac_cnn** out);          /* all parameters zero */
+int ac_cnn_destroy(ac_cnn* cnn);
+/* Copies parameters (host, ac_cnn_param_count() floats) and the ln kappa normalisation;
+ * resets the optimiser state.  Synchronises. */
+int ac_cnn_set_params(ac_cnn* cnn, const float* params, double c0, double c1);
+int ac_cnn_get_params(const ac_cnn* cnn, float* params, double* c0, double* c1);
+/* Device workspace for ac_cnn_forward / ac_cnn_grad on a batch of B images H x W. */
+int ac_cnn_workspace_size(int batch, int height, int width, size_t* bytes);
+int ac_cnn_forward(ac_cnn* cnn, const uint16_t* x, int batch, int height, int width, float* y, void* ws,
+                   size_t ws_bytes);
+/* Loss L = (1/B) sum_b sum_mask |y_b - t_b|^2 / tnorm_b (mask: cells at least `border`
+ * away from the image edge; tnorm_b = sum_mask |t_b|^2, device floats) and its gradient
+ * with respect to every parameter (kept for ac_cnn_adam_step; copied to grad if not
+ * NULL).  Synchronises. */
+int ac_cnn_grad(ac_cnn* cnn, const uint16_t* x, const float* t, const float* tnorm, int border, int batch,
+                int height, int width, void* ws, size_t ws_bytes, double* loss, float* grad);
+/* One Adam step (bias-corrected) with the last gradient. */
+int ac_cnn_adam_step(ac_cnn* cnn, double lr, double beta1, double beta2, double eps);
+/* Network inputs x (device bf16 [l_s][N][16]) for every shift slot of a spectral
+ * buffer rhat (layout of ac_spectral_offsets); slot order m = 0, then m = l/2 (even
+ * l), then m = 1, 2, ...; scales: host, l_s RMS values in slot order (or NULL). */
+int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* cnn, int precision, const void* rhat, uint16_t* x,
+                       double* scales);
+/* Attaches the network used by AC_INNER_CHEB_CNN (NULL detaches; not owned). */
+int ac_problem_attach_cnn(ac_problem* p, ac_cnn* cnn);
+
 #ifdef __cplusplus
 }
 #endif

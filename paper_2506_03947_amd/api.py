@@ -264,3 +264,104 @@ def complex_to_spectral(p: Problem, precision: int, slices) -> torch.Tensor:
         else:
             buf[off[m]: off[m] + 2 * p.n] = torch.stack([s.real, s.imag], dim=1).reshape(-1).to(dt)
     return buf
+
+
+# ---- learned warm start ---------------------------------------------------------------
+
+class Cnn:
+    def __init__(self, handle, ctx):
+        self.h = handle
+        self.ctx = ctx
+
+    def __del__(self):
+        if getattr(self, "h", None) and L is not None and L._lib is not None:
+            L._lib.ac_cnn_destroy(self.h)
+        self.h = None
+
+
+def ac_cnn_param_count() -> int:
+    return L.load().ac_cnn_param_count()
+
+
+def ac_cnn_create(ctx: Ctx) -> Cnn:
+    h = C.c_void_p()
+    check(L.load().ac_cnn_create(ctx.h, C.byref(h)), "ac_cnn_create")
+    return Cnn(h, ctx)
+
+
+def ac_cnn_set_params(cnn: Cnn, params, c0: float, c1: float) -> None:
+    import numpy as np
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float32).reshape(-1))
+    if p.size != ac_cnn_param_count():
+        raise ValueError(f"expected {ac_cnn_param_count()} parameters, got {p.size}")
+    check(L.load().ac_cnn_set_params(cnn.h, p.ctypes.data_as(C.POINTER(C.c_float)), float(c0), float(c1)),
+          "ac_cnn_set_params")
+
+
+def ac_cnn_get_params(cnn: Cnn):
+    import numpy as np
+    p = np.empty(ac_cnn_param_count(), dtype=np.float32)
+    c0, c1 = C.c_double(), C.c_double()
+    check(L.load().ac_cnn_get_params(cnn.h, p.ctypes.data_as(C.POINTER(C.c_float)), C.byref(c0), C.byref(c1)),
+          "ac_cnn_get_params")
+    return p, c0.value, c1.value
+
+
+def ac_cnn_workspace_size(batch: int, height: int, width: int) -> int:
+    n = C.c_size_t()
+    check(L.load().ac_cnn_workspace_size(batch, height, width, C.byref(n)), "ac_cnn_workspace_size")
+    return n.value
+
+
+def _u16(t: torch.Tensor, n: int, name: str):
+    if t.dtype not in (torch.int16, torch.uint16) or t.numel() != n:
+        raise ValueError(f"{name}: expected {n} 16-bit values, got {t.numel()} {t.dtype}")
+    return _ptr(t)
+
+
+def _f32(t: torch.Tensor, n: int, name: str):
+    if t.dtype != torch.float32 or t.numel() != n:
+        raise ValueError(f"{name}: expected {n} float32 values, got {t.numel()} {t.dtype}")
+    return _ptr(t)
+
+
+def ac_cnn_forward(cnn: Cnn, x: torch.Tensor, batch: int, height: int, width: int, y: torch.Tensor,
+                   ws: torch.Tensor) -> None:
+    npx = batch * height * width
+    check(L.load().ac_cnn_forward(cnn.h, _u16(x, npx * 16, "x"), batch, height, width, _f32(y, npx * 2, "y"),
+                                  _ptr(ws), ws.numel()), "ac_cnn_forward")
+
+
+def ac_cnn_grad(cnn: Cnn, x: torch.Tensor, t: torch.Tensor, tnorm: torch.Tensor, border: int, batch: int,
+                height: int, width: int, ws: torch.Tensor, want_grad: bool = False):
+    import numpy as np
+    npx = batch * height * width
+    loss = C.c_double()
+    g = np.empty(ac_cnn_param_count(), dtype=np.float32) if want_grad else None
+    check(L.load().ac_cnn_grad(cnn.h, _u16(x, npx * 16, "x"), _f32(t, npx * 2, "t"), _f32(tnorm, batch, "tnorm"),
+                               border, batch, height, width, _ptr(ws), ws.numel(), C.byref(loss),
+                               g.ctypes.data_as(C.POINTER(C.c_float)) if g is not None else None), "ac_cnn_grad")
+    return loss.value, g
+
+
+def ac_cnn_adam_step(cnn: Cnn, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    check(L.load().ac_cnn_adam_step(cnn.h, lr, beta1, beta2, eps), "ac_cnn_adam_step")
+
+
+def ac_cnn_make_inputs(p: Problem, cnn: Cnn, precision: int, rhat: torch.Tensor, x: torch.Tensor):
+    import numpy as np
+    sc = np.empty(p.ns, dtype=np.float64)
+    check(L.load().ac_cnn_make_inputs(p.h, cnn.h, precision, _ptr(rhat), _u16(x, p.ns * p.n * 16, "x"),
+                                      sc.ctypes.data_as(C.POINTER(C.c_double))), "ac_cnn_make_inputs")
+    return sc
+
+
+def ac_problem_attach_cnn(p: Problem, cnn: Cnn | None) -> None:
+    check(L.load().ac_problem_attach_cnn(p.h, cnn.h if cnn is not None else None), "ac_problem_attach_cnn")
+    p._cnn = cnn  # keep the network alive while attached
+
+
+def slot_order(p: Problem) -> list[int]:
+    """Frequency m of each shift slot (real shifts first, then complex m = 1, 2, ...)."""
+    real = [0] + ([p.ell // 2] if p.ell % 2 == 0 else [])
+    return real + [m for m in range(1, (p.ell + 1) // 2)]

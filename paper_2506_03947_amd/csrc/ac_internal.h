@@ -131,6 +131,57 @@ hipError_t launch_maxpy(const VecSet& Z, int nv, const double* coef_host_scaled,
 hipError_t launch_norm2(const double* w, long long len, double* partial, hipStream_t s);
 hipError_t launch_reduce(const double* partial, int nblk, int nq, int nq_stride, double* out, hipStream_t s);
 
+// ---- warm-start network (cnn.hip) ---------------------------------------------
+// Parameters: [W1 (9x16x16), b1 (16), W2, b2, W3, b3], weights as [tap][out][in].
+constexpr int kCnnParams = 3 * (9 * 256 + 16);
+
+struct CnnConvArgs {
+    const uint16_t* in;    // bf16 [B][H][W][16]
+    const uint16_t* w;     // bf16 [9][16 out][16 in]
+    const float* bias;     // [16] or null
+    const uint16_t* mask;  // bf16 [B][H][W][16]: output zeroed where mask <= 0 (null: none)
+    uint16_t* out16;       // bf16 [B][H][W][16] or null
+    float* out32;          // float [B][H][W][nout] or null
+    int nout;
+    int B, H, W;
+    int relu;
+};
+
+struct CnnWgradArgs {
+    const uint16_t* act;  // layer input, bf16 [B][H][W][16]
+    const uint16_t* dz;   // gradient of the layer output, bf16 [B][H][W][16]
+    int B, H, W;
+    float* partial;       // cnn_wgrad_waves(tiles) x (9*256 + 16)
+};
+
+struct CnnPrepArgs {
+    Geom g;
+    long long n;
+    int ns;
+    const void* rhat;                  // spectral buffer (inner real type)
+    unsigned soff[kMaxShift];          // slot offsets (elements)
+    int is_real[kMaxShift];
+    float lam_re[kMaxShift], lam_im[kMaxShift];
+    float inv_scale[kMaxShift], scale[kMaxShift];
+    const double* kappa;
+    double c0, c1;                     // input normalisation of ln kappa
+    uint16_t* x;                       // bf16 [ns][N][16]
+};
+
+int cnn_wgrad_waves(long long ntiles);
+hipError_t launch_cnn_conv(const CnnConvArgs& a, hipStream_t s);
+hipError_t launch_cnn_wgrad(const CnnWgradArgs& a, float* grad, hipStream_t s);
+hipError_t launch_cnn_loss(const float* y, const float* t, const float* tnorm, int B, int H, int W, int border,
+                           uint16_t* dy16, float* partial, int* nblocks, hipStream_t s);
+hipError_t launch_cnn_adam(float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                           float bc1, float bc2, hipStream_t s);
+hipError_t launch_cnn_weights(const float* w, uint16_t* wf, uint16_t* wb, float* bias, hipStream_t s);
+hipError_t launch_cnn_prep(int prec, const CnnPrepArgs& a, hipStream_t s);
+hipError_t launch_cnn_post(int prec, const CnnPrepArgs& a, const float* y, void* x0buf, hipStream_t s);
+hipError_t launch_cnn_resid(int prec, const CnnPrepArgs& a, const void* x0buf, const void* kap, double* partial,
+                            int nblk, hipStream_t s);
+hipError_t launch_zero_bytes(void* buf, long long off_bytes, long long nbytes, hipStream_t s);
+
 // ---- setup kernels (setup.hip) -----------------------------------------------
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,
                               int nblk, hipStream_t s);

@@ -86,6 +86,21 @@ struct ac_problem {
     uint16_t* k16 = nullptr;
     double bounds[3][2] = {};  // per precision: mu_lo, mu_hi
     double kmin64 = 0;
+    ac_cnn* cnn = nullptr;     // warm-start network (not owned)
+};
+
+struct ac_cnn {
+    ac_ctx* ctx = nullptr;
+    char* mem = nullptr;       // one allocation for everything below
+    float* w = nullptr;        // float32 master parameters
+    float* g = nullptr;        // last gradient
+    float* m = nullptr;        // Adam moments
+    float* v = nullptr;
+    uint16_t* wf = nullptr;    // bf16 forward weights [3][9][16][16]
+    uint16_t* wb = nullptr;    // bf16 flipped/transposed weights for input gradients
+    float* bias = nullptr;     // [3][16]
+    double c0 = 0.0, c1 = 1.0; // ln kappa normalisation
+    int t = 0;                 // Adam steps taken
 };
 
 // ---------------------------------------------------------------------------
@@ -227,7 +242,7 @@ int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>&
     if (!o) return fail(AC_ERR_ARG, "opts is NULL");
     if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
     if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN) return fail(AC_ERR_ARG, "unknown inner mode");
-    if (o->inner == AC_INNER_CHEB_CNN) return fail(AC_ERR_UNSUPPORTED, "no warm-start network attached");
+    if (o->inner == AC_INNER_CHEB_CNN && !p->cnn) return fail(AC_ERR_ARG, "no warm-start network attached");
     pm.assign(p->ell, 0);
     for (int m = 0; m < p->ell; ++m) {
         const int v = o->p_per_shift ? o->p_per_shift[m] : o->p_uniform;
@@ -240,15 +255,28 @@ int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>&
 }
 
 // Prec workspace: rhat + 2 iterate buffers (+ a warm-start buffer) of the spectral size.
-size_t prec_ws_bytes(const ac_problem* p, int prec) {
+constexpr int kResidBlocks = 512;
+
+// CNN inference buffers: inputs and two hidden activations (bf16, 16 channels), the
+// float32 output (2 channels), per-slot reduction partials.
+size_t cnn_ws_bytes(const ac_problem* p) {
+    const size_t px = static_cast<size_t>(p->ns) * static_cast<size_t>(p->g.n);
+    return 3 * align_up(px * 32, 256) + align_up(px * 8, 256) +
+           align_up(static_cast<size_t>(kResidBlocks) * 2 * kMaxShift * sizeof(double), 256);
+}
+
+size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
-    return 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
+    size_t b = 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
+    if (inner == AC_INNER_CHEB_CNN) b += cnn_ws_bytes(p);
+    return b;
 }
 
 struct PrecBufs {
     char* rhat;
     char* buf[2];
+    char* cnn;  // start of the CNN buffers (valid when they were sized in)
 };
 
 PrecBufs carve_prec(const ac_problem* p, int prec, void* ws) {
@@ -256,7 +284,7 @@ PrecBufs carve_prec(const ac_problem* p, int prec, void* ws) {
     spectral_offsets(p, off);
     const size_t sz = align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256);
     char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
-    return {base, {base + sz, base + 2 * sz}};
+    return {base, {base + sz, base + 2 * sz}, base + 3 * sz};
 }
 
 // slot pointer into a spectral buffer
@@ -459,11 +487,135 @@ int run_cheb(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, ch
     return run_cheb_t<float>(p, prec, pm, rhat, buf, warm, z, where);
 }
 
+// Builds the per-slot arguments shared by the CNN input/output/residual kernels.
+ac::CnnPrepArgs cnn_args(const ac_problem* p, int prec, const char* rhat) {
+    ac::CnnPrepArgs a{};
+    a.g = p->g;
+    a.n = p->g.n;
+    a.ns = p->ns;
+    a.rhat = rhat;
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    for (int s = 0; s < p->ns; ++s) {
+        const int m = slot_to_m(p, s);
+        a.soff[s] = static_cast<unsigned>(off[m]);
+        a.is_real[s] = slot_is_real(p, s) ? 1 : 0;
+        const cplx lam = std::polar(std::pow(p->alpha, 1.0 / p->ell), -2.0 * kPi * m / p->ell);
+        a.lam_re[s] = static_cast<float>(lam.real());
+        a.lam_im[s] = static_cast<float>(lam.imag());
+        a.inv_scale[s] = 1.f;
+        a.scale[s] = 1.f;
+    }
+    a.kappa = p->k64;
+    a.c0 = p->cnn ? p->cnn->c0 : 0.0;
+    a.c1 = p->cnn ? p->cnn->c1 : 1.0;
+    return a;
+}
+
+// Per-slot sums of |rhat|^2 and |rhat - (A - lambda) x0|^2 (x0 == nullptr: first only).
+int slot_residuals(ac_problem* p, int prec, const ac::CnnPrepArgs& a, const char* x0, double* partial,
+                   std::vector<double>& rr, std::vector<double>& res) {
+    const void* kap = prec == AC_PREC_FP64 ? static_cast<const void*>(p->k64)
+                      : prec == AC_PREC_MIXED_BF16K ? static_cast<const void*>(p->k16)
+                                                    : static_cast<const void*>(p->k32);
+    AC_HIP(ac::launch_cnn_resid(prec, a, x0, kap, partial, kResidBlocks, p->ctx->stream));
+    std::vector<double> h(static_cast<size_t>(kResidBlocks) * 2 * kMaxShift);
+    AC_HIP(hipMemcpyAsync(h.data(), partial, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->ctx->stream));
+    AC_HIP(hipStreamSynchronize(p->ctx->stream));
+    rr.assign(p->ns, 0.0);
+    res.assign(p->ns, 0.0);
+    for (int b = 0; b < kResidBlocks; ++b)
+        for (int s = 0; s < p->ns; ++s) {
+            rr[s] += h[static_cast<size_t>(b) * 2 * kMaxShift + 2 * s];
+            res[s] += h[static_cast<size_t>(b) * 2 * kMaxShift + 2 * s + 1];
+        }
+    return AC_OK;
+}
+
+int cnn_forward_impl(ac_cnn* c, const uint16_t* x, int B, int H, int W, float* y, uint16_t* a1, uint16_t* a2,
+                     hipStream_t st) {
+    ac::CnnConvArgs ca{};
+    ca.B = B;
+    ca.H = H;
+    ca.W = W;
+    ca.in = x;
+    ca.w = c->wf;
+    ca.bias = c->bias;
+    ca.relu = 1;
+    ca.out16 = a1;
+    AC_HIP(ac::launch_cnn_conv(ca, st));
+    ca.in = a1;
+    ca.w = c->wf + 2304;
+    ca.bias = c->bias + 16;
+    ca.out16 = a2;
+    AC_HIP(ac::launch_cnn_conv(ca, st));
+    ca.in = a2;
+    ca.w = c->wf + 2 * 2304;
+    ca.bias = c->bias + 32;
+    ca.relu = 0;
+    ca.out16 = nullptr;
+    ca.out32 = y;
+    ca.nout = 2;
+    AC_HIP(ac::launch_cnn_conv(ca, st));
+    return AC_OK;
+}
+
+// Learned initial guesses for every shift slot, written into buf0; a slot whose
+// guess does not reduce the residual (||rhat - B x0|| >= ||rhat||) is reset to zero.
+int cnn_warm_start(ac_problem* p, int prec, char* rhat, char* buf0, char* cws, int* fallbacks) {
+    const size_t px = static_cast<size_t>(p->ns) * static_cast<size_t>(p->g.n);
+    uint16_t* X = reinterpret_cast<uint16_t*>(cws);
+    uint16_t* A1 = reinterpret_cast<uint16_t*>(cws + align_up(px * 32, 256));
+    uint16_t* A2 = reinterpret_cast<uint16_t*>(cws + 2 * align_up(px * 32, 256));
+    float* Y = reinterpret_cast<float*>(cws + 3 * align_up(px * 32, 256));
+    double* partial = reinterpret_cast<double*>(cws + 3 * align_up(px * 32, 256) + align_up(px * 8, 256));
+    ac::CnnPrepArgs a = cnn_args(p, prec, rhat);
+    std::vector<double> rr, res;
+    {
+        ProfScope ps(p->ctx, AC_K_CNN, 0.0);
+        AC_TRY(slot_residuals(p, prec, a, nullptr, partial, rr, res));
+    }
+    for (int s = 0; s < p->ns; ++s) {
+        const double rms = std::sqrt(rr[s] / static_cast<double>(p->g.n));
+        a.scale[s] = static_cast<float>(rms);
+        a.inv_scale[s] = rms > 0 ? static_cast<float>(1.0 / rms) : 0.f;
+    }
+    a.x = X;
+    {
+        const double bytes = static_cast<double>(px) * (32.0 * 7 + 8.0 * 2) + 8.0 * p->g.n;
+        ProfScope ps(p->ctx, AC_K_CNN, bytes);
+        AC_HIP(ac::launch_cnn_prep(prec, a, p->ctx->stream));
+        AC_TRY(cnn_forward_impl(p->cnn, X, p->ns, p->g.ny, p->g.nx, Y, A1, A2, p->ctx->stream));
+        AC_HIP(ac::launch_cnn_post(prec, a, Y, buf0, p->ctx->stream));
+    }
+    {
+        ProfScope ps(p->ctx, AC_K_CNN, 0.0);
+        AC_TRY(slot_residuals(p, prec, a, buf0, partial, rr, res));
+    }
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    for (int s = 0; s < p->ns; ++s) {
+        if (!(res[s] < rr[s])) {
+            const int m = slot_to_m(p, s);
+            AC_HIP(ac::launch_zero_bytes(buf0, off[m] * static_cast<long long>(inner_elem(prec)),
+                                         slice_elems(p, m) * static_cast<long long>(inner_elem(prec)),
+                                         p->ctx->stream));
+            if (fallbacks) ++*fallbacks;
+        }
+    }
+    return AC_OK;
+}
+
 int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* r, double* z,
-                    void* ws, double in_scale) {
+                    void* ws, double in_scale, int* fallbacks = nullptr) {
     const PrecBufs b = carve_prec(p, o->precision, ws);
     AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
-    AC_TRY(run_cheb(p, o->precision, pm, b.rhat, b.buf, false, z, nullptr));
+    if (o->inner == AC_INNER_CHEB_CNN) {
+        AC_TRY(cnn_warm_start(p, o->precision, b.rhat, b.buf[0], b.cnn, fallbacks));
+        AC_TRY(run_cheb(p, o->precision, pm, b.rhat, b.buf, true, z, nullptr));
+    } else {
+        AC_TRY(run_cheb(p, o->precision, pm, b.rhat, b.buf, false, z, nullptr));
+    }
     return AC_OK;
 }
 
@@ -730,7 +882,7 @@ int ac_alloc_nc1(const ac_problem* p, double budget, int* out) {
 int ac_prec_workspace_size(const ac_problem* p, const ac_solve_opts* o, size_t* bytes) {
     if (!p || !o || !bytes) return fail(AC_ERR_ARG, "NULL argument");
     if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
-    *bytes = prec_ws_bytes(p, o->precision);
+    *bytes = prec_ws_bytes(p, o->precision, o->inner);
     return AC_OK;
 }
 
@@ -751,7 +903,7 @@ size_t solve_ws_bytes(const ac_problem* p, const ac_solve_opts* o) {
     b += align_up(static_cast<size_t>(ac::krylov_blocks()) * 72 * sizeof(double), 256);
     b += align_up(static_cast<size_t>(calA_partials(p)) * sizeof(double), 256);
     b += align_up(128 * sizeof(double), 256);
-    b += prec_ws_bytes(p, o->precision);
+    b += prec_ws_bytes(p, o->precision, o->inner);
     return b;
 }
 SolveWs carve_solve(const ac_problem* p, const ac_solve_opts* o, void* ws) {
@@ -789,7 +941,7 @@ int ac_apply_prec(ac_problem* p, const ac_solve_opts* o, const double* r, double
     if (!p || !r || !z) return fail(AC_ERR_ARG, "NULL argument");
     std::vector<int> pm;
     AC_TRY(validate_opts(p, o, pm));
-    if (!ws || ws_bytes < prec_ws_bytes(p, o->precision)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    if (!ws || ws_bytes < prec_ws_bytes(p, o->precision, o->inner)) return fail(AC_ERR_WORKSPACE, "workspace too small");
     AC_HIP(hipSetDevice(p->ctx->device));
     return apply_prec_impl(p, o, pm, r, z, ws, 1.0);
 }
@@ -938,7 +1090,7 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
     }
     double beta = 0;
     AC_TRY(residual(beta));
-    int total = 0, restarts = 0;
+    int total = 0, restarts = 0, fallbacks = 0;
     double orth_loss = 0.0;
     std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), scale(m + 1), y(m), Lg(m * m), hcol(m + 1);
     int status = AC_OK;
@@ -956,11 +1108,7 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
         int kdone = 0;
         for (int j = 0; j < m; ++j) {
             // z_j = P^{-1} v_j with v_j = scale_j * V_j (scale folded into the transform)
-            {
-                const PrecBufs pb = carve_prec(p, o->precision, w.prec);
-                AC_TRY(run_fwd(p, o->precision, w.V[j], pb.rhat, scale[j]));
-                AC_TRY(run_cheb(p, o->precision, pm, pb.rhat, pb.buf, false, w.Z[j], nullptr));
-            }
+            AC_TRY(apply_prec_impl(p, o, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
             AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
             matvecs += p->ell + psum;
             ac::VecSet vs{};
@@ -1042,7 +1190,7 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
         info->matvecs_A = matvecs;
         info->rel_residual_true = beta / bnorm;
         info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        info->cnn_fallbacks = 0;
+        info->cnn_fallbacks = fallbacks;
         info->reserved = 0;
         info->orth_loss = orth_loss;
     }
@@ -1059,5 +1207,239 @@ int ac_ctx_set_tiling(ac_ctx* c, int rows_per_wave, int waves_per_block, int poi
     c->tile_h = rows_per_wave;
     c->tile_wpb = waves_per_block;
     c->tile_vx = points_per_lane;
+    return AC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// warm-start network
+
+namespace {
+size_t cnn_train_ws_bytes(long long B, long long H, long long W) {
+    const size_t px = static_cast<size_t>(B * H * W);
+    const long long tiles = B * H * ((W + 15) / 16);
+    return 5 * align_up(px * 32, 256) + align_up(px * 8, 256) +
+           align_up(static_cast<size_t>(ac::cnn_wgrad_waves(tiles)) * (9 * 256 + 16) * sizeof(float), 256) +
+           align_up(static_cast<size_t>((px + 255) / 256) * sizeof(float), 256) + 256;
+}
+int cnn_check_shape(int B, int H, int W) {
+    if (B < 1 || H < 1 || W < 1) return fail(AC_ERR_ARG, "batch and image sizes must be positive");
+    if (static_cast<long long>(B) * H * W > (1LL << 31)) return fail(AC_ERR_UNSUPPORTED, "batch too large");
+    return AC_OK;
+}
+}  // namespace
+
+int ac_cnn_param_count(void) { return ac::kCnnParams; }
+
+int ac_cnn_create(ac_ctx* c, ac_cnn** out) {
+    if (!c || !out) return fail(AC_ERR_ARG, "NULL argument");
+    *out = nullptr;
+    AC_HIP(hipSetDevice(c->device));
+    auto* n = new ac_cnn();
+    n->ctx = c;
+    const size_t P = ac::kCnnParams;
+    const size_t bytes = 4 * align_up(P * 4, 256) + 2 * align_up(3 * 2304 * 2, 256) + 256;
+    hipError_t e = hipMalloc(&n->mem, bytes);
+    if (e != hipSuccess) {
+        delete n;
+        return fail(AC_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+    }
+    char* b = n->mem;
+    n->w = reinterpret_cast<float*>(b);
+    b += align_up(P * 4, 256);
+    n->g = reinterpret_cast<float*>(b);
+    b += align_up(P * 4, 256);
+    n->m = reinterpret_cast<float*>(b);
+    b += align_up(P * 4, 256);
+    n->v = reinterpret_cast<float*>(b);
+    b += align_up(P * 4, 256);
+    n->wf = reinterpret_cast<uint16_t*>(b);
+    b += align_up(3 * 2304 * 2, 256);
+    n->wb = reinterpret_cast<uint16_t*>(b);
+    b += align_up(3 * 2304 * 2, 256);
+    n->bias = reinterpret_cast<float*>(b);
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((bytes / 8 + 255) / 256)), dim3(256), 0, c->stream,
+                       reinterpret_cast<double*>(n->mem), static_cast<long long>(bytes / 8));
+    e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(n->mem);
+        delete n;
+        return fail(AC_ERR_HIP, std::string("cnn init: ") + hipGetErrorString(e));
+    }
+    *out = n;
+    return AC_OK;
+}
+
+int ac_cnn_destroy(ac_cnn* n) {
+    if (!n) return AC_OK;
+    (void)hipSetDevice(n->ctx->device);
+    (void)hipStreamSynchronize(n->ctx->stream);
+    (void)hipFree(n->mem);
+    delete n;
+    return AC_OK;
+}
+
+int ac_cnn_set_params(ac_cnn* n, const float* params, double c0, double c1) {
+    if (!n || !params) return fail(AC_ERR_ARG, "NULL argument");
+    if (!(c1 > 0.0) || !std::isfinite(c0) || !std::isfinite(c1)) return fail(AC_ERR_ARG, "need finite c0 and c1 > 0");
+    for (int q = 0; q < ac::kCnnParams; ++q)
+        if (!std::isfinite(params[q])) return fail(AC_ERR_NONFINITE, "parameters must be finite");
+    AC_HIP(hipSetDevice(n->ctx->device));
+    hipStream_t st = n->ctx->stream;
+    AC_HIP(hipMemcpyAsync(n->w, params, ac::kCnnParams * sizeof(float), hipMemcpyHostToDevice, st));
+    const size_t P = ac::kCnnParams;
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((P + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<double*>(n->m), static_cast<long long>(P / 2));
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((P + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<double*>(n->v), static_cast<long long>(P / 2));
+    // entries outside the network are forced to zero by an Adam step of size 0
+    AC_HIP(ac::launch_cnn_adam(n->w, n->g, n->m, n->v, 0.f, 0.9f, 0.999f, 1e-8f, 1.f, 1.f, st));
+    AC_HIP(ac::launch_cnn_weights(n->w, n->wf, n->wb, n->bias, st));
+    AC_HIP(hipStreamSynchronize(st));
+    n->c0 = c0;
+    n->c1 = c1;
+    n->t = 0;
+    return AC_OK;
+}
+
+int ac_cnn_get_params(const ac_cnn* n, float* params, double* c0, double* c1) {
+    if (!n) return fail(AC_ERR_ARG, "NULL argument");
+    AC_HIP(hipSetDevice(n->ctx->device));
+    if (params) {
+        AC_HIP(hipMemcpyAsync(params, n->w, ac::kCnnParams * sizeof(float), hipMemcpyDeviceToHost, n->ctx->stream));
+        AC_HIP(hipStreamSynchronize(n->ctx->stream));
+    }
+    if (c0) *c0 = n->c0;
+    if (c1) *c1 = n->c1;
+    return AC_OK;
+}
+
+int ac_cnn_workspace_size(int B, int H, int W, size_t* bytes) {
+    if (!bytes) return fail(AC_ERR_ARG, "NULL argument");
+    AC_TRY(cnn_check_shape(B, H, W));
+    *bytes = cnn_train_ws_bytes(B, H, W);
+    return AC_OK;
+}
+
+int ac_cnn_forward(ac_cnn* n, const uint16_t* x, int B, int H, int W, float* y, void* ws, size_t ws_bytes) {
+    if (!n || !x || !y) return fail(AC_ERR_ARG, "NULL argument");
+    AC_TRY(cnn_check_shape(B, H, W));
+    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(n->ctx->device));
+    const size_t px = static_cast<size_t>(B) * H * W;
+    char* b = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
+    uint16_t* a1 = reinterpret_cast<uint16_t*>(b);
+    uint16_t* a2 = reinterpret_cast<uint16_t*>(b + align_up(px * 32, 256));
+    ProfScope ps(n->ctx, AC_K_CNN, static_cast<double>(px) * (32.0 * 5 + 8.0));
+    return cnn_forward_impl(n, x, B, H, W, y, a1, a2, n->ctx->stream);
+}
+
+int ac_cnn_grad(ac_cnn* n, const uint16_t* x, const float* t, const float* tnorm, int border, int B, int H, int W,
+                void* ws, size_t ws_bytes, double* loss, float* grad_host) {
+    if (!n || !x || !t || !tnorm) return fail(AC_ERR_ARG, "NULL argument");
+    AC_TRY(cnn_check_shape(B, H, W));
+    if (border < 0 || 2 * border >= H || 2 * border >= W) return fail(AC_ERR_ARG, "border too wide");
+    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(n->ctx->device));
+    hipStream_t st = n->ctx->stream;
+    const size_t px = static_cast<size_t>(B) * H * W;
+    const long long tiles = static_cast<long long>(B) * H * ((W + 15) / 16);
+    char* b = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
+    const size_t a16 = align_up(px * 32, 256);
+    uint16_t* A1 = reinterpret_cast<uint16_t*>(b);
+    uint16_t* A2 = reinterpret_cast<uint16_t*>(b + a16);
+    uint16_t* dY = reinterpret_cast<uint16_t*>(b + 2 * a16);
+    uint16_t* dZ2 = reinterpret_cast<uint16_t*>(b + 3 * a16);
+    uint16_t* dZ1 = reinterpret_cast<uint16_t*>(b + 4 * a16);
+    float* Y = reinterpret_cast<float*>(b + 5 * a16);
+    float* wpart = reinterpret_cast<float*>(b + 5 * a16 + align_up(px * 8, 256));
+    float* lpart = reinterpret_cast<float*>(reinterpret_cast<char*>(wpart) +
+                                            align_up(static_cast<size_t>(ac::cnn_wgrad_waves(tiles)) * 2320 * 4, 256));
+    int nblk = 0;
+    {
+        ProfScope ps(n->ctx, AC_K_CNN, static_cast<double>(px) * (32.0 * 14 + 8.0 * 3));
+        AC_TRY(cnn_forward_impl(n, x, B, H, W, Y, A1, A2, st));
+        AC_HIP(ac::launch_cnn_loss(Y, t, tnorm, B, H, W, border, dY, lpart, &nblk, st));
+        ac::CnnWgradArgs wa{};
+        wa.B = B;
+        wa.H = H;
+        wa.W = W;
+        wa.partial = wpart;
+        wa.act = A2;
+        wa.dz = dY;
+        AC_HIP(ac::launch_cnn_wgrad(wa, n->g + 2 * 2320, st));
+        ac::CnnConvArgs ca{};
+        ca.B = B;
+        ca.H = H;
+        ca.W = W;
+        ca.in = dY;
+        ca.w = n->wb + 2 * 2304;
+        ca.mask = A2;
+        ca.out16 = dZ2;
+        AC_HIP(ac::launch_cnn_conv(ca, st));
+        wa.act = A1;
+        wa.dz = dZ2;
+        AC_HIP(ac::launch_cnn_wgrad(wa, n->g + 2320, st));
+        ca.in = dZ2;
+        ca.w = n->wb + 2304;
+        ca.mask = A1;
+        ca.out16 = dZ1;
+        AC_HIP(ac::launch_cnn_conv(ca, st));
+        wa.act = x;
+        wa.dz = dZ1;
+        AC_HIP(ac::launch_cnn_wgrad(wa, n->g, st));
+    }
+    std::vector<float> lp(nblk);
+    AC_HIP(hipMemcpyAsync(lp.data(), lpart, nblk * sizeof(float), hipMemcpyDeviceToHost, st));
+    if (grad_host) AC_HIP(hipMemcpyAsync(grad_host, n->g, ac::kCnnParams * sizeof(float), hipMemcpyDeviceToHost, st));
+    AC_HIP(hipStreamSynchronize(st));
+    double l = 0.0;
+    for (float v : lp) l += v;
+    if (loss) *loss = l / B;
+    return AC_OK;
+}
+
+int ac_cnn_adam_step(ac_cnn* n, double lr, double beta1, double beta2, double eps) {
+    if (!n) return fail(AC_ERR_ARG, "NULL argument");
+    if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
+        return fail(AC_ERR_ARG, "invalid Adam hyper-parameters");
+    AC_HIP(hipSetDevice(n->ctx->device));
+    n->t += 1;
+    const float bc1 = static_cast<float>(1.0 - std::pow(beta1, n->t));
+    const float bc2 = static_cast<float>(1.0 - std::pow(beta2, n->t));
+    AC_HIP(ac::launch_cnn_adam(n->w, n->g, n->m, n->v, static_cast<float>(lr), static_cast<float>(beta1),
+                               static_cast<float>(beta2), static_cast<float>(eps), bc1, bc2, n->ctx->stream));
+    AC_HIP(ac::launch_cnn_weights(n->w, n->wf, n->wb, n->bias, n->ctx->stream));
+    return AC_OK;
+}
+
+int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* n, int prec, const void* rhat, uint16_t* x, double* scales) {
+    if (!p || !n || !rhat || !x) return fail(AC_ERR_ARG, "NULL argument");
+    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    ac_cnn* keep = p->cnn;
+    p->cnn = const_cast<ac_cnn*>(n);
+    ac::CnnPrepArgs a = cnn_args(p, prec, static_cast<const char*>(rhat));
+    p->cnn = keep;
+    double* partial = nullptr;
+    AC_HIP(hipMalloc(&partial, static_cast<size_t>(kResidBlocks) * 2 * kMaxShift * sizeof(double)));
+    std::vector<double> rr, res;
+    const int st = slot_residuals(p, prec, a, nullptr, partial, rr, res);
+    (void)hipFree(partial);
+    if (st < 0) return st;
+    for (int s = 0; s < p->ns; ++s) {
+        const double rms = std::sqrt(rr[s] / static_cast<double>(p->g.n));
+        a.scale[s] = static_cast<float>(rms);
+        a.inv_scale[s] = rms > 0 ? static_cast<float>(1.0 / rms) : 0.f;
+        if (scales) scales[s] = rms;
+    }
+    a.x = x;
+    AC_HIP(ac::launch_cnn_prep(prec, a, p->ctx->stream));
+    return AC_OK;
+}
+
+int ac_problem_attach_cnn(ac_problem* p, ac_cnn* n) {
+    if (!p) return fail(AC_ERR_ARG, "problem is NULL");
+    if (n && n->ctx != p->ctx) return fail(AC_ERR_ARG, "network and problem belong to different contexts");
+    p->cnn = n;
     return AC_OK;
 }

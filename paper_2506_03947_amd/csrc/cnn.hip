@@ -1,0 +1,454 @@
+// Learned warm start for the shifted inner solves: a three-layer 3x3 convolutional
+// network (5 -> 16 -> 16 -> 2 channels, ReLU after the first two layers), bfloat16
+// weights and activations, float32 accumulation on the matrix cores.
+//
+// Activations are NHWC with 16 channels per pixel (bf16 bits in uint16_t).  A 3x3
+// convolution is nine chained 16x16x16 MFMAs per 16-pixel tile: for tap t the A
+// operand holds 16 pixels x 16 input channels shifted by the tap offset, the B
+// operand the 16x16 weight matrix of that tap.  The input gradient is the same
+// convolution with flipped, transposed weights; the weight gradient reduces over
+// pixels on the matrix cores after an LDS transpose of each 16-pixel block.
+//
+// Operand layouts of v_mfma_f32_16x16x16_bf16 (wave64): lane l holds
+//   A[l % 16][4 (l / 16) + j], B[4 (l / 16) + j][l % 16], D[4 (l / 16) + j][l % 16], j = 0..3.
+#include <hip/hip_runtime.h>
+
+#include "ac_internal.h"
+
+namespace ac {
+namespace {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kC = 16;  // channels per pixel in every activation tensor
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even (finite inputs)
+    return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(static_cast<uint32_t>(b) << 16); }
+
+__device__ __forceinline__ bf16x4 ld4(const uint16_t* p) { return *reinterpret_cast<const bf16x4*>(p); }
+
+// 16 bf16 values -> two 16-byte stores
+__device__ __forceinline__ void store16(uint16_t* dst, const uint16_t (&h)[kC]) {
+    uint4 a, b;
+    a.x = h[0] | (static_cast<uint32_t>(h[1]) << 16);
+    a.y = h[2] | (static_cast<uint32_t>(h[3]) << 16);
+    a.z = h[4] | (static_cast<uint32_t>(h[5]) << 16);
+    a.w = h[6] | (static_cast<uint32_t>(h[7]) << 16);
+    b.x = h[8] | (static_cast<uint32_t>(h[9]) << 16);
+    b.y = h[10] | (static_cast<uint32_t>(h[11]) << 16);
+    b.z = h[12] | (static_cast<uint32_t>(h[13]) << 16);
+    b.w = h[14] | (static_cast<uint32_t>(h[15]) << 16);
+    reinterpret_cast<uint4*>(dst)[0] = a;
+    reinterpret_cast<uint4*>(dst)[1] = b;
+}
+
+// ---------------------------------------------------------------------------
+// 3x3 convolution, one wave per tile of 16 consecutive pixels of one row.
+__global__ __launch_bounds__(256) void conv3x3_kernel(const CnnConvArgs a) {
+    const long long ntx = (a.W + 15) / 16;
+    const long long ntiles = static_cast<long long>(a.B) * a.H * ntx;
+    const long long tile = static_cast<long long>(blockIdx.x) * 4 + (threadIdx.x >> 6);
+    if (tile >= ntiles) return;
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, g = lane >> 4;
+    const int xt = static_cast<int>(tile % ntx);
+    const long long rest = tile / ntx;
+    const int y = static_cast<int>(rest % a.H);
+    const int b = static_cast<int>(rest / a.H);
+    const int x0 = xt * 16;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1;
+        const int xx = x0 + i + t % 3 - 1;
+        bf16x4 av = {0, 0, 0, 0};
+        if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+            av = ld4(a.in + ((static_cast<long long>(b) * a.H + yy) * a.W + xx) * kC + 4 * g);
+        const bf16x4 bv = ld4(a.w + (t * kC + i) * kC + 4 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    }
+    // lane holds output channel i of pixels x0 + 4g + j
+    const float bias = a.bias ? a.bias[i] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int px = x0 + 4 * g + j;
+        if (px >= a.W) continue;
+        const long long pix = (static_cast<long long>(b) * a.H + y) * a.W + px;
+        float v = acc[j] + bias;
+        if (a.relu) v = fmaxf(v, 0.f);
+        if (a.mask && !(bf2f(a.mask[pix * kC + i]) > 0.f)) v = 0.f;
+        if (a.out16) a.out16[pix * kC + i] = f2bf(v);
+        if (a.out32 && i < a.nout) a.out32[pix * a.nout + i] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight and bias gradients: dW[t][o][c] = sum_p act[p + off_t][c] dz[p][o],
+// db[o] = sum_p dz[p][o].  Each wave accumulates the nine 16x16 tap blocks over its
+// share of tiles and writes a partial; a second kernel reduces the partials in a
+// fixed order.  All waves of a block run the same trip count (barriers).
+__global__ __launch_bounds__(256) void wgrad_kernel(const CnnWgradArgs a) {
+    __shared__ uint16_t dzs[4][16 * kC];
+    __shared__ uint16_t acts[4][3 * 18 * kC];
+    const int wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int i = lane & 15, g = lane >> 4;
+    const long long ntx = (a.W + 15) / 16;
+    const long long ntiles = static_cast<long long>(a.B) * a.H * ntx;
+    const long long nwaves = static_cast<long long>(gridDim.x) * 4;
+    const long long gw = static_cast<long long>(blockIdx.x) * 4 + wv;
+    const long long trips = (ntiles + nwaves - 1) / nwaves;
+    f32x4 acc[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t] = {0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.f;
+    for (long long it = 0; it < trips; ++it) {
+        const long long tile = gw + it * nwaves;
+        const bool ok = tile < ntiles;
+        int x0 = 0, y = 0, b = 0;
+        if (ok) {
+            x0 = static_cast<int>(tile % ntx) * 16;
+            const long long rest = tile / ntx;
+            y = static_cast<int>(rest % a.H);
+            b = static_cast<int>(rest / a.H);
+        }
+        // dz block: 16 pixels x 16 channels
+        {
+            bf16x4 v = {0, 0, 0, 0};
+            const int px = x0 + i;
+            if (ok && px < a.W) v = ld4(a.dz + ((static_cast<long long>(b) * a.H + y) * a.W + px) * kC + 4 * g);
+            *reinterpret_cast<bf16x4*>(&dzs[wv][i * kC + 4 * g]) = v;
+        }
+        // activation halo region: rows y-1..y+1, pixels x0-1..x0+16
+        for (int c = lane; c < 3 * 18 * 4; c += 64) {
+            const int r = c / 72, rem = c % 72, px = rem / 4, g4 = rem % 4;
+            const int yy = y + r - 1, xx = x0 + px - 1;
+            bf16x4 v = {0, 0, 0, 0};
+            if (ok && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                v = ld4(a.act + ((static_cast<long long>(b) * a.H + yy) * a.W + xx) * kC + 4 * g4);
+            *reinterpret_cast<bf16x4*>(&acts[wv][(r * 18 + px) * kC + 4 * g4]) = v;
+        }
+        __syncthreads();
+        // A = dz^T (M = output channel i, K = pixel), bias partial from the same values
+        bf16x4 av;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint16_t u = dzs[wv][(4 * g + j) * kC + i];
+            av[j] = static_cast<short>(u);
+            bacc += bf2f(u);
+        }
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            bf16x4 bv;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                bv[j] = static_cast<short>(acts[wv][((1 + dy) * 18 + (4 * g + j) + 1 + dx) * kC + i]);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[t], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D[o = 4g + j][c = i] of tap t
+    float* out = a.partial + gw * (9 * 256 + 16);
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) out[t * 256 + (4 * g + j) * kC + i] = acc[t][j];
+    // bias: lanes i, i+16, i+32, i+48 hold disjoint pixel subsets of channel i
+    bacc += __shfl_down(bacc, 32, 64);
+    bacc += __shfl_down(bacc, 16, 64);
+    if (lane < 16) out[9 * 256 + lane] = bacc;
+}
+
+__global__ __launch_bounds__(256) void wgrad_reduce_kernel(const float* __restrict__ partial, long long nwaves,
+                                                           float* __restrict__ grad) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= 9 * 256 + 16) return;
+    double s = 0.0;
+    for (long long w = 0; w < nwaves; ++w) s += partial[w * (9 * 256 + 16) + q];
+    grad[q] = static_cast<float>(s);
+}
+
+// ---------------------------------------------------------------------------
+// Masked relative squared error and its gradient (channels 0, 1; others zero).
+__global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ y, const float* __restrict__ t,
+                                                   const float* __restrict__ tnorm, int B, int H, int W, int border,
+                                                   uint16_t* __restrict__ dy16, float* __restrict__ partial) {
+    const long long npix = static_cast<long long>(B) * H * W;
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    float l = 0.f;
+    if (p < npix) {
+        const int x = static_cast<int>(p % W);
+        const int yy = static_cast<int>((p / W) % H);
+        const int b = static_cast<int>(p / (static_cast<long long>(W) * H));
+        const bool in = x >= border && x < W - border && yy >= border && yy < H - border;
+        const float inv = 1.f / tnorm[b];
+        uint16_t g[kC];
+#pragma unroll
+        for (int c = 0; c < kC; ++c) g[c] = 0;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const float d = in ? (y[p * 2 + c] - t[p * 2 + c]) : 0.f;
+            l += d * d * inv;
+            g[c] = f2bf(2.f * d * inv / static_cast<float>(B));
+        }
+        store16(dy16 + p * kC, g);
+    }
+    // block sum
+    __shared__ float red[4];
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the float32 master parameters, then the bf16 forward weights
+// wf[L][t][n][k] = W_L[t][n][k] and backward weights wb[L][t][c][o] = W_L[8 - t][o][c].
+// Parameter vector: [W1 (9x16x16), b1 (16), W2, b2, W3, b3]; entries outside the
+// network (input channels >= 5 of layer 1, outputs >= 2 of layer 3) stay zero.
+__device__ __forceinline__ bool frozen(int q) {
+    const int L = q / 2320, r = q % 2320;
+    if (r < 2304) {
+        const int o = (r % 256) / 16, c = r % 16;
+        if (L == 0 && c >= 5) return true;
+        if (L == 2 && o >= 2) return true;
+    } else if (L == 2 && r - 2304 >= 2) {
+        return true;
+    }
+    return false;
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
+                                                   float* __restrict__ m, float* __restrict__ v, float lr, float b1,
+                                                   float b2, float eps, float bc1, float bc2) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= kCnnParams) return;
+    if (frozen(q)) {
+        w[q] = 0.f;
+        return;
+    }
+    const float gq = g[q];
+    const float mq = b1 * m[q] + (1.f - b1) * gq;
+    const float vq = b2 * v[q] + (1.f - b2) * gq * gq;
+    m[q] = mq;
+    v[q] = vq;
+    w[q] -= lr * (mq / bc1) / (sqrtf(vq / bc2) + eps);
+}
+
+__global__ __launch_bounds__(256) void weights_bf16_kernel(const float* __restrict__ w, uint16_t* __restrict__ wf,
+                                                           uint16_t* __restrict__ wb, float* __restrict__ bias) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;  // over 3 x 2304
+    if (q < 3 * 16) bias[q] = w[(q / 16) * 2320 + 2304 + q % 16];
+    if (q >= 3 * 2304) return;
+    const int L = q / 2304, r = q % 2304;
+    const int t = r / 256, n = (r % 256) / 16, k = r % 16;
+    wf[q] = f2bf(w[L * 2320 + r]);
+    // wb[L][t][c = n][o = k] = W_L[8 - t][o = k][c = n]
+    wb[q] = f2bf(w[L * 2320 + (8 - t) * 256 + k * 16 + n]);
+}
+
+// ---------------------------------------------------------------------------
+// Inference plumbing.
+
+// Network inputs for every shift slot: X[s][p][0..15] = (Re rhat_s / sc_s, Im rhat_s / sc_s,
+// Re lambda_s, Im lambda_s, (ln kappa - c0) / c1, 0, ...).
+template <typename R>
+__global__ __launch_bounds__(256) void prep_kernel(const CnnPrepArgs a) {
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    const float lk = static_cast<float>((log(a.kappa[p]) - a.c0) / a.c1);
+    for (int s = 0; s < a.ns; ++s) {
+        const R* src = static_cast<const R*>(a.rhat) + a.soff[s];
+        float re, im;
+        if (a.is_real[s]) {
+            re = static_cast<float>(src[p]);
+            im = 0.f;
+        } else {
+            re = static_cast<float>(src[2 * p]);
+            im = static_cast<float>(src[2 * p + 1]);
+        }
+        uint16_t h[kC];
+#pragma unroll
+        for (int c = 0; c < kC; ++c) h[c] = 0;
+        h[0] = f2bf(re * a.inv_scale[s]);
+        h[1] = f2bf(im * a.inv_scale[s]);
+        h[2] = f2bf(a.lam_re[s]);
+        h[3] = f2bf(a.lam_im[s]);
+        h[4] = f2bf(lk);
+        store16(a.x + (static_cast<long long>(s) * a.n + p) * kC, h);
+    }
+}
+
+// x0 slot s = scale_s * (y0 + i y1)
+template <typename R>
+__global__ __launch_bounds__(256) void post_kernel(const CnnPrepArgs a, const float* __restrict__ y, void* x0buf) {
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= a.n) return;
+    for (int s = 0; s < a.ns; ++s) {
+        R* dst = static_cast<R*>(x0buf) + a.soff[s];
+        const float* ys = y + (static_cast<long long>(s) * a.n + p) * 2;
+        const float sc = a.scale[s];
+        if (a.is_real[s]) {
+            dst[p] = static_cast<R>(sc * ys[0]);
+        } else {
+            dst[2 * p] = static_cast<R>(sc * ys[0]);
+            dst[2 * p + 1] = static_cast<R>(sc * ys[1]);
+        }
+    }
+}
+
+// Per-slot partial sums of |rhat|^2 and |rhat - (A - lambda) x0|^2 (x0 may be null).
+template <typename R, typename KS>
+__global__ __launch_bounds__(256) void resid_kernel(const CnnPrepArgs a, const void* x0buf, const void* kap,
+                                                    double* partial) {
+    const Geom g = a.g;
+    double acc[2 * kMaxShift];
+#pragma unroll
+    for (int q = 0; q < 2 * kMaxShift; ++q) acc[q] = 0.0;
+    const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
+    const KS* k = static_cast<const KS*>(kap);
+    auto kv = [&](long long i) -> double {
+        if constexpr (sizeof(KS) == 2) return static_cast<double>(bf2f(k[i]));
+        else return static_cast<double>(k[i]);
+    };
+    for (long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; p < a.n; p += step) {
+        const int ix = static_cast<int>(p % g.nx), iy = static_cast<int>(p / g.nx);
+        const double kc = kv(p);
+        long long nb[4];
+        double f[4];
+        int nf = 0;
+        const int dxs[4] = {1, -1, 0, 0}, dys[4] = {0, 0, 1, -1};
+        double diag = 1.0;
+        for (int d = 0; d < (g.dim == 2 ? 4 : 2); ++d) {
+            int jx = ix + dxs[d], jy = iy + dys[d];
+            const bool inside = jx >= 0 && jx < g.nx && jy >= 0 && jy < g.ny;
+            if (inside || g.periodic) {
+                jx = (jx + g.nx) % g.nx;
+                jy = (jy + g.ny) % g.ny;
+                const long long q = static_cast<long long>(jy) * g.nx + jx;
+                const double fq = 0.5 * (kc + kv(q));
+                diag += fq;
+                nb[nf] = q;
+                f[nf] = fq;
+                ++nf;
+            } else {
+                diag += kc;
+            }
+        }
+        for (int s = 0; s < a.ns; ++s) {
+            const R* rh = static_cast<const R*>(a.rhat) + a.soff[s];
+            const R* x0 = x0buf ? static_cast<const R*>(x0buf) + a.soff[s] : nullptr;
+            const bool re = a.is_real[s];
+            const double rr = re ? rh[p] : rh[2 * p], ri = re ? 0.0 : rh[2 * p + 1];
+            acc[2 * s] += rr * rr + ri * ri;
+            if (x0) {
+                const double xr = re ? x0[p] : x0[2 * p], xi = re ? 0.0 : x0[2 * p + 1];
+                const double lr = a.lam_re[s], li = a.lam_im[s];
+                double br = (diag - lr) * xr + li * xi, bi = (diag - lr) * xi - li * xr;
+                for (int d = 0; d < nf; ++d) {
+                    br -= f[d] * (re ? x0[nb[d]] : x0[2 * nb[d]]);
+                    bi -= re ? 0.0 : f[d] * x0[2 * nb[d] + 1];
+                }
+                acc[2 * s + 1] += (rr - br) * (rr - br) + (ri - bi) * (ri - bi);
+            }
+        }
+    }
+    __shared__ double red[4][2 * kMaxShift];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int q = 0; q < 2 * a.ns; ++q) {
+        double v = acc[q];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+        if (lane == 0) red[wid][q] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * a.ns)
+        partial[blockIdx.x * 2 * kMaxShift + threadIdx.x] =
+            red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+__global__ void zero_slot_kernel(void* buf, long long off_bytes, long long nbytes) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < nbytes / 4) reinterpret_cast<uint32_t*>(static_cast<char*>(buf) + off_bytes)[i] = 0u;
+}
+
+}  // namespace
+
+int cnn_wgrad_waves(long long ntiles) {
+    long long w = ntiles < 2048 ? ntiles : 2048;
+    w = (w + 3) / 4 * 4;
+    return static_cast<int>(w < 4 ? 4 : w);
+}
+
+hipError_t launch_cnn_conv(const CnnConvArgs& a, hipStream_t s) {
+    const long long ntiles = static_cast<long long>(a.B) * a.H * ((a.W + 15) / 16);
+    const int blocks = static_cast<int>((ntiles + 3) / 4);
+    hipLaunchKernelGGL(conv3x3_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_wgrad(const CnnWgradArgs& a, float* grad, hipStream_t s) {
+    const long long ntiles = static_cast<long long>(a.B) * a.H * ((a.W + 15) / 16);
+    const int waves = cnn_wgrad_waves(ntiles);
+    hipLaunchKernelGGL(wgrad_kernel, dim3(waves / 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((9 * 256 + 16 + 255) / 256), dim3(256), 0, s, a.partial,
+                       static_cast<long long>(waves), grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_loss(const float* y, const float* t, const float* tnorm, int B, int H, int W, int border,
+                           uint16_t* dy16, float* partial, int* nblocks, hipStream_t s) {
+    const long long npix = static_cast<long long>(B) * H * W;
+    const int blocks = static_cast<int>((npix + 255) / 256);
+    *nblocks = blocks;
+    hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, s, y, t, tnorm, B, H, W, border, dy16, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_adam(float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
+                           float bc1, float bc2, hipStream_t s) {
+    hipLaunchKernelGGL(adam_kernel, dim3((kCnnParams + 255) / 256), dim3(256), 0, s, w, g, m, v, lr, b1, b2, eps,
+                       bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_weights(const float* w, uint16_t* wf, uint16_t* wb, float* bias, hipStream_t s) {
+    hipLaunchKernelGGL(weights_bf16_kernel, dim3((3 * 2304 + 255) / 256), dim3(256), 0, s, w, wf, wb, bias);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_prep(int prec, const CnnPrepArgs& a, hipStream_t s) {
+    const int blocks = static_cast<int>((a.n + 255) / 256);
+    if (prec == 0) hipLaunchKernelGGL(prep_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(prep_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_post(int prec, const CnnPrepArgs& a, const float* y, void* x0buf, hipStream_t s) {
+    const int blocks = static_cast<int>((a.n + 255) / 256);
+    if (prec == 0) hipLaunchKernelGGL(post_kernel<double>, dim3(blocks), dim3(256), 0, s, a, y, x0buf);
+    else hipLaunchKernelGGL(post_kernel<float>, dim3(blocks), dim3(256), 0, s, a, y, x0buf);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_resid(int prec, const CnnPrepArgs& a, const void* x0buf, const void* kap, double* partial,
+                            int nblk, hipStream_t s) {
+    if (prec == 0) hipLaunchKernelGGL((resid_kernel<double, double>), dim3(nblk), dim3(256), 0, s, a, x0buf, kap, partial);
+    else if (prec == 1) hipLaunchKernelGGL((resid_kernel<float, uint16_t>), dim3(nblk), dim3(256), 0, s, a, x0buf, kap, partial);
+    else hipLaunchKernelGGL((resid_kernel<float, float>), dim3(nblk), dim3(256), 0, s, a, x0buf, kap, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_bytes(void* buf, long long off_bytes, long long nbytes, hipStream_t s) {
+    const long long words = nbytes / 4;
+    hipLaunchKernelGGL(zero_slot_kernel, dim3(static_cast<int>((words + 255) / 256)), dim3(256), 0, s, buf, off_bytes,
+                       nbytes);
+    return hipGetLastError();
+}
+
+}  // namespace ac
