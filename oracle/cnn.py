@@ -11,8 +11,15 @@ first two:
 
 Convolution is cross-correlation: conv(X, W)[y, x, o] =
 sum_{dy, dx in -1..1} sum_c X[y+dy, x+dx, c] W[dy+1, dx+1, c, o] (+ bias).
-Loss over a batch of crops with a border mask M (zero within `border` cells of a
-crop edge): L = (1/B) sum_b sum M |Y_b - T_b|^2 / sum M |T_b|^2.
+Two losses over a batch of crops with a border mask M (zero within `border`
+cells of a crop edge):
+  solution space:  L = (1/B) sum_b sum M |Y_b - T_b|^2 / sum M |T_b|^2;
+  residual space:  L = (1/B) sum_b sum M |rhat_b - B_b y_b|^2 / sum M |rhat_b|^2,
+where y_b = Y_b[..., 0] + i Y_b[..., 1] and B_b = A_b - lambda_b I is the shifted
+operator of Section 3 restricted to the crop (A_b from the coefficient crop, zero
+outside it).  The residual loss is what the warm start must make small: the
+Chebyshev steps that follow contract the initial residual, and the guess is
+rejected when its residual is not below that of x0 = 0.
 Optimiser: Adam (Kingma & Ba 2015) with bias correction.
 
 Parity unpinned by the paper (it has no learned component).  Pinned here by
@@ -24,6 +31,8 @@ closed-form first Adam step.
 from __future__ import annotations
 
 import numpy as np
+
+from .operators import build_A
 
 C_IN, C_HID, C_OUT = 5, 16, 2
 
@@ -125,6 +134,46 @@ def loss_and_grads(params, X, T, mask):
     Y, cache = forward(params, X)
     L = loss(Y, T, mask)
     return L, backward(params, cache, loss_grad(Y, T, mask))
+
+
+def shifted_apply(Y, kappa, lam):
+    """(A_b - lambda_b I) y_b for every crop b: Y (B, H, W, 2) real/imaginary parts,
+    kappa (B, H, W), lam (B,) complex; A_b is the operator of the crop with zero
+    Dirichlet values outside it.  Returns a complex (B, H, W) array."""
+    Bn, H, Wd, _ = Y.shape
+    out = np.empty((Bn, H, Wd), dtype=np.complex128)
+    for b in range(Bn):
+        A = build_A(2, Wd, H, kappa[b].reshape(-1))
+        y = (Y[b, ..., 0] + 1j * Y[b, ..., 1]).reshape(-1)
+        out[b] = (A @ y - lam[b] * y).reshape(H, Wd)
+    return out
+
+
+def residual_loss(Y, Rhat, kappa, lam, mask):
+    """Mean over the batch of the masked relative squared residual."""
+    r = Rhat[..., 0] + 1j * Rhat[..., 1]
+    e = mask[None] * (r - shifted_apply(Y, kappa, lam))
+    num = np.sum(np.abs(e) ** 2, axis=(1, 2))
+    den = np.sum(mask[None] * np.abs(r) ** 2, axis=(1, 2))
+    return float(np.mean(num / den))
+
+
+def residual_loss_grad(Y, Rhat, kappa, lam, mask):
+    """dL/dY: with e = M (rhat - B y), the gradient with respect to (Re y, Im y) is
+    -2 B^H M e / (batch * den); B^H = A - conj(lambda) I since A is symmetric."""
+    Bn = Y.shape[0]
+    r = Rhat[..., 0] + 1j * Rhat[..., 1]
+    e = mask[None] * (r - shifted_apply(Y, kappa, lam))
+    den = np.sum(mask[None] * np.abs(r) ** 2, axis=(1, 2))
+    E = np.stack([e.real, e.imag], axis=-1)
+    g = -2.0 * shifted_apply(E, kappa, np.conj(lam)) / (Bn * den[:, None, None])
+    return np.stack([g.real, g.imag], axis=-1)
+
+
+def residual_loss_and_grads(params, X, Rhat, kappa, lam, mask):
+    Y, cache = forward(params, X)
+    return residual_loss(Y, Rhat, kappa, lam, mask), backward(
+        params, cache, residual_loss_grad(Y, Rhat, kappa, lam, mask))
 
 
 class Adam:

@@ -87,3 +87,93 @@ def test_linear_special_case():
         ref = ndimage.correlate(ref, k, mode="constant", cval=0.0)
     assert np.max(np.abs(Y[0, :, :, 0] - ref)) < 1e-12
     assert np.max(np.abs(Y[0, :, :, 1])) == 0.0
+
+
+def _res_case(seed=5, Bn=2, H=7, Wd=6):
+    rng = np.random.default_rng(seed)
+    Y = rng.standard_normal((Bn, H, Wd, 2))
+    R = rng.standard_normal((Bn, H, Wd, 2))
+    kap = rng.uniform(0.5, 3.0, (Bn, H, Wd))
+    lam = rng.standard_normal(Bn) + 1j * rng.standard_normal(Bn)
+    return rng, Y, R, kap, lam
+
+
+def test_shifted_apply_interior_by_loops():
+    """Interior points of the crop operator by the five-point formula written out:
+    (B y)_i = (1 - lambda) y_i + sum_faces (kappa_i + kappa_nb)/2 (y_i - y_nb)."""
+    _, Y, _, kap, lam = _res_case()
+    got = cnn.shifted_apply(Y, kap, lam)
+    y = Y[..., 0] + 1j * Y[..., 1]
+    for b in range(Y.shape[0]):
+        for i in range(1, Y.shape[1] - 1):
+            for j in range(1, Y.shape[2] - 1):
+                v = (1 - lam[b]) * y[b, i, j]
+                for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                    kf = 0.5 * (kap[b, i, j] + kap[b, i + di, j + dj])
+                    v += kf * (y[b, i, j] - y[b, i + di, j + dj])
+                assert abs(got[b, i, j] - v) < 1e-12 * max(1.0, abs(v))
+
+
+def test_residual_loss_vanishes_at_the_crop_solution():
+    """y = (A_crop - lambda I)^{-1} rhat (sparse direct solve) has zero residual."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    from oracle.operators import build_A
+    _, _, R, kap, lam = _res_case(6)
+    Bn, H, Wd, _ = R.shape
+    Y = np.empty_like(R)
+    for b in range(Bn):
+        M = (build_A(2, Wd, H, kap[b].reshape(-1)) - lam[b] * sp.identity(H * Wd)).tocsc()
+        y = spla.spsolve(M, (R[b, ..., 0] + 1j * R[b, ..., 1]).reshape(-1)).reshape(H, Wd)
+        Y[b, ..., 0], Y[b, ..., 1] = y.real, y.imag
+    assert cnn.residual_loss(Y, R, kap, lam, cnn.border_mask(H, Wd, 1)) < 1e-24
+    assert cnn.residual_loss(np.zeros_like(R), R, kap, lam, cnn.border_mask(H, Wd, 1)) == pytest.approx(1.0)
+
+
+def test_residual_loss_without_diffusion():
+    """kappa = 0: B = (1 - lambda) I and the loss is a pointwise closed form."""
+    _, Y, R, kap, lam = _res_case(7)
+    mask = cnn.border_mask(Y.shape[1], Y.shape[2], 1)
+    y = Y[..., 0] + 1j * Y[..., 1]
+    r = R[..., 0] + 1j * R[..., 1]
+    num = np.sum(mask * np.abs(r - (1 - lam[:, None, None]) * y) ** 2, axis=(1, 2))
+    den = np.sum(mask * np.abs(r) ** 2, axis=(1, 2))
+    assert cnn.residual_loss(Y, R, 0 * kap, lam, mask) == pytest.approx(np.mean(num / den), rel=1e-13)
+
+
+def test_residual_loss_gradient_matches_finite_differences():
+    rng, Y, R, kap, lam = _res_case(8)
+    mask = cnn.border_mask(Y.shape[1], Y.shape[2], 1)
+    g = cnn.residual_loss_grad(Y, R, kap, lam, mask)
+    h = 1e-6
+    for idx in [tuple(rng.integers(0, s) for s in Y.shape) for _ in range(12)] + [(0, 0, 0, 1), (1, 3, 2, 0)]:
+        Yp, Ym = Y.copy(), Y.copy()
+        Yp[idx] += h
+        Ym[idx] -= h
+        fd = (cnn.residual_loss(Yp, R, kap, lam, mask) - cnn.residual_loss(Ym, R, kap, lam, mask)) / (2 * h)
+        assert abs(fd - g[idx]) <= 1e-6 * max(1.0, abs(fd)), (idx, fd, g[idx])
+
+
+def test_residual_loss_network_gradients_match_finite_differences():
+    rng = np.random.default_rng(9)
+    params = cnn.init_params(4)
+    for k in params:
+        params[k] = params[k] + 0.05 * rng.standard_normal(params[k].shape)
+    X = rng.standard_normal((2, 6, 5, cnn.C_IN))
+    R = rng.standard_normal((2, 6, 5, 2))
+    kap = rng.uniform(0.5, 2.0, (2, 6, 5))
+    lam = np.array([0.3 - 0.2j, -0.5 + 0.1j])
+    mask = cnn.border_mask(6, 5, 1)
+    L, g = cnn.residual_loss_and_grads(params, X, R, kap, lam, mask)
+    h = 1e-6
+    for k in ["W1", "b1", "W2", "b3", "W3"]:
+        flat = params[k].reshape(-1)
+        for i in rng.choice(flat.size, size=min(5, flat.size), replace=False):
+            old = flat[i]
+            flat[i] = old + h
+            Lp = cnn.residual_loss(cnn.forward(params, X)[0], R, kap, lam, mask)
+            flat[i] = old - h
+            Lm = cnn.residual_loss(cnn.forward(params, X)[0], R, kap, lam, mask)
+            flat[i] = old
+            fd = (Lp - Lm) / (2 * h)
+            assert abs(fd - g[k].reshape(-1)[i]) <= 1e-6 * max(1.0, abs(fd)), (k, i)
