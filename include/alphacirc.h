@@ -169,6 +169,10 @@ int ac_problem_destroy(ac_problem* p);
 int ac_spectral_bounds(const ac_problem* p, double* mu_lo, double* mu_hi);
 /* Sizes: N, l and l_s = floor(l/2) + 1 (host outputs, any may be NULL). */
 int ac_problem_dims(const ac_problem* p, long long* n, int* ell, int* n_shifts);
+/* The shifts of eq. (3) with the sign of the forward transform used here:
+ * lambda_m = alpha^{1/l} exp(-2 pi i m / l), m = 0..l-1; lam: host, 2 l doubles
+ * (Re, Im pairs). */
+int ac_problem_shifts(const ac_problem* p, double* lam);
 
 /* ---- inner-iteration allocation (Section 5.1, Table 1) ------------------- */
 /* NC2, Algorithm 1: sigma_m from the condition number of Re(A - lambda_m I),
@@ -209,6 +213,11 @@ int ac_shifted_cheb(ac_problem* p, const ac_solve_opts* opts, const void* rhat, 
  * yhat_{l-m} = conj(yhat_m). */
 int ac_tdft_inverse(ac_problem* p, int precision, const void* yhat, double* z);
 
+/* rel[m] = ||rhat_m - (A - lambda_m I) yhat_m|| / ||rhat_m||, m = 0..l_s-1 (host output),
+ * the inner residual of shifted solutions in the spectral layout (float64 sums).
+ * Synchronises. */
+int ac_shifted_residual(ac_problem* p, int precision, const void* rhat, const void* yhat, double* rel);
+
 /* ---- outer solve ---------------------------------------------------------- */
 /* Right-preconditioned flexible GMRES(restart_m) on calA x = b with P_NC^{-1},
  * Arnoldi by modified Gram-Schmidt in inverse compact WY form (two sweeps over
@@ -219,6 +228,13 @@ int ac_tdft_inverse(ac_problem* p, int precision, const void* yhat, double* z);
  * iteration.  info may be NULL.  Returns AC_NOT_CONVERGED after max_outer. */
 int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws, size_t ws_bytes,
              ac_solve_info* info);
+/* ac_solve that also copies the first rec_count vectors handed to the
+ * preconditioner (the Arnoldi basis vectors v_j, unnormalised, in order; device,
+ * rec_count * l * N float64) into rec; *recorded (host) receives how many were
+ * written.  Used to draw training inputs for the warm start from the plain method.
+ * Synchronises. */
+int ac_solve_record(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws,
+                    size_t ws_bytes, ac_solve_info* info, double* rec, int rec_count, int* recorded);
 
 /* ---- learned warm start (not part of the paper's method) ----------------------
  * A three-layer 3x3 convolutional network (5 -> 16 -> 16 -> 2 channels, ReLU after
@@ -227,8 +243,11 @@ int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* 
  * solve; the Chebyshev steps then correct it (AC_INNER_CHEB_CNN).  Inputs per shift
  * m and grid point: Re rhat_m / s_m, Im rhat_m / s_m, Re lambda_m, Im lambda_m,
  * (ln kappa - c0) / c1 with s_m = RMS(rhat_m); outputs Re x0_m / s_m, Im x0_m / s_m.
- * A guess with ||rhat_m - (A - lambda_m) x0_m|| >= ||rhat_m|| is replaced by zero
- * (counted in ac_solve_info.cnn_fallbacks).
+ * Each guess is multiplied by the complex factor c_m that minimises
+ * ||rhat_m - c_m (A - lambda_m) x0_m|| (a one-dimensional minimal-residual step; can be
+ * switched off), and a guess with ||rhat_m - (A - lambda_m) x0_m|| >= tau ||rhat_m||
+ * (tau = 1 by default), or not finite, is replaced by zero (counted in
+ * ac_solve_info.cnn_fallbacks); see ac_cnn_set_guess_policy.
  * Parameter vector (float, host): [W1, b1, W2, b2, W3, b3], each W as [tap = 3 ky + kx]
  * [out 16][in 16] and each b as [16]; entries beyond 5 inputs (layer 1) and 2 outputs
  * (layer 3) are held at zero.
@@ -252,6 +271,17 @@ int ac_cnn_forward(ac_cnn* cnn, const uint16_t* x, int batch, int height, int wi
  * NULL).  Synchronises. */
 int ac_cnn_grad(ac_cnn* cnn, const uint16_t* x, const float* t, const float* tnorm, int border, int batch,
                 int height, int width, void* ws, size_t ws_bytes, double* loss, float* grad);
+/* Residual-space loss of the shifted solves of Section 3 on crops:
+ * L = (1/B) sum_b sum_mask |rhat_b - (A_b - lambda_b) y_b|^2 / rnorm_b, y_b the network
+ * output read as a complex field, A_b the five-point operator of the coefficient crop
+ * kappa_b (face value (kappa_i + kappa_nb)/2), rnorm_b = sum_mask |rhat_b|^2.  Device
+ * arrays: rhat float [B][H][W][2] (the same scaled field as input channels 0, 1),
+ * kappa float [B][H][W], lam float [B][2] (Re, Im of the crop's shift), rnorm float
+ * [B].  border >= 1 (every masked point's neighbours lie in the crop), else
+ * AC_ERR_ARG.  Same workspace, gradient and synchronisation as ac_cnn_grad. */
+int ac_cnn_grad_residual(ac_cnn* cnn, const uint16_t* x, const float* rhat, const float* kappa, const float* lam,
+                         const float* rnorm, int border, int batch, int height, int width, void* ws,
+                         size_t ws_bytes, double* loss, float* grad);
 /* One Adam step (bias-corrected) with the last gradient. */
 int ac_cnn_adam_step(ac_cnn* cnn, double lr, double beta1, double beta2, double eps);
 /* Network inputs x (device bf16 [l_s][N][16]) for every shift slot of a spectral
@@ -259,6 +289,18 @@ int ac_cnn_adam_step(ac_cnn* cnn, double lr, double beta1, double beta2, double 
  * l), then m = 1, 2, ...; scales: host, l_s RMS values in slot order (or NULL). */
 int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* cnn, int precision, const void* rhat, uint16_t* x,
                        double* scales);
+/* The attached network's initial guesses x0hat (spectral layout) for every shift of
+ * rhat, exactly as AC_INNER_CHEB_CNN forms them (scaling and fallback included);
+ * rejected (host, may be NULL) receives the number of slots reset to zero.  Workspace
+ * from ac_cnn_guess_workspace_size.  Synchronises. */
+int ac_cnn_guess_workspace_size(const ac_problem* p, size_t* bytes);
+int ac_cnn_guess(ac_problem* p, int precision, const void* rhat, void* x0hat, void* ws, size_t ws_bytes,
+                 int* rejected);
+/* Guess policy: scaling != 0 (default) multiplies each guess by its
+ * residual-minimising complex factor; a guess is kept only if
+ * ||rhat_m - (A - lambda_m) x0_m|| < accept_ratio ||rhat_m||, accept_ratio in (0, 1]
+ * (default 1, the plain fallback rule). */
+int ac_cnn_set_guess_policy(ac_cnn* cnn, int scaling, double accept_ratio);
 /* Attaches the network used by AC_INNER_CHEB_CNN (NULL detaches; not owned). */
 int ac_problem_attach_cnn(ac_problem* p, ac_cnn* cnn);
 

@@ -107,6 +107,8 @@ SIGNATURES = {
     "ac_shifted_cheb": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _VP, _SZ]),
     "ac_tdft_inverse": (_I, [_VP, _I, _VP, _VP]),
     "ac_solve": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _SZ, C.POINTER(ac_solve_info)]),
+    "ac_solve_record": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _SZ, C.POINTER(ac_solve_info), _VP, _I,
+                             C.POINTER(_I)]),
     "ac_cnn_param_count": (_I, []),
     "ac_cnn_create": (_I, [_VP, C.POINTER(_VP)]),
     "ac_cnn_destroy": (_I, [_VP]),
@@ -115,9 +117,16 @@ SIGNATURES = {
     "ac_cnn_workspace_size": (_I, [_I, _I, _I, C.POINTER(_SZ)]),
     "ac_cnn_forward": (_I, [_VP, _VP, _I, _I, _I, _VP, _VP, _SZ]),
     "ac_cnn_grad": (_I, [_VP, _VP, _VP, _VP, _I, _I, _I, _I, _VP, _SZ, C.POINTER(_D), C.POINTER(C.c_float)]),
+    "ac_cnn_grad_residual": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _I, _I, _I, _I, _VP, _SZ, C.POINTER(_D),
+                                  C.POINTER(C.c_float)]),
+    "ac_problem_shifts": (_I, [_VP, C.POINTER(_D)]),
     "ac_cnn_adam_step": (_I, [_VP, _D, _D, _D, _D]),
     "ac_cnn_make_inputs": (_I, [_VP, _VP, _I, _VP, _VP, C.POINTER(_D)]),
     "ac_problem_attach_cnn": (_I, [_VP, _VP]),
+    "ac_shifted_residual": (_I, [_VP, _I, _VP, _VP, C.POINTER(_D)]),
+    "ac_cnn_guess_workspace_size": (_I, [_VP, C.POINTER(_SZ)]),
+    "ac_cnn_guess": (_I, [_VP, _I, _VP, _VP, _VP, _SZ, C.POINTER(_I)]),
+    "ac_cnn_set_guess_policy": (_I, [_VP, _I, _D]),
 }
 
 _lib = None

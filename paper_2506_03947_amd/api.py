@@ -146,6 +146,15 @@ def ac_spectral_bounds(p: Problem) -> tuple[float, float]:
     return lo.value, hi.value
 
 
+def ac_problem_shifts(p: Problem):
+    """lambda_m, m = 0..l-1, as a complex numpy array."""
+    import numpy as np
+    buf = (C.c_double * (2 * p.ell))()
+    check(L.load().ac_problem_shifts(p.h, buf), "ac_problem_shifts")
+    v = np.frombuffer(buf, dtype=np.float64).copy()
+    return v[0::2] + 1j * v[1::2]
+
+
 def ac_alloc_nc2(p: Problem, budget: float) -> list[int]:
     out = (C.c_int * p.ell)()
     check(L.load().ac_alloc_nc2(p.h, float(budget), out), "ac_alloc_nc2")
@@ -220,6 +229,25 @@ def ac_solve(p: Problem, opts: Opts, b: torch.Tensor, x: torch.Tensor, ws: torch
     info = L.ac_solve_info()
     st = check(L.load().ac_solve(p.h, C.byref(o), _f64(b, n, "b"), _f64(x, n, "x"), _ptr(ws), ws.numel(),
                                  C.byref(info)), "ac_solve")
+    return _info_dict(st, info)
+
+
+def ac_solve_record(p: Problem, opts: Opts, b: torch.Tensor, x: torch.Tensor, ws: torch.Tensor,
+                    rec: torch.Tensor) -> tuple[dict, int]:
+    """ac_solve that copies the first rec.shape[0] preconditioner inputs into rec
+    ([count, l*N] float64); returns (info, number recorded)."""
+    n = p.ell * p.n
+    o, keep = opts.to_c(p.ell)
+    info = L.ac_solve_info()
+    done = C.c_int()
+    count = rec.shape[0]
+    st = check(L.load().ac_solve_record(p.h, C.byref(o), _f64(b, n, "b"), _f64(x, n, "x"), _ptr(ws), ws.numel(),
+                                        C.byref(info), _f64(rec, count * n, "rec"), count, C.byref(done)),
+               "ac_solve_record")
+    return _info_dict(st, info), done.value
+
+
+def _info_dict(st, info) -> dict:
     return {
         "status": st,
         "converged": st == L.AC_OK,
@@ -344,6 +372,21 @@ def ac_cnn_grad(cnn: Cnn, x: torch.Tensor, t: torch.Tensor, tnorm: torch.Tensor,
     return loss.value, g
 
 
+def ac_cnn_grad_residual(cnn: Cnn, x: torch.Tensor, rhat: torch.Tensor, kappa: torch.Tensor, lam: torch.Tensor,
+                         rnorm: torch.Tensor, border: int, batch: int, height: int, width: int, ws: torch.Tensor,
+                         want_grad: bool = False):
+    """Residual-space loss (rhat [B,H,W,2], kappa [B,H,W], lam [B,2], rnorm [B], float32)."""
+    import numpy as np
+    npx = batch * height * width
+    loss = C.c_double()
+    g = np.zeros(L.load().ac_cnn_param_count(), dtype=np.float32) if want_grad else None
+    check(L.load().ac_cnn_grad_residual(
+        cnn.h, _u16(x, npx * 16, "x"), _f32(rhat, npx * 2, "rhat"), _f32(kappa, npx, "kappa"),
+        _f32(lam, batch * 2, "lam"), _f32(rnorm, batch, "rnorm"), border, batch, height, width, _ptr(ws), ws.numel(),
+        C.byref(loss), g.ctypes.data_as(C.POINTER(C.c_float)) if g is not None else None), "ac_cnn_grad_residual")
+    return loss.value, g
+
+
 def ac_cnn_adam_step(cnn: Cnn, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
     check(L.load().ac_cnn_adam_step(cnn.h, lr, beta1, beta2, eps), "ac_cnn_adam_step")
 
@@ -365,3 +408,29 @@ def slot_order(p: Problem) -> list[int]:
     """Frequency m of each shift slot (real shifts first, then complex m = 1, 2, ...)."""
     real = [0] + ([p.ell // 2] if p.ell % 2 == 0 else [])
     return real + [m for m in range(1, (p.ell + 1) // 2)]
+
+
+def ac_shifted_residual(p: Problem, precision: int, rhat: torch.Tensor, yhat: torch.Tensor):
+    import numpy as np
+    rel = np.empty(p.ns, dtype=np.float64)
+    check(L.load().ac_shifted_residual(p.h, precision, _ptr(rhat), _ptr(yhat),
+                                       rel.ctypes.data_as(C.POINTER(C.c_double))), "ac_shifted_residual")
+    return rel
+
+
+def ac_cnn_guess_workspace_size(p: Problem) -> int:
+    n = C.c_size_t()
+    check(L.load().ac_cnn_guess_workspace_size(p.h, C.byref(n)), "ac_cnn_guess_workspace_size")
+    return n.value
+
+
+def ac_cnn_guess(p: Problem, precision: int, rhat: torch.Tensor, x0hat: torch.Tensor, ws: torch.Tensor) -> int:
+    """Writes the warm start's guesses into x0hat; returns the number of rejected slots."""
+    rej = C.c_int()
+    check(L.load().ac_cnn_guess(p.h, precision, _ptr(rhat), _ptr(x0hat), _ptr(ws), ws.numel(), C.byref(rej)),
+          "ac_cnn_guess")
+    return rej.value
+
+
+def ac_cnn_set_guess_policy(cnn: Cnn, scaling: bool, accept_ratio: float = 1.0) -> None:
+    check(L.load().ac_cnn_set_guess_policy(cnn.h, 1 if scaling else 0, accept_ratio), "ac_cnn_set_guess_policy")

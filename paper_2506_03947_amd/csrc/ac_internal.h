@@ -163,6 +163,7 @@ struct CnnPrepArgs {
     int is_real[kMaxShift];
     float lam_re[kMaxShift], lam_im[kMaxShift];
     float inv_scale[kMaxShift], scale[kMaxShift];
+    float fac_re[kMaxShift], fac_im[kMaxShift];  // complex factor applied to the output
     const double* kappa;
     double c0, c1;                     // input normalisation of ln kappa
     uint16_t* x;                       // bf16 [ns][N][16]
@@ -173,6 +174,9 @@ hipError_t launch_cnn_conv(const CnnConvArgs& a, hipStream_t s);
 hipError_t launch_cnn_wgrad(const CnnWgradArgs& a, float* grad, hipStream_t s);
 hipError_t launch_cnn_loss(const float* y, const float* t, const float* tnorm, int B, int H, int W, int border,
                            uint16_t* dy16, float* partial, int* nblocks, hipStream_t s);
+hipError_t launch_cnn_resloss(const float* y, const float* rhat, const float* kap, const float* lam,
+                              const float* rnorm, int B, int H, int W, int border, float* e, uint16_t* dy16,
+                              float* partial, int* nblocks, hipStream_t s);
 hipError_t launch_cnn_adam(float* w, const float* g, float* m, float* v, float lr, float b1, float b2, float eps,
                            float bc1, float bc2, hipStream_t s);
 hipError_t launch_cnn_weights(const float* w, uint16_t* wf, uint16_t* wb, float* bias, hipStream_t s);

@@ -75,6 +75,8 @@ struct ac_ctx {
     int tile_h = 0, tile_wpb = 0, tile_vx = 0;
 };
 
+constexpr int kResidBlocks = 512;  // blocks of the warm-start residual-statistics kernel
+
 struct ac_problem {
     ac_ctx* ctx = nullptr;
     Geom g{};
@@ -86,6 +88,7 @@ struct ac_problem {
     uint16_t* k16 = nullptr;
     double bounds[3][2] = {};  // per precision: mu_lo, mu_hi
     double kmin64 = 0;
+    double* rpart = nullptr;   // per-block partial sums of the warm-start residual test
     ac_cnn* cnn = nullptr;     // warm-start network (not owned)
 };
 
@@ -101,6 +104,8 @@ struct ac_cnn {
     float* bias = nullptr;     // [3][16]
     double c0 = 0.0, c1 = 1.0; // ln kappa normalisation
     int t = 0;                 // Adam steps taken
+    int scaled = 1;            // scale each guess by its residual-minimising factor
+    double accept = 1.0;       // keep a guess only if |rhat - B x0| < accept |rhat|
 };
 
 // ---------------------------------------------------------------------------
@@ -206,6 +211,10 @@ Tiling calA_tiling(const ac_problem* p) {
 //   rho_0 = delta/theta, rho_k = 1/(2 theta/delta - rho_{k-1}),
 //   x_{k+1} = x_k + rho_k rho_{k-1} (x_k - x_{k-1}) + (2 rho_k/delta)(rhat - B x_k),
 //   x_1 = x_0 + (rhat - B x_0)/theta.
+// lambda_m = alpha^{1/l} exp(-2 pi i m / l): the eigenvalue of C_alpha on the m-th
+// column of the (negative-exponent) DFT that the forward transform applies.
+cplx shift_of(const ac_problem* p, int m) { return std::polar(std::pow(p->alpha, 1.0 / p->ell), -2.0 * kPi * m / p->ell); }
+
 struct ChebShift {
     cplx lam, theta;
     double delta;
@@ -215,7 +224,7 @@ struct ChebShift {
 ChebShift cheb_tables(const ac_problem* p, int prec, int m, int steps) {
     ChebShift s;
     const double lo = p->bounds[prec][0], hi = p->bounds[prec][1];
-    s.lam = std::polar(std::pow(p->alpha, 1.0 / p->ell), -2.0 * kPi * m / p->ell);
+    s.lam = shift_of(p, m);
     s.theta = cplx(0.5 * (hi + lo), 0.0) - s.lam;
     s.delta = 0.5 * (hi - lo);
     s.a.assign(std::max(steps, 1), cplx(0));
@@ -254,15 +263,11 @@ int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>&
     return AC_OK;
 }
 
-// Prec workspace: rhat + 2 iterate buffers (+ a warm-start buffer) of the spectral size.
-constexpr int kResidBlocks = 512;
-
-// CNN inference buffers: inputs and two hidden activations (bf16, 16 channels), the
-// float32 output (2 channels), per-slot reduction partials.
+// CNN inference buffers: inputs and two hidden activations (bf16, 16 channels) and the
+// float32 output (2 channels).
 size_t cnn_ws_bytes(const ac_problem* p) {
     const size_t px = static_cast<size_t>(p->ns) * static_cast<size_t>(p->g.n);
-    return 3 * align_up(px * 32, 256) + align_up(px * 8, 256) +
-           align_up(static_cast<size_t>(kResidBlocks) * 2 * kMaxShift * sizeof(double), 256);
+    return 3 * align_up(px * 32, 256) + align_up(px * 8, 256) + 256;
 }
 
 size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
@@ -500,11 +505,13 @@ ac::CnnPrepArgs cnn_args(const ac_problem* p, int prec, const char* rhat) {
         const int m = slot_to_m(p, s);
         a.soff[s] = static_cast<unsigned>(off[m]);
         a.is_real[s] = slot_is_real(p, s) ? 1 : 0;
-        const cplx lam = std::polar(std::pow(p->alpha, 1.0 / p->ell), -2.0 * kPi * m / p->ell);
+        const cplx lam = shift_of(p, m);
         a.lam_re[s] = static_cast<float>(lam.real());
         a.lam_im[s] = static_cast<float>(lam.imag());
         a.inv_scale[s] = 1.f;
         a.scale[s] = 1.f;
+        a.fac_re[s] = 1.f;
+        a.fac_im[s] = 0.f;
     }
     a.kappa = p->k64;
     a.c0 = p->cnn ? p->cnn->c0 : 0.0;
@@ -512,24 +519,47 @@ ac::CnnPrepArgs cnn_args(const ac_problem* p, int prec, const char* rhat) {
     return a;
 }
 
-// Per-slot sums of |rhat|^2 and |rhat - (A - lambda) x0|^2 (x0 == nullptr: first only).
-int slot_residuals(ac_problem* p, int prec, const ac::CnnPrepArgs& a, const char* x0, double* partial,
-                   std::vector<double>& rr, std::vector<double>& res) {
+// Per-slot sums over the grid for rhat and a guess x0 (B = A - lambda I):
+// rr = |rhat|^2, bb = |B x0|^2, (cr, ci) = sum conj(B x0) rhat (zero without x0).
+struct SlotStats {
+    std::vector<double> rr, bb, cr, ci;
+    // |rhat - c B x0|^2 for the complex factor c
+    double res(int s, double c_re = 1.0, double c_im = 0.0) const {
+        return rr[s] - 2.0 * (c_re * cr[s] - c_im * ci[s]) + (c_re * c_re + c_im * c_im) * bb[s];
+    }
+};
+
+int slot_residuals(ac_problem* p, int prec, const ac::CnnPrepArgs& a, const char* x0, SlotStats& out) {
     const void* kap = prec == AC_PREC_FP64 ? static_cast<const void*>(p->k64)
                       : prec == AC_PREC_MIXED_BF16K ? static_cast<const void*>(p->k16)
                                                     : static_cast<const void*>(p->k32);
-    AC_HIP(ac::launch_cnn_resid(prec, a, x0, kap, partial, kResidBlocks, p->ctx->stream));
-    std::vector<double> h(static_cast<size_t>(kResidBlocks) * 2 * kMaxShift);
-    AC_HIP(hipMemcpyAsync(h.data(), partial, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->ctx->stream));
+    AC_HIP(ac::launch_cnn_resid(prec, a, x0, kap, p->rpart, kResidBlocks, p->ctx->stream));
+    std::vector<double> h(static_cast<size_t>(kResidBlocks) * 4 * kMaxShift);
+    AC_HIP(hipMemcpyAsync(h.data(), p->rpart, h.size() * sizeof(double), hipMemcpyDeviceToHost, p->ctx->stream));
     AC_HIP(hipStreamSynchronize(p->ctx->stream));
-    rr.assign(p->ns, 0.0);
-    res.assign(p->ns, 0.0);
+    out.rr.assign(p->ns, 0.0);
+    out.bb.assign(p->ns, 0.0);
+    out.cr.assign(p->ns, 0.0);
+    out.ci.assign(p->ns, 0.0);
     for (int b = 0; b < kResidBlocks; ++b)
         for (int s = 0; s < p->ns; ++s) {
-            rr[s] += h[static_cast<size_t>(b) * 2 * kMaxShift + 2 * s];
-            res[s] += h[static_cast<size_t>(b) * 2 * kMaxShift + 2 * s + 1];
+            const double* q = &h[static_cast<size_t>(b) * 4 * kMaxShift + 4 * s];
+            out.rr[s] += q[0];
+            out.bb[s] += q[1];
+            out.cr[s] += q[2];
+            out.ci[s] += q[3];
         }
     return AC_OK;
+}
+
+// Input scales s_m = RMS(rhat_m) into the argument block (and optionally to the host).
+void set_rms_scales(const ac_problem* p, const SlotStats& st, ac::CnnPrepArgs& a, double* scales) {
+    for (int s = 0; s < p->ns; ++s) {
+        const double rms = std::sqrt(st.rr[s] / static_cast<double>(p->g.n));
+        a.scale[s] = static_cast<float>(rms);
+        a.inv_scale[s] = rms > 0 ? static_cast<float>(1.0 / rms) : 0.f;
+        if (scales) scales[s] = rms;
+    }
 }
 
 int cnn_forward_impl(ac_cnn* c, const uint16_t* x, int B, int H, int W, float* y, uint16_t* a1, uint16_t* a2,
@@ -560,48 +590,63 @@ int cnn_forward_impl(ac_cnn* c, const uint16_t* x, int B, int H, int W, float* y
     return AC_OK;
 }
 
-// Learned initial guesses for every shift slot, written into buf0; a slot whose
-// guess does not reduce the residual (||rhat - B x0|| >= ||rhat||) is reset to zero.
-int cnn_warm_start(ac_problem* p, int prec, char* rhat, char* buf0, char* cws, int* fallbacks) {
+// Learned initial guesses for every shift slot, written into x0buf.  With scaling on
+// each slot's output is multiplied by the complex factor c that minimises
+// |rhat - c B x0| (a one-dimensional minimal-residual step).  A slot whose (scaled)
+// guess leaves a residual of at least accept * |rhat|, or is not finite, is reset to
+// zero.
+int cnn_warm_start(ac_problem* p, int prec, const char* rhat, char* x0buf, char* cws, int* fallbacks) {
     const size_t px = static_cast<size_t>(p->ns) * static_cast<size_t>(p->g.n);
     uint16_t* X = reinterpret_cast<uint16_t*>(cws);
     uint16_t* A1 = reinterpret_cast<uint16_t*>(cws + align_up(px * 32, 256));
     uint16_t* A2 = reinterpret_cast<uint16_t*>(cws + 2 * align_up(px * 32, 256));
     float* Y = reinterpret_cast<float*>(cws + 3 * align_up(px * 32, 256));
-    double* partial = reinterpret_cast<double*>(cws + 3 * align_up(px * 32, 256) + align_up(px * 8, 256));
     ac::CnnPrepArgs a = cnn_args(p, prec, rhat);
-    std::vector<double> rr, res;
+    SlotStats st;
     {
         ProfScope ps(p->ctx, AC_K_CNN, 0.0);
-        AC_TRY(slot_residuals(p, prec, a, nullptr, partial, rr, res));
+        AC_TRY(slot_residuals(p, prec, a, nullptr, st));
     }
-    for (int s = 0; s < p->ns; ++s) {
-        const double rms = std::sqrt(rr[s] / static_cast<double>(p->g.n));
-        a.scale[s] = static_cast<float>(rms);
-        a.inv_scale[s] = rms > 0 ? static_cast<float>(1.0 / rms) : 0.f;
-    }
+    set_rms_scales(p, st, a, nullptr);
     a.x = X;
     {
         const double bytes = static_cast<double>(px) * (32.0 * 7 + 8.0 * 2) + 8.0 * p->g.n;
         ProfScope ps(p->ctx, AC_K_CNN, bytes);
         AC_HIP(ac::launch_cnn_prep(prec, a, p->ctx->stream));
         AC_TRY(cnn_forward_impl(p->cnn, X, p->ns, p->g.ny, p->g.nx, Y, A1, A2, p->ctx->stream));
-        AC_HIP(ac::launch_cnn_post(prec, a, Y, buf0, p->ctx->stream));
+        AC_HIP(ac::launch_cnn_post(prec, a, Y, x0buf, p->ctx->stream));
     }
     {
         ProfScope ps(p->ctx, AC_K_CNN, 0.0);
-        AC_TRY(slot_residuals(p, prec, a, buf0, partial, rr, res));
+        AC_TRY(slot_residuals(p, prec, a, x0buf, st));
+    }
+    std::vector<int> reject(p->ns, 0);
+    bool rescale = false;
+    for (int s = 0; s < p->ns; ++s) {
+        double c_re = 1.0, c_im = 0.0;
+        if (p->cnn->scaled && st.bb[s] > 0.0) {
+            c_re = st.cr[s] / st.bb[s];
+            c_im = st.ci[s] / st.bb[s];
+        }
+        const double res = st.res(s, c_re, c_im);
+        const double bound = p->cnn->accept * p->cnn->accept * st.rr[s];
+        reject[s] = !(std::isfinite(res) && std::isfinite(c_re) && std::isfinite(c_im) && res < bound);
+        a.fac_re[s] = static_cast<float>(c_re);
+        a.fac_im[s] = static_cast<float>(c_im);
+        rescale = rescale || (!reject[s] && (c_re != 1.0 || c_im != 0.0));
+    }
+    if (rescale) {
+        ProfScope ps(p->ctx, AC_K_CNN, static_cast<double>(px) * 16.0);
+        AC_HIP(ac::launch_cnn_post(prec, a, Y, x0buf, p->ctx->stream));
     }
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     for (int s = 0; s < p->ns; ++s) {
-        if (!(res[s] < rr[s])) {
-            const int m = slot_to_m(p, s);
-            AC_HIP(ac::launch_zero_bytes(buf0, off[m] * static_cast<long long>(inner_elem(prec)),
-                                         slice_elems(p, m) * static_cast<long long>(inner_elem(prec)),
-                                         p->ctx->stream));
-            if (fallbacks) ++*fallbacks;
-        }
+        if (!reject[s]) continue;
+        const int m = slot_to_m(p, s);
+        AC_HIP(ac::launch_zero_bytes(x0buf, off[m] * static_cast<long long>(inner_elem(prec)),
+                                     slice_elems(p, m) * static_cast<long long>(inner_elem(prec)), p->ctx->stream));
+        if (fallbacks) ++*fallbacks;
     }
     return AC_OK;
 }
@@ -762,12 +807,14 @@ int ac_problem_create(ac_ctx* c, const ac_grid* grid, const double* kappa, int e
         if (p->k64) (void)hipFree(p->k64);
         if (p->k32) (void)hipFree(p->k32);
         if (p->k16) (void)hipFree(p->k16);
+        if (p->rpart) (void)hipFree(p->rpart);
         if (partial) (void)hipFree(partial);
         delete p;
     };
     hipError_t e = hipMalloc(&p->k64, n * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&p->k32, align_up(n * sizeof(float), 256));
     if (e == hipSuccess) e = hipMalloc(&p->k16, align_up(n * sizeof(uint16_t), 256));
+    if (e == hipSuccess) e = hipMalloc(&p->rpart, static_cast<size_t>(kResidBlocks) * 4 * kMaxShift * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&partial, nblk * 7 * sizeof(double));
     if (e == hipSuccess) e = hipMemcpyAsync(p->k64, kappa, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = ac::launch_kappa_setup(p->g, p->k64, p->k32, p->k16, partial, nblk, c->stream);
@@ -831,6 +878,7 @@ int ac_problem_destroy(ac_problem* p) {
     (void)hipFree(p->k64);
     (void)hipFree(p->k32);
     (void)hipFree(p->k16);
+    (void)hipFree(p->rpart);
     delete p;
     return AC_OK;
 }
@@ -847,6 +895,16 @@ int ac_problem_dims(const ac_problem* p, long long* n, int* ell, int* ns) {
     if (n) *n = p->g.n;
     if (ell) *ell = p->ell;
     if (ns) *ns = p->ns;
+    return AC_OK;
+}
+
+int ac_problem_shifts(const ac_problem* p, double* lam) {
+    if (!p || !lam) return fail(AC_ERR_ARG, "NULL argument");
+    for (int m = 0; m < p->ell; ++m) {
+        const cplx l = shift_of(p, m);
+        lam[2 * m] = l.real();
+        lam[2 * m + 1] = l.imag();
+    }
     return AC_OK;
 }
 
@@ -1035,8 +1093,9 @@ int ac_tdft_inverse(ac_problem* p, int prec, const void* yhat, double* z) {
 // ---------------------------------------------------------------------------
 // FGMRES
 
-int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
-             ac_solve_info* info) {
+namespace {
+int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
+               ac_solve_info* info, double* rec, int rec_count, int* rec_done) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!p || !b || !x) return fail(AC_ERR_ARG, "NULL argument");
     std::vector<int> pm;
@@ -1107,6 +1166,11 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
         scale[0] = 1.0 / beta;
         int kdone = 0;
         for (int j = 0; j < m; ++j) {
+            if (rec && *rec_done < rec_count) {
+                AC_HIP(hipMemcpyAsync(rec + static_cast<size_t>(*rec_done) * len, w.V[j], len * sizeof(double),
+                                      hipMemcpyDeviceToDevice, st));
+                ++*rec_done;
+            }
             // z_j = P^{-1} v_j with v_j = scale_j * V_j (scale folded into the transform)
             AC_TRY(apply_prec_impl(p, o, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
             AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
@@ -1194,7 +1258,21 @@ int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, 
         info->reserved = 0;
         info->orth_loss = orth_loss;
     }
+    if (rec) AC_HIP(hipStreamSynchronize(st));
     return status;
+}
+}  // namespace
+
+int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
+             ac_solve_info* info) {
+    return solve_impl(p, o, b, x, ws, ws_bytes, info, nullptr, 0, nullptr);
+}
+
+int ac_solve_record(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
+                    ac_solve_info* info, double* rec, int rec_count, int* recorded) {
+    if (!rec || rec_count < 1 || !recorded) return fail(AC_ERR_ARG, "record buffer, count and counter are required");
+    *recorded = 0;
+    return solve_impl(p, o, b, x, ws, ws_bytes, info, rec, rec_count, recorded);
 }
 
 // ---------------------------------------------------------------------------
@@ -1333,12 +1411,13 @@ int ac_cnn_forward(ac_cnn* n, const uint16_t* x, int B, int H, int W, float* y, 
     return cnn_forward_impl(n, x, B, H, W, y, a1, a2, n->ctx->stream);
 }
 
-int ac_cnn_grad(ac_cnn* n, const uint16_t* x, const float* t, const float* tnorm, int border, int B, int H, int W,
-                void* ws, size_t ws_bytes, double* loss, float* grad_host) {
-    if (!n || !x || !t || !tnorm) return fail(AC_ERR_ARG, "NULL argument");
-    AC_TRY(cnn_check_shape(B, H, W));
-    if (border < 0 || 2 * border >= H || 2 * border >= W) return fail(AC_ERR_ARG, "border too wide");
-    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+namespace {
+// Forward pass, one loss kernel (which writes dL/dY as bf16) and the backward pass
+// into n->g.  The loss scratch (px float2) shares the dZ2 buffer, which is written
+// only after dY has been consumed.
+template <class LossFn>
+int cnn_train_pass(ac_cnn* n, const uint16_t* x, int B, int H, int W, void* ws, double* loss, float* grad_host,
+                   LossFn launch_loss) {
     AC_HIP(hipSetDevice(n->ctx->device));
     hipStream_t st = n->ctx->stream;
     const size_t px = static_cast<size_t>(B) * H * W;
@@ -1358,7 +1437,7 @@ int ac_cnn_grad(ac_cnn* n, const uint16_t* x, const float* t, const float* tnorm
     {
         ProfScope ps(n->ctx, AC_K_CNN, static_cast<double>(px) * (32.0 * 14 + 8.0 * 3));
         AC_TRY(cnn_forward_impl(n, x, B, H, W, Y, A1, A2, st));
-        AC_HIP(ac::launch_cnn_loss(Y, t, tnorm, B, H, W, border, dY, lpart, &nblk, st));
+        AC_HIP(launch_loss(Y, dY, reinterpret_cast<float*>(dZ2), lpart, &nblk, st));
         ac::CnnWgradArgs wa{};
         wa.B = B;
         wa.H = H;
@@ -1397,6 +1476,34 @@ int ac_cnn_grad(ac_cnn* n, const uint16_t* x, const float* t, const float* tnorm
     if (loss) *loss = l / B;
     return AC_OK;
 }
+}  // namespace
+
+int ac_cnn_grad(ac_cnn* n, const uint16_t* x, const float* t, const float* tnorm, int border, int B, int H, int W,
+                void* ws, size_t ws_bytes, double* loss, float* grad_host) {
+    if (!n || !x || !t || !tnorm) return fail(AC_ERR_ARG, "NULL argument");
+    AC_TRY(cnn_check_shape(B, H, W));
+    if (border < 0 || 2 * border >= H || 2 * border >= W) return fail(AC_ERR_ARG, "border too wide");
+    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    return cnn_train_pass(n, x, B, H, W, ws, loss, grad_host,
+                          [&](const float* Y, uint16_t* dY, float*, float* lpart, int* nblk, hipStream_t st) {
+                              return ac::launch_cnn_loss(Y, t, tnorm, B, H, W, border, dY, lpart, nblk, st);
+                          });
+}
+
+int ac_cnn_grad_residual(ac_cnn* n, const uint16_t* x, const float* rhat, const float* kappa, const float* lam,
+                         const float* rnorm, int border, int B, int H, int W, void* ws, size_t ws_bytes,
+                         double* loss, float* grad_host) {
+    if (!n || !x || !rhat || !kappa || !lam || !rnorm) return fail(AC_ERR_ARG, "NULL argument");
+    AC_TRY(cnn_check_shape(B, H, W));
+    if (border < 1 || 2 * border >= H || 2 * border >= W)
+        return fail(AC_ERR_ARG, "border must be at least 1 and leave an interior");
+    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    return cnn_train_pass(n, x, B, H, W, ws, loss, grad_host,
+                          [&](const float* Y, uint16_t* dY, float* e, float* lpart, int* nblk, hipStream_t st) {
+                              return ac::launch_cnn_resloss(Y, rhat, kappa, lam, rnorm, B, H, W, border, e, dY,
+                                                            lpart, nblk, st);
+                          });
+}
 
 int ac_cnn_adam_step(ac_cnn* n, double lr, double beta1, double beta2, double eps) {
     if (!n) return fail(AC_ERR_ARG, "NULL argument");
@@ -1416,22 +1523,12 @@ int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* n, int prec, const void* rha
     if (!p || !n || !rhat || !x) return fail(AC_ERR_ARG, "NULL argument");
     if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
     AC_HIP(hipSetDevice(p->ctx->device));
-    ac_cnn* keep = p->cnn;
-    p->cnn = const_cast<ac_cnn*>(n);
     ac::CnnPrepArgs a = cnn_args(p, prec, static_cast<const char*>(rhat));
-    p->cnn = keep;
-    double* partial = nullptr;
-    AC_HIP(hipMalloc(&partial, static_cast<size_t>(kResidBlocks) * 2 * kMaxShift * sizeof(double)));
-    std::vector<double> rr, res;
-    const int st = slot_residuals(p, prec, a, nullptr, partial, rr, res);
-    (void)hipFree(partial);
-    if (st < 0) return st;
-    for (int s = 0; s < p->ns; ++s) {
-        const double rms = std::sqrt(rr[s] / static_cast<double>(p->g.n));
-        a.scale[s] = static_cast<float>(rms);
-        a.inv_scale[s] = rms > 0 ? static_cast<float>(1.0 / rms) : 0.f;
-        if (scales) scales[s] = rms;
-    }
+    a.c0 = n->c0;
+    a.c1 = n->c1;
+    SlotStats st;
+    AC_TRY(slot_residuals(p, prec, a, nullptr, st));
+    set_rms_scales(p, st, a, scales);
     a.x = x;
     AC_HIP(ac::launch_cnn_prep(prec, a, p->ctx->stream));
     return AC_OK;
@@ -1441,5 +1538,47 @@ int ac_problem_attach_cnn(ac_problem* p, ac_cnn* n) {
     if (!p) return fail(AC_ERR_ARG, "problem is NULL");
     if (n && n->ctx != p->ctx) return fail(AC_ERR_ARG, "network and problem belong to different contexts");
     p->cnn = n;
+    return AC_OK;
+}
+
+int ac_shifted_residual(ac_problem* p, int prec, const void* rhat, const void* yhat, double* rel) {
+    if (!p || !rhat || !yhat || !rel) return fail(AC_ERR_ARG, "NULL argument");
+    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    ac::CnnPrepArgs a = cnn_args(p, prec, static_cast<const char*>(rhat));
+    SlotStats st;
+    AC_TRY(slot_residuals(p, prec, a, static_cast<const char*>(yhat), st));
+    for (int s = 0; s < p->ns; ++s) {
+        const double r = std::max(st.res(s), 0.0);
+        rel[slot_to_m(p, s)] = st.rr[s] > 0 ? std::sqrt(r / st.rr[s]) : 0.0;
+    }
+    return AC_OK;
+}
+
+int ac_cnn_guess_workspace_size(const ac_problem* p, size_t* bytes) {
+    if (!p || !bytes) return fail(AC_ERR_ARG, "NULL argument");
+    *bytes = cnn_ws_bytes(p) + 256;
+    return AC_OK;
+}
+
+int ac_cnn_guess(ac_problem* p, int prec, const void* rhat, void* x0hat, void* ws, size_t ws_bytes,
+                 int* rejected) {
+    if (!p || !rhat || !x0hat) return fail(AC_ERR_ARG, "NULL argument");
+    if (!p->cnn) return fail(AC_ERR_ARG, "no warm-start network attached");
+    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
+    if (!ws || ws_bytes < cnn_ws_bytes(p) + 256) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    char* cws = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
+    int fb = 0;
+    AC_TRY(cnn_warm_start(p, prec, static_cast<const char*>(rhat), static_cast<char*>(x0hat), cws, &fb));
+    if (rejected) *rejected = fb;
+    return AC_OK;
+}
+
+int ac_cnn_set_guess_policy(ac_cnn* n, int scaling, double accept_ratio) {
+    if (!n) return fail(AC_ERR_ARG, "network is NULL");
+    if (!(accept_ratio > 0.0 && accept_ratio <= 1.0)) return fail(AC_ERR_ARG, "accept_ratio must be in (0, 1]");
+    n->scaled = scaling ? 1 : 0;
+    n->accept = accept_ratio;
     return AC_OK;
 }

@@ -208,6 +208,89 @@ __global__ __launch_bounds__(256) void loss_kernel(const float* __restrict__ y, 
 }
 
 // ---------------------------------------------------------------------------
+// Residual-space loss on crops: e = M (rhat - (A - lambda) y), A the five-point
+// operator of the crop's coefficients with face values (kappa_i + kappa_nb)/2.  With
+// border >= 1 every masked point has its four neighbours inside the crop.  Writes e
+// (zero outside the mask) and per-block sums of |e|^2 / rnorm_b.
+__global__ __launch_bounds__(256) void resloss_kernel(const float2* __restrict__ y, const float2* __restrict__ rhat,
+                                                      const float* __restrict__ kap, const float2* __restrict__ lam,
+                                                      const float* __restrict__ rnorm, int B, int H, int W,
+                                                      int border, float2* __restrict__ e,
+                                                      float* __restrict__ partial) {
+    const long long npix = static_cast<long long>(B) * H * W;
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    float l = 0.f;
+    if (p < npix) {
+        const int x = static_cast<int>(p % W);
+        const int yy = static_cast<int>((p / W) % H);
+        const int b = static_cast<int>(p / (static_cast<long long>(W) * H));
+        float2 ev = make_float2(0.f, 0.f);
+        if (x >= border && x < W - border && yy >= border && yy < H - border) {
+            const float k0 = kap[p];
+            const float2 yc = y[p];
+            const long long nb[4] = {p - 1, p + 1, p - W, p + W};
+            float ar = 0.f, ai = 0.f;
+#pragma unroll
+            for (int f = 0; f < 4; ++f) {
+                const float kf = 0.5f * (k0 + kap[nb[f]]);
+                const float2 yn = y[nb[f]];
+                ar += kf * (yc.x - yn.x);
+                ai += kf * (yc.y - yn.y);
+            }
+            const float2 lm = lam[b];
+            const float br = yc.x + ar - (lm.x * yc.x - lm.y * yc.y);
+            const float bi = yc.y + ai - (lm.x * yc.y + lm.y * yc.x);
+            const float2 r = rhat[p];
+            ev = make_float2(r.x - br, r.y - bi);
+            l = (ev.x * ev.x + ev.y * ev.y) / rnorm[b];
+        }
+        e[p] = ev;
+    }
+    __shared__ float red[4];
+    for (int off = 32; off > 0; off >>= 1) l += __shfl_down(l, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = l;
+    __syncthreads();
+    if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// dL/dy = -2 (A - conj(lambda)) e / (B rnorm_b) (A is symmetric), as bf16 into
+// channels 0, 1 of the 16-channel gradient tensor.  Faces to points outside the crop
+// are skipped: e vanishes there and at every unmasked point, so they add nothing.
+__global__ __launch_bounds__(256) void resgrad_kernel(const float2* __restrict__ e, const float* __restrict__ kap,
+                                                      const float2* __restrict__ lam, const float* __restrict__ rnorm,
+                                                      int B, int H, int W, uint16_t* __restrict__ dy16) {
+    const long long npix = static_cast<long long>(B) * H * W;
+    const long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const int x = static_cast<int>(p % W);
+    const int yy = static_cast<int>((p / W) % H);
+    const int b = static_cast<int>(p / (static_cast<long long>(W) * H));
+    const float k0 = kap[p];
+    const float2 ec = e[p];
+    float ar = 0.f, ai = 0.f;
+    const bool ok[4] = {x > 0, x < W - 1, yy > 0, yy < H - 1};
+    const long long nb[4] = {p - 1, p + 1, p - W, p + W};
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+        if (!ok[f]) continue;
+        const float kf = 0.5f * (k0 + kap[nb[f]]);
+        const float2 en = e[nb[f]];
+        ar += kf * (ec.x - en.x);
+        ai += kf * (ec.y - en.y);
+    }
+    const float2 lm = lam[b];  // conj(lambda) e = (lr e.x + li e.y, lr e.y - li e.x)
+    const float gr = ec.x + ar - (lm.x * ec.x + lm.y * ec.y);
+    const float gi = ec.y + ai - (lm.x * ec.y - lm.y * ec.x);
+    const float sc = -2.f / (static_cast<float>(B) * rnorm[b]);
+    uint16_t g[kC];
+#pragma unroll
+    for (int c = 0; c < kC; ++c) g[c] = 0;
+    g[0] = f2bf(sc * gr);
+    g[1] = f2bf(sc * gi);
+    store16(dy16 + p * kC, g);
+}
+
+// ---------------------------------------------------------------------------
 // Adam on the float32 master parameters, then the bf16 forward weights
 // wf[L][t][n][k] = W_L[t][n][k] and backward weights wb[L][t][c][o] = W_L[8 - t][o][c].
 // Parameter vector: [W1 (9x16x16), b1 (16), W2, b2, W3, b3]; entries outside the
@@ -293,24 +376,28 @@ __global__ __launch_bounds__(256) void post_kernel(const CnnPrepArgs a, const fl
     for (int s = 0; s < a.ns; ++s) {
         R* dst = static_cast<R*>(x0buf) + a.soff[s];
         const float* ys = y + (static_cast<long long>(s) * a.n + p) * 2;
-        const float sc = a.scale[s];
+        // x0 = scale * c * y with the per-slot complex factor c
+        const float cr = a.scale[s] * a.fac_re[s], ci = a.scale[s] * a.fac_im[s];
         if (a.is_real[s]) {
-            dst[p] = static_cast<R>(sc * ys[0]);
+            dst[p] = static_cast<R>(cr * ys[0]);
         } else {
-            dst[2 * p] = static_cast<R>(sc * ys[0]);
-            dst[2 * p + 1] = static_cast<R>(sc * ys[1]);
+            dst[2 * p] = static_cast<R>(cr * ys[0] - ci * ys[1]);
+            dst[2 * p + 1] = static_cast<R>(cr * ys[1] + ci * ys[0]);
         }
     }
 }
 
-// Per-slot partial sums of |rhat|^2 and |rhat - (A - lambda) x0|^2 (x0 may be null).
+// Per-slot partial sums, four per slot: |rhat|^2, and with a guess x0 (else zero)
+// |B x0|^2, Re and Im of sum conj(B x0) rhat, where B = A - lambda I.  The residual
+// of c x0 for any complex c follows: |rhat - c B x0|^2 = |rhat|^2 - 2 Re(c conj-dot)
+// + |c|^2 |B x0|^2.
 template <typename R, typename KS>
 __global__ __launch_bounds__(256) void resid_kernel(const CnnPrepArgs a, const void* x0buf, const void* kap,
                                                     double* partial) {
     const Geom g = a.g;
-    double acc[2 * kMaxShift];
+    double acc[4 * kMaxShift];
 #pragma unroll
-    for (int q = 0; q < 2 * kMaxShift; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 4 * kMaxShift; ++q) acc[q] = 0.0;
     const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
     const KS* k = static_cast<const KS*>(kap);
     auto kv = [&](long long i) -> double {
@@ -346,7 +433,7 @@ __global__ __launch_bounds__(256) void resid_kernel(const CnnPrepArgs a, const v
             const R* x0 = x0buf ? static_cast<const R*>(x0buf) + a.soff[s] : nullptr;
             const bool re = a.is_real[s];
             const double rr = re ? rh[p] : rh[2 * p], ri = re ? 0.0 : rh[2 * p + 1];
-            acc[2 * s] += rr * rr + ri * ri;
+            acc[4 * s] += rr * rr + ri * ri;
             if (x0) {
                 const double xr = re ? x0[p] : x0[2 * p], xi = re ? 0.0 : x0[2 * p + 1];
                 const double lr = a.lam_re[s], li = a.lam_im[s];
@@ -355,20 +442,22 @@ __global__ __launch_bounds__(256) void resid_kernel(const CnnPrepArgs a, const v
                     br -= f[d] * (re ? x0[nb[d]] : x0[2 * nb[d]]);
                     bi -= re ? 0.0 : f[d] * x0[2 * nb[d] + 1];
                 }
-                acc[2 * s + 1] += (rr - br) * (rr - br) + (ri - bi) * (ri - bi);
+                acc[4 * s + 1] += br * br + bi * bi;
+                acc[4 * s + 2] += br * rr + bi * ri;
+                acc[4 * s + 3] += br * ri - bi * rr;
             }
         }
     }
-    __shared__ double red[4][2 * kMaxShift];
+    __shared__ double red[4][4 * kMaxShift];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int q = 0; q < 2 * a.ns; ++q) {
+    for (int q = 0; q < 4 * a.ns; ++q) {
         double v = acc[q];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
         if (lane == 0) red[wid][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 2 * a.ns)
-        partial[blockIdx.x * 2 * kMaxShift + threadIdx.x] =
+    if (threadIdx.x < 4 * a.ns)
+        partial[blockIdx.x * 4 * kMaxShift + threadIdx.x] =
             red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
@@ -407,6 +496,20 @@ hipError_t launch_cnn_loss(const float* y, const float* t, const float* tnorm, i
     const int blocks = static_cast<int>((npix + 255) / 256);
     *nblocks = blocks;
     hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, s, y, t, tnorm, B, H, W, border, dy16, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_resloss(const float* y, const float* rhat, const float* kap, const float* lam,
+                              const float* rnorm, int B, int H, int W, int border, float* e, uint16_t* dy16,
+                              float* partial, int* nblocks, hipStream_t s) {
+    const long long npix = static_cast<long long>(B) * H * W;
+    const int blocks = static_cast<int>((npix + 255) / 256);
+    *nblocks = blocks;
+    const float2* lm = reinterpret_cast<const float2*>(lam);
+    float2* e2 = reinterpret_cast<float2*>(e);
+    hipLaunchKernelGGL(resloss_kernel, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const float2*>(y),
+                       reinterpret_cast<const float2*>(rhat), kap, lm, rnorm, B, H, W, border, e2, partial);
+    hipLaunchKernelGGL(resgrad_kernel, dim3(blocks), dim3(256), 0, s, e2, kap, lm, rnorm, B, H, W, dy16);
     return hipGetLastError();
 }
 

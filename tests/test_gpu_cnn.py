@@ -107,6 +107,41 @@ def test_gradient_parity_and_loss():
     assert np.all(g[2 * 2320:2 * 2320 + 2304].reshape(9, 16, 16)[:, 2:, :] == 0)
 
 
+def test_residual_loss_gradient_parity():
+    """Residual-space loss of the crop's shifted operator: loss and every parameter
+    gradient against the oracle (same bf16 error budget as the solution-space loss)."""
+    rng, vec, qp, X = _setup(3, B=3, H=24, W=40)
+    B, H, W = X.shape[:3]
+    R = rng.standard_normal((B, H, W, 2)).astype(np.float32).astype(np.float64)
+    kap = rng.uniform(0.5, 4.0, (B, H, W)).astype(np.float32).astype(np.float64)
+    lam = (rng.uniform(-0.6, 0.6, B) + 1j * rng.uniform(-0.6, 0.6, B)).astype(np.complex64).astype(np.complex128)
+    border = 2
+    mask = ocnn.border_mask(H, W, border)
+    rnorm = np.sum(mask[None] * (R[..., 0] ** 2 + R[..., 1] ** 2), axis=(1, 2))
+    cnn = api.ac_cnn_create(G.ctx())
+    api.ac_cnn_set_params(cnn, vec, 0.0, 1.0)
+    ws = api.workspace(api.ac_cnn_workspace_size(B, H, W))
+    lam2 = np.stack([lam.real, lam.imag], -1).astype(np.float32)
+    loss, g = api.ac_cnn_grad_residual(cnn, bf16_bits(X), G.dev(R.astype(np.float32)), G.dev(kap.astype(np.float32)),
+                                       G.dev(lam2), G.dev(rnorm.astype(np.float32)), border, B, H, W, ws,
+                                       want_grad=True)
+    L_ref, g_ref = ocnn.residual_loss_and_grads(qp, X[..., :5], R, kap, lam, mask)
+    assert abs(loss - L_ref) < 1e-2 * L_ref
+    got = oracle_from_packed(g)
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        assert G.rel(got[k], g_ref[k]) < 5e-2, k
+
+
+def test_residual_loss_rejects_zero_border():
+    B, H, W = 1, 8, 8
+    cnn = api.ac_cnn_create(G.ctx())
+    ws = api.workspace(api.ac_cnn_workspace_size(B, H, W))
+    z = torch.zeros(B * H * W * 16, dtype=torch.int16, device="cuda:0")
+    f = torch.ones(B * H * W * 2, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(api.L.AlphacircError):
+        api.ac_cnn_grad_residual(cnn, z, f, f[: B * H * W], f[:2], f[:1], 0, B, H, W, ws)
+
+
 def test_adam_step_matches_oracle():
     rng, vec, qp, X = _setup(2, B=2, H=16, W=32)
     B, H, W = X.shape[:3]
@@ -146,7 +181,7 @@ def _solve_problem():
 
 @pytest.mark.parametrize("scale", [1.0, 1e4])
 def test_warm_started_solve_and_fallback(scale):
-    """A random network (scale 1) and a corrupted one (scale 1e4, every guess rejected):
+    """A random network (scale 1) and a corrupted one (scale 1e4: every guess rejected):
     the warm-started FGMRES solve still converges to the sequential solution."""
     p, A, b, kap, ell = _solve_problem()
     params = ocnn.init_params(7)
@@ -154,6 +189,7 @@ def test_warm_started_solve_and_fallback(scale):
     cnn = api.ac_cnn_create(G.ctx())
     lk = np.log(kap)
     api.ac_cnn_set_params(cnn, vec, float(lk.mean()), float(lk.std()))
+    api.ac_cnn_set_guess_policy(cnn, False, 1.0)
     api.ac_problem_attach_cnn(p, cnn)
     opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, inner=L.AC_INNER_CHEB_CNN, p=8, tol=1e-10, restart_m=20,
                     max_outer=500)
