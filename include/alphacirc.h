@@ -236,6 +236,25 @@ int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* 
 int ac_solve_record(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws,
                     size_t ws_bytes, ac_solve_info* info, double* rec, int rec_count, int* recorded);
 
+/* ---- batched solves ------------------------------------------------------
+ * Solves count independent systems calA_q x_q = b_q (eq. (1)), each with its own
+ * grid, coefficient field, l and alpha, as ac_solve does one: the FGMRES iterations
+ * of all problems advance in lockstep, every stencil stage runs as one launch per
+ * kernel variant over a work list of all problems' tiles, the per-iteration launch
+ * sequence is captured once into a hipGraph per Arnoldi index and replayed, and a
+ * problem that has converged is masked out of every later launch.  Sweep tiles
+ * follow each problem's tiling (ac_tune_tiling).
+ * Requirements: every problem on ctx, Dirichlet grids, opts shared by all with
+ * inner = AC_INNER_CHEB and p_per_shift = NULL (uniform p_uniform); count <= 256.
+ * b, x: host arrays of count device pointers (x: initial guess in, solution out).
+ * infos: host array of count entries or NULL.  Runs on a stream of its own after
+ * synchronising the context stream (kernel profiling is suspended); synchronises
+ * before returning.  Returns AC_NOT_CONVERGED if any problem reached max_outer. */
+int ac_batch_workspace_size(ac_ctx* ctx, int count, ac_problem* const* problems, const ac_solve_opts* opts,
+                            size_t* bytes);
+int ac_batch_solve(ac_ctx* ctx, int count, ac_problem* const* problems, const ac_solve_opts* opts,
+                   const double* const* b, double* const* x, void* ws, size_t ws_bytes, ac_solve_info* infos);
+
 /* ---- learned warm start (not part of the paper's method) ----------------------
  * A three-layer 3x3 convolutional network (5 -> 16 -> 16 -> 2 channels, ReLU after
  * the first two layers, zero padding), bfloat16 weights/activations with float32

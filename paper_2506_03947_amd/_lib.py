@@ -107,6 +107,9 @@ SIGNATURES = {
     "ac_shifted_cheb": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _VP, _SZ]),
     "ac_tdft_inverse": (_I, [_VP, _I, _VP, _VP]),
     "ac_solve": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _SZ, C.POINTER(ac_solve_info)]),
+    "ac_batch_workspace_size": (_I, [_VP, _I, C.POINTER(_VP), C.POINTER(ac_solve_opts), C.POINTER(_SZ)]),
+    "ac_batch_solve": (_I, [_VP, _I, C.POINTER(_VP), C.POINTER(ac_solve_opts), C.POINTER(_VP), C.POINTER(_VP), _VP,
+                            _SZ, C.POINTER(ac_solve_info)]),
     "ac_solve_record": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _SZ, C.POINTER(ac_solve_info), _VP, _I,
                              C.POINTER(_I)]),
     "ac_cnn_param_count": (_I, []),

@@ -247,6 +247,34 @@ def ac_solve_record(p: Problem, opts: Opts, b: torch.Tensor, x: torch.Tensor, ws
     return _info_dict(st, info), done.value
 
 
+def _handles(items):
+    arr = (C.c_void_p * len(items))()
+    for i, h in enumerate(items):
+        arr[i] = h.value if isinstance(h, C.c_void_p) else h
+    return arr
+
+
+def ac_batch_workspace_size(ctx: Ctx, problems: list, opts: Opts) -> int:
+    o, keep = opts.to_c(problems[0].ell)
+    n = C.c_size_t()
+    check(L.load().ac_batch_workspace_size(ctx.h, len(problems), _handles([p.h for p in problems]), C.byref(o),
+                                           C.byref(n)), "ac_batch_workspace_size")
+    return n.value
+
+
+def ac_batch_solve(ctx: Ctx, problems: list, opts: Opts, bs: list, xs: list, ws: torch.Tensor) -> list[dict]:
+    """Solves every problem (device b, x tensors) in one batched run; returns the
+    per-problem info dicts."""
+    k = len(problems)
+    o, keep = opts.to_c(problems[0].ell)
+    bp = _handles([_f64(b, p.ell * p.n, "b") for b, p in zip(bs, problems)])
+    xp = _handles([_f64(x, p.ell * p.n, "x") for x, p in zip(xs, problems)])
+    infos = (L.ac_solve_info * k)()
+    st = check(L.load().ac_batch_solve(ctx.h, k, _handles([p.h for p in problems]), C.byref(o), bp, xp, _ptr(ws),
+                                       ws.numel(), infos), "ac_batch_solve")
+    return [_info_dict(st, infos[i]) for i in range(k)]
+
+
 def _info_dict(st, info) -> dict:
     return {
         "status": st,

@@ -44,7 +44,7 @@ def common_flags(debug: bool) -> list[str]:
     ]
 
 
-PER_ELL = "stencil_ell.hip"   # compiled once per number of time blocks
+PER_ELL = ("stencil_ell.hip", "stencil_batch_ell.hip")   # compiled once per number of time blocks
 ELLS = range(2, 17)
 
 
@@ -76,7 +76,7 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = True, in
     srcs = sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hip"))
     work = []
     for s in srcs:
-        if os.path.basename(s) == PER_ELL:
+        if os.path.basename(s) in PER_ELL:
             work += [(s, ell) for ell in ELLS]
         else:
             work.append((s, None))

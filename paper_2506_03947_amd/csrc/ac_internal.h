@@ -99,6 +99,30 @@ struct CalAArgs {
     int ell;
 };
 
+// Work list of a batched launch over independent problems: list entry q has
+// arguments args[q] (the launch's own argument struct), owns blocks
+// [first[q], first[q+1]) and belongs to problem pid[q]; live[pid] == 0 skips it and
+// scale[pid] (forward transform only, may be null) multiplies its input.
+struct BatchList {
+    const void* args;
+    const int* first;   // nprob + 1 entries
+    const int* pid;
+    const int* live;
+    const double* scale;
+    int nprob;
+    int blocks;         // first[nprob]
+    int wpb;            // waves per block, equal for every entry
+};
+
+enum BatchOp : int { BOP_FWD = 0, BOP_STEP = 1, BOP_FINAL = 2, BOP_CALA = 3 };
+
+// Grid of the forward transform for n points: vx points per thread, 256 threads.
+inline void fwd_geometry(long long n, int& vx, int& blocks) {
+    vx = (n % 2 == 0) ? 2 : 1;
+    const long long threads = (n + vx - 1) / vx;
+    blocks = static_cast<int>((threads + 255) / 256);
+}
+
 // ---- launchers (stencil.hip) ----------------------------------------------
 // prec: 0 = FP64 (double, kappa double), 1 = float + bf16 kappa, 2 = float + float kappa
 // curk selects the stencil operand (SRC_RHAT: x_1 = rhat/theta, else a buffer);
@@ -108,6 +132,9 @@ hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipS
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);
+// One batched launch of op (BatchOp) for lists whose entries share l, precision,
+// operand kind (sweeps), points per lane and waves per block; Dirichlet grids only.
+hipError_t launch_batch(int op, int ell, int prec, int curk, int vx, const BatchList& L, hipStream_t s);
 
 // ---- Krylov vector kernels (krylov.hip) ------------------------------------
 struct VecSet {

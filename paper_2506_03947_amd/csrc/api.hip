@@ -55,6 +55,13 @@ constexpr double kPi = 3.14159265358979323846;
 // ---------------------------------------------------------------------------
 // opaque types
 
+// One stencil launch captured while a context records (batched driver): the op
+// (ac::BatchOp), its kernel variant, grid and argument bytes.
+struct ac_launch_rec {
+    int op, ell, prec, curk, vx, wpb, blocks;
+    std::vector<char> args;
+};
+
 struct ac_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -73,9 +80,14 @@ struct ac_ctx {
     double bytes[AC_K_COUNT] = {};
     // tiling overrides (0 = automatic): rows per wave, waves per block, points per lane
     int tile_h = 0, tile_wpb = 0, tile_vx = 0;
+    // while set, stencil launch sites append records here instead of launching
+    std::vector<ac_launch_rec>* rec = nullptr;
 };
 
 constexpr int kResidBlocks = 512;  // blocks of the warm-start residual-statistics kernel
+// pinned host staging per context: reductions of up to 256 batched problems plus
+// their per-step scales and masks
+constexpr size_t kPinnedDoubles = 32768;
 
 struct ac_problem {
     ac_ctx* ctx = nullptr;
@@ -90,6 +102,8 @@ struct ac_problem {
     double kmin64 = 0;
     double* rpart = nullptr;   // per-block partial sums of the warm-start residual test
     ac_cnn* cnn = nullptr;     // warm-start network (not owned)
+    // sweep tiling chosen for this problem (0 = the context's setting)
+    int tile_h = 0, tile_wpb = 0, tile_vx = 0;
 };
 
 struct ac_cnn {
@@ -198,7 +212,17 @@ Tiling make_tiling(const ac_problem* p, int vx_pref, int h_pref, int wpb_pref) {
     return t;
 }
 
-Tiling sweep_tiling(const ac_problem* p) { return make_tiling(p, p->ctx->tile_vx, p->ctx->tile_h, p->ctx->tile_wpb); }
+Tiling sweep_tiling(const ac_problem* p) {
+    return make_tiling(p, p->tile_vx ? p->tile_vx : p->ctx->tile_vx, p->tile_h ? p->tile_h : p->ctx->tile_h,
+                       p->tile_wpb ? p->tile_wpb : p->ctx->tile_wpb);
+}
+
+template <class A>
+void record_launch(ac_ctx* c, int op, int ell, int prec, int curk, int vx, int wpb, int blocks, const A& a) {
+    ac_launch_rec r{op, ell, prec, curk, vx, wpb, blocks, std::vector<char>(sizeof(A))};
+    std::memcpy(r.args.data(), &a, sizeof(A));
+    c->rec->push_back(std::move(r));
+}
 
 Tiling calA_tiling(const ac_problem* p) {
     // float64 operand with l blocks per point: one point per lane past l = 8
@@ -315,6 +339,12 @@ int run_fwd(ac_problem* p, int prec, const double* r, char* rhat, double in_scal
     for (int s = 0; s < p->ns; ++s) a.rhat[s] = slot_ptr(p, prec, rhat, s);
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
+    if (p->ctx->rec) {
+        int vx, blocks;
+        ac::fwd_geometry(a.n, vx, blocks);
+        record_launch(p->ctx, ac::BOP_FWD, p->ell, prec, 0, vx, 4, blocks, a);
+        return AC_OK;
+    }
     const double bytes = 8.0 * p->ell * p->g.n + static_cast<double>(off[p->ns]) * inner_elem(prec);
     ProfScope ps(p->ctx, AC_K_TDFT_FWD, bytes);
     AC_HIP(ac::launch_tdft_fwd(p->ell, prec, a, p->ctx->stream));
@@ -407,6 +437,15 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         fill_twiddles(p->ell, a.cw, a.sw);
         a.z = z;
     };
+    auto launch = [&](bool fin, int curk, const ac::SweepArgs<R>& a) -> hipError_t {
+        if (p->ctx->rec) {
+            record_launch(p->ctx, fin ? ac::BOP_FINAL : ac::BOP_STEP, p->ell, prec, curk, a.t.vx, a.t.wpb, a.t.blocks,
+                          a);
+            return hipSuccess;
+        }
+        return fin ? ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream)
+                   : ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream);
+    };
     // consecutive steady-state sweeps share one event pair (no per-launch event cost)
     std::unique_ptr<ProfScope> steady;
     for (int k = k_first; k <= k_last; ++k) {
@@ -443,10 +482,10 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             bytes += 8.0 * p->ell * p->g.n;
             fill_final(a);
             ProfScope ps_(p->ctx, AC_K_CHEB_FINAL, bytes);
-            AC_HIP(ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream));
+            AC_HIP(launch(true, curk, a));
         } else if (curk == ac::SRC_RHAT) {
             ProfScope ps_(p->ctx, AC_K_CHEB_FIRST, bytes);
-            AC_HIP(ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream));
+            AC_HIP(launch(false, curk, a));
         } else {
             if (!steady) {
                 steady = std::make_unique<ProfScope>(p->ctx, AC_K_CHEB_STEP, 0.0);
@@ -454,7 +493,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             }
             steady->bytes += bytes;
             steady->launches += 1;
-            AC_HIP(ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream));
+            AC_HIP(launch(false, curk, a));
         }
         if (steady && (k + 1 > k_last || (fuse && k + 1 == k_last))) steady.reset();
     }
@@ -472,7 +511,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         bytes = bytes * p->g.n + 8.0 * p->ell * p->g.n;
         fill_final(a);
         ProfScope ps_(p->ctx, AC_K_CHEB_FINAL, bytes);
-        AC_HIP(ac::launch_cheb_final(p->ell, prec, ac::SRC_BUF, &a, p->ctx->stream));
+        AC_HIP(launch(true, ac::SRC_BUF, a));
     }
     if (where) {
         where->clear();
@@ -674,6 +713,11 @@ int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double
     a.b = b;
     a.partial = partial;
     a.ell = p->ell;
+    if (p->ctx->rec) {
+        if (b) return fail(AC_ERR_UNSUPPORTED, "residual-mode calA is not recorded");
+        record_launch(p->ctx, ac::BOP_CALA, p->ell, 0, 0, a.t.vx, a.t.wpb, a.t.blocks, a);
+        return AC_OK;
+    }
     const double bytes = (b ? 24.0 : 16.0) * p->ell * p->g.n + 8.0 * p->g.n;
     ProfScope ps(p->ctx, AC_K_APPLY_CALA, bytes);
     AC_HIP(ac::launch_apply_calA(p->ell, b != nullptr, a, p->ctx->stream));
@@ -714,7 +758,7 @@ int ac_ctx_create(int device, void* stream, ac_ctx** out) {
     auto* c = new ac_ctx();
     c->device = device;
     c->stream = static_cast<hipStream_t>(stream);
-    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), 8192 * sizeof(double), hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&c->pinned), kPinnedDoubles * sizeof(double), hipHostMallocDefault);
     if (e != hipSuccess) {
         delete c;
         return fail(AC_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
@@ -1273,6 +1317,421 @@ int ac_solve_record(ac_problem* p, const ac_solve_opts* o, const double* b, doub
     if (!rec || rec_count < 1 || !recorded) return fail(AC_ERR_ARG, "record buffer, count and counter are required");
     *recorded = 0;
     return solve_impl(p, o, b, x, ws, ws_bytes, info, rec, rec_count, recorded);
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves: many independent problems (uneven grids and l) advance their
+// FGMRES iterations in lockstep.  Per Arnoldi index j the preconditioner and the
+// calA product of every problem are recorded once as launch records, aligned
+// records are grouped by kernel variant into work lists, and each j's sequence of
+// batched launches is captured into a hipGraph that every later cycle replays.  The
+// per-step input scales and the convergence mask live in device memory and are
+// updated before each replay.  Krylov kernels run per problem, but every problem's
+// reductions are fetched with one synchronisation per phase.
+
+namespace {
+
+constexpr int kMaxBatch = 256;
+constexpr int kFetchStride = 2 * ac::kMaxBasis + 2;  // pinned doubles per problem per fetch
+
+struct BatchLaunch {
+    int op, ell, prec, curk, vx;
+    ac::BatchList list;
+};
+
+size_t max_args_bytes() {
+    return std::max(std::max(sizeof(ac::SweepArgs<double>), sizeof(ac::SweepArgs<float>)),
+                    std::max(sizeof(ac::FwdArgs), sizeof(ac::CalAArgs)));
+}
+
+// Device bytes for the work lists: per j at most p + 3 launch positions, each with
+// at most `count` groups.
+size_t batch_list_bytes(int count, const ac_solve_opts* o) {
+    const size_t per_pos = static_cast<size_t>(count) * (align_up(max_args_bytes(), 16) + 8) +
+                           static_cast<size_t>(count) * (3 * 256 + 8);
+    return static_cast<size_t>(o->restart_m) * static_cast<size_t>(o->p_uniform + 3) * per_pos + 256;
+}
+
+size_t batch_ws_bytes(int count, ac_problem* const* probs, const ac_solve_opts* o) {
+    size_t b = batch_list_bytes(count, o) + align_up(static_cast<size_t>(count) * 12, 256) + 256;
+    for (int q = 0; q < count; ++q) b += align_up(solve_ws_bytes(probs[q], o), 256);
+    return b;
+}
+
+int validate_batch(ac_ctx* c, int count, ac_problem* const* probs, const ac_solve_opts* o) {
+    if (!c || !probs || !o) return fail(AC_ERR_ARG, "NULL argument");
+    if (count < 1 || count > kMaxBatch) return fail(AC_ERR_UNSUPPORTED, "batch size must be in [1, 256]");
+    if (o->inner != AC_INNER_CHEB) return fail(AC_ERR_UNSUPPORTED, "batched solves use the plain inner solver");
+    if (o->p_per_shift) return fail(AC_ERR_UNSUPPORTED, "batched solves take a uniform inner count (p_uniform)");
+    if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
+    if (!(o->tol > 0.0)) return fail(AC_ERR_ARG, "tol must be positive");
+    if (o->max_outer < 1) return fail(AC_ERR_ARG, "max_outer must be >= 1");
+    for (int q = 0; q < count; ++q) {
+        if (!probs[q]) return fail(AC_ERR_ARG, "NULL problem");
+        if (probs[q]->ctx != c) return fail(AC_ERR_ARG, "every problem must belong to the context");
+        if (probs[q]->g.periodic) return fail(AC_ERR_UNSUPPORTED, "batched solves take Dirichlet grids");
+        std::vector<int> pm;
+        AC_TRY(validate_opts(probs[q], o, pm));
+    }
+    return AC_OK;
+}
+
+struct BatchState {
+    ac_problem* p;
+    SolveWs w;
+    std::vector<int> pm;
+    long long len = 0, psum = 0, matvecs = 0;
+    double bnorm = 0, beta = 0, orth = 0;
+    int total = 0, restarts = 0, kdone = 0, status = AC_OK;
+    bool finished = false, in_cycle = false;
+    std::vector<double> H, cs, sn, g, scale, y, Lg, hcol;
+};
+
+// Restores the context and frees the graphs and the capture stream on every exit path.
+struct BatchGuard {
+    ac_ctx* c;
+    hipStream_t user, own = nullptr;
+    bool prof;
+    std::vector<hipGraphExec_t> execs;
+    ~BatchGuard() {
+        c->rec = nullptr;
+        if (own) (void)hipStreamSynchronize(own);
+        for (auto e : execs)
+            if (e) (void)hipGraphExecDestroy(e);
+        if (own) (void)hipStreamDestroy(own);
+        c->stream = user;
+        c->profiling = prof;
+    }
+};
+
+}  // namespace
+
+int ac_batch_workspace_size(ac_ctx* c, int count, ac_problem* const* probs, const ac_solve_opts* o,
+                            size_t* bytes) {
+    if (!bytes) return fail(AC_ERR_ARG, "NULL argument");
+    AC_TRY(validate_batch(c, count, probs, o));
+    *bytes = batch_ws_bytes(count, probs, o);
+    return AC_OK;
+}
+
+int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solve_opts* o, const double* const* b,
+                   double* const* x, void* ws, size_t ws_bytes, ac_solve_info* infos) {
+    const auto t0 = std::chrono::steady_clock::now();
+    AC_TRY(validate_batch(c, count, probs, o));
+    if (!b || !x) return fail(AC_ERR_ARG, "NULL argument");
+    for (int q = 0; q < count; ++q)
+        if (!b[q] || !x[q]) return fail(AC_ERR_ARG, "NULL right-hand side or solution");
+    if (!ws || ws_bytes < batch_ws_bytes(count, probs, o)) return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(c->device));
+    const int m = o->restart_m;
+    // The legacy default stream cannot be captured: work on a stream of our own.
+    AC_HIP(hipStreamSynchronize(c->stream));
+    BatchGuard guard{c, c->stream, nullptr, c->profiling, std::vector<hipGraphExec_t>(m, nullptr)};
+    AC_HIP(hipStreamCreateWithFlags(&guard.own, hipStreamNonBlocking));
+    hipStream_t st = guard.own;
+    c->stream = st;
+    c->profiling = false;
+
+    // workspace: [lists][scale doubles | live ints][per-problem solve workspaces]
+    char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
+    char* lists = base;
+    const size_t list_cap = batch_list_bytes(count, o);
+    double* dscale = reinterpret_cast<double*>(base + align_up(list_cap, 256));
+    int* dlive = reinterpret_cast<int*>(dscale + count);
+    char* pw = base + align_up(list_cap, 256) + align_up(static_cast<size_t>(count) * 12, 256);
+    std::vector<BatchState> S(count);
+    for (int q = 0; q < count; ++q) {
+        BatchState& s = S[q];
+        s.p = probs[q];
+        AC_TRY(validate_opts(s.p, o, s.pm));
+        s.w = carve_solve(s.p, o, pw);
+        pw += align_up(solve_ws_bytes(s.p, o), 256);
+        s.len = static_cast<long long>(s.p->ell) * s.p->g.n;
+        for (int v : s.pm) s.psum += v;
+        s.H.assign((m + 1) * m, 0.0);
+        s.cs.assign(m, 0.0);
+        s.sn.assign(m, 0.0);
+        s.g.assign(m + 1, 0.0);
+        s.scale.assign(m + 1, 0.0);
+        s.y.assign(m, 0.0);
+        s.Lg.assign(m * m, 0.0);
+        s.hcol.assign(m + 1, 0.0);
+    }
+
+    // record every problem's launches for each j and group aligned records
+    std::vector<std::vector<BatchLaunch>> plan(m);
+    std::vector<char> host(list_cap, 0);
+    size_t used = 0;
+    auto take = [&](size_t bytes, size_t align) -> size_t {
+        used = align_up(used, align);
+        const size_t off = used;
+        used += bytes;
+        return off;
+    };
+    struct Pending {
+        BatchLaunch l;
+        size_t args_off, first_off, pid_off;
+    };
+    std::vector<std::vector<Pending>> pend(m);
+    for (int j = 0; j < m; ++j) {
+        std::vector<std::vector<ac_launch_rec>> recs(count);
+        for (int q = 0; q < count; ++q) {
+            BatchState& s = S[q];
+            c->rec = &recs[q];
+            const int e1 = apply_prec_impl(s.p, o, s.pm, s.w.V[j], s.w.Z[j], s.w.prec, 1.0);
+            const int e2 = e1 < 0 ? e1 : calA_impl(s.p, s.w.Z[j], s.w.V[j + 1], nullptr, nullptr);
+            c->rec = nullptr;
+            if (e2 < 0) return e2;
+            if (recs[q].size() != recs[0].size()) return fail(AC_ERR_UNSUPPORTED, "batch launch sequences differ");
+        }
+        const size_t npos = recs[0].size();
+        for (size_t i = 0; i < npos; ++i) {
+            std::vector<int> done(count, 0);
+            for (int q0 = 0; q0 < count; ++q0) {
+                if (done[q0]) continue;
+                const ac_launch_rec& r0 = recs[q0][i];
+                std::vector<int> members;
+                for (int q = q0; q < count; ++q) {
+                    const ac_launch_rec& r = recs[q][i];
+                    if (r.op != r0.op) return fail(AC_ERR_UNSUPPORTED, "batch launch sequences differ");
+                    if (!done[q] && r.ell == r0.ell && r.prec == r0.prec && r.curk == r0.curk && r.vx == r0.vx &&
+                        r.wpb == r0.wpb) {
+                        members.push_back(q);
+                        done[q] = 1;
+                    }
+                }
+                const size_t asz = r0.args.size();
+                Pending pg{};
+                pg.l = BatchLaunch{r0.op, r0.ell, r0.prec, r0.curk, r0.vx, ac::BatchList{}};
+                const int n = static_cast<int>(members.size());
+                pg.args_off = take(asz * n, 256);
+                pg.first_off = take(sizeof(int) * (n + 1), 16);
+                pg.pid_off = take(sizeof(int) * n, 16);
+                if (used > list_cap) return fail(AC_ERR_WORKSPACE, "batch work lists exceed their bound");
+                int* first = reinterpret_cast<int*>(host.data() + pg.first_off);
+                int* pid = reinterpret_cast<int*>(host.data() + pg.pid_off);
+                int blocks = 0;
+                for (int k = 0; k < n; ++k) {
+                    const ac_launch_rec& r = recs[members[k]][i];
+                    std::memcpy(host.data() + pg.args_off + asz * k, r.args.data(), asz);
+                    first[k] = blocks;
+                    pid[k] = members[k];
+                    blocks += r.blocks;
+                }
+                first[n] = blocks;
+                pg.l.list.nprob = n;
+                pg.l.list.blocks = blocks;
+                pg.l.list.wpb = r0.wpb;
+                pend[j].push_back(pg);
+            }
+        }
+    }
+    AC_HIP(hipMemcpyAsync(lists, host.data(), used, hipMemcpyHostToDevice, st));
+    for (int j = 0; j < m; ++j)
+        for (auto& pg : pend[j]) {
+            BatchLaunch l = pg.l;
+            l.list.args = lists + pg.args_off;
+            l.list.first = reinterpret_cast<const int*>(lists + pg.first_off);
+            l.list.pid = reinterpret_cast<const int*>(lists + pg.pid_off);
+            l.list.live = dlive;
+            l.list.scale = l.op == ac::BOP_FWD ? dscale : nullptr;
+            plan[j].push_back(l);
+        }
+
+    // host staging for the scales and the mask (pinned, after the fetch area)
+    double* hscale = c->pinned + static_cast<size_t>(kMaxBatch) * kFetchStride;
+    int* hlive = reinterpret_cast<int*>(hscale + count);
+    auto fetch = [&](const std::vector<int>& qs, int nq) -> int {
+        for (int q : qs)
+            AC_HIP(hipMemcpyAsync(c->pinned + static_cast<size_t>(q) * kFetchStride, S[q].w.red,
+                                  nq * sizeof(double), hipMemcpyDeviceToHost, st));
+        AC_HIP(hipStreamSynchronize(st));
+        return AC_OK;
+    };
+    auto fetched = [&](int q) { return c->pinned + static_cast<size_t>(q) * kFetchStride; };
+    auto residuals = [&](const std::vector<int>& qs) -> int {
+        for (int q : qs) {
+            BatchState& s = S[q];
+            AC_TRY(calA_impl(s.p, x[q], s.w.V[0], b[q], s.w.partial2));
+            AC_HIP(ac::launch_reduce(s.w.partial2, static_cast<int>(calA_partials(s.p)), 1, 1, s.w.red, st));
+            s.matvecs += s.p->ell;
+        }
+        AC_TRY(fetch(qs, 1));
+        for (int q : qs) S[q].beta = std::sqrt(fetched(q)[0]);
+        return AC_OK;
+    };
+    const int kb = ac::krylov_blocks();
+
+    // ||b|| and the first residuals
+    std::vector<int> all(count);
+    for (int q = 0; q < count; ++q) {
+        all[q] = q;
+        AC_HIP(ac::launch_norm2(b[q], S[q].len, S[q].w.partial, st));
+        AC_HIP(ac::launch_reduce(S[q].w.partial, kb, 1, 1, S[q].w.red, st));
+    }
+    AC_TRY(fetch(all, 1));
+    std::vector<int> live_q;
+    for (int q = 0; q < count; ++q) {
+        S[q].bnorm = std::sqrt(fetched(q)[0]);
+        if (!std::isfinite(S[q].bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
+        if (S[q].bnorm == 0.0) {
+            hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((S[q].len + 255) / 256)), dim3(256), 0, st, x[q],
+                               S[q].len);
+            AC_HIP(hipGetLastError());
+            S[q].finished = true;
+        } else {
+            live_q.push_back(q);
+        }
+    }
+    AC_TRY(residuals(live_q));
+
+    while (true) {
+        // cycle start
+        std::vector<int> cyc;
+        for (int q = 0; q < count; ++q) {
+            BatchState& s = S[q];
+            s.in_cycle = false;
+            if (s.finished) continue;
+            if (!std::isfinite(s.beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
+            if (s.beta / s.bnorm <= o->tol) {
+                s.finished = true;
+                continue;
+            }
+            if (s.total >= o->max_outer) {
+                s.finished = true;
+                s.status = AC_NOT_CONVERGED;
+                continue;
+            }
+            s.in_cycle = true;
+            std::fill(s.H.begin(), s.H.end(), 0.0);
+            std::fill(s.g.begin(), s.g.end(), 0.0);
+            s.g[0] = s.beta;
+            s.scale[0] = 1.0 / s.beta;
+            s.kdone = 0;
+            cyc.push_back(q);
+        }
+        if (cyc.empty()) break;
+        for (int j = 0; j < m; ++j) {
+            std::vector<int> act;
+            for (int q = 0; q < count; ++q) {
+                hlive[q] = S[q].in_cycle ? 1 : 0;
+                hscale[q] = S[q].in_cycle ? S[q].scale[j] : 0.0;
+                if (S[q].in_cycle) act.push_back(q);
+            }
+            if (act.empty()) break;
+            AC_HIP(hipMemcpyAsync(dscale, hscale, static_cast<size_t>(count) * 12, hipMemcpyHostToDevice, st));
+            if (!guard.execs[j]) {
+                AC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                hipError_t le = hipSuccess;
+                for (const BatchLaunch& l : plan[j]) {
+                    le = ac::launch_batch(l.op, l.ell, l.prec, l.curk, l.vx, l.list, st);
+                    if (le != hipSuccess) break;
+                }
+                hipGraph_t graph = nullptr;
+                const hipError_t ee = hipStreamEndCapture(st, &graph);
+                if (le != hipSuccess || ee != hipSuccess) {
+                    if (graph) (void)hipGraphDestroy(graph);
+                    return fail(AC_ERR_HIP, std::string("batch graph capture: ") +
+                                                hipGetErrorString(le != hipSuccess ? le : ee));
+                }
+                const hipError_t ie = hipGraphInstantiate(&guard.execs[j], graph, nullptr, nullptr, 0);
+                (void)hipGraphDestroy(graph);
+                if (ie != hipSuccess) return fail(AC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            }
+            AC_HIP(hipGraphLaunch(guard.execs[j], st));
+            // Arnoldi: one-reduce modified Gram-Schmidt, as in ac_solve
+            const int nv = j + 1;
+            for (int q : act) {
+                BatchState& s = S[q];
+                s.matvecs += s.p->ell + s.psum;
+                AC_HIP(ac::launch_mdot_strided(s.w.V[0], static_cast<long long>(vec_bytes(s.p) / sizeof(double)), nv,
+                                               j >= 1, s.w.V[j + 1], s.len, s.w.partial, 72, st));
+                AC_HIP(ac::launch_reduce(s.w.partial, kb, j >= 1 ? 2 * nv : nv + 1, 72, s.w.red, st));
+            }
+            AC_TRY(fetch(act, 2 * nv + 1));
+            std::vector<ac::VecSet> vsets(count);
+            for (int q : act) {
+                BatchState& s = S[q];
+                const double* hd = fetched(q);
+                ac::VecSet& vs = vsets[q];
+                for (int i = 0; i <= j; ++i) vs.v[i] = s.w.V[i];
+                for (int i = 0; i < j; ++i) {
+                    s.Lg[j * m + i] = s.scale[i] * s.scale[j] * hd[nv + 1 + i];
+                    s.orth = std::max(s.orth, std::abs(s.Lg[j * m + i]));
+                }
+                for (int i = 0; i <= j; ++i) {
+                    double hi = s.scale[i] * hd[i];
+                    for (int k = 0; k < i; ++k) hi -= s.Lg[i * m + k] * s.hcol[k];
+                    s.hcol[i] = hi;
+                    s.H[i * m + j] = hi;
+                    vs.s2[i] = s.scale[i] * hi;
+                }
+                AC_HIP(ac::launch_axpy_norm(vs, nv, nullptr, s.w.V[j + 1], s.len, s.w.partial, 72, st));
+                AC_HIP(ac::launch_reduce(s.w.partial, kb, 1, 72, s.w.red, st));
+            }
+            AC_TRY(fetch(act, 1));
+            for (int q : act) {
+                BatchState& s = S[q];
+                const double hn = std::sqrt(fetched(q)[0]);
+                if (!std::isfinite(hn)) return fail(AC_ERR_NONFINITE, "Arnoldi produced a non-finite value");
+                double* H = s.H.data();
+                H[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    const double t = s.cs[i] * H[i * m + j] + s.sn[i] * H[(i + 1) * m + j];
+                    H[(i + 1) * m + j] = -s.sn[i] * H[i * m + j] + s.cs[i] * H[(i + 1) * m + j];
+                    H[i * m + j] = t;
+                }
+                const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
+                s.cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
+                s.sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
+                H[j * m + j] = den;
+                H[(j + 1) * m + j] = 0.0;
+                s.g[j + 1] = -s.sn[j] * s.g[j];
+                s.g[j] = s.cs[j] * s.g[j];
+                ++s.total;
+                s.kdone = j + 1;
+                if (std::abs(s.g[j + 1]) / s.bnorm <= o->tol || s.total >= o->max_outer || hn == 0.0)
+                    s.in_cycle = false;  // masked for the rest of this cycle
+                else
+                    s.scale[j + 1] = 1.0 / hn;
+            }
+        }
+        // x += Z y for every problem of the cycle, then the true residuals
+        for (int q : cyc) {
+            BatchState& s = S[q];
+            const int kd = s.kdone;
+            for (int i = kd - 1; i >= 0; --i) {
+                double t = s.g[i];
+                for (int k = i + 1; k < kd; ++k) t -= s.H[i * m + k] * s.y[k];
+                s.y[i] = s.H[i * m + i] != 0.0 ? t / s.H[i * m + i] : 0.0;
+            }
+            ac::VecSet zs{};
+            for (int i = 0; i < kd; ++i) {
+                zs.v[i] = s.w.Z[i];
+                zs.s2[i] = s.y[i];
+            }
+            AC_HIP(ac::launch_maxpy(zs, kd, nullptr, x[q], s.len, st));
+            ++s.restarts;
+        }
+        AC_TRY(residuals(cyc));
+    }
+    AC_HIP(hipStreamSynchronize(st));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = AC_OK;
+    for (int q = 0; q < count; ++q) {
+        const BatchState& s = S[q];
+        if (s.status == AC_NOT_CONVERGED) worst = AC_NOT_CONVERGED;
+        if (!infos) continue;
+        ac_solve_info& in = infos[q];
+        in = ac_solve_info{};
+        in.outer_iters = s.total;
+        in.restarts = s.restarts;
+        in.matvecs_A = s.matvecs;
+        in.rel_residual_true = s.bnorm > 0 ? s.beta / s.bnorm : 0.0;
+        in.seconds = secs;
+        in.orth_loss = s.orth;
+    }
+    return worst;
 }
 
 // ---------------------------------------------------------------------------

@@ -51,9 +51,8 @@ hipError_t AC_CAT(sweep_ell_, AC_ELL)(bool final, int prec, int vx, int curk, co
 
 hipError_t AC_CAT(fwd_ell_, AC_ELL)(int prec, const FwdArgs& a, hipStream_t s) {
     constexpr int ELL = AC_ELL;
-    const int vx = (a.n % 2 == 0) ? 2 : 1;
-    const long long threads = (a.n + vx - 1) / vx;
-    const int blocks = static_cast<int>((threads + 255) / 256);
+    int vx, blocks;
+    fwd_geometry(a.n, vx, blocks);
     if (prec == 0) {
         if (vx == 2) hipLaunchKernelGGL((tdft_fwd_kernel<double, ELL, 2>), dim3(blocks), dim3(256), 0, s, a);
         else hipLaunchKernelGGL((tdft_fwd_kernel<double, ELL, 1>), dim3(blocks), dim3(256), 0, s, a);

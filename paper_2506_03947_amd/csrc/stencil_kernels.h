@@ -124,10 +124,8 @@ __device__ __forceinline__ float shfl_dn1(float v) { return __shfl_down(v, 1, kW
 __device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, kWave); }
 __device__ __forceinline__ double shfl_dn1(double v) { return __shfl_down(v, 1, kWave); }
 
-// XCD-aware tile index of the calling wave; -1 if the wave has no tile.
-__device__ __forceinline__ long long tile_of_wave(const Tiling& t) {
-    const int nb = gridDim.x;
-    const int bid = blockIdx.x;
+// XCD-aware tile index of the calling wave (block bid of nb); -1 if the wave has no tile.
+__device__ __forceinline__ long long tile_of_wave(const Tiling& t, int bid, int nb) {
     const int per = nb >> 3;
     const int full = per << 3;
     const int b2 = (bid < full) ? (bid & 7) * per + (bid >> 3) : bid;
@@ -273,14 +271,14 @@ __device__ __forceinline__ Faces<K> faces(const Geom& g, int px, int py, K kc, K
 // few uniform base pointers.
 
 template <typename R, typename KS, int ELL, int VX, bool CUR_RHAT, bool FINAL, bool PER>
-__global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
+__device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, int nb) {
     constexpr int NSR = (ELL % 2 == 0) ? 2 : 1;
     constexpr int NSC = (ELL - NSR) / 2;
     constexpr int NSCA = NSC > 0 ? NSC : 1;  // array extent (l = 2 has no complex shift)
     constexpr int NS = NSR + NSC;
     using K = R;
 
-    const long long tile = tile_of_wave(a.t);
+    const long long tile = tile_of_wave(a.t, bid, nb);
     if (tile < 0) return;
     const int nx = a.g.nx, ny = a.g.ny;
     const int lane = threadIdx.x & (kWave - 1);
@@ -561,25 +559,30 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
     }
 }
 
+template <typename R, typename KS, int ELL, int VX, bool CUR_RHAT, bool FINAL, bool PER>
+__global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
+    cheb_sweep_body<R, KS, ELL, VX, CUR_RHAT, FINAL, PER>(a, blockIdx.x, gridDim.x);
+}
+
 // ---------------------------------------------------------------------------
 // Forward scaled time-DFT: per grid point, t_k = gam_k r_k and
 // rhat_m = sum_k t_k exp(-2 pi i m k / l) for the l_s unique m, in float64,
 // stored in the inner real type.
 
 template <typename R, int ELL, int VX>
-__global__ __launch_bounds__(256) void tdft_fwd_kernel(const FwdArgs a) {
+__device__ __forceinline__ void tdft_fwd_body(const FwdArgs& a, int bid, double mul) {
     constexpr int NSR = (ELL % 2 == 0) ? 2 : 1;
     constexpr int NSC = (ELL - NSR) / 2;
-    constexpr int NSCA = NSC > 0 ? NSC : 1;  // array extent (l = 2 has no complex shift)
-    const long long i0 = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) * VX;
+    const long long i0 = (static_cast<long long>(bid) * blockDim.x + threadIdx.x) * VX;
     if (i0 >= a.n) return;
     double t[ELL][VX];
 #pragma unroll
     for (int k = 0; k < ELL; ++k) {
         double v[VX];
         ldv<double, VX>(a.r + static_cast<long long>(k) * a.n + i0, v);
+        const double gk = a.gam[k] * mul;
 #pragma unroll
-        for (int x = 0; x < VX; ++x) t[k][x] = a.gam[k] * v[x];
+        for (int x = 0; x < VX; ++x) t[k][x] = gk * v[x];
     }
     // real slots
     {
@@ -616,6 +619,11 @@ __global__ __launch_bounds__(256) void tdft_fwd_kernel(const FwdArgs a) {
         }
         stv<R, 2 * VX>(static_cast<R*>(a.rhat[NSR + c]) + 2 * i0, o);
     }
+}
+
+template <typename R, int ELL, int VX>
+__global__ __launch_bounds__(256) void tdft_fwd_kernel(const FwdArgs a) {
+    tdft_fwd_body<R, ELL, VX>(a, blockIdx.x, 1.0);
 }
 
 // Inverse scaled time-DFT (standalone stage).
@@ -668,8 +676,8 @@ __global__ __launch_bounds__(256) void tdft_inv_kernel(const InvArgs a) {
 // residual mode y = b - calA x together with per-tile sums of y^2.
 
 template <int ELL, int VX, bool RESID>
-__global__ __launch_bounds__(256) void apply_calA_kernel(const CalAArgs a) {
-    const long long tile = tile_of_wave(a.t);
+__device__ __forceinline__ void apply_calA_body(const CalAArgs& a, int bid, int nb) {
+    const long long tile = tile_of_wave(a.t, bid, nb);
     const int lane = threadIdx.x & (kWave - 1);
     double ssq = 0.0;
     if (tile >= 0) {
@@ -757,6 +765,51 @@ __global__ __launch_bounds__(256) void apply_calA_kernel(const CalAArgs a) {
         for (int off = kWave / 2; off > 0; off >>= 1) ssq += __shfl_down(ssq, off, kWave);
         if (lane == 0 && tile >= 0) a.partial[tile] = ssq;
     }
+}
+
+template <int ELL, int VX, bool RESID>
+__global__ __launch_bounds__(256) void apply_calA_kernel(const CalAArgs a) {
+    apply_calA_body<ELL, VX, RESID>(a, blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Batched launches over a work list of independent problems (uneven grids): problem
+// q owns blocks [first[q], first[q+1]) and its arguments are args[q]; a problem whose
+// live flag is zero returns at once (convergence mask).  The block-to-problem search
+// is uniform across the block.
+__device__ __forceinline__ int batch_problem(const BatchList& L, int bid) {
+    int lo = 0, hi = L.nprob - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (L.first[mid] <= bid) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <typename R, typename KS, int ELL, int VX, bool CUR_RHAT, bool FINAL>
+__global__ __launch_bounds__(256) void cheb_sweep_batch_kernel(const BatchList L) {
+    const int q = batch_problem(L, blockIdx.x);
+    if (!L.live[L.pid[q]]) return;
+    const SweepArgs<R> a = static_cast<const SweepArgs<R>*>(L.args)[q];
+    cheb_sweep_body<R, KS, ELL, VX, CUR_RHAT, FINAL, false>(a, blockIdx.x - L.first[q], L.first[q + 1] - L.first[q]);
+}
+
+template <typename R, int ELL, int VX>
+__global__ __launch_bounds__(256) void tdft_fwd_batch_kernel(const BatchList L) {
+    const int q = batch_problem(L, blockIdx.x);
+    const int pid = L.pid[q];
+    if (!L.live[pid]) return;
+    const FwdArgs a = static_cast<const FwdArgs*>(L.args)[q];
+    tdft_fwd_body<R, ELL, VX>(a, blockIdx.x - L.first[q], L.scale ? L.scale[pid] : 1.0);
+}
+
+template <int ELL, int VX>
+__global__ __launch_bounds__(256) void apply_calA_batch_kernel(const BatchList L) {
+    const int q = batch_problem(L, blockIdx.x);
+    if (!L.live[L.pid[q]]) return;
+    const CalAArgs a = static_cast<const CalAArgs*>(L.args)[q];
+    apply_calA_body<ELL, VX, false>(a, blockIdx.x - L.first[q], L.first[q + 1] - L.first[q]);
 }
 
 }  // namespace
