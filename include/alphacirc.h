@@ -236,6 +236,23 @@ int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* 
 int ac_solve_record(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws,
                     size_t ws_bytes, ac_solve_info* info, double* rec, int rec_count, int* recorded);
 
+/* ---- tiling ----------------------------------------------------------------
+ * Sweep tiling of one problem (overrides the context's ac_ctx_set_tiling; 0 keeps
+ * the context's value): rows per wave, waves per block (1..4), points per lane
+ * (1 or 2; 1 is forced for odd or narrow grids). */
+int ac_problem_set_tiling(ac_problem* p, int rows_per_wave, int waves_per_block, int points_per_lane);
+/* Tile tuner: times the shifted Chebyshev sweeps of p at the given precision for
+ * candidate tilings (points per lane 1 and 2, 4..64 rows per wave, 1, 2 or 4 waves
+ * per block), keeps the fastest for p (single and batched solves), and, when
+ * cache_path is not NULL, records it in that JSON file keyed by (nx, ny, l,
+ * precision); an entry already there is applied without timing.  ws: a device
+ * workspace of ac_prec_workspace_size bytes for the plain inner solver (its contents
+ * are overwritten).  out (host, 3 ints, may be NULL): rows per wave, waves per block,
+ * points per lane; us (may be NULL): time per sweep in microseconds (0 when taken
+ * from the cache).  Synchronises. */
+int ac_tune_tiling(ac_problem* p, int precision, const char* cache_path, void* ws, size_t ws_bytes, int* out,
+                   double* us);
+
 /* ---- batched solves ------------------------------------------------------
  * Solves count independent systems calA_q x_q = b_q (eq. (1)), each with its own
  * grid, coefficient field, l and alpha, as ac_solve does one: the FGMRES iterations

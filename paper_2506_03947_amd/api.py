@@ -254,6 +254,22 @@ def _handles(items):
     return arr
 
 
+def ac_problem_set_tiling(p: Problem, rows_per_wave: int = 0, waves_per_block: int = 0,
+                          points_per_lane: int = 0) -> None:
+    check(L.load().ac_problem_set_tiling(p.h, rows_per_wave, waves_per_block, points_per_lane),
+          "ac_problem_set_tiling")
+
+
+def ac_tune_tiling(p: Problem, precision: int, ws: torch.Tensor, cache_path: str | None = None) -> tuple[list, float]:
+    """Tunes p's sweep tiling; returns ([rows per wave, waves per block, points per
+    lane], microseconds per sweep or 0.0 when read from the cache)."""
+    out = (C.c_int * 3)()
+    us = C.c_double()
+    check(L.load().ac_tune_tiling(p.h, precision, cache_path.encode() if cache_path else None, _ptr(ws), ws.numel(),
+                                  out, C.byref(us)), "ac_tune_tiling")
+    return list(out), us.value
+
+
 def ac_batch_workspace_size(ctx: Ctx, problems: list, opts: Opts) -> int:
     o, keep = opts.to_c(problems[0].ell)
     n = C.c_size_t()
