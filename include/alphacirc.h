@@ -90,6 +90,14 @@ typedef struct {
     double mu_hi;  /* upper end */
 } ac_bounds;
 
+/* Outer iteration of ac_solve:
+ *   AC_OUTER_FGMRES     right-preconditioned flexible GMRES(restart_m);
+ *   AC_OUTER_CHEBYSHEV  the paper's outer solver: Chebyshev semi-iteration on
+ *                       P^{-1} calA with the eigenvalue interval of Corollary 1,
+ *                       [1, mu_lo^l / (mu_lo^l - alpha)], mu_lo the lower spectral bound
+ *                       of A; valid for a linear preconditioner (AC_INNER_CHEB). */
+typedef enum { AC_OUTER_FGMRES = 0, AC_OUTER_CHEBYSHEV = 1 } ac_outer;
+
 typedef struct {
     int precision;           /* ac_precision */
     int inner;               /* ac_inner */
@@ -97,9 +105,9 @@ typedef struct {
                                 entries must be equal), or NULL to use p_uniform */
     int p_uniform;           /* inner Chebyshev steps per shift when p_per_shift == NULL */
     double tol;              /* ac_solve: stop when ||b - calA x||_2 / ||b||_2 <= tol */
-    int restart_m;           /* ac_solve: FGMRES restart length, 1..32 */
-    int max_outer;           /* ac_solve: maximum total FGMRES iterations */
-    int reserved;            /* set to 0 */
+    int restart_m;           /* ac_solve: FGMRES restart length, 1..32 (also >= 1 for Chebyshev) */
+    int max_outer;           /* ac_solve: maximum total outer iterations */
+    int outer;               /* ac_outer (0 = FGMRES) */
 } ac_solve_opts;
 
 typedef struct {

@@ -31,6 +31,8 @@ AC_PREC_MIXED_FP32K = 2
 
 AC_INNER_CHEB = 0
 AC_INNER_CHEB_CNN = 1
+AC_OUTER_FGMRES = 0
+AC_OUTER_CHEBYSHEV = 1
 
 AC_K_TDFT_FWD = 0
 AC_K_CHEB_STEP = 1
@@ -60,7 +62,7 @@ class ac_solve_opts(C.Structure):
         ("tol", C.c_double),
         ("restart_m", C.c_int),
         ("max_outer", C.c_int),
-        ("reserved", C.c_int),
+        ("outer", C.c_int),
     ]
 
 

@@ -66,6 +66,7 @@ class Opts:
     tol: float = 1e-8
     restart_m: int = 30
     max_outer: int = 500
+    outer: int = L.AC_OUTER_FGMRES
 
     def to_c(self, ell: int):
         o = L.ac_solve_opts()
@@ -83,7 +84,7 @@ class Opts:
         o.tol = float(self.tol)
         o.restart_m = int(self.restart_m)
         o.max_outer = int(self.max_outer)
-        o.reserved = 0
+        o.outer = int(self.outer)
         return o, keep
 
 

@@ -156,6 +156,9 @@ hipError_t launch_axpy_norm(const VecSet& V, int nv, const double* dcoef, double
 hipError_t launch_maxpy(const VecSet& Z, int nv, const double* coef_host_scaled, double* x, long long len,
                         hipStream_t s);
 hipError_t launch_norm2(const double* w, long long len, double* partial, hipStream_t s);
+// x = x + (d = a d + c z)
+hipError_t launch_cheb_update(double* x, double* d, const double* z, double a, double c, long long len,
+                              hipStream_t s);
 hipError_t launch_reduce(const double* partial, int nblk, int nq, int nq_stride, double* out, hipStream_t s);
 
 // ---- warm-start network (cnn.hip) ---------------------------------------------

@@ -1139,6 +1139,86 @@ int ac_tdft_inverse(ac_problem* p, int prec, const void* yhat, double* z) {
 // FGMRES
 
 namespace {
+// The paper's outer solver (Section 5): Chebyshev semi-iteration on P^{-1} calA with
+// the Corollary 1 interval [1, mu^l/(mu^l - alpha)] and a zero-residual-norm stop.
+// Residual form: r = b - calA x, z = P^{-1} r, d_0 = z/theta, x_{k+1} = x_k + d_k,
+// rho_0 = delta/theta, rho_{k+1} = 1/(2 theta/delta - rho_k),
+// d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) z_{k+1}.
+int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* b, double* x,
+                    void* ws, ac_solve_info* info, std::chrono::steady_clock::time_point t0) {
+    if (o->inner != AC_INNER_CHEB)
+        return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration needs a linear preconditioner");
+    ac_ctx* c = p->ctx;
+    hipStream_t st = c->stream;
+    const long long len = static_cast<long long>(p->ell) * p->g.n;
+    SolveWs w = carve_solve(p, o, ws);
+    double* r = w.V[0];
+    double* d = w.V[1];
+    double* z = w.Z[0];
+    const int kb = ac::krylov_blocks();
+    const int ptiles = static_cast<int>(calA_partials(p));
+    long long psum = 0;
+    for (int v : pm) psum += v;
+    const double mul = std::pow(p->bounds[AC_PREC_FP64][0], p->ell);
+    const double lo = 1.0, hi = mul / (mul - p->alpha);
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
+    auto fetch1 = [&](double& v) -> int {
+        AC_HIP(hipMemcpyAsync(c->pinned, w.red, sizeof(double), hipMemcpyDeviceToHost, st));
+        AC_HIP(hipStreamSynchronize(st));
+        v = c->pinned[0];
+        return AC_OK;
+    };
+    double bb = 0.0;
+    {
+        ProfScope ps(c, AC_K_KRYLOV, 8.0 * len);
+        AC_HIP(ac::launch_norm2(b, len, w.partial, st));
+        AC_HIP(ac::launch_reduce(w.partial, kb, 1, 1, w.red, st));
+    }
+    AC_TRY(fetch1(bb));
+    const double bnorm = std::sqrt(bb);
+    if (!std::isfinite(bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
+    long long matvecs = 0;
+    int it = 0, status = AC_OK;
+    double beta = 0.0, rho = delta / theta;
+    while (true) {
+        AC_TRY(calA_impl(p, x, r, b, w.partial2));
+        AC_HIP(ac::launch_reduce(w.partial2, ptiles, 1, 1, w.red, st));
+        double rr = 0.0;
+        AC_TRY(fetch1(rr));
+        matvecs += p->ell;
+        beta = std::sqrt(rr);
+        if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
+        if (bnorm == 0.0 || beta / bnorm <= o->tol) break;
+        if (it >= o->max_outer) {
+            status = AC_NOT_CONVERGED;
+            break;
+        }
+        AC_TRY(apply_prec_impl(p, o, pm, r, z, w.prec, 1.0));
+        matvecs += psum;
+        double a_k = 0.0, c_k = 1.0 / theta;
+        if (it > 0 && delta > 0.0) {
+            const double rn = 1.0 / (2.0 * theta / delta - rho);
+            a_k = rn * rho;
+            c_k = 2.0 * rn / delta;
+            rho = rn;
+        }
+        ProfScope ps(c, AC_K_KRYLOV, 40.0 * len);
+        AC_HIP(ac::launch_cheb_update(x, d, z, a_k, c_k, len, st));
+        ++it;
+    }
+    // the residual evaluations count l products each; the paper counts l per
+    // iteration, so drop the final check's product from the total
+    if (it > 0) matvecs -= p->ell;
+    if (info) {
+        *info = ac_solve_info{};
+        info->outer_iters = it;
+        info->matvecs_A = matvecs;
+        info->rel_residual_true = bnorm > 0 ? beta / bnorm : 0.0;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return status;
+}
+
 int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
                ac_solve_info* info, double* rec, int rec_count, int* rec_done) {
     const auto t0 = std::chrono::steady_clock::now();
@@ -1148,8 +1228,13 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
     if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
     if (!(o->tol > 0.0)) return fail(AC_ERR_ARG, "tol must be positive");
     if (o->max_outer < 1) return fail(AC_ERR_ARG, "max_outer must be >= 1");
+    if (o->outer != AC_OUTER_FGMRES && o->outer != AC_OUTER_CHEBYSHEV) return fail(AC_ERR_ARG, "unknown outer solver");
     if (!ws || ws_bytes < solve_ws_bytes(p, o)) return fail(AC_ERR_WORKSPACE, "workspace too small");
     AC_HIP(hipSetDevice(p->ctx->device));
+    if (o->outer == AC_OUTER_CHEBYSHEV) {
+        if (rec) return fail(AC_ERR_UNSUPPORTED, "recording needs the FGMRES outer solver");
+        return outer_cheb_impl(p, o, pm, b, x, ws, info, t0);
+    }
     ac_ctx* c = p->ctx;
     hipStream_t st = c->stream;
     const int m = o->restart_m;
@@ -1363,6 +1448,7 @@ int validate_batch(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
     if (!c || !probs || !o) return fail(AC_ERR_ARG, "NULL argument");
     if (count < 1 || count > kMaxBatch) return fail(AC_ERR_UNSUPPORTED, "batch size must be in [1, 256]");
     if (o->inner != AC_INNER_CHEB) return fail(AC_ERR_UNSUPPORTED, "batched solves use the plain inner solver");
+    if (o->outer != AC_OUTER_FGMRES) return fail(AC_ERR_UNSUPPORTED, "batched solves use the FGMRES outer solver");
     if (o->p_per_shift) return fail(AC_ERR_UNSUPPORTED, "batched solves take a uniform inner count (p_uniform)");
     if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
     if (!(o->tol > 0.0)) return fail(AC_ERR_ARG, "tol must be positive");

@@ -318,6 +318,24 @@ hipError_t launch_maxpy(const VecSet& Z, int nv, const double* /*unused*/, doubl
     return hipGetLastError();
 }
 
+// Outer Chebyshev update: d = a d + c z, then x = x + d.
+__global__ __launch_bounds__(256) void cheb_update_kernel(double* __restrict__ x, double* __restrict__ d,
+                                                          const double* __restrict__ z, double a, double c,
+                                                          long long len) {
+    const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < len; i += step) {
+        const double dn = c * z[i] + (a != 0.0 ? a * d[i] : 0.0);  // d is not read on the first step
+        d[i] = dn;
+        x[i] += dn;
+    }
+}
+
+hipError_t launch_cheb_update(double* x, double* d, const double* z, double a, double c, long long len,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(cheb_update_kernel, dim3(kBlocks), dim3(kThreads), 0, s, x, d, z, a, c, len);
+    return hipGetLastError();
+}
+
 hipError_t launch_norm2(const double* w, long long len, double* partial, hipStream_t s) {
     hipLaunchKernelGGL(norm2_kernel, dim3(kBlocks), dim3(kThreads), 0, s, w, len, partial);
     return hipGetLastError();

@@ -1,0 +1,106 @@
+"""The paper's outer solver on the GPU: Chebyshev semi-iteration on P_NC^{-1} calA
+with the Corollary 1 interval and a 1e-6 relative-residual stop (Section 5).
+
+Parity: iteration counts and solutions against the oracle's outer_chebyshev on the
+paper's constant-coefficient operator and on a log-normal field.  Context: the
+printed counts of Tables 3 and 8 (alpha = 0.01, NC2); the matvecs per iteration
+(l + sum of the Algorithm 1 allocation) match the tables exactly, the iteration
+counts are pinned where this reading of the method reproduces them (eta = 0.3:
+within 1; eta = 0.2: at most 3 above)."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import operators as ops
+from oracle import precond as pc
+from oracle.alloc import alg1_allocation, nc1_allocation, paper_operator_kappa
+from oracle.bounds import cor1_interval
+from oracle.krylov import outer_chebyshev
+from paper_2506_03947_amd import api
+from synth import first_block_rhs, lognormal_kappa
+from tests import gpu_util as G
+
+L = api.L
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "nc2_tables.json")
+
+
+def _gpu_outer(kap, nx, ell, alpha, pm, lo, hi, b, precision=L.AC_PREC_FP64):
+    p = G.problem(2, nx, nx, kap, ell, alpha, bounds=(lo, hi))
+    opts = api.Opts(precision=precision, p=list(pm), tol=1e-6, restart_m=1, max_outer=3000,
+                    outer=L.AC_OUTER_CHEBYSHEV)
+    x = G.dev(np.zeros_like(b))
+    info = api.ac_solve(p, opts, G.dev(b), x, api.workspace(api.ac_solve_workspace_size(p, opts)))
+    return p, info, G.host(x)
+
+
+@pytest.mark.parametrize("nx,method,alpha,eta", [(50, "NC2", 0.01, 0.2), (50, "NC1", 1.0, 0.3),
+                                                 (40, "NC2", 1.0, 0.2)])
+def test_outer_chebyshev_matches_oracle(nx, method, alpha, eta):
+    ell = 10
+    kap = paper_operator_kappa(nx, ell)
+    lo, hi = ops.constant_interval(2, nx, nx, kap)
+    A = ops.build_A(2, nx, nx, kap)
+    budget = ell * nx * eta
+    pm = alg1_allocation(ell, budget, lo, hi, alpha) if method == "NC2" else nc1_allocation(ell, budget)
+    b = first_block_rhs(nx * nx, ell, seed=0)
+    a, bnd = cor1_interval(lo, ell, alpha)
+    x_ref, it_ref = outer_chebyshev(lambda v: ops.apply_calA(A, v, ell), b,
+                                    lambda v: pc.apply_prec_nc(A, v, ell, alpha, lo, hi, pm), a, bnd, 1e-6)
+    p, info, x = _gpu_outer(kap, nx, ell, alpha, pm, lo, hi, b)
+    assert info["converged"] and info["rel_residual_true"] < 1e-6
+    assert abs(info["outer_iters"] - it_ref) <= 1, (info["outer_iters"], it_ref)
+    assert info["matvecs_A"] == info["outer_iters"] * (ell + int(np.sum(pm)))
+    # both iterates solve to 1e-6; they are the same iteration up to rounding
+    assert G.rel(x, x_ref) < 1e-6 if info["outer_iters"] == it_ref else G.rel(x, x_ref) < 1e-4
+
+
+def test_outer_chebyshev_variable_kappa_mixed():
+    nx, ell, alpha = 64, 6, 1e-2
+    kap = lognormal_kappa(nx, nx, 5.0, 6.0, 0.5, seed=3)
+    lo, hi = ops.spectral_interval(2, nx, nx, kap)
+    A = ops.build_A(2, nx, nx, kap)
+    pm = [12] * ell
+    b = first_block_rhs(nx * nx, ell, seed=1)
+    a, bnd = cor1_interval(lo, ell, alpha)
+    x_ref, it_ref = outer_chebyshev(lambda v: ops.apply_calA(A, v, ell), b,
+                                    lambda v: pc.apply_prec_nc(A, v, ell, alpha, lo, hi, pm), a, bnd, 1e-6)
+    _, info, x = _gpu_outer(kap, nx, ell, alpha, pm, lo, hi, b, precision=L.AC_PREC_MIXED_FP32K)
+    assert info["converged"] and abs(info["outer_iters"] - it_ref) <= 1
+    assert G.rel(x, ops.sequential_solve(A, b, ell)) < 1e-4
+
+
+def test_outer_chebyshev_rejects_nonlinear_inner():
+    nx, ell = 32, 4
+    p = G.problem(2, nx, nx, 2.0, ell, 1e-2)
+    cnn = api.ac_cnn_create(G.ctx())
+    api.ac_problem_attach_cnn(p, cnn)
+    opts = api.Opts(inner=L.AC_INNER_CHEB_CNN, p=4, outer=L.AC_OUTER_CHEBYSHEV)
+    with pytest.raises(api.L.AlphacircError):
+        api.ac_solve(p, opts, G.dev(np.ones(ell * nx * nx)), G.dev(np.zeros(ell * nx * nx)),
+                     api.workspace(api.ac_solve_workspace_size(p, opts)))
+
+
+def _rows(eta):
+    rows = json.load(open(GOLDEN))["rows"]
+    return [r for r in rows if r["method"] == "NC2" and r["alpha"] == 0.01 and r["ell"] == 10 and r["eta"] == eta
+            and r["source"] in ("Table 3", "Table 8")]
+
+
+@pytest.mark.parametrize("eta,below,above", [(0.3, 1, 1), (0.2, 0, 3)])
+def test_paper_counts_alpha_001(eta, below, above):
+    for r in _rows(eta):
+        nx, ell = r["nx"], r["ell"]
+        kap = paper_operator_kappa(nx, ell)
+        lo, hi = ops.constant_interval(2, nx, nx, kap)
+        p = G.problem(2, nx, nx, kap, ell, r["alpha"], bounds=(lo, hi))
+        pm = api.ac_alloc_nc2(p, ell * nx * eta)
+        assert (ell + sum(pm)) * r["iterations"] == r["matvecs"], r
+        _, info, _ = _gpu_outer(kap, nx, ell, r["alpha"], pm, lo, hi, first_block_rhs(nx * nx, ell, seed=0))
+        d = info["outer_iters"] - r["iterations"]
+        print(f"{r['source']} nx={nx} eta={eta}: paper {r['iterations']} ours {info['outer_iters']}")
+        assert info["converged"] and -below <= d <= above, (r, info["outer_iters"])
