@@ -244,6 +244,12 @@ int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* 
 int ac_solve_record(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws,
                     size_t ws_bytes, ac_solve_info* info, double* rec, int rec_count, int* recorded);
 
+/* Steady Chebyshev sweeps in shift groups: mode -1 (default) groups problems with 5
+ * or more unique shifts, 0 never, 1 always.  A group holds at most one real and two
+ * complex shifts and runs as its own launch; results are those of the all-shift
+ * sweep.  Problems with grouped sweeps default to 8 rows per wave. */
+int ac_ctx_set_shift_groups(ac_ctx* ctx, int mode);
+
 /* ---- tiling ----------------------------------------------------------------
  * Sweep tiling of one problem (overrides the context's ac_ctx_set_tiling; 0 keeps
  * the context's value): rows per wave, waves per block (1..4), points per lane

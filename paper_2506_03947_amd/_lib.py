@@ -126,6 +126,7 @@ SIGNATURES = {
                                   C.POINTER(C.c_float)]),
     "ac_problem_shifts": (_I, [_VP, C.POINTER(_D)]),
     "ac_problem_set_tiling": (_I, [_VP, _I, _I, _I]),
+    "ac_ctx_set_shift_groups": (_I, [_VP, _I]),
     "ac_tune_tiling": (_I, [_VP, _I, C.c_char_p, _VP, _SZ, C.POINTER(C.c_int), C.POINTER(_D)]),
     "ac_cnn_adam_step": (_I, [_VP, _D, _D, _D, _D]),
     "ac_cnn_make_inputs": (_I, [_VP, _VP, _I, _VP, _VP, C.POINTER(_D)]),

@@ -83,6 +83,8 @@ struct ac_ctx {
     int tile_h = 0, tile_wpb = 0, tile_vx = 0;
     // while set, stencil launch sites append records here instead of launching
     std::vector<ac_launch_rec>* rec = nullptr;
+    // steady sweeps in shift groups: -1 automatic (5 or more unique shifts), 0 off, 1 on
+    int shift_groups = -1;
 };
 
 constexpr int kResidBlocks = 512;  // blocks of the warm-start residual-statistics kernel
@@ -197,13 +199,25 @@ void spectral_offsets(const ac_problem* p, long long* off) {
     off[p->ns] = o;
 }
 
+// Steady Chebyshev sweeps of problems with many unique shifts run as several
+// launches of the (one real, two complex shifts) kernel variant over slot groups:
+// the all-shift variant needs more than 168 VGPRs at l = 10 (two waves per SIMD),
+// the group variant about 110 (four waves per SIMD), which hides more memory latency
+// at the price of reading kappa once per group.  Every shift is computed exactly as
+// in the all-shift variant.
+bool use_shift_groups(const ac_problem* p) {
+    const int mode = p->ctx->shift_groups;
+    if (mode == 0) return false;
+    return mode == 1 ? p->ns >= 2 : p->ns >= 5;
+}
+
 Tiling make_tiling(const ac_problem* p, int vx_pref, int h_pref, int wpb_pref) {
     Tiling t{};
     const Geom& g = p->g;
     int vx = vx_pref > 0 ? vx_pref : 2;
     if (g.nx % 2 != 0 || g.nx < 128 || g.periodic) vx = 1;  // periodic sweeps use one point per lane
     t.vx = vx;
-    t.h = h_pref > 0 ? h_pref : 16;
+    t.h = h_pref > 0 ? h_pref : (use_shift_groups(p) ? 8 : 16);
     if (t.h > g.ny) t.h = g.ny;
     t.wpb = wpb_pref > 0 ? wpb_pref : 4;
     t.nsx = (g.nx + ac::kWave * vx - 1) / (ac::kWave * vx);
@@ -438,14 +452,51 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         fill_twiddles(p->ell, a.cw, a.sw);
         a.z = z;
     };
+    // group g: real slot g (if any) and complex slots nsr + 2g, nsr + 2g + 1 (if any),
+    // as slots 0, 1, 2 of the l = 5 variant; absent slots do not compute
+    auto launch_groups = [&](int curk, const ac::SweepArgs<R>& a) -> hipError_t {
+        const int ngroups = std::max(p->nsr, (p->nsc + 1) / 2);
+        for (int grp = 0; grp < ngroups; ++grp) {
+            ac::SweepArgs<R> ga = a;
+            const int map[3] = {grp < p->nsr ? grp : -1, 2 * grp < p->nsc ? p->nsr + 2 * grp : -1,
+                                2 * grp + 1 < p->nsc ? p->nsr + 2 * grp + 1 : -1};
+            bool anyc = false;
+            for (int j = 0; j < 3; ++j) {
+                const int sl = map[j];
+                if (sl < 0) {
+                    ga.src[j] = ac::SRC_BUF;
+                    ga.soff[j] = 0;
+                    continue;
+                }
+                ga.src[j] = a.src[sl];
+                ga.fbuf[j] = a.fbuf[sl];
+                ga.soff[j] = a.soff[sl];
+                ga.cf.lam_re[j] = a.cf.lam_re[sl];
+                ga.cf.lam_im[j] = a.cf.lam_im[sl];
+                ga.cf.a_re[j] = a.cf.a_re[sl];
+                ga.cf.a_im[j] = a.cf.a_im[sl];
+                ga.cf.c_re[j] = a.cf.c_re[sl];
+                ga.cf.c_im[j] = a.cf.c_im[sl];
+                ga.cf.s_re[j] = a.cf.s_re[sl];
+                ga.cf.s_im[j] = a.cf.s_im[sl];
+                anyc = anyc || a.src[sl] == ac::SRC_COMPUTE;
+            }
+            if (!anyc) continue;
+            const hipError_t e = ac::launch_cheb_step(5, prec, curk, &ga, p->ctx->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    const bool groups = use_shift_groups(p);
     auto launch = [&](bool fin, int curk, const ac::SweepArgs<R>& a) -> hipError_t {
         if (p->ctx->rec) {
             record_launch(p->ctx, fin ? ac::BOP_FINAL : ac::BOP_STEP, p->ell, prec, curk, a.t.vx, a.t.wpb, a.t.blocks,
                           a);
             return hipSuccess;
         }
-        return fin ? ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream)
-                   : ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream);
+        if (fin) return ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream);
+        if (groups) return launch_groups(curk, a);
+        return ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream);
     };
     // consecutive steady-state sweeps share one event pair (no per-launch event cost)
     std::unique_ptr<ProfScope> steady;
@@ -1823,6 +1874,13 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
 
 // ---------------------------------------------------------------------------
 // tiling control (used by the tile tuner)
+int ac_ctx_set_shift_groups(ac_ctx* c, int mode) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    if (mode < -1 || mode > 1) return fail(AC_ERR_ARG, "mode must be -1, 0 or 1");
+    c->shift_groups = mode;
+    return AC_OK;
+}
+
 int ac_ctx_set_tiling(ac_ctx* c, int rows_per_wave, int waves_per_block, int points_per_lane) {
     if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
     if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
