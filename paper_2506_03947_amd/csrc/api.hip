@@ -452,6 +452,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         fill_twiddles(p->ell, a.cw, a.sw);
         a.z = z;
     };
+    int launched = 0;  // kernel launches of the current step (several with shift groups)
     // group g: real slot g (if any) and complex slots nsr + 2g, nsr + 2g + 1 (if any),
     // as slots 0, 1, 2 of the l = 5 variant; absent slots do not compute
     auto launch_groups = [&](int curk, const ac::SweepArgs<R>& a) -> hipError_t {
@@ -484,18 +485,23 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             if (!anyc) continue;
             const hipError_t e = ac::launch_cheb_step(5, prec, curk, &ga, p->ctx->stream);
             if (e != hipSuccess) return e;
+            ++launched;
         }
         return hipSuccess;
     };
     const bool groups = use_shift_groups(p);
     auto launch = [&](bool fin, int curk, const ac::SweepArgs<R>& a) -> hipError_t {
+        launched = 1;
         if (p->ctx->rec) {
             record_launch(p->ctx, fin ? ac::BOP_FINAL : ac::BOP_STEP, p->ell, prec, curk, a.t.vx, a.t.wpb, a.t.blocks,
                           a);
             return hipSuccess;
         }
         if (fin) return ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream);
-        if (groups) return launch_groups(curk, a);
+        if (groups) {
+            launched = 0;
+            return launch_groups(curk, a);
+        }
         return ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream);
     };
     // consecutive steady-state sweeps share one event pair (no per-launch event cost)
@@ -544,8 +550,8 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 steady->launches = 0;
             }
             steady->bytes += bytes;
-            steady->launches += 1;
             AC_HIP(launch(false, curk, a));
+            steady->launches += launched;
         }
         if (steady && (k + 1 > k_last || (fuse && k + 1 == k_last))) steady.reset();
     }
@@ -2012,16 +2018,25 @@ int ac_tune_tiling(ac_problem* p, int prec, const char* cache_path, void* ws, si
                 seen.push_back(key);
                 double ms_best = 1e300;
                 for (int rep = 0; rep < 4 && status == AC_OK; ++rep) {
-                    hipEventRecord(e0, c->stream);
+                    if (hipEventRecord(e0, c->stream) != hipSuccess) {
+                        status = fail(AC_ERR_HIP, "tile tuner: hipEventRecord failed");
+                        break;
+                    }
                     status = run_cheb(p, prec, pm, bufs.rhat, bufs.buf, false, nullptr, nullptr);
-                    hipEventRecord(e1, c->stream);
                     if (status != AC_OK) break;
+                    if (hipEventRecord(e1, c->stream) != hipSuccess) {
+                        status = fail(AC_ERR_HIP, "tile tuner: hipEventRecord failed");
+                        break;
+                    }
                     if (hipEventSynchronize(e1) != hipSuccess) {
                         status = fail(AC_ERR_HIP, "tile tuner: event synchronisation failed");
                         break;
                     }
                     float ms = 0.f;
-                    hipEventElapsedTime(&ms, e0, e1);
+                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        status = fail(AC_ERR_HIP, "tile tuner: hipEventElapsedTime failed");
+                        break;
+                    }
                     if (rep > 0) ms_best = std::min(ms_best, static_cast<double>(ms));
                 }
                 if (status != AC_OK) break;
