@@ -75,8 +75,11 @@ typedef enum { AC_BC_DIRICHLET = 0, AC_BC_PERIODIC = 1 } ac_bc;
 typedef enum { AC_PREC_FP64 = 0, AC_PREC_MIXED_BF16K = 1, AC_PREC_MIXED_FP32K = 2 } ac_precision;
 
 /* Inner initial guess: zero (the paper's method), or the learned warm start
- * attached with ac_cnn_attach (makes the preconditioner nonlinear). */
-typedef enum { AC_INNER_CHEB = 0, AC_INNER_CHEB_CNN = 1 } ac_inner;
+ * attached with ac_problem_attach_cnn (makes the preconditioner nonlinear): for every
+ * preconditioner application (AC_INNER_CHEB_CNN), or only for the first vector of
+ * each FGMRES cycle, the true residual, with zero guesses inside the cycle
+ * (AC_INNER_CHEB_CNN_CYCLE; ac_apply_prec treats it as AC_INNER_CHEB_CNN). */
+typedef enum { AC_INNER_CHEB = 0, AC_INNER_CHEB_CNN = 1, AC_INNER_CHEB_CNN_CYCLE = 2 } ac_inner;
 
 typedef struct {
     int dim;   /* 1 or 2 */

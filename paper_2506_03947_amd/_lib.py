@@ -31,6 +31,7 @@ AC_PREC_MIXED_FP32K = 2
 
 AC_INNER_CHEB = 0
 AC_INNER_CHEB_CNN = 1
+AC_INNER_CHEB_CNN_CYCLE = 2
 AC_OUTER_FGMRES = 0
 AC_OUTER_CHEBYSHEV = 1
 

@@ -289,8 +289,9 @@ ChebShift cheb_tables(const ac_problem* p, int prec, int m, int steps) {
 int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>& pm) {
     if (!o) return fail(AC_ERR_ARG, "opts is NULL");
     if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
-    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN) return fail(AC_ERR_ARG, "unknown inner mode");
-    if (o->inner == AC_INNER_CHEB_CNN && !p->cnn) return fail(AC_ERR_ARG, "no warm-start network attached");
+    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN && o->inner != AC_INNER_CHEB_CNN_CYCLE)
+        return fail(AC_ERR_ARG, "unknown inner mode");
+    if (o->inner != AC_INNER_CHEB && !p->cnn) return fail(AC_ERR_ARG, "no warm-start network attached");
     pm.assign(p->ell, 0);
     for (int m = 0; m < p->ell; ++m) {
         const int v = o->p_per_shift ? o->p_per_shift[m] : o->p_uniform;
@@ -313,7 +314,7 @@ size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     size_t b = 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
-    if (inner == AC_INNER_CHEB_CNN) b += cnn_ws_bytes(p);
+    if (inner != AC_INNER_CHEB) b += cnn_ws_bytes(p);
     return b;
 }
 
@@ -752,7 +753,7 @@ int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
                     void* ws, double in_scale, int* fallbacks = nullptr) {
     const PrecBufs b = carve_prec(p, o->precision, ws);
     AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
-    if (o->inner == AC_INNER_CHEB_CNN) {
+    if (o->inner != AC_INNER_CHEB) {
         AC_TRY(cnn_warm_start(p, o->precision, b.rhat, b.buf[0], b.cnn, fallbacks));
         AC_TRY(run_cheb(p, o->precision, pm, b.rhat, b.buf, true, z, nullptr));
     } else {
@@ -1358,8 +1359,11 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
                                       hipMemcpyDeviceToDevice, st));
                 ++*rec_done;
             }
-            // z_j = P^{-1} v_j with v_j = scale_j * V_j (scale folded into the transform)
-            AC_TRY(apply_prec_impl(p, o, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
+            // z_j = P^{-1} v_j with v_j = scale_j * V_j (scale folded into the transform);
+            // AC_INNER_CHEB_CNN_CYCLE warm-starts only the cycle's first vector
+            ac_solve_opts oj = *o;
+            if (o->inner == AC_INNER_CHEB_CNN_CYCLE && j > 0) oj.inner = AC_INNER_CHEB;
+            AC_TRY(apply_prec_impl(p, &oj, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
             AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
             matvecs += p->ell + psum;
             ac::VecSet vs{};

@@ -46,7 +46,7 @@ class _Buffers:
         return self.ws[key]
 
 
-def preconditioner_inputs(prob, b, p_inner, count, bufs, restart=30, warm=False):
+def preconditioner_inputs(prob, b, p_inner, count, bufs, restart=8, warm=False):
     """The first `count` vectors FGMRES(restart) from x = 0 hands to the preconditioner
     (its Arnoldi basis vectors), recorded by the library; with warm=True the solve uses
     the attached network, so the inputs carry that network's own residual patterns."""
@@ -99,7 +99,7 @@ class PairSet:
 
 
 def generate_pairs(ctx, nx, ny, ell, alpha, kappa_fn, kappa_seeds, b_seeds, n_record, pick_every, p_inner, crop,
-                   crops_per_plane, c0, c1, seed=0, log=print, net=None):
+                   crops_per_plane, c0, c1, seed=0, log=print, net=None, restart=8):
     """Crops from every `pick_every`-th of the first `n_record` preconditioner inputs
     of solves for each coefficient seed and right-hand-side seed: plain solves, or
     solves warm-started by `net` when given."""
@@ -117,7 +117,7 @@ def generate_pairs(ctx, nx, ny, ell, alpha, kappa_fn, kappa_seeds, b_seeds, n_re
             api.ac_problem_attach_cnn(prob, net)
         for bs in b_seeds:
             b = torch.as_tensor(first_block_rhs(nx * ny, ell, seed=bs), device="cuda:0")
-            inputs = preconditioner_inputs(prob, b, p_inner, n_record, bufs, warm=net is not None)
+            inputs = preconditioner_inputs(prob, b, p_inner, n_record, bufs, restart=restart, warm=net is not None)
             for v in inputs[::pick_every]:
                 X, R, lam = field_pairs(prob, cnn, v.contiguous())
                 X = X.view(prob.ns, ny, nx, 16)
@@ -216,17 +216,19 @@ def inner_gain(prob, cnn, r, p_inner, bufs):
             "warm": api.ac_shifted_residual(prob, prec, rhat, y_warm).tolist()}
 
 
-def compare_solves(ctx, cnn, nx, ny, ell, alpha, kappa, b_seed, p_inner, tol=1e-8, restart=30):
-    """Plain and warm-started FGMRES on one problem: outer iterations, wall time, fallbacks,
-    plus the mean inner residuals per shift on inputs the plain method's preconditioner
-    receives."""
+def compare_solves(ctx, cnn, nx, ny, ell, alpha, kappa, b_seed, p_inner, tol=1e-8, restart=8):
+    """Plain and warm-started FGMRES (network on every preconditioner input, and on the
+    first vector of each cycle only) on one problem: outer iterations, wall time,
+    fallbacks, plus the mean inner residuals per shift on inputs the plain method's
+    preconditioner receives."""
     from synth import first_block_rhs
     prob = make_problem(ctx, nx, ny, ell, alpha, kappa)
     api.ac_problem_attach_cnn(prob, cnn)
     b = torch.as_tensor(first_block_rhs(nx * ny, ell, seed=b_seed), device="cuda:0")
     out = {}
     bufs = _Buffers()
-    for name, inner in (("plain", L.AC_INNER_CHEB), ("cnn", L.AC_INNER_CHEB_CNN)):
+    for name, inner in (("plain", L.AC_INNER_CHEB), ("cnn", L.AC_INNER_CHEB_CNN),
+                        ("cnn_cycle", L.AC_INNER_CHEB_CNN_CYCLE)):
         opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, inner=inner, p=p_inner, tol=tol, restart_m=restart,
                         max_outer=3000)
         ws = bufs.get("solve" + name, api.ac_solve_workspace_size(prob, opts))
@@ -241,7 +243,7 @@ def compare_solves(ctx, cnn, nx, ny, ell, alpha, kappa, b_seed, p_inner, tol=1e-
         out[name] = info
     # inner residuals on preconditioner inputs of the plain method (every 5th of 30)
     gains = [inner_gain(prob, cnn, v.contiguous(), p_inner, bufs)
-             for v in preconditioner_inputs(prob, b, p_inner, 30, bufs)[::5]]
+             for v in preconditioner_inputs(prob, b, p_inner, 30, bufs, restart=restart)[::5]]
     out["inner"] = {k: np.mean([g[k] for g in gains], axis=0).tolist() for k in ("guess", "cold", "warm")}
     return out
 
@@ -271,6 +273,9 @@ def main():
     ap.add_argument("--batch", type=int, default=64)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--border", type=int, default=3)
+    ap.add_argument("--restart", type=int, default=8, help="FGMRES restart length")
+    ap.add_argument("--rounds", type=int, default=1,
+                    help="extra rounds of pairs drawn from solves warm-started by the current network")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     nx = ny = a.nx
@@ -284,17 +289,23 @@ def main():
     per_plane = max(1, a.pairs // (len(train_seeds) * len(b_seeds) * (n_record // pick) * (a.ell // 2 + 1)))
     t0 = time.perf_counter()
     train = generate_pairs(ctx, nx, ny, a.ell, a.alpha, kfn, train_seeds, b_seeds, n_record, pick, a.p, a.crop, per_plane,
-                           c0, c1)
+                           c0, c1, restart=a.restart)
     held = generate_pairs(ctx, nx, ny, a.ell, a.alpha, kfn, [test_seed], b_seeds, n_record, pick, a.p, a.crop, per_plane,
-                          c0, c1, seed=1)
+                          c0, c1, seed=1, restart=a.restart)
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
     cnn, hist = train_network(ctx, train, a.steps, a.batch, a.lr, a.border, c0, c1)
+    for rnd in range(a.rounds):
+        more = generate_pairs(ctx, nx, ny, a.ell, a.alpha, kfn, train_seeds, b_seeds[:1], n_record, pick, a.p, a.crop,
+                              per_plane, c0, c1, seed=10 + rnd, net=cnn, restart=a.restart)
+        train = train.join(more)
+        cnn, hist2 = train_network(ctx, train, a.steps // 3, a.batch, a.lr / 2, a.border, c0, c1, cnn=cnn)
+        hist += hist2
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
-    res = compare_solves(ctx, cnn, nx, ny, a.ell, a.alpha, kfn(test_seed), 7, a.p)
-    record = {"grid": [nx, ny], "ell": a.ell, "alpha": a.alpha, "p": a.p, "pairs": len(train),
+    res = compare_solves(ctx, cnn, nx, ny, a.ell, a.alpha, kfn(test_seed), 7, a.p, restart=a.restart)
+    record = {"grid": [nx, ny], "ell": a.ell, "alpha": a.alpha, "p": a.p, "restart": a.restart, "pairs": len(train),
               "held_out_pairs": len(held), "crop": a.crop, "gen_s": t_gen, "train_s": t_train, "steps": a.steps,
               "first_loss": float(np.mean(hist[:20])), "final_loss": float(np.mean(hist[-100:])),
               "held_out_loss": eval_loss(ctx, cnn, held, a.border), "held_out_solve": res}
