@@ -349,6 +349,10 @@ int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* cnn, int precision, const vo
 int ac_cnn_guess_workspace_size(const ac_problem* p, size_t* bytes);
 int ac_cnn_guess(ac_problem* p, int precision, const void* rhat, void* x0hat, void* ws, size_t ws_bytes,
                  int* rejected);
+/* Inference kernels for the guesses: fused != 0 (default) evaluates all three layers
+ * per 16 x 16 tile in LDS straight from rhat and kappa; 0 runs input packing, three
+ * convolution launches and output scaling (the training kernels).  Same results. */
+int ac_cnn_set_inference(ac_cnn* cnn, int fused);
 /* Guess policy: scaling != 0 (default) multiplies each guess by its
  * residual-minimising complex factor; a guess is kept only if
  * ||rhat_m - (A - lambda_m) x0_m|| < accept_ratio ||rhat_m||, accept_ratio in (0, 1]

@@ -136,6 +136,7 @@ SIGNATURES = {
     "ac_cnn_guess_workspace_size": (_I, [_VP, C.POINTER(_SZ)]),
     "ac_cnn_guess": (_I, [_VP, _I, _VP, _VP, _VP, _SZ, C.POINTER(_I)]),
     "ac_cnn_set_guess_policy": (_I, [_VP, _I, _D]),
+    "ac_cnn_set_inference": (_I, [_VP, _I]),
 }
 
 _lib = None

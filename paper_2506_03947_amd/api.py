@@ -481,5 +481,9 @@ def ac_cnn_guess(p: Problem, precision: int, rhat: torch.Tensor, x0hat: torch.Te
     return rej.value
 
 
+def ac_cnn_set_inference(cnn: Cnn, fused: bool) -> None:
+    check(L.load().ac_cnn_set_inference(cnn.h, 1 if fused else 0), "ac_cnn_set_inference")
+
+
 def ac_cnn_set_guess_policy(cnn: Cnn, scaling: bool, accept_ratio: float = 1.0) -> None:
     check(L.load().ac_cnn_set_guess_policy(cnn.h, 1 if scaling else 0, accept_ratio), "ac_cnn_set_guess_policy")

@@ -211,6 +211,9 @@ hipError_t launch_cnn_adam(float* w, const float* g, float* m, float* v, float l
                            float bc1, float bc2, hipStream_t s);
 hipError_t launch_cnn_weights(const float* w, uint16_t* wf, uint16_t* wb, float* bias, hipStream_t s);
 hipError_t launch_cnn_prep(int prec, const CnnPrepArgs& a, hipStream_t s);
+// all three layers per 16 x 16 tile in LDS, rhat and kappa read directly, x0 = scale * y
+hipError_t launch_cnn_fused(int prec, const CnnPrepArgs& a, const uint16_t* wf, const float* bias, void* x0buf,
+                            hipStream_t s);
 hipError_t launch_cnn_post(int prec, const CnnPrepArgs& a, const float* y, void* x0buf, hipStream_t s);
 hipError_t launch_cnn_resid(int prec, const CnnPrepArgs& a, const void* x0buf, const void* kap, double* partial,
                             int nblk, hipStream_t s);

@@ -121,6 +121,7 @@ struct ac_cnn {
     float* bias = nullptr;     // [3][16]
     double c0 = 0.0, c1 = 1.0; // ln kappa normalisation
     int t = 0;                 // Adam steps taken
+    int fused = 1;             // inference by the fused (all layers in LDS) kernel
     int scaled = 1;            // scale each guess by its residual-minimising factor
     double accept = 1.0;       // keep a guess only if |rhat - B x0| < accept |rhat|
 };
@@ -688,6 +689,20 @@ int cnn_forward_impl(ac_cnn* c, const uint16_t* x, int B, int H, int W, float* y
     return AC_OK;
 }
 
+// In-place complex scaling of one spectral slot (n points, interleaved if complex).
+template <typename R>
+__global__ void slot_scale_kernel(R* x, long long n, int cplx_, R sr, R si) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (cplx_) {
+        const R a = x[2 * i], b = x[2 * i + 1];
+        x[2 * i] = sr * a - si * b;
+        x[2 * i + 1] = sr * b + si * a;
+    } else {
+        x[i] = sr * x[i];
+    }
+}
+
 // Learned initial guesses for every shift slot, written into x0buf.  With scaling on
 // each slot's output is multiplied by the complex factor c that minimises
 // |rhat - c B x0| (a one-dimensional minimal-residual step).  A slot whose (scaled)
@@ -707,7 +722,14 @@ int cnn_warm_start(ac_problem* p, int prec, const char* rhat, char* x0buf, char*
     }
     set_rms_scales(p, st, a, nullptr);
     a.x = X;
-    {
+    const bool fused = p->cnn->fused != 0;
+    if (fused) {
+        long long off[kMaxShift + 1];
+        spectral_offsets(p, off);
+        const double bytes = 2.0 * static_cast<double>(off[p->ns]) * inner_elem(prec) + 8.0 * p->g.n;
+        ProfScope ps(p->ctx, AC_K_CNN, bytes);
+        AC_HIP(ac::launch_cnn_fused(prec, a, p->cnn->wf, p->cnn->bias, x0buf, p->ctx->stream));
+    } else {
         const double bytes = static_cast<double>(px) * (32.0 * 7 + 8.0 * 2) + 8.0 * p->g.n;
         ProfScope ps(p->ctx, AC_K_CNN, bytes);
         AC_HIP(ac::launch_cnn_prep(prec, a, p->ctx->stream));
@@ -733,9 +755,26 @@ int cnn_warm_start(ac_problem* p, int prec, const char* rhat, char* x0buf, char*
         a.fac_im[s] = static_cast<float>(c_im);
         rescale = rescale || (!reject[s] && (c_re != 1.0 || c_im != 0.0));
     }
-    if (rescale) {
+    if (rescale && !fused) {
         ProfScope ps(p->ctx, AC_K_CNN, static_cast<double>(px) * 16.0);
         AC_HIP(ac::launch_cnn_post(prec, a, Y, x0buf, p->ctx->stream));
+    } else if (rescale) {
+        // the fused kernel wrote scale * y: multiply by the factor in place
+        ProfScope ps(p->ctx, AC_K_CNN, static_cast<double>(px) * 16.0);
+        const int blocks = static_cast<int>((p->g.n + 255) / 256);
+        for (int s = 0; s < p->ns; ++s) {
+            if (reject[s] || (a.fac_re[s] == 1.f && a.fac_im[s] == 0.f)) continue;
+            char* base = slot_ptr(p, prec, x0buf, s);
+            const int cx = slot_is_real(p, s) ? 0 : 1;
+            if (prec == AC_PREC_FP64)
+                hipLaunchKernelGGL((slot_scale_kernel<double>), dim3(blocks), dim3(256), 0, p->ctx->stream,
+                                   reinterpret_cast<double*>(base), p->g.n, cx, static_cast<double>(a.fac_re[s]),
+                                   static_cast<double>(a.fac_im[s]));
+            else
+                hipLaunchKernelGGL((slot_scale_kernel<float>), dim3(blocks), dim3(256), 0, p->ctx->stream,
+                                   reinterpret_cast<float*>(base), p->g.n, cx, a.fac_re[s], a.fac_im[s]);
+            AC_HIP(hipGetLastError());
+        }
     }
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
@@ -2358,6 +2397,12 @@ int ac_cnn_guess(ac_problem* p, int prec, const void* rhat, void* x0hat, void* w
     int fb = 0;
     AC_TRY(cnn_warm_start(p, prec, static_cast<const char*>(rhat), static_cast<char*>(x0hat), cws, &fb));
     if (rejected) *rejected = fb;
+    return AC_OK;
+}
+
+int ac_cnn_set_inference(ac_cnn* n, int fused) {
+    if (!n) return fail(AC_ERR_ARG, "network is NULL");
+    n->fused = fused ? 1 : 0;
     return AC_OK;
 }
 

@@ -368,6 +368,134 @@ __global__ __launch_bounds__(256) void prep_kernel(const CnnPrepArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference: the three layers for one 16 x 16 output tile of every shift slot,
+// intermediate activations in LDS.  The layer-1 input region is the tile plus a
+// 3-pixel ring (22 x 22), built directly from rhat and kappa; layer 1 is evaluated on
+// 20 x 20, layer 2 on 18 x 18, layer 3 on the tile.  Region pixels outside the grid
+// are zero at every layer (the zero padding of the layer-by-layer evaluation), taps
+// are chained in the same order, so the result equals that evaluation.  Each region
+// is covered by 16-pixel chunks (flattened row-major), one 9-MFMA chain per chunk.
+constexpr int kFT = 16;         // output tile edge
+constexpr int kR0 = kFT + 6;    // layer-1 input region edge
+constexpr int kR1 = kFT + 4;    // layer-1 output region edge
+constexpr int kR2 = kFT + 2;    // layer-2 output region edge
+
+// One layer on the RO x RO output region from the (RO + 2) x (RO + 2) input region;
+// (gx0, gy0): grid coordinates of the output region's origin.
+template <int RO>
+__device__ __forceinline__ void fused_layer(const uint16_t* __restrict__ in, uint16_t* __restrict__ out,
+                                            const bf16x4 (&wt)[9], float bias, int gx0, int gy0, int nx, int ny) {
+    constexpr int RI = RO + 2;
+    constexpr int NPIX = RO * RO;
+    constexpr int NCH = (NPIX + 15) / 16;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    for (int c = wv; c < NCH; c += 4) {
+        const int q = 16 * c + i;  // this lane's A row: output pixel q of the chunk
+        const bool qok = q < NPIX;
+        const int qy = qok ? q / RO : 0, qx = qok ? q % RO : 0;
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            bf16x4 av = {0, 0, 0, 0};
+            if (qok) av = *reinterpret_cast<const bf16x4*>(in + ((qy + t / 3) * RI + qx + t % 3) * kC + 4 * g);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, wt[t], acc, 0, 0, 0);
+        }
+        // lane holds output channel i of chunk pixels 4g + j
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int qq = 16 * c + 4 * g + j;
+            if (qq >= NPIX) continue;
+            const int oy = qq / RO, ox = qq % RO;
+            const int gy = gy0 + oy, gx = gx0 + ox;
+            float v = fmaxf(acc[j] + bias, 0.f);
+            if (gy < 0 || gy >= ny || gx < 0 || gx >= nx) v = 0.f;
+            out[qq * kC + i] = f2bf(v);
+        }
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void cnn_fused_kernel(const CnnPrepArgs a, const uint16_t* __restrict__ wf,
+                                                        const float* __restrict__ bias, void* x0buf) {
+    __shared__ __align__(16) uint16_t in0[kR0 * kR0 * kC];
+    __shared__ __align__(16) uint16_t in1[kR1 * kR1 * kC];
+    __shared__ __align__(16) uint16_t in2[kR2 * kR2 * kC];
+    __shared__ uint16_t lks[kR0 * kR0];
+    const int nx = a.g.nx, ny = a.g.ny;
+    const int ntx = (nx + kFT - 1) / kFT;
+    const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+    const int X0 = tx * kFT - 3, Y0 = ty * kFT - 3;  // grid coordinates of the input region's origin
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int i = lane & 15, g = lane >> 4;
+    bf16x4 w1[9], w2[9], w3[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        w1[t] = ld4(wf + (t * kC + i) * kC + 4 * g);
+        w2[t] = ld4(wf + 2304 + (t * kC + i) * kC + 4 * g);
+        w3[t] = ld4(wf + 2 * 2304 + (t * kC + i) * kC + 4 * g);
+    }
+    const float b1 = bias[i], b2 = bias[16 + i], b3 = bias[32 + i];
+    for (int q = threadIdx.x; q < kR0 * kR0; q += blockDim.x) {
+        const int gy = Y0 + q / kR0, gx = X0 + q % kR0;
+        uint16_t v = 0;
+        if (gy >= 0 && gy < ny && gx >= 0 && gx < nx)
+            v = f2bf(static_cast<float>((log(a.kappa[static_cast<long long>(gy) * nx + gx]) - a.c0) / a.c1));
+        lks[q] = v;
+    }
+    for (int s = 0; s < a.ns; ++s) {
+        __syncthreads();  // lks written; the previous slot's layer-1 reads of in0 are done
+        const R* src = static_cast<const R*>(a.rhat) + a.soff[s];
+        const bool re_only = a.is_real[s];
+        for (int q = threadIdx.x; q < kR0 * kR0; q += blockDim.x) {
+            const int gy = Y0 + q / kR0, gx = X0 + q % kR0;
+            uint16_t h[kC];
+#pragma unroll
+            for (int c = 0; c < kC; ++c) h[c] = 0;
+            if (gy >= 0 && gy < ny && gx >= 0 && gx < nx) {
+                const long long p = static_cast<long long>(gy) * nx + gx;
+                const float re = static_cast<float>(re_only ? src[p] : src[2 * p]);
+                const float im = re_only ? 0.f : static_cast<float>(src[2 * p + 1]);
+                h[0] = f2bf(re * a.inv_scale[s]);
+                h[1] = f2bf(im * a.inv_scale[s]);
+                h[2] = f2bf(a.lam_re[s]);
+                h[3] = f2bf(a.lam_im[s]);
+                h[4] = lks[q];
+            }
+            store16(in0 + q * kC, h);
+        }
+        __syncthreads();
+        fused_layer<kR1>(in0, in1, w1, b1, X0 + 1, Y0 + 1, nx, ny);
+        __syncthreads();
+        fused_layer<kR2>(in1, in2, w2, b2, X0 + 2, Y0 + 2, nx, ny);
+        __syncthreads();
+        // layer 3 on the tile: chunk c is tile row c; lanes i = 0, 1 hold Re, Im
+        R* dst = static_cast<R*>(x0buf) + a.soff[s];
+        const float sc = a.scale[s];
+        for (int c = wv; c < kFT; c += 4) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const bf16x4 av = *reinterpret_cast<const bf16x4*>(in2 + ((c + t / 3) * kR2 + i + t % 3) * kC + 4 * g);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, w3[t], acc, 0, 0, 0);
+            }
+            const int gy = ty * kFT + c;
+            if (i < 2 && gy < ny && !(re_only && i == 1)) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const int gx = tx * kFT + 4 * g + j;
+                    if (gx >= nx) continue;
+                    const long long p = static_cast<long long>(gy) * nx + gx;
+                    const float v = sc * (acc[j] + b3);
+                    if (re_only) dst[p] = static_cast<R>(v);
+                    else dst[2 * p + i] = static_cast<R>(v);
+                }
+            }
+        }
+    }
+}
+
 // x0 slot s = scale_s * (y0 + i y1)
 template <typename R>
 __global__ __launch_bounds__(256) void post_kernel(const CnnPrepArgs a, const float* __restrict__ y, void* x0buf) {
@@ -529,6 +657,14 @@ hipError_t launch_cnn_prep(int prec, const CnnPrepArgs& a, hipStream_t s) {
     const int blocks = static_cast<int>((a.n + 255) / 256);
     if (prec == 0) hipLaunchKernelGGL(prep_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(prep_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_cnn_fused(int prec, const CnnPrepArgs& a, const uint16_t* wf, const float* bias, void* x0buf,
+                            hipStream_t s) {
+    const int tiles = ((a.g.nx + kFT - 1) / kFT) * ((a.g.ny + kFT - 1) / kFT);
+    if (prec == 0) hipLaunchKernelGGL(cnn_fused_kernel<double>, dim3(tiles), dim3(256), 0, s, a, wf, bias, x0buf);
+    else hipLaunchKernelGGL(cnn_fused_kernel<float>, dim3(tiles), dim3(256), 0, s, a, wf, bias, x0buf);
     return hipGetLastError();
 }
 

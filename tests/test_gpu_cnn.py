@@ -225,3 +225,48 @@ def test_cnn_inputs_layout():
         ref = ocnn.make_inputs(R[m].reshape(64, 96), lam[m], kap, 3.0, 1.5, sc)
         assert G.max_rel(got[s, :, :, :5], to_bfloat16(ref)) < 1e-2
         assert not got[s, :, :, 5:].any()
+
+
+@pytest.mark.parametrize("precision", [L.AC_PREC_FP64, L.AC_PREC_MIXED_BF16K])
+@pytest.mark.parametrize("scaling", [False, True])
+def test_fused_inference_equals_layer_by_layer(precision, scaling):
+    """The fused kernel (all layers per 16 x 16 tile in LDS) against input packing +
+    three convolution launches + output scaling, on a grid ragged against the tiles:
+    identical guesses without the minimal-residual factor (same roundings, same tap
+    order), equal to float32 rounding with it."""
+    nx, ny, ell = 100, 70, 6
+    rng = np.random.default_rng(11)
+    kap = 20.0 * (1.0 + 0.05 * rng.uniform(-1, 1, nx * ny))  # nearly constant: the hand-made guess is kept
+    p = G.problem(2, nx, ny, kap, ell, 1e-2)
+    # a network whose guesses are kept: x0 ~ rhat / (1 + 4 mean kappa) through
+    # sign-split ReLU channels (centre taps), plus small perturbations of every weight
+    w = 1.0 / (1.0 + 4.0 * float(np.mean(kap)))
+    params = {k: 0.01 * rng.standard_normal(v.shape) for k, v in ocnn.init_params(12).items()}
+    params["W3"] *= w
+    for cin, cout, sgn in ((0, 0, 1.0), (0, 1, -1.0), (1, 2, 1.0), (1, 3, -1.0)):
+        params["W1"][1, 1, cin, cout] += sgn
+    for k in range(4):
+        params["W2"][1, 1, k, k] += 1.0
+    for cin, cout, sgn in ((0, 0, 1.0), (1, 0, -1.0), (2, 1, 1.0), (3, 1, -1.0)):
+        params["W3"][1, 1, cin, cout] += sgn * w
+    cnn = api.ac_cnn_create(G.ctx())
+    api.ac_cnn_set_params(cnn, packed_from_oracle(params).astype(np.float32), float(np.log(kap).mean()), 1.0)
+    api.ac_cnn_set_guess_policy(cnn, scaling, 1.0)
+    api.ac_problem_attach_cnn(p, cnn)
+    off = api.ac_spectral_offsets(p, precision)
+    dt = torch.float64 if precision == L.AC_PREC_FP64 else torch.float32
+    rhat = torch.zeros(off[-1], dtype=dt, device="cuda:0")
+    api.ac_tdft_forward(p, precision, G.dev(rng.standard_normal(ell * nx * ny)), rhat)
+    ws = api.workspace(api.ac_cnn_guess_workspace_size(p))
+    out = []
+    for fused in (False, True):
+        api.ac_cnn_set_inference(cnn, fused)
+        x0 = torch.zeros_like(rhat)
+        rej = api.ac_cnn_guess(p, precision, rhat, x0, ws)
+        out.append((G.host(x0), rej))
+    assert out[0][1] == out[1][1] < p.ns
+    if scaling:
+        assert G.max_rel(out[1][0], out[0][0]) < 1e-5
+    else:
+        assert np.array_equal(out[1][0], out[0][0])
+    assert np.abs(out[1][0]).max() > 0
