@@ -106,6 +106,47 @@ def sequential_solve(A: sp.spmatrix, b: np.ndarray, ell: int) -> np.ndarray:
     return X.reshape(-1)
 
 
+# ---------------------------------------------------------------------------
+# Varying diagonal blocks (Conclusions): calA = blockdiag(A_1, ..., A_l) - S (x) I,
+# preconditioned through a representative block A_hat.
+
+def build_calA_blocks(As) -> sp.csr_matrix:
+    """All-at-once matrix with block k on the diagonal and -I below it."""
+    ell, n = len(As), As[0].shape[0]
+    return (sp.block_diag(As) - sp.kron(shift_matrix(ell), sp.identity(n))).tocsr()
+
+
+def apply_calA_blocks(As, x: np.ndarray) -> np.ndarray:
+    """y_k = A_k x_k - x_{k-1} (x_0 := 0)."""
+    ell, n = len(As), As[0].shape[0]
+    X = x.reshape(ell, n)
+    Y = np.empty_like(X, dtype=np.float64)
+    for k in range(ell):
+        Y[k] = As[k] @ X[k]
+        if k > 0:
+            Y[k] -= X[k - 1]
+    return Y.reshape(-1)
+
+
+def sequential_solve_blocks(As, b: np.ndarray) -> np.ndarray:
+    """The chain A_1 x_1 = b_1, A_k x_k = b_k + x_{k-1}."""
+    ell, n = len(As), As[0].shape[0]
+    B = b.reshape(ell, n)
+    X = np.empty((ell, n))
+    prev = np.zeros(n)
+    for k in range(ell):
+        X[k] = spla.spsolve(As[k].tocsc(), B[k] + prev)
+        prev = X[k]
+    return X.reshape(-1)
+
+
+def mean_block_kappa(kappas: np.ndarray) -> np.ndarray:
+    """Cell coefficients of the representative block: the pointwise mean of the
+    blocks' coefficients.  A is affine in kappa (face values are means of cell
+    values), so A(mean kappa) is the mean of the blocks A_k."""
+    return np.asarray(kappas, dtype=np.float64).reshape(len(kappas), -1).mean(axis=0)
+
+
 def dirichlet_eigs_1d(n: int, kappa: float) -> np.ndarray:
     """Eigenvalues 1 + 4 kappa sin^2(k pi / (2(n+1))), k = 1..n (Appendix A, 1D factor)."""
     k = np.arange(1, n + 1)

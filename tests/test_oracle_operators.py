@@ -123,3 +123,41 @@ def test_all_at_once_equals_sequential(ell):
     x2 = np.linalg.solve(A.toarray(), x1)
     assert np.allclose(x_seq[:n], x1, rtol=1e-13, atol=1e-15)
     assert np.allclose(x_seq[n:2 * n], x2, rtol=1e-13, atol=1e-15)
+
+
+def test_varying_blocks_reduce_to_constant_blocks():
+    rng = np.random.default_rng(21)
+    nx, ny, ell = 6, 5, 4
+    kap = rng.uniform(0.5, 3.0, nx * ny)
+    A = ops.build_A(2, nx, ny, kap)
+    x = rng.standard_normal(ell * nx * ny)
+    assert np.allclose(ops.apply_calA_blocks([A] * ell, x), ops.apply_calA(A, x, ell), rtol=0, atol=1e-14)
+    assert abs(ops.build_calA_blocks([A] * ell) - ops.build_calA(A, ell)).max() == 0
+
+
+def test_varying_blocks_sequential_equals_direct_solve():
+    rng = np.random.default_rng(22)
+    nx, ny, ell = 5, 4, 5
+    kaps = rng.uniform(0.2, 4.0, (ell, nx * ny))
+    As = [ops.build_A(2, nx, ny, k) for k in kaps]
+    b = rng.standard_normal(ell * nx * ny)
+    M = ops.build_calA_blocks(As).toarray()
+    # block structure by hand: A_k on the diagonal, -I below it
+    n = nx * ny
+    for k in range(ell):
+        assert np.array_equal(M[k * n:(k + 1) * n, k * n:(k + 1) * n], As[k].toarray())
+        if k > 0:
+            assert np.array_equal(M[k * n:(k + 1) * n, (k - 1) * n:k * n], -np.eye(n))
+    x = ops.sequential_solve_blocks(As, b)
+    assert np.linalg.norm(M @ x - b) < 1e-12 * np.linalg.norm(b)
+    assert np.allclose(x, np.linalg.solve(M, b), rtol=0, atol=1e-12)
+
+
+def test_mean_kappa_gives_the_mean_block():
+    """A is affine in the cell coefficients: A(mean kappa_k) = mean A(kappa_k)."""
+    rng = np.random.default_rng(23)
+    nx, ny, ell = 7, 3, 6
+    kaps = rng.uniform(0.1, 5.0, (ell, nx * ny))
+    Am = ops.build_A(2, nx, ny, ops.mean_block_kappa(kaps))
+    mean = sum(ops.build_A(2, nx, ny, k) for k in kaps) / ell
+    assert abs(Am - mean).max() < 1e-13
