@@ -176,6 +176,17 @@ int ac_ctx_set_tiling(ac_ctx* ctx, int rows_per_wave, int waves_per_block, int p
 int ac_problem_create(ac_ctx* ctx, const ac_grid* grid, const double* kappa_dev, int ell, double alpha,
                       const ac_bounds* bounds, ac_problem** out);
 int ac_problem_destroy(ac_problem* p);
+/* Varying diagonal blocks A_1, ..., A_l (the extension named in the Conclusions):
+ * calA = blockdiag(A_k) - S (x) I_N with A_k built from the k-th coefficient field of
+ * kappa_blocks (device, l * N float64, block-major, each finite and positive).  The
+ * preconditioner uses the representative block A(mean_k kappa_k), which equals the
+ * mean of the A_k (A is affine in kappa); its spectral bounds and the alpha check
+ * refer to that block.  Every ac_* call on the problem then applies the varying
+ * blocks in calA (ac_apply_A, the residuals of ac_solve).  Corollary 1 no longer
+ * bounds the spectrum, so the outer Chebyshev iteration and batched solves return
+ * AC_ERR_UNSUPPORTED; FGMRES is the outer solver.  Synchronises. */
+int ac_problem_create_blocks(ac_ctx* ctx, const ac_grid* grid, const double* kappa_blocks, int ell, double alpha,
+                             const ac_bounds* bounds, ac_problem** out);
 /* Interval used for the FP64 inner solve (host outputs). */
 int ac_spectral_bounds(const ac_problem* p, double* mu_lo, double* mu_hi);
 /* Sizes: N, l and l_s = floor(l/2) + 1 (host outputs, any may be NULL). */

@@ -96,6 +96,7 @@ SIGNATURES = {
     "ac_ctx_reset_stats": (_I, [_VP]),
     "ac_ctx_set_tiling": (_I, [_VP, _I, _I, _I]),
     "ac_problem_create": (_I, [_VP, C.POINTER(ac_grid), _VP, _I, _D, C.POINTER(ac_bounds), C.POINTER(_VP)]),
+    "ac_problem_create_blocks": (_I, [_VP, C.POINTER(ac_grid), _VP, _I, _D, C.POINTER(ac_bounds), C.POINTER(_VP)]),
     "ac_problem_destroy": (_I, [_VP]),
     "ac_spectral_bounds": (_I, [_VP, C.POINTER(_D), C.POINTER(_D)]),
     "ac_problem_dims": (_I, [_VP, C.POINTER(C.c_longlong), C.POINTER(_I), C.POINTER(_I)]),

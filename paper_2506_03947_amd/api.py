@@ -141,6 +141,22 @@ def ac_problem_create(ctx: Ctx, dim: int, nx: int, ny: int, kappa: torch.Tensor,
     return Problem(h, ctx, nn.value, ee.value, ns.value)
 
 
+def ac_problem_create_blocks(ctx: Ctx, dim: int, nx: int, ny: int, kappa_blocks: torch.Tensor, ell: int,
+                             alpha: float, bc: int = L.AC_BC_DIRICHLET,
+                             bounds: tuple[float, float] | None = None) -> Problem:
+    """Varying diagonal blocks: kappa_blocks holds l coefficient fields (l * N float64)."""
+    lib = L.load()
+    g = L.ac_grid(dim, nx, ny, bc)
+    kp = _f64(kappa_blocks, ell * nx * ny, "kappa_blocks")
+    bp = C.byref(L.ac_bounds(float(bounds[0]), float(bounds[1]))) if bounds is not None else None
+    h = C.c_void_p()
+    check(lib.ac_problem_create_blocks(ctx.h, C.byref(g), kp, ell, float(alpha), bp, C.byref(h)),
+          "ac_problem_create_blocks")
+    nn, ee, ns = C.c_longlong(), C.c_int(), C.c_int()
+    check(lib.ac_problem_dims(h, C.byref(nn), C.byref(ee), C.byref(ns)), "ac_problem_dims")
+    return Problem(h, ctx, nn.value, ee.value, ns.value)
+
+
 def ac_spectral_bounds(p: Problem) -> tuple[float, float]:
     lo, hi = C.c_double(), C.c_double()
     check(L.load().ac_spectral_bounds(p.h, C.byref(lo), C.byref(hi)), "ac_spectral_bounds")

@@ -132,6 +132,9 @@ hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipS
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);
+// Varying diagonal blocks: a.kappa holds l coefficient fields (block-major); residual
+// mode writes l * tiles partials (index k * tiles + tile).
+hipError_t launch_apply_calA_var(int ell, bool resid, const CalAArgs& a, hipStream_t s);
 // One batched launch of op (BatchOp) for lists whose entries share l, precision,
 // operand kind (sweeps), points per lane and waves per block; Dirichlet grids only.
 hipError_t launch_batch(int op, int ell, int prec, int curk, int vx, const BatchList& L, hipStream_t s);
@@ -222,6 +225,9 @@ hipError_t launch_zero_bytes(void* buf, long long off_bytes, long long nbytes, h
 // ---- setup kernels (setup.hip) -----------------------------------------------
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,
                               int nblk, hipStream_t s);
+// Pointwise mean of l coefficient fields; bad[b] (setup_blocks() entries) counts the
+// entries that are not finite and positive.
+hipError_t launch_kappa_mean(const double* kb, int ell, long long n, double* mean, double* bad, hipStream_t s);
 int setup_blocks();
 
 }  // namespace ac

@@ -104,6 +104,7 @@ struct ac_problem {
     double bounds[3][2] = {};  // per precision: mu_lo, mu_hi
     double kmin64 = 0;
     double* rpart = nullptr;   // per-block partial sums of the warm-start residual test
+    double* kblocks = nullptr; // varying diagonal blocks: l coefficient fields for calA (k64 is their mean)
     ac_cnn* cnn = nullptr;     // warm-start network (not owned)
     // sweep tiling chosen for this problem (0 = the context's setting)
     int tile_h = 0, tile_wpb = 0, tile_vx = 0;
@@ -811,18 +812,22 @@ int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double
     a.b = b;
     a.partial = partial;
     a.ell = p->ell;
+    if (p->kblocks) a.kappa = p->kblocks;
     if (p->ctx->rec) {
         if (b) return fail(AC_ERR_UNSUPPORTED, "residual-mode calA is not recorded");
+        if (p->kblocks) return fail(AC_ERR_UNSUPPORTED, "varying diagonal blocks are not batched");
         record_launch(p->ctx, ac::BOP_CALA, p->ell, 0, 0, a.t.vx, a.t.wpb, a.t.blocks, a);
         return AC_OK;
     }
-    const double bytes = (b ? 24.0 : 16.0) * p->ell * p->g.n + 8.0 * p->g.n;
+    const double kbytes = p->kblocks ? 8.0 * p->ell * p->g.n : 8.0 * p->g.n;
+    const double bytes = (b ? 24.0 : 16.0) * p->ell * p->g.n + kbytes;
     ProfScope ps(p->ctx, AC_K_APPLY_CALA, bytes);
-    AC_HIP(ac::launch_apply_calA(p->ell, b != nullptr, a, p->ctx->stream));
+    if (p->kblocks) AC_HIP(ac::launch_apply_calA_var(p->ell, b != nullptr, a, p->ctx->stream));
+    else AC_HIP(ac::launch_apply_calA(p->ell, b != nullptr, a, p->ctx->stream));
     return AC_OK;
 }
 
-long long calA_partials(const ac_problem* p) { return calA_tiling(p).tiles; }
+long long calA_partials(const ac_problem* p) { return calA_tiling(p).tiles * (p->kblocks ? p->ell : 1); }
 
 }  // namespace
 
@@ -1013,6 +1018,60 @@ int ac_problem_create(ac_ctx* c, const ac_grid* grid, const double* kappa, int e
     return AC_OK;
 }
 
+int ac_problem_create_blocks(ac_ctx* c, const ac_grid* grid, const double* kappa_blocks, int ell, double alpha,
+                             const ac_bounds* bounds, ac_problem** out) {
+    if (!out) return fail(AC_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!c || !grid || !kappa_blocks) return fail(AC_ERR_ARG, "NULL argument");
+    if (ell < 2 || ell > kMaxEll) return fail(AC_ERR_UNSUPPORTED, "l must be in [2, 16]");
+    if (grid->nx < 1 || grid->ny < 1) return fail(AC_ERR_ARG, "grid sizes must be positive");
+    if (static_cast<long long>(grid->nx) * grid->ny > (1LL << 31) - 1) return fail(AC_ERR_UNSUPPORTED, "N too large");
+    AC_HIP(hipSetDevice(c->device));
+    const size_t n = static_cast<size_t>(grid->nx) * static_cast<size_t>(grid->ny);
+    const int nblk = ac::setup_blocks();
+    double* mean = nullptr;
+    double* bad = nullptr;
+    double* kb = nullptr;
+    auto cleanup = [&]() {
+        if (mean) (void)hipFree(mean);
+        if (bad) (void)hipFree(bad);
+        if (kb) (void)hipFree(kb);
+    };
+    hipError_t e = hipMalloc(&mean, n * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&bad, nblk * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&kb, static_cast<size_t>(ell) * n * sizeof(double));
+    if (e == hipSuccess) e = hipMemcpyAsync(kb, kappa_blocks, static_cast<size_t>(ell) * n * sizeof(double),
+                                            hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = ac::launch_kappa_mean(kb, ell, static_cast<long long>(n), mean, bad, c->stream);
+    std::vector<double> h(nblk);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), bad, nblk * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        cleanup();
+        return fail(AC_ERR_HIP, std::string("block coefficients: ") + hipGetErrorString(e));
+    }
+    double nbad = 0.0;
+    for (double v : h) nbad += v;
+    if (nbad != 0.0) {
+        cleanup();
+        return fail(AC_ERR_NONFINITE, "every block's kappa must be finite and positive");
+    }
+    // the representative block A(mean kappa) defines the preconditioner and its bounds
+    ac_problem* p = nullptr;
+    const int st = ac_problem_create(c, grid, mean, ell, alpha, bounds, &p);
+    (void)hipFree(mean);
+    mean = nullptr;
+    (void)hipFree(bad);
+    bad = nullptr;
+    if (st < 0) {
+        cleanup();
+        return st;
+    }
+    p->kblocks = kb;
+    *out = p;
+    return AC_OK;
+}
+
 int ac_problem_destroy(ac_problem* p) {
     if (!p) return AC_OK;
     (void)hipSetDevice(p->ctx->device);
@@ -1021,6 +1080,7 @@ int ac_problem_destroy(ac_problem* p) {
     (void)hipFree(p->k32);
     (void)hipFree(p->k16);
     (void)hipFree(p->rpart);
+    if (p->kblocks) (void)hipFree(p->kblocks);
     delete p;
     return AC_OK;
 }
@@ -1245,6 +1305,8 @@ int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
                     void* ws, ac_solve_info* info, std::chrono::steady_clock::time_point t0) {
     if (o->inner != AC_INNER_CHEB)
         return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration needs a linear preconditioner");
+    if (p->kblocks)
+        return fail(AC_ERR_UNSUPPORTED, "no eigenvalue interval is known for varying diagonal blocks (use FGMRES)");
     ac_ctx* c = p->ctx;
     hipStream_t st = c->stream;
     const long long len = static_cast<long long>(p->ell) * p->g.n;
@@ -1557,6 +1619,7 @@ int validate_batch(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
         if (!probs[q]) return fail(AC_ERR_ARG, "NULL problem");
         if (probs[q]->ctx != c) return fail(AC_ERR_ARG, "every problem must belong to the context");
         if (probs[q]->g.periodic) return fail(AC_ERR_UNSUPPORTED, "batched solves take Dirichlet grids");
+        if (probs[q]->kblocks) return fail(AC_ERR_UNSUPPORTED, "batched solves take one block operator per problem");
         std::vector<int> pm;
         AC_TRY(validate_opts(probs[q], o, pm));
     }

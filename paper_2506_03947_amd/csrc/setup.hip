@@ -93,6 +93,32 @@ __global__ __launch_bounds__(kThreads) void kappa_setup_kernel(const Geom g, con
     }
 }
 
+// Pointwise mean of l coefficient fields (block-major) and per-block counts of
+// entries that are not finite and positive.
+__global__ __launch_bounds__(kThreads) void kappa_mean_kernel(const double* __restrict__ kb, int ell, long long n,
+                                                              double* __restrict__ mean, double* __restrict__ bad) {
+    double nbad = 0.0;
+    const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
+    for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += step) {
+        double s = 0.0;
+        for (int k = 0; k < ell; ++k) {
+            const double v = kb[static_cast<long long>(k) * n + i];
+            if (!(v > 0.0 && v < 1.0e300)) nbad += 1.0;
+            s += v;
+        }
+        mean[i] = s / ell;
+    }
+    __shared__ double red[kThreads / 64];
+    for (int off = 32; off > 0; off >>= 1) nbad += __shfl_down(nbad, off, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nbad;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+        bad[blockIdx.x] = t;
+    }
+}
+
 }  // namespace
 
 int setup_blocks() { return kBlocks; }
@@ -100,6 +126,11 @@ int setup_blocks() { return kBlocks; }
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,
                               int nblk, hipStream_t s) {
     hipLaunchKernelGGL(kappa_setup_kernel, dim3(nblk), dim3(kThreads), 0, s, g, kappa, k32, k16, partial);
+    return hipGetLastError();
+}
+
+hipError_t launch_kappa_mean(const double* kb, int ell, long long n, double* mean, double* bad, hipStream_t s) {
+    hipLaunchKernelGGL(kappa_mean_kernel, dim3(kBlocks), dim3(kThreads), 0, s, kb, ell, n, mean, bad);
     return hipGetLastError();
 }
 
