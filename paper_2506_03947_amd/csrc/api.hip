@@ -207,6 +207,8 @@ void spectral_offsets(const ac_problem* p, long long* off) {
 // the group variant about 110 (four waves per SIMD), which hides more memory latency
 // at the price of reading kappa once per group.  Every shift is computed exactly as
 // in the all-shift variant.
+constexpr int kMaxGroups = 4;  // groups of (1 real, 2 complex) slots cover l <= 16
+
 bool use_shift_groups(const ac_problem* p) {
     const int mode = p->ctx->shift_groups;
     if (mode == 0) return false;
@@ -458,9 +460,11 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     int launched = 0;  // kernel launches of the current step (several with shift groups)
     // group g: real slot g (if any) and complex slots nsr + 2g, nsr + 2g + 1 (if any),
     // as slots 0, 1, 2 of the l = 5 variant; absent slots do not compute
-    auto launch_groups = [&](int curk, const ac::SweepArgs<R>& a) -> hipError_t {
+    // (recording for a batch: always kMaxGroups records per step, empty ones with no
+    // blocks, so that problems with different l record aligned sequences)
+    auto launch_groups = [&](int curk, const ac::SweepArgs<R>& a, bool rec) -> hipError_t {
         const int ngroups = std::max(p->nsr, (p->nsc + 1) / 2);
-        for (int grp = 0; grp < ngroups; ++grp) {
+        for (int grp = 0; grp < (rec ? kMaxGroups : ngroups); ++grp) {
             ac::SweepArgs<R> ga = a;
             const int map[3] = {grp < p->nsr ? grp : -1, 2 * grp < p->nsc ? p->nsr + 2 * grp : -1,
                                 2 * grp + 1 < p->nsc ? p->nsr + 2 * grp + 1 : -1};
@@ -485,6 +489,10 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 ga.cf.s_im[j] = a.cf.s_im[sl];
                 anyc = anyc || a.src[sl] == ac::SRC_COMPUTE;
             }
+            if (rec) {
+                record_launch(p->ctx, ac::BOP_STEP, 5, prec, curk, a.t.vx, a.t.wpb, anyc ? a.t.blocks : 0, ga);
+                continue;
+            }
             if (!anyc) continue;
             const hipError_t e = ac::launch_cheb_step(5, prec, curk, &ga, p->ctx->stream);
             if (e != hipSuccess) return e;
@@ -496,14 +504,14 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     auto launch = [&](bool fin, int curk, const ac::SweepArgs<R>& a) -> hipError_t {
         launched = 1;
         if (p->ctx->rec) {
-            record_launch(p->ctx, fin ? ac::BOP_FINAL : ac::BOP_STEP, p->ell, prec, curk, a.t.vx, a.t.wpb, a.t.blocks,
-                          a);
+            if (!fin) return launch_groups(curk, a, true);
+            record_launch(p->ctx, ac::BOP_FINAL, p->ell, prec, curk, a.t.vx, a.t.wpb, a.t.blocks, a);
             return hipSuccess;
         }
         if (fin) return ac::launch_cheb_final(p->ell, prec, curk, &a, p->ctx->stream);
         if (groups) {
             launched = 0;
-            return launch_groups(curk, a);
+            return launch_groups(curk, a, false);
         }
         return ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream);
     };
@@ -1592,12 +1600,12 @@ size_t max_args_bytes() {
                     std::max(sizeof(ac::FwdArgs), sizeof(ac::CalAArgs)));
 }
 
-// Device bytes for the work lists: per j at most p + 3 launch positions, each with
-// at most `count` groups.
+// Device bytes for the work lists: per j at most 4p + 3 launch positions (a sweep step
+// records kMaxGroups shift groups), each with at most `count` groups.
 size_t batch_list_bytes(int count, const ac_solve_opts* o) {
     const size_t per_pos = static_cast<size_t>(count) * (align_up(max_args_bytes(), 16) + 8) +
                            static_cast<size_t>(count) * (3 * 256 + 8);
-    return static_cast<size_t>(o->restart_m) * static_cast<size_t>(o->p_uniform + 3) * per_pos + 256;
+    return static_cast<size_t>(o->restart_m) * static_cast<size_t>(kMaxGroups * o->p_uniform + 3) * per_pos + 256;
 }
 
 size_t batch_ws_bytes(int count, ac_problem* const* probs, const ac_solve_opts* o) {
@@ -1737,13 +1745,16 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
         const size_t npos = recs[0].size();
         for (size_t i = 0; i < npos; ++i) {
             std::vector<int> done(count, 0);
+            for (int q = 0; q < count; ++q) {
+                if (recs[q][i].op != recs[0][i].op) return fail(AC_ERR_UNSUPPORTED, "batch launch sequences differ");
+                if (recs[q][i].blocks == 0) done[q] = 1;  // an empty shift group
+            }
             for (int q0 = 0; q0 < count; ++q0) {
                 if (done[q0]) continue;
                 const ac_launch_rec& r0 = recs[q0][i];
                 std::vector<int> members;
                 for (int q = q0; q < count; ++q) {
                     const ac_launch_rec& r = recs[q][i];
-                    if (r.op != r0.op) return fail(AC_ERR_UNSUPPORTED, "batch launch sequences differ");
                     if (!done[q] && r.ell == r0.ell && r.prec == r0.prec && r.curk == r0.curk && r.vx == r0.vx &&
                         r.wpb == r0.wpb) {
                         members.push_back(q);
