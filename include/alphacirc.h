@@ -74,12 +74,25 @@ typedef enum { AC_BC_DIRICHLET = 0, AC_BC_PERIODIC = 1 } ac_bc;
  *   AC_PREC_MIXED_FP32K complex64 iterates, float32 kappa */
 typedef enum { AC_PREC_FP64 = 0, AC_PREC_MIXED_BF16K = 1, AC_PREC_MIXED_FP32K = 2 } ac_precision;
 
-/* Inner initial guess: zero (the paper's method), or the learned warm start
- * attached with ac_problem_attach_cnn (makes the preconditioner nonlinear): for every
- * preconditioner application (AC_INNER_CHEB_CNN), or only for the first vector of
- * each FGMRES cycle, the true residual, with zero guesses inside the cycle
- * (AC_INNER_CHEB_CNN_CYCLE; ac_apply_prec treats it as AC_INNER_CHEB_CNN). */
-typedef enum { AC_INNER_CHEB = 0, AC_INNER_CHEB_CNN = 1, AC_INNER_CHEB_CNN_CYCLE = 2 } ac_inner;
+/* Inner shifted solves.  Chebyshev from a zero initial guess (the paper's method), or
+ * from the learned warm start attached with ac_problem_attach_cnn (makes the
+ * preconditioner nonlinear): for every preconditioner application
+ * (AC_INNER_CHEB_CNN), or only for the first vector of each FGMRES cycle, the true
+ * residual, with zero guesses inside the cycle (AC_INNER_CHEB_CNN_CYCLE; ac_apply_prec
+ * treats it as AC_INNER_CHEB_CNN).
+ * AC_INNER_EXACT applies P_alpha^{-1} itself (eq. (4) with direct shifted solves; the
+ * paper's reference preconditioner, Section 2 and Fig. 2): only for a constant
+ * coefficient on a Dirichlet grid, where the sine transform of Appendix A diagonalises
+ * A along x and every shifted solve reduces to tridiagonal systems along y (dense
+ * transforms by rocBLAS GEMMs in the inner precision).  p_uniform and p_per_shift are
+ * ignored and count no products with A.  AC_ERR_UNSUPPORTED for a varying coefficient
+ * (or varying diagonal blocks whose mean is not constant) or periodic grids. */
+typedef enum {
+    AC_INNER_CHEB = 0,
+    AC_INNER_CHEB_CNN = 1,
+    AC_INNER_CHEB_CNN_CYCLE = 2,
+    AC_INNER_EXACT = 3
+} ac_inner;
 
 typedef struct {
     int dim;   /* 1 or 2 */
@@ -98,7 +111,8 @@ typedef struct {
  *   AC_OUTER_CHEBYSHEV  the paper's outer solver: Chebyshev semi-iteration on
  *                       P^{-1} calA with the eigenvalue interval of Corollary 1,
  *                       [1, mu_lo^l / (mu_lo^l - alpha)], mu_lo the lower spectral bound
- *                       of A; valid for a linear preconditioner (AC_INNER_CHEB). */
+ *                       of A; valid for a linear preconditioner (AC_INNER_CHEB,
+ *                       AC_INNER_EXACT). */
 typedef enum { AC_OUTER_FGMRES = 0, AC_OUTER_CHEBYSHEV = 1 } ac_outer;
 
 typedef struct {
@@ -134,7 +148,8 @@ typedef enum {
     AC_K_KRYLOV = 4,     /* multi-dot / multi-axpy / norms, float64 */
     AC_K_CNN = 5,        /* warm-start network */
     AC_K_CHEB_FIRST = 6, /* the first sweep from a zero guess (x_2 from x_1 = rhat/theta) */
-    AC_K_COUNT = 7
+    AC_K_EXACT = 7,      /* AC_INNER_EXACT: sine transforms, tridiagonal solves, inverse time-DFT */
+    AC_K_COUNT = 8
 } ac_kernel_class;
 
 /* ---- status ------------------------------------------------------------- */
@@ -228,7 +243,8 @@ int ac_spectral_offsets(const ac_problem* p, int precision, long long* offsets);
 /* rhat_m = sum_k alpha^{k/l} r_k exp(-2 pi i m k / l), m = 0..l_s-1 (unnormalised). */
 int ac_tdft_forward(ac_problem* p, int precision, const double* r, void* rhat);
 /* yhat_m = p_m Chebyshev steps on (A - lambda_m I) y = rhat_m from zero (or from x0hat
- * when non-NULL, same layout).  yhat may not alias rhat. */
+ * when non-NULL, same layout).  yhat may not alias rhat.  AC_ERR_UNSUPPORTED for
+ * inner = AC_INNER_EXACT. */
 int ac_shifted_cheb(ac_problem* p, const ac_solve_opts* opts, const void* rhat, const void* x0hat, void* yhat,
                     void* ws, size_t ws_bytes);
 /* z_k = alpha^{-k/l} (1/l) Re sum_{m=0}^{l-1} yhat_m exp(+2 pi i m k / l), using

@@ -32,6 +32,7 @@ AC_PREC_MIXED_FP32K = 2
 AC_INNER_CHEB = 0
 AC_INNER_CHEB_CNN = 1
 AC_INNER_CHEB_CNN_CYCLE = 2
+AC_INNER_EXACT = 3
 AC_OUTER_FGMRES = 0
 AC_OUTER_CHEBYSHEV = 1
 
@@ -42,8 +43,9 @@ AC_K_APPLY_CALA = 3
 AC_K_KRYLOV = 4
 AC_K_CNN = 5
 AC_K_CHEB_FIRST = 6
-AC_K_COUNT = 7
-KERNEL_CLASS_NAMES = ["tdft_fwd", "cheb_step", "cheb_final", "apply_calA", "krylov", "cnn", "cheb_first"]
+AC_K_EXACT = 7
+AC_K_COUNT = 8
+KERNEL_CLASS_NAMES = ["tdft_fwd", "cheb_step", "cheb_final", "apply_calA", "krylov", "cnn", "cheb_first", "exact"]
 
 
 class ac_grid(C.Structure):

@@ -222,6 +222,28 @@ hipError_t launch_cnn_resid(int prec, const CnnPrepArgs& a, const void* x0buf, c
                             int nblk, hipStream_t s);
 hipError_t launch_zero_bytes(void* buf, long long off_bytes, long long nbytes, hipStream_t s);
 
+// ---- exact shifted solves for a constant coefficient (exact.hip) -------------
+// Slot s of a spectral buffer (interleaved complex, or real) maps to plane
+// plane[s] (and plane[s] + 1 for the imaginary part) of a planar buffer of
+// n-point planes; lambda_s = lr[s] + i li[s].
+struct ExactArgs {
+    long long n;
+    int nx, ny, dim, nslot;
+    double kappa;
+    void* slot[kMaxShift];
+    int cplx[kMaxShift];
+    int plane[kMaxShift];
+    double lr[kMaxShift], li[kMaxShift];
+};
+// prec 0: double, else float.  S: n x n orthonormal DST-I matrix (symmetric).
+hipError_t launch_dst_matrix(int prec, void* S, int n, hipStream_t s);
+// split: spectral slots -> planes; else planes -> spectral slots
+hipError_t launch_exact_planes(int prec, bool split, const ExactArgs& a, void* planes, hipStream_t s);
+// In the sine basis along x, solve the tridiagonal systems along y of every slot:
+// t holds the transformed right-hand sides (overwritten by elimination factors),
+// the solutions go to u.
+hipError_t launch_exact_tridiag(int prec, const ExactArgs& a, void* t, void* u, hipStream_t s);
+
 // ---- setup kernels (setup.hip) -----------------------------------------------
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,
                               int nblk, hipStream_t s);

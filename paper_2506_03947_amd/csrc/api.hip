@@ -2,6 +2,7 @@
 // flexible GMRES outer solve.  Host orchestration only; every vector operation
 // runs in the kernels of stencil.hip / krylov.hip / setup.hip.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <array>
@@ -39,6 +40,13 @@ int fail(int status, const std::string& msg) {
         hipError_t e_ = (call);                                                                      \
         if (e_ != hipSuccess)                                                                        \
             return fail(AC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));              \
+    } while (0)
+
+#define AC_BLAS(call)                                                                                \
+    do {                                                                                             \
+        rocblas_status b_ = (call);                                                                  \
+        if (b_ != rocblas_status_success)                                                            \
+            return fail(AC_ERR_HIP, std::string(#call) + ": " + rocblas_status_to_string(b_));       \
     } while (0)
 
 #define AC_TRY(call)              \
@@ -85,6 +93,8 @@ struct ac_ctx {
     std::vector<ac_launch_rec>* rec = nullptr;
     // steady sweeps in shift groups: -1 automatic (5 or more unique shifts), 0 off, 1 on
     int shift_groups = -1;
+    // dense sine transforms of the exact inner solve (workspace set per call)
+    rocblas_handle blas = nullptr;
 };
 
 constexpr int kResidBlocks = 512;  // blocks of the warm-start residual-statistics kernel
@@ -102,7 +112,7 @@ struct ac_problem {
     float* k32 = nullptr;
     uint16_t* k16 = nullptr;
     double bounds[3][2] = {};  // per precision: mu_lo, mu_hi
-    double kmin64 = 0;
+    double kmin64 = 0, kmax64 = 0;
     double* rpart = nullptr;   // per-block partial sums of the warm-start residual test
     double* kblocks = nullptr; // varying diagonal blocks: l coefficient fields for calA (k64 is their mean)
     ac_cnn* cnn = nullptr;     // warm-start network (not owned)
@@ -293,10 +303,16 @@ ChebShift cheb_tables(const ac_problem* p, int prec, int m, int steps) {
 int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>& pm) {
     if (!o) return fail(AC_ERR_ARG, "opts is NULL");
     if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
-    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN && o->inner != AC_INNER_CHEB_CNN_CYCLE)
+    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN && o->inner != AC_INNER_CHEB_CNN_CYCLE &&
+        o->inner != AC_INNER_EXACT)
         return fail(AC_ERR_ARG, "unknown inner mode");
-    if (o->inner != AC_INNER_CHEB && !p->cnn) return fail(AC_ERR_ARG, "no warm-start network attached");
     pm.assign(p->ell, 0);
+    if (o->inner == AC_INNER_EXACT) {
+        if (p->g.periodic) return fail(AC_ERR_UNSUPPORTED, "the exact inner solve needs Dirichlet boundaries");
+        if (p->kmin64 != p->kmax64) return fail(AC_ERR_UNSUPPORTED, "the exact inner solve needs a constant coefficient");
+        return AC_OK;
+    }
+    if (o->inner != AC_INNER_CHEB && !p->cnn) return fail(AC_ERR_ARG, "no warm-start network attached");
     for (int m = 0; m < p->ell; ++m) {
         const int v = o->p_per_shift ? o->p_per_shift[m] : o->p_uniform;
         if (v < 1 || v > 100000) return fail(AC_ERR_ARG, "inner iteration counts must be in [1, 100000]");
@@ -314,18 +330,27 @@ size_t cnn_ws_bytes(const ac_problem* p) {
     return 3 * align_up(px * 32, 256) + align_up(px * 8, 256) + 256;
 }
 
+// rocBLAS workspace of the exact inner solve (plain GEMMs of these shapes need none;
+// the margin is for library kernels that split the reduction)
+constexpr size_t kBlasWs = 32u << 20;
+
+size_t exact_extra_bytes(const ac_problem* p, int prec) {
+    return align_up(static_cast<size_t>(p->g.nx) * p->g.nx * inner_elem(prec), 256) + kBlasWs;
+}
+
 size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     size_t b = 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
-    if (inner != AC_INNER_CHEB) b += cnn_ws_bytes(p);
+    if (inner == AC_INNER_EXACT) b += exact_extra_bytes(p, prec);
+    else if (inner != AC_INNER_CHEB) b += cnn_ws_bytes(p);
     return b;
 }
 
 struct PrecBufs {
     char* rhat;
     char* buf[2];
-    char* cnn;  // start of the CNN buffers (valid when they were sized in)
+    char* cnn;  // start of the CNN buffers or of the exact solve's extra buffers
 };
 
 PrecBufs carve_prec(const ac_problem* p, int prec, void* ws) {
@@ -797,11 +822,86 @@ int cnn_warm_start(ac_problem* p, int prec, const char* rhat, char* x0buf, char*
     return AC_OK;
 }
 
+ac::InvArgs inv_args(const ac_problem* p, int prec, char* yhat, double* z) {
+    ac::InvArgs a{};
+    a.n = p->g.n;
+    for (int k = 0; k < p->ell; ++k) a.ginv[k] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(k) / p->ell));
+    fill_twiddles(p->ell, a.cw, a.sw);
+    for (int s = 0; s < p->ns; ++s) a.yhat[s] = slot_ptr(p, prec, yhat, s);
+    a.z = z;
+    return a;
+}
+
+// Exact shifted solves (A - lambda_m I) yhat_m = rhat_m for a constant coefficient,
+// then the inverse time-DFT into z.  The slots are split into planes P (one per real
+// slot, two per complex slot), transformed by T = S_x P (one GEMM over all planes),
+// solved along y into P, transformed back T = S_x P and merged into the rhat slots.
+int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
+    ac_ctx* c = p->ctx;
+    hipStream_t st = c->stream;
+    const int nx = p->g.nx, ny = p->g.ny;
+    char* P = b.buf[0];
+    char* T = b.buf[1];
+    char* S = b.cnn;
+    char* bw = S + align_up(static_cast<size_t>(nx) * nx * inner_elem(prec), 256);
+    ac::ExactArgs a{};
+    a.n = p->g.n;
+    a.nx = nx;
+    a.ny = ny;
+    a.dim = p->g.dim;
+    a.nslot = p->ns;
+    a.kappa = p->kmin64;
+    int planes = 0;
+    for (int s = 0; s < p->ns; ++s) {
+        const cplx lam = shift_of(p, slot_to_m(p, s));
+        a.slot[s] = slot_ptr(p, prec, b.rhat, s);
+        a.cplx[s] = slot_is_real(p, s) ? 0 : 1;
+        a.plane[s] = planes;
+        // the real slots' shifts are real; drop the rounding residue of the polar form
+        a.lr[s] = lam.real();
+        a.li[s] = a.cplx[s] ? lam.imag() : 0.0;
+        planes += a.cplx[s] ? 2 : 1;
+    }
+    const double esz = static_cast<double>(inner_elem(prec));
+    const double pn = static_cast<double>(planes) * p->g.n;
+    // split/merge 4 pn, two GEMM operand passes 4 pn + S twice, tridiagonal 6 pn, inverse DFT
+    const double bytes = esz * (14.0 * pn + 2.0 * nx * nx) + 8.0 * p->ell * p->g.n +
+                         esz * static_cast<double>(p->nsr + 2 * p->nsc) * p->g.n;
+    ProfScope ps(c, AC_K_EXACT, bytes);
+    AC_HIP(ac::launch_dst_matrix(prec, S, nx, st));
+    AC_HIP(ac::launch_exact_planes(prec, true, a, P, st));
+    AC_BLAS(rocblas_set_stream(c->blas, st));
+    AC_BLAS(rocblas_set_workspace(c->blas, bw, kBlasWs));
+    const rocblas_int m = nx, n = static_cast<rocblas_int>(static_cast<long long>(ny) * planes), k = nx;
+    auto gemm = [&](const char* Bm, char* Cm) -> int {
+        if (prec == AC_PREC_FP64) {
+            const double one = 1.0, zero = 0.0;
+            AC_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m, n, k, &one,
+                                  reinterpret_cast<const double*>(S), nx, reinterpret_cast<const double*>(Bm), nx,
+                                  &zero, reinterpret_cast<double*>(Cm), nx));
+        } else {
+            const float one = 1.0f, zero = 0.0f;
+            AC_BLAS(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m, n, k, &one,
+                                  reinterpret_cast<const float*>(S), nx, reinterpret_cast<const float*>(Bm), nx,
+                                  &zero, reinterpret_cast<float*>(Cm), nx));
+        }
+        return AC_OK;
+    };
+    AC_TRY(gemm(P, T));
+    AC_HIP(ac::launch_exact_tridiag(prec, a, T, P, st));
+    AC_TRY(gemm(P, T));
+    AC_HIP(ac::launch_exact_planes(prec, false, a, T, st));
+    AC_HIP(ac::launch_tdft_inv(p->ell, prec, inv_args(p, prec, b.rhat, z), st));
+    return AC_OK;
+}
+
 int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* r, double* z,
                     void* ws, double in_scale, int* fallbacks = nullptr) {
     const PrecBufs b = carve_prec(p, o->precision, ws);
     AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
-    if (o->inner != AC_INNER_CHEB) {
+    if (o->inner == AC_INNER_EXACT) {
+        AC_TRY(exact_inner(p, o->precision, b, z));
+    } else if (o->inner != AC_INNER_CHEB) {
         AC_TRY(cnn_warm_start(p, o->precision, b.rhat, b.buf[0], b.cnn, fallbacks));
         AC_TRY(run_cheb(p, o->precision, pm, b.rhat, b.buf, true, z, nullptr));
     } else {
@@ -874,6 +974,12 @@ int ac_ctx_create(int device, void* stream, ac_ctx** out) {
         delete c;
         return fail(AC_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
+    const rocblas_status bs = rocblas_create_handle(&c->blas);
+    if (bs != rocblas_status_success) {
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return fail(AC_ERR_HIP, std::string("rocblas_create_handle: ") + rocblas_status_to_string(bs));
+    }
     *out = c;
     return AC_OK;
 }
@@ -890,6 +996,7 @@ int ac_ctx_destroy(ac_ctx* c) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
     }
+    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
     return AC_OK;
@@ -970,10 +1077,10 @@ int ac_problem_create(ac_ctx* c, const ac_grid* grid, const double* kappa, int e
     if (e == hipSuccess) e = hipMalloc(&p->k32, align_up(n * sizeof(float), 256));
     if (e == hipSuccess) e = hipMalloc(&p->k16, align_up(n * sizeof(uint16_t), 256));
     if (e == hipSuccess) e = hipMalloc(&p->rpart, static_cast<size_t>(kResidBlocks) * 4 * kMaxShift * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&partial, nblk * 7 * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&partial, nblk * 8 * sizeof(double));
     if (e == hipSuccess) e = hipMemcpyAsync(p->k64, kappa, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = ac::launch_kappa_setup(p->g, p->k64, p->k32, p->k16, partial, nblk, c->stream);
-    std::vector<double> h(nblk * 7);
+    std::vector<double> h(nblk * 8);
     if (e == hipSuccess)
         e = hipMemcpyAsync(h.data(), partial, h.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -983,10 +1090,13 @@ int ac_problem_create(ac_ctx* c, const ac_grid* grid, const double* kappa, int e
     }
     (void)hipFree(partial);
     partial = nullptr;
-    double q[7] = {1e308, 0, 1e308, 0, 1e308, 0, 0};
+    // 0 min kappa, 1 max Gershgorin (float64), 2/3 the same in float32, 4/5 in bf16,
+    // 6 count of invalid kappa, 7 max kappa
+    double q[8] = {1e308, 0, 1e308, 0, 1e308, 0, 0, 0};
     for (int b = 0; b < nblk; ++b) {
-        for (int i = 0; i < 6; ++i) q[i] = (i % 2 == 0) ? std::min(q[i], h[b * 7 + i]) : std::max(q[i], h[b * 7 + i]);
-        q[6] += h[b * 7 + 6];
+        for (int i = 0; i < 6; ++i) q[i] = (i % 2 == 0) ? std::min(q[i], h[b * 8 + i]) : std::max(q[i], h[b * 8 + i]);
+        q[6] += h[b * 8 + 6];
+        q[7] = std::max(q[7], h[b * 8 + 7]);
     }
     if (q[6] != 0.0 || !(q[0] > 0.0)) {
         cleanup();
@@ -999,6 +1109,7 @@ int ac_problem_create(ac_ctx* c, const ac_grid* grid, const double* kappa, int e
         if (p->g.dim == 2) lmin += 4.0 * std::pow(std::sin(kPi / (2.0 * (p->g.ny + 1))), 2);
     }
     p->kmin64 = q[0];
+    p->kmax64 = q[7];
     if (bounds) {
         if (!(bounds->mu_lo >= 1.0 - 1e-12) || !(bounds->mu_hi >= bounds->mu_lo) || !std::isfinite(bounds->mu_hi)) {
             cleanup();
@@ -1270,6 +1381,7 @@ int ac_shifted_cheb(ac_problem* p, const ac_solve_opts* o, const void* rhat, con
     if (!p || !rhat || !yhat) return fail(AC_ERR_ARG, "NULL argument");
     std::vector<int> pm;
     AC_TRY(validate_opts(p, o, pm));
+    if (o->inner == AC_INNER_EXACT) return fail(AC_ERR_UNSUPPORTED, "ac_shifted_cheb runs the Chebyshev solves");
     if (!ws || ws_bytes < prec_ws_bytes(p, o->precision)) return fail(AC_ERR_WORKSPACE, "workspace too small");
     AC_HIP(hipSetDevice(p->ctx->device));
     const int prec = o->precision;
@@ -1290,12 +1402,7 @@ int ac_tdft_inverse(ac_problem* p, int prec, const void* yhat, double* z) {
     if (!p || !yhat || !z) return fail(AC_ERR_ARG, "NULL argument");
     if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
     AC_HIP(hipSetDevice(p->ctx->device));
-    ac::InvArgs a{};
-    a.n = p->g.n;
-    for (int k = 0; k < p->ell; ++k) a.ginv[k] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(k) / p->ell));
-    fill_twiddles(p->ell, a.cw, a.sw);
-    for (int s = 0; s < p->ns; ++s) a.yhat[s] = slot_ptr(p, prec, const_cast<char*>(static_cast<const char*>(yhat)), s);
-    a.z = z;
+    const ac::InvArgs a = inv_args(p, prec, const_cast<char*>(static_cast<const char*>(yhat)), z);
     AC_HIP(ac::launch_tdft_inv(p->ell, prec, a, p->ctx->stream));
     return AC_OK;
 }
@@ -1311,7 +1418,7 @@ namespace {
 // d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) z_{k+1}.
 int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* b, double* x,
                     void* ws, ac_solve_info* info, std::chrono::steady_clock::time_point t0) {
-    if (o->inner != AC_INNER_CHEB)
+    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_EXACT)
         return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration needs a linear preconditioner");
     if (p->kblocks)
         return fail(AC_ERR_UNSUPPORTED, "no eigenvalue interval is known for varying diagonal blocks (use FGMRES)");

@@ -9,7 +9,7 @@ namespace {
 
 constexpr int kBlocks = 512;
 constexpr int kThreads = 256;
-constexpr int kNQ = 7;
+constexpr int kNQ = 8;
 
 // float -> bfloat16 bits, round to nearest even (inputs are finite here)
 __device__ __forceinline__ uint16_t to_bf16_rne(float f) {
@@ -49,8 +49,8 @@ __device__ double gersh(const Geom& g, int ix, int iy, F kap) {
 
 __global__ __launch_bounds__(kThreads) void kappa_setup_kernel(const Geom g, const double* __restrict__ k64,
                                                                float* k32, uint16_t* k16, double* partial) {
-    // q: 0 min k64, 1 max gersh64, 2 min k32, 3 max gersh32, 4 min k16, 5 max gersh16, 6 bad count
-    double acc[kNQ] = {1e308, 0.0, 1e308, 0.0, 1e308, 0.0, 0.0};
+    // q: 0 min k64, 1 max gersh64, 2 min k32, 3 max gersh32, 4 min k16, 5 max gersh16, 6 bad count, 7 max k64
+    double acc[kNQ] = {1e308, 0.0, 1e308, 0.0, 1e308, 0.0, 0.0, 0.0};
     const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
     for (long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; i < g.n; i += step) {
         const double k = k64[i];
@@ -67,6 +67,7 @@ __global__ __launch_bounds__(kThreads) void kappa_setup_kernel(const Geom g, con
             return from_bf16(to_bf16_rne(static_cast<float>(k64[static_cast<long long>(y) * g.nx + x])));
         };
         acc[0] = fmin(acc[0], k);
+        acc[7] = fmax(acc[7], k);
         acc[1] = fmax(acc[1], gersh(g, ix, iy, a64));
         acc[2] = fmin(acc[2], static_cast<double>(kf));
         acc[3] = fmax(acc[3], gersh(g, ix, iy, a32));
