@@ -2,7 +2,7 @@
 mixed precision against float64 inner solves, with the shifted-stencil roofline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium]
-                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch]
+                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact]
 
 One step = one FGMRES(30) solve of calA x = b (b = (b_1, 0, ..., 0)) from x = 0
 on resident device inputs, preconditioned by the nested-Chebyshev block
@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
                          "(the launch set used for hardware-counter runs); batch: many uneven problems "
                          "solved one by one and as one batch")
@@ -143,6 +143,79 @@ def batch_mode(a):
     }))
 
 
+def exact_mode(a):
+    """Constant coefficient kappa = 50 on the 2048 x 2048 grid, l = 10, alpha = 1e-2:
+    FGMRES(restart) to 1e-8 with the exact P_alpha (inner float64 and float32) against
+    the nested-Chebyshev P_NC (p inner steps, complex64 / bfloat16 kappa) on the same
+    problem.  Reports seconds per solve, outer iterations and the per-application cost
+    of the exact inner solve (forward and inverse sine transforms, each two half-size
+    GEMMs of 2 (ceil(n_x/2)^2 + floor(n_x/2)^2) (n_y planes) flops, planes = real slots
+    + 2 complex slots)."""
+    import torch
+    from paper_2506_03947_amd import api
+    from synth import first_block_rhs
+    L = api.L
+    dev = torch.device("cuda:0")
+    nx = ny = 2048
+    ell, alpha, kappa = 10, 1e-2, 50.0
+    n = nx * ny
+    ctx = api.ac_ctx_create(0)
+    prob = api.ac_problem_create(ctx, 2, nx, ny, torch.full((n,), kappa, dtype=torch.float64, device=dev), ell,
+                                 alpha)
+    b = torch.from_numpy(first_block_rhs(n, ell, seed=a.seed)).to(dev)
+    planes = prob.ns + (prob.ns - (2 if ell % 2 == 0 else 1))  # real slots once, complex twice
+    h, h2 = (nx + 1) // 2, nx // 2
+    # forward and inverse sine transforms, each two half-size GEMMs (even / odd modes)
+    gemm_flops = 2 * 2.0 * (h * h + h2 * h2) * ny * planes
+    out = {}
+    cases = {"exact_f64": api.Opts(precision=L.AC_PREC_FP64, inner=L.AC_INNER_EXACT, tol=a.tol,
+                                   restart_m=a.restart, max_outer=3000),
+             "exact_f32": api.Opts(precision=L.AC_PREC_MIXED_FP32K, inner=L.AC_INNER_EXACT, tol=a.tol,
+                                   restart_m=a.restart, max_outer=3000),
+             "nested_cheb_p%d" % a.p: api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=a.p, tol=a.tol,
+                                               restart_m=a.restart, max_outer=3000)}
+    for name, opts in cases.items():
+        ws = api.workspace(api.ac_solve_workspace_size(prob, opts))
+        x = torch.zeros_like(b)
+        api.ac_solve(prob, opts, b, x, ws)  # warm-up (library kernels load here)
+        times = []
+        for _ in range(max(a.steps, 1)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = api.ac_solve(prob, opts, b, x, ws)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        api.ac_ctx_set_profiling(ctx, True)
+        api.ac_ctx_reset_stats(ctx)
+        x.zero_()
+        api.ac_solve(prob, opts, b, x, ws)
+        st = api.ac_ctx_kernel_stats(ctx)
+        api.ac_ctx_set_profiling(ctx, False)
+        rec = {"seconds": min(times), "outer_iters": info["outer_iters"], "converged": info["converged"],
+               "rel_residual": info["rel_residual_true"]}
+        if opts.inner == L.AC_INNER_EXACT:
+            e = st["exact"]
+            per = e["ms"] / max(e["launches"], 1)
+            rec.update({"exact_apply_ms": per, "gemm_flops_per_apply": gemm_flops,
+                        "gemm_TFLOPs_lower_bound": gemm_flops / per / 1e9})
+        log(f"{name}: {rec}")
+        out[name] = rec
+        del ws
+    f64 = out["exact_f64"]
+    print(json.dumps({
+        "metric": "seconds per all-at-once solve to 1e-8, exact P_alpha (constant kappa)", "value": f64["seconds"],
+        "unit": "s/solve", "n_gpus": 1, "steps": max(a.steps, 1), "warmup": 1, "ms_per_step": 1000 * f64["seconds"],
+        "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "2048x2048 constant kappa 50, l 10, alpha 1e-2, FGMRES(%d)" % a.restart},
+        "roofline": {"bound": "mfma", "achieved": f64["gemm_TFLOPs_lower_bound"], "peak": 78.6,
+                     "unit": "TFLOP/s", "frac": f64["gemm_TFLOPs_lower_bound"] / 78.6, "traffic": None,
+                     "note": "whole exact inner solve (GEMMs, tridiagonal, split/merge, inverse time-DFT) "
+                             "timed against the GEMM flops only"},
+        "cases": out,
+    }), flush=True)
+
+
 def kernels_only(a, api, prob, ell, n):
     """A few P_NC^{-1} applications in the solve's precision and launch shape, then a
     plain device copy of known size (reference for the FETCH_SIZE/WRITE_SIZE scale)."""
@@ -230,6 +303,9 @@ def main():
         sys.exit(2)
     if a.mode == "batch":
         batch_mode(a)
+        return
+    if a.mode == "exact":
+        exact_mode(a)
         return
     import torch
     from paper_2506_03947_amd import api

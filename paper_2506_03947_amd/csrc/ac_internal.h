@@ -235,14 +235,18 @@ struct ExactArgs {
     int plane[kMaxShift];
     double lr[kMaxShift], li[kMaxShift];
 };
-// prec 0: double, else float.  S: n x n orthonormal DST-I matrix (symmetric).
-hipError_t launch_dst_matrix(int prec, void* S, int n, hipStream_t s);
-// split: spectral slots -> planes; else planes -> spectral slots
+// prec 0: double, else float.  S: the even-mode and odd-mode halves of the n x n
+// orthonormal DST-I matrix, column-major, ceil(n/2)^2 + floor(n/2)^2 entries.
+long long dst_half_elems(int n);
+hipError_t launch_dst_half(int prec, void* S, int n, hipStream_t s);
+// split: spectral slots -> planes (with the even/odd butterfly along x); else the
+// inverse butterfly from planes -> spectral slots
 hipError_t launch_exact_planes(int prec, bool split, const ExactArgs& a, void* planes, hipStream_t s);
 // In the sine basis along x, solve the tridiagonal systems along y of every slot:
-// t holds the transformed right-hand sides (overwritten by elimination factors),
-// the solutions go to u.
-hipError_t launch_exact_tridiag(int prec, const ExactArgs& a, void* t, void* u, hipStream_t s);
+// t holds the transformed right-hand sides (overwritten), the solutions go to u.
+// carry: exact_carry_bytes(nx, ny, nslot) bytes of device scratch.
+size_t exact_carry_bytes(int nx, int ny, int nslot);
+hipError_t launch_exact_tridiag(int prec, const ExactArgs& a, void* t, void* u, void* carry, hipStream_t s);
 
 // ---- setup kernels (setup.hip) -----------------------------------------------
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,

@@ -334,8 +334,10 @@ size_t cnn_ws_bytes(const ac_problem* p) {
 // the margin is for library kernels that split the reduction)
 constexpr size_t kBlasWs = 32u << 20;
 
+// exact inner solve: DST matrix, tridiagonal-scan carries, rocBLAS workspace
 size_t exact_extra_bytes(const ac_problem* p, int prec) {
-    return align_up(static_cast<size_t>(p->g.nx) * p->g.nx * inner_elem(prec), 256) + kBlasWs;
+    return align_up(static_cast<size_t>(ac::dst_half_elems(p->g.nx)) * inner_elem(prec), 256) +
+           align_up(ac::exact_carry_bytes(p->g.nx, p->g.ny, p->ns), 256) + kBlasWs;
 }
 
 size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
@@ -834,8 +836,10 @@ ac::InvArgs inv_args(const ac_problem* p, int prec, char* yhat, double* z) {
 
 // Exact shifted solves (A - lambda_m I) yhat_m = rhat_m for a constant coefficient,
 // then the inverse time-DFT into z.  The slots are split into planes P (one per real
-// slot, two per complex slot), transformed by T = S_x P (one GEMM over all planes),
-// solved along y into P, transformed back T = S_x P and merged into the rhat slots.
+// slot, two per complex slot) with the even/odd butterfly along x, transformed by the
+// two half sine matrices (one GEMM each over all planes), solved along y into P,
+// transformed back by the transposed halves and merged into the rhat slots with the
+// inverse butterfly.
 int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
     ac_ctx* c = p->ctx;
     hipStream_t st = c->stream;
@@ -843,7 +847,8 @@ int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
     char* P = b.buf[0];
     char* T = b.buf[1];
     char* S = b.cnn;
-    char* bw = S + align_up(static_cast<size_t>(nx) * nx * inner_elem(prec), 256);
+    char* carry = S + align_up(static_cast<size_t>(ac::dst_half_elems(nx)) * inner_elem(prec), 256);
+    char* bw = carry + align_up(ac::exact_carry_bytes(nx, ny, p->ns), 256);
     ac::ExactArgs a{};
     a.n = p->g.n;
     a.nx = nx;
@@ -864,32 +869,44 @@ int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
     }
     const double esz = static_cast<double>(inner_elem(prec));
     const double pn = static_cast<double>(planes) * p->g.n;
-    // split/merge 4 pn, two GEMM operand passes 4 pn + S twice, tridiagonal 6 pn, inverse DFT
-    const double bytes = esz * (14.0 * pn + 2.0 * nx * nx) + 8.0 * p->ell * p->g.n +
+    const int h = (nx + 1) / 2, h2 = nx / 2;
+    // split/merge 4 pn, two GEMM operand passes 4 pn + the half matrices twice,
+    // tridiagonal scan 6 pn, inverse DFT
+    const double bytes = esz * (14.0 * pn + 2.0 * ac::dst_half_elems(nx)) + 8.0 * p->ell * p->g.n +
                          esz * static_cast<double>(p->nsr + 2 * p->nsc) * p->g.n;
     ProfScope ps(c, AC_K_EXACT, bytes);
-    AC_HIP(ac::launch_dst_matrix(prec, S, nx, st));
+    AC_HIP(ac::launch_dst_half(prec, S, nx, st));
     AC_HIP(ac::launch_exact_planes(prec, true, a, P, st));
     AC_BLAS(rocblas_set_stream(c->blas, st));
     AC_BLAS(rocblas_set_workspace(c->blas, bw, kBlasWs));
-    const rocblas_int m = nx, n = static_cast<rocblas_int>(static_cast<long long>(ny) * planes), k = nx;
-    auto gemm = [&](const char* Bm, char* Cm) -> int {
-        if (prec == AC_PREC_FP64) {
-            const double one = 1.0, zero = 0.0;
-            AC_BLAS(rocblas_dgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m, n, k, &one,
-                                  reinterpret_cast<const double*>(S), nx, reinterpret_cast<const double*>(Bm), nx,
-                                  &zero, reinterpret_cast<double*>(Cm), nx));
-        } else {
-            const float one = 1.0f, zero = 0.0f;
-            AC_BLAS(rocblas_sgemm(c->blas, rocblas_operation_none, rocblas_operation_none, m, n, k, &one,
-                                  reinterpret_cast<const float*>(S), nx, reinterpret_cast<const float*>(Bm), nx,
-                                  &zero, reinterpret_cast<float*>(Cm), nx));
+    const rocblas_int cols = static_cast<rocblas_int>(static_cast<long long>(ny) * planes);
+    // Cm[off.., :] = op(half) * Bm[off.., :]; even block rows [0, h), odd block rows [h, nx)
+    auto gemm = [&](bool inverse, const char* Bm, char* Cm) -> int {
+        const rocblas_operation op = inverse ? rocblas_operation_transpose : rocblas_operation_none;
+        for (int half = 0; half < 2; ++half) {
+            const rocblas_int d = half == 0 ? h : h2;
+            if (d == 0) continue;
+            const size_t moff = half == 0 ? 0 : static_cast<size_t>(h) * h;  // matrix entries
+            const size_t roff = half == 0 ? 0 : static_cast<size_t>(h);      // block row
+            if (prec == AC_PREC_FP64) {
+                const double one = 1.0, zero = 0.0;
+                const double* A = reinterpret_cast<const double*>(S) + moff;
+                AC_BLAS(rocblas_dgemm(c->blas, op, rocblas_operation_none, d, cols, d, &one, A, d,
+                                      reinterpret_cast<const double*>(Bm) + roff, nx, &zero,
+                                      reinterpret_cast<double*>(Cm) + roff, nx));
+            } else {
+                const float one = 1.0f, zero = 0.0f;
+                const float* A = reinterpret_cast<const float*>(S) + moff;
+                AC_BLAS(rocblas_sgemm(c->blas, op, rocblas_operation_none, d, cols, d, &one, A, d,
+                                      reinterpret_cast<const float*>(Bm) + roff, nx, &zero,
+                                      reinterpret_cast<float*>(Cm) + roff, nx));
+            }
         }
         return AC_OK;
     };
-    AC_TRY(gemm(P, T));
-    AC_HIP(ac::launch_exact_tridiag(prec, a, T, P, st));
-    AC_TRY(gemm(P, T));
+    AC_TRY(gemm(false, P, T));
+    AC_HIP(ac::launch_exact_tridiag(prec, a, T, P, carry, st));
+    AC_TRY(gemm(true, P, T));
     AC_HIP(ac::launch_exact_planes(prec, false, a, T, st));
     AC_HIP(ac::launch_tdft_inv(p->ell, prec, inv_args(p, prec, b.rhat, z), st));
     return AC_OK;
