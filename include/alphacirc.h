@@ -21,7 +21,9 @@
  *          owned by the caller; the library never frees them.  Small arrays
  *          documented as "host" are host pointers.  The library allocates
  *          device memory only inside ac_ctx_create and ac_problem_create (and
- *          ac_cnn_create) and frees it in the matching _destroy.
+ *          ac_cnn_create) and frees it in the matching _destroy.  ac_ctx_create
+ *          also creates the rocBLAS handle of AC_INNER_EXACT, whose GEMMs run in
+ *          the caller's workspace (rocBLAS loads its kernels on first use).
  * Layout   Block vectors are float64, block-major: x[k*N + i], k in [0, l),
  *          grid index i = iy*nx + ix (x fastest).  Cell-centred coefficient
  *          kappa[i] > 0, float64, length N.
