@@ -21,7 +21,8 @@
  *          owned by the caller; the library never frees them.  Small arrays
  *          documented as "host" are host pointers.  The library allocates
  *          device memory only inside ac_ctx_create and ac_problem_create (and
- *          ac_cnn_create) and frees it in the matching _destroy.  ac_ctx_create
+ *          ac_cnn_create, ac_problem_create_multigrid) and frees it in the matching
+ *          _destroy.  ac_ctx_create
  *          also creates the rocBLAS handle of AC_INNER_EXACT, whose GEMMs run in
  *          the caller's workspace (rocBLAS loads its kernels on first use).
  * Layout   Block vectors are float64, block-major: x[k*N + i], k in [0, l),
@@ -88,12 +89,21 @@ typedef enum { AC_PREC_FP64 = 0, AC_PREC_MIXED_BF16K = 1, AC_PREC_MIXED_FP32K = 
  * A along x and every shifted solve reduces to tridiagonal systems along y (dense
  * transforms by rocBLAS GEMMs in the inner precision).  p_uniform and p_per_shift are
  * ignored and count no products with A.  AC_ERR_UNSUPPORTED for a varying coefficient
- * (or varying diagonal blocks whose mean is not constant) or periodic grids. */
+ * (or varying diagonal blocks whose mean is not constant) or periodic grids.
+ * AC_INNER_SP is the saddle-point preconditioner P_SP (Section 4): each complex shift's
+ * system in the real saddle form of eq. (saddlesystem), solved by preconditioned MINRES
+ * with P_D of eq. (minresprecond), each real shift by preconditioned CG (Section 5),
+ * P_D and the CG preconditioner applied by one geometric multigrid V-cycle (built by
+ * ac_problem_create_multigrid; the paper uses a black-box algebraic multigrid there).
+ * p_uniform (or equal p_per_shift entries) iterations per shift from a zero guess;
+ * float64 only; nonlinear (use FGMRES, or the outer Chebyshev iteration as the paper
+ * does); two products with A per MINRES step and one per CG step are counted. */
 typedef enum {
     AC_INNER_CHEB = 0,
     AC_INNER_CHEB_CNN = 1,
     AC_INNER_CHEB_CNN_CYCLE = 2,
-    AC_INNER_EXACT = 3
+    AC_INNER_EXACT = 3,
+    AC_INNER_SP = 4
 } ac_inner;
 
 typedef struct {
@@ -114,7 +124,8 @@ typedef struct {
  *                       P^{-1} calA with the eigenvalue interval of Corollary 1,
  *                       [1, mu_lo^l / (mu_lo^l - alpha)], mu_lo the lower spectral bound
  *                       of A; valid for a linear preconditioner (AC_INNER_CHEB,
- *                       AC_INNER_EXACT). */
+ *                       AC_INNER_EXACT); also run with AC_INNER_SP, whose inner
+ *                       MINRES / CG make it nonlinear (the paper's setting). */
 typedef enum { AC_OUTER_FGMRES = 0, AC_OUTER_CHEBYSHEV = 1 } ac_outer;
 
 typedef struct {
@@ -151,7 +162,8 @@ typedef enum {
     AC_K_CNN = 5,        /* warm-start network */
     AC_K_CHEB_FIRST = 6, /* the first sweep from a zero guess (x_2 from x_1 = rhat/theta) */
     AC_K_EXACT = 7,      /* AC_INNER_EXACT: sine transforms, tridiagonal solves, inverse time-DFT */
-    AC_K_COUNT = 8
+    AC_K_SADDLE = 8,     /* AC_INNER_SP: MINRES / CG with multigrid V-cycles (whole inner solve) */
+    AC_K_COUNT = 9
 } ac_kernel_class;
 
 /* ---- status ------------------------------------------------------------- */
@@ -193,6 +205,26 @@ int ac_ctx_set_tiling(ac_ctx* ctx, int rows_per_wave, int waves_per_block, int p
 int ac_problem_create(ac_ctx* ctx, const ac_grid* grid, const double* kappa_dev, int ell, double alpha,
                       const ac_bounds* bounds, ac_problem** out);
 int ac_problem_destroy(ac_problem* p);
+
+/* Multigrid hierarchy of A for AC_INNER_SP (no paper definition: the paper uses a
+ * black-box AMG).  Vertex-centred geometric V-cycle: each dimension of n > 1 points
+ * coarsens to floor(n/2) (coarse point J = fine point 2J + 1) until at most 4 points
+ * remain; coarse face coefficients are the harmonic combination of the two fine faces
+ * in series divided by 4 (a Dirichlet face at the high end of an even n: halved),
+ * averaged 1/4, 1/2, 1/4 along a coarsened tangential direction; linear interpolation,
+ * full weighting, two damped-Jacobi sweeps (omega 0.8) before and after, an exact
+ * solve on the last level.  Built from the problem's float64 coefficient (for varying
+ * blocks: their mean, the representative block), owned by the problem, freed by
+ * ac_problem_destroy; a second call does nothing.  Dirichlet grids only.
+ * Synchronises. */
+int ac_problem_create_multigrid(ac_problem* p);
+/* Device bytes for ac_mg_vcycle over nvec vectors (1 <= nvec <= 18). */
+int ac_mg_workspace_size(const ac_problem* p, int nvec, size_t* bytes);
+/* u_q = one V-cycle for (A - shifts[q] I) u_q = b_q from zero, q < nvec: b and u hold
+ * nvec vectors of N float64 back to back (u may not alias b); shifts is a host array,
+ * each shift below mu_lo (so that A - c I is SPD). */
+int ac_mg_vcycle(ac_problem* p, int nvec, const double* shifts, const double* b, double* u, void* ws,
+                 size_t ws_bytes);
 /* Varying diagonal blocks A_1, ..., A_l (the extension named in the Conclusions):
  * calA = blockdiag(A_k) - S (x) I_N with A_k built from the k-th coefficient field of
  * kappa_blocks (device, l * N float64, block-major, each finite and positive).  The

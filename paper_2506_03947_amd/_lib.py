@@ -33,6 +33,7 @@ AC_INNER_CHEB = 0
 AC_INNER_CHEB_CNN = 1
 AC_INNER_CHEB_CNN_CYCLE = 2
 AC_INNER_EXACT = 3
+AC_INNER_SP = 4
 AC_OUTER_FGMRES = 0
 AC_OUTER_CHEBYSHEV = 1
 
@@ -44,8 +45,10 @@ AC_K_KRYLOV = 4
 AC_K_CNN = 5
 AC_K_CHEB_FIRST = 6
 AC_K_EXACT = 7
-AC_K_COUNT = 8
-KERNEL_CLASS_NAMES = ["tdft_fwd", "cheb_step", "cheb_final", "apply_calA", "krylov", "cnn", "cheb_first", "exact"]
+AC_K_SADDLE = 8
+AC_K_COUNT = 9
+KERNEL_CLASS_NAMES = ["tdft_fwd", "cheb_step", "cheb_final", "apply_calA", "krylov", "cnn", "cheb_first", "exact",
+                      "saddle"]
 
 
 class ac_grid(C.Structure):
@@ -100,6 +103,9 @@ SIGNATURES = {
     "ac_problem_create": (_I, [_VP, C.POINTER(ac_grid), _VP, _I, _D, C.POINTER(ac_bounds), C.POINTER(_VP)]),
     "ac_problem_create_blocks": (_I, [_VP, C.POINTER(ac_grid), _VP, _I, _D, C.POINTER(ac_bounds), C.POINTER(_VP)]),
     "ac_problem_destroy": (_I, [_VP]),
+    "ac_problem_create_multigrid": (_I, [_VP]),
+    "ac_mg_workspace_size": (_I, [_VP, _I, C.POINTER(_SZ)]),
+    "ac_mg_vcycle": (_I, [_VP, _I, C.POINTER(_D), _VP, _VP, _VP, _SZ]),
     "ac_spectral_bounds": (_I, [_VP, C.POINTER(_D), C.POINTER(_D)]),
     "ac_problem_dims": (_I, [_VP, C.POINTER(C.c_longlong), C.POINTER(_I), C.POINTER(_I)]),
     "ac_alloc_nc2": (_I, [_VP, _D, C.POINTER(_I)]),

@@ -464,6 +464,25 @@ def ac_cnn_make_inputs(p: Problem, cnn: Cnn, precision: int, rhat: torch.Tensor,
     return sc
 
 
+def ac_problem_create_multigrid(p: Problem) -> None:
+    """Build the multigrid hierarchy of A used by AC_INNER_SP (owned by the problem)."""
+    check(L.load().ac_problem_create_multigrid(p.h), "ac_problem_create_multigrid")
+
+
+def ac_mg_workspace_size(p: Problem, nvec: int) -> int:
+    n = C.c_size_t()
+    check(L.load().ac_mg_workspace_size(p.h, nvec, C.byref(n)), "ac_mg_workspace_size")
+    return n.value
+
+
+def ac_mg_vcycle(p: Problem, shifts, b: torch.Tensor, u: torch.Tensor, ws: torch.Tensor) -> None:
+    """u_q = V-cycle for (A - shifts[q] I) from b_q; b, u: len(shifts) * N float64."""
+    nv = len(shifts)
+    arr = (C.c_double * nv)(*[float(c) for c in shifts])
+    check(L.load().ac_mg_vcycle(p.h, nv, arr, _f64(b, nv * p.n, "b"), _f64(u, nv * p.n, "u"), _ptr(ws),
+                                ws.numel()), "ac_mg_vcycle")
+
+
 def ac_problem_attach_cnn(p: Problem, cnn: Cnn | None) -> None:
     check(L.load().ac_problem_attach_cnn(p.h, cnn.h if cnn is not None else None), "ac_problem_attach_cnn")
     p._cnn = cnn  # keep the network alive while attached

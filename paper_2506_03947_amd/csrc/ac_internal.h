@@ -248,6 +248,55 @@ hipError_t launch_exact_planes(int prec, bool split, const ExactArgs& a, void* p
 size_t exact_carry_bytes(int nx, int ny, int nslot);
 hipError_t launch_exact_tridiag(int prec, const ExactArgs& a, void* t, void* u, void* carry, hipStream_t s);
 
+// ---- geometric multigrid for A - c I (mg.hip) --------------------------------
+// Vertex-centred V-cycle: coarse point J = fine point 2J + 1 per coarsened dimension,
+// harmonic face coarsening, linear interpolation, full weighting, two damped-Jacobi
+// sweeps before and after, exact solve on the last level (at most 4 points).
+constexpr int kMgMaxLevels = 32;
+constexpr int kMgMaxVec = 2 * kMaxShift;
+struct MgLevel {
+    int nx, ny, dim;
+    int cx, cy;  // made by coarsening x (y) of the previous level
+    long long n;
+    // wx / wy: face to the x+1 / y+1 neighbour (0 past the last point); bx0/bx1 (per
+    // row) and by0/by1 (per column): Dirichlet faces; diag = 1 + all faces of a point
+    double *diag, *wx, *wy, *bx0, *bx1, *by0, *by1;
+};
+struct MgHierarchy {
+    int nlev;
+    MgLevel lev[kMgMaxLevels];
+};
+// Level sizes of the hierarchy of a dim-dimensional nx x ny grid; returns the count.
+int mg_plan(int dim, int nx, int ny, MgLevel* out);
+// doubles of one level's arrays
+size_t mg_level_doubles(const MgLevel& L);
+// Fills every level's arrays from the fine coefficient (pointers assigned by the caller).
+hipError_t mg_build(const MgHierarchy& h, const double* kappa, hipStream_t s);
+// scratch doubles of a V-cycle over nv vectors
+size_t mg_scratch_doubles(const MgHierarchy& h, int nv);
+// u[v] = V-cycle applied to b[v] for the operator A - c[v] I (host arrays of nv <=
+// kMgMaxVec device pointers / shifts); u may not alias b.
+hipError_t mg_vcycle(const MgHierarchy& h, int nv, const double* const* b, double* const* u, const double* c,
+                     double* scratch, hipStream_t s);
+
+// ---- saddle-point inner solves of P_SP (sp.hip) ---------------------------------
+// nc complex shifts (MINRES on the real saddle form, P_D by V-cycles) and nr real
+// shifts (CG, V-cycle preconditioner), iters iterations each, in lockstep.
+struct SpProblem {
+    const MgHierarchy* h;
+    long long n;
+    int nc, nr;
+    double sigma[kMaxShift], rho[kMaxShift];  // complex: |Im lambda|, Re lambda
+    int im_pos[kMaxShift];                    // complex: Im lambda > 0
+    double lam[kMaxShift];                    // real shifts
+    const double* bc[kMaxShift];              // complex right-hand sides (interleaved, n points)
+    double* yc[kMaxShift];                    // complex solutions (interleaved)
+    const double* br[kMaxShift];              // real right-hand sides (n)
+    double* yr[kMaxShift];                    // real solutions
+};
+size_t sp_ws_doubles(const MgHierarchy& h, long long n, int nc, int nr);
+hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s);
+
 // ---- setup kernels (setup.hip) -----------------------------------------------
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,
                               int nblk, hipStream_t s);

@@ -118,6 +118,9 @@ struct ac_problem {
     ac_cnn* cnn = nullptr;     // warm-start network (not owned)
     // sweep tiling chosen for this problem (0 = the context's setting)
     int tile_h = 0, tile_wpb = 0, tile_vx = 0;
+    // multigrid hierarchy of A (AC_INNER_SP), built by ac_problem_create_multigrid
+    ac::MgHierarchy mg{};
+    double* mgmem = nullptr;
 };
 
 struct ac_cnn {
@@ -304,9 +307,20 @@ int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>&
     if (!o) return fail(AC_ERR_ARG, "opts is NULL");
     if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
     if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN && o->inner != AC_INNER_CHEB_CNN_CYCLE &&
-        o->inner != AC_INNER_EXACT)
+        o->inner != AC_INNER_EXACT && o->inner != AC_INNER_SP)
         return fail(AC_ERR_ARG, "unknown inner mode");
     pm.assign(p->ell, 0);
+    if (o->inner == AC_INNER_SP) {
+        if (!p->mgmem) return fail(AC_ERR_ARG, "no multigrid hierarchy (ac_problem_create_multigrid)");
+        if (o->precision != AC_PREC_FP64) return fail(AC_ERR_UNSUPPORTED, "P_SP runs in float64");
+        for (int m = 0; m < p->ell; ++m) {
+            const int v = o->p_per_shift ? o->p_per_shift[m] : o->p_uniform;
+            if (v < 1 || v > 100000) return fail(AC_ERR_ARG, "inner iteration counts must be in [1, 100000]");
+            if (m > 0 && v != pm[0]) return fail(AC_ERR_UNSUPPORTED, "P_SP runs the same iteration count for every shift");
+            pm[m] = v;
+        }
+        return AC_OK;
+    }
     if (o->inner == AC_INNER_EXACT) {
         if (p->g.periodic) return fail(AC_ERR_UNSUPPORTED, "the exact inner solve needs Dirichlet boundaries");
         if (p->kmin64 != p->kmax64) return fail(AC_ERR_UNSUPPORTED, "the exact inner solve needs a constant coefficient");
@@ -340,11 +354,17 @@ size_t exact_extra_bytes(const ac_problem* p, int prec) {
            align_up(ac::exact_carry_bytes(p->g.nx, p->g.ny, p->ns), 256) + kBlasWs;
 }
 
+size_t sp_extra_bytes(const ac_problem* p) {
+    if (!p->mgmem) return 0;
+    return ac::sp_ws_doubles(p->mg, p->g.n, p->nsc, p->nsr) * sizeof(double) + 256;
+}
+
 size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     size_t b = 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
     if (inner == AC_INNER_EXACT) b += exact_extra_bytes(p, prec);
+    else if (inner == AC_INNER_SP) b += sp_extra_bytes(p);
     else if (inner != AC_INNER_CHEB) b += cnn_ws_bytes(p);
     return b;
 }
@@ -912,11 +932,46 @@ int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
     return AC_OK;
 }
 
+// P_SP: every shifted solve by saddle-point MINRES (complex shifts) or CG (real shifts)
+// with multigrid preconditioners, pm[0] iterations each, then the inverse time-DFT.
+int sp_inner(ac_problem* p, int iters, const PrecBufs& b, double* z) {
+    ac::SpProblem P{};
+    P.h = &p->mg;
+    P.n = p->g.n;
+    for (int s = 0; s < p->ns; ++s) {
+        const cplx lam = shift_of(p, slot_to_m(p, s));
+        char* in = slot_ptr(p, AC_PREC_FP64, b.rhat, s);
+        char* out = slot_ptr(p, AC_PREC_FP64, b.buf[0], s);
+        if (slot_is_real(p, s)) {
+            P.lam[P.nr] = lam.real();
+            P.br[P.nr] = reinterpret_cast<const double*>(in);
+            P.yr[P.nr++] = reinterpret_cast<double*>(out);
+        } else {
+            P.sigma[P.nc] = std::abs(lam.imag());
+            P.rho[P.nc] = lam.real();
+            P.im_pos[P.nc] = lam.imag() > 0.0 ? 1 : 0;
+            P.bc[P.nc] = reinterpret_cast<const double*>(in);
+            P.yc[P.nc++] = reinterpret_cast<double*>(out);
+        }
+    }
+    char* ws = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(b.cnn), 256));
+    // per iteration: the saddle / CG operators (2 resp. 1 products with A), a V-cycle per
+    // vector, the Lanczos / CG vector updates and two inner products
+    const double n8 = 8.0 * p->g.n;
+    const double bytes = iters * n8 * (p->nsc * 2.0 * 12.0 + p->nsr * 10.0);
+    ProfScope ps(p->ctx, AC_K_SADDLE, bytes);
+    AC_HIP(ac::sp_solve(P, iters, reinterpret_cast<double*>(ws), p->ctx->stream));
+    AC_HIP(ac::launch_tdft_inv(p->ell, AC_PREC_FP64, inv_args(p, AC_PREC_FP64, b.buf[0], z), p->ctx->stream));
+    return AC_OK;
+}
+
 int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* r, double* z,
                     void* ws, double in_scale, int* fallbacks = nullptr) {
     const PrecBufs b = carve_prec(p, o->precision, ws);
     AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
-    if (o->inner == AC_INNER_EXACT) {
+    if (o->inner == AC_INNER_SP) {
+        AC_TRY(sp_inner(p, pm[0], b, z));
+    } else if (o->inner == AC_INNER_EXACT) {
         AC_TRY(exact_inner(p, o->precision, b, z));
     } else if (o->inner != AC_INNER_CHEB) {
         AC_TRY(cnn_warm_start(p, o->precision, b.rhat, b.buf[0], b.cnn, fallbacks));
@@ -1217,7 +1272,72 @@ int ac_problem_destroy(ac_problem* p) {
     (void)hipFree(p->k16);
     (void)hipFree(p->rpart);
     if (p->kblocks) (void)hipFree(p->kblocks);
+    if (p->mgmem) (void)hipFree(p->mgmem);
     delete p;
+    return AC_OK;
+}
+
+int ac_problem_create_multigrid(ac_problem* p) {
+    if (!p) return fail(AC_ERR_ARG, "problem is NULL");
+    if (p->mgmem) return AC_OK;
+    if (p->g.periodic) return fail(AC_ERR_UNSUPPORTED, "the multigrid hierarchy needs Dirichlet boundaries");
+    ac::MgHierarchy h{};
+    h.nlev = ac::mg_plan(p->g.dim, p->g.nx, p->g.ny, h.lev);
+    if (h.nlev < 1) return fail(AC_ERR_UNSUPPORTED, "grid too large for the multigrid hierarchy");
+    size_t total = 0;
+    for (int l = 0; l < h.nlev; ++l) total += align_up(ac::mg_level_doubles(h.lev[l]), 32);
+    AC_HIP(hipSetDevice(p->ctx->device));
+    double* mem = nullptr;
+    AC_HIP(hipMalloc(reinterpret_cast<void**>(&mem), total * sizeof(double)));
+    double* q = mem;
+    for (int l = 0; l < h.nlev; ++l) {
+        ac::MgLevel& L = h.lev[l];
+        double* b = q;
+        L.diag = b;
+        L.wx = b + L.n;
+        L.wy = b + 2 * L.n;
+        L.bx0 = b + 3 * L.n;
+        L.bx1 = L.bx0 + L.ny;
+        L.by0 = L.bx1 + L.ny;
+        L.by1 = L.by0 + L.nx;
+        q += align_up(ac::mg_level_doubles(L), 32);
+    }
+    hipError_t e = ac::mg_build(h, p->k64, p->ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->ctx->stream);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return fail(AC_ERR_HIP, std::string("multigrid set-up: ") + hipGetErrorString(e));
+    }
+    p->mg = h;
+    p->mgmem = mem;
+    return AC_OK;
+}
+
+int ac_mg_workspace_size(const ac_problem* p, int nvec, size_t* bytes) {
+    if (!p || !bytes) return fail(AC_ERR_ARG, "NULL argument");
+    if (!p->mgmem) return fail(AC_ERR_ARG, "no multigrid hierarchy (ac_problem_create_multigrid)");
+    if (nvec < 1 || nvec > ac::kMgMaxVec) return fail(AC_ERR_ARG, "nvec out of range");
+    *bytes = ac::mg_scratch_doubles(p->mg, nvec) * sizeof(double) + 256;
+    return AC_OK;
+}
+
+int ac_mg_vcycle(ac_problem* p, int nvec, const double* shifts, const double* b, double* u, void* ws, size_t ws_bytes) {
+    if (!p || !shifts || !b || !u) return fail(AC_ERR_ARG, "NULL argument");
+    if (!p->mgmem) return fail(AC_ERR_ARG, "no multigrid hierarchy (ac_problem_create_multigrid)");
+    if (nvec < 1 || nvec > ac::kMgMaxVec) return fail(AC_ERR_ARG, "nvec out of range");
+    for (int q = 0; q < nvec; ++q)
+        if (!(shifts[q] < p->bounds[AC_PREC_FP64][0])) return fail(AC_ERR_ARG, "every shift must be below mu_lo");
+    if (!ws || ws_bytes < ac::mg_scratch_doubles(p->mg, nvec) * sizeof(double) + 256)
+        return fail(AC_ERR_WORKSPACE, "workspace too small");
+    AC_HIP(hipSetDevice(p->ctx->device));
+    const double* bs[ac::kMgMaxVec];
+    double* us[ac::kMgMaxVec];
+    for (int q = 0; q < nvec; ++q) {
+        bs[q] = b + static_cast<size_t>(q) * p->g.n;
+        us[q] = u + static_cast<size_t>(q) * p->g.n;
+    }
+    double* scratch = reinterpret_cast<double*>(align_up(reinterpret_cast<size_t>(ws), 256));
+    AC_HIP(ac::mg_vcycle(p->mg, nvec, bs, us, shifts, scratch, p->ctx->stream));
     return AC_OK;
 }
 
@@ -1398,7 +1518,8 @@ int ac_shifted_cheb(ac_problem* p, const ac_solve_opts* o, const void* rhat, con
     if (!p || !rhat || !yhat) return fail(AC_ERR_ARG, "NULL argument");
     std::vector<int> pm;
     AC_TRY(validate_opts(p, o, pm));
-    if (o->inner == AC_INNER_EXACT) return fail(AC_ERR_UNSUPPORTED, "ac_shifted_cheb runs the Chebyshev solves");
+    if (o->inner == AC_INNER_EXACT || o->inner == AC_INNER_SP)
+        return fail(AC_ERR_UNSUPPORTED, "ac_shifted_cheb runs the Chebyshev solves");
     if (!ws || ws_bytes < prec_ws_bytes(p, o->precision)) return fail(AC_ERR_WORKSPACE, "workspace too small");
     AC_HIP(hipSetDevice(p->ctx->device));
     const int prec = o->precision;
@@ -1428,6 +1549,16 @@ int ac_tdft_inverse(ac_problem* p, int prec, const void* yhat, double* z) {
 // FGMRES
 
 namespace {
+// Products with A per preconditioner application, counted over all l shifts as in
+// Table 1: p_m per Chebyshev solve; for P_SP two per MINRES step (complex shifts) and
+// one per CG step (real shifts); none for the exact solve.
+long long prec_products(const ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm) {
+    if (o->inner == AC_INNER_EXACT) return 0;
+    if (o->inner == AC_INNER_SP) return static_cast<long long>(pm[0]) * (2LL * (p->ell - p->nsr) + p->nsr);
+    long long s = 0;
+    for (int v : pm) s += v;
+    return s;
+}
 // The paper's outer solver (Section 5): Chebyshev semi-iteration on P^{-1} calA with
 // the Corollary 1 interval [1, mu^l/(mu^l - alpha)] and a zero-residual-norm stop.
 // Residual form: r = b - calA x, z = P^{-1} r, d_0 = z/theta, x_{k+1} = x_k + d_k,
@@ -1435,8 +1566,9 @@ namespace {
 // d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) z_{k+1}.
 int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* b, double* x,
                     void* ws, ac_solve_info* info, std::chrono::steady_clock::time_point t0) {
-    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_EXACT)
-        return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration needs a linear preconditioner");
+    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_EXACT && o->inner != AC_INNER_SP)
+        return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration takes the Chebyshev, exact or saddle-point "
+                                        "inner solves");
     if (p->kblocks)
         return fail(AC_ERR_UNSUPPORTED, "no eigenvalue interval is known for varying diagonal blocks (use FGMRES)");
     ac_ctx* c = p->ctx;
@@ -1448,8 +1580,7 @@ int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
     double* z = w.Z[0];
     const int kb = ac::krylov_blocks();
     const int ptiles = static_cast<int>(calA_partials(p));
-    long long psum = 0;
-    for (int v : pm) psum += v;
+    const long long psum = prec_products(p, o, pm);
     const double mul = std::pow(p->bounds[AC_PREC_FP64][0], p->ell);
     const double lo = 1.0, hi = mul / (mul - p->alpha);
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
@@ -1533,8 +1664,7 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
     SolveWs w = carve_solve(p, o, ws);
     const int kb = ac::krylov_blocks();
     const int ptiles = static_cast<int>(calA_partials(p));
-    long long psum = 0;
-    for (int v : pm) psum += v;
+    const long long psum = prec_products(p, o, pm);
     long long matvecs = 0;
 
     auto fetch = [&](int nq) -> int {
