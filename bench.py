@@ -2,7 +2,7 @@
 mixed precision against float64 inner solves, with the shifted-stencil roofline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium]
-                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact]
+                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact|sp]
 
 One step = one FGMRES(30) solve of calA x = b (b = (b_1, 0, ..., 0)) from x = 0
 on resident device inputs, preconditioned by the nested-Chebyshev block
@@ -48,10 +48,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
                          "(the launch set used for hardware-counter runs); batch: many uneven problems "
                          "solved one by one and as one batch")
+    ap.add_argument("--sp-iters", type=int, nargs="*", default=None,
+                    help="sp mode: inner MINRES / CG iteration counts to time")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-restart", type=int, default=30,
                     help="FGMRES restart of the batch mode (p = 10: restart 8 leaves one of the 64 problems unconverged)")
@@ -216,6 +218,63 @@ def exact_mode(a):
     }), flush=True)
 
 
+def sp_mode(a):
+    """The default workload (2048 x 2048 log-normal kappa, l = 10, alpha = 1e-2,
+    FGMRES(restart) to 1e-8) with the saddle-point preconditioner P_SP (Section 4:
+    MINRES / CG inner solves, multigrid P_D, float64) at a few inner iteration counts."""
+    import torch
+    from paper_2506_03947_amd import api
+    from synth import first_block_rhs, lognormal_kappa
+    L = api.L
+    dev = torch.device("cuda:0")
+    w = WORKLOADS[a.workload]
+    nx, ny, ell, alpha = w["nx"], w["ny"], w["ell"], w["alpha"]
+    n = nx * ny
+    kap = lognormal_kappa(nx, ny, w["kappa0"], w["corr"], w["std"], seed=a.seed)
+    ctx = api.ac_ctx_create(0)
+    prob = api.ac_problem_create(ctx, 2, nx, ny, torch.from_numpy(kap).to(dev), ell, alpha)
+    t0 = time.perf_counter()
+    api.ac_problem_create_multigrid(prob)
+    t_setup = time.perf_counter() - t0
+    b = torch.from_numpy(first_block_rhs(n, ell, seed=a.seed)).to(dev)
+    out = {}
+    for iters in (a.sp_iters or [4, 8]):
+        opts = api.Opts(precision=L.AC_PREC_FP64, inner=L.AC_INNER_SP, p=iters, tol=a.tol, restart_m=a.restart,
+                        max_outer=3000)
+        ws = api.workspace(api.ac_solve_workspace_size(prob, opts))
+        x = torch.zeros_like(b)
+        api.ac_solve(prob, opts, b, x, ws)
+        times = []
+        for _ in range(max(a.steps, 1)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = api.ac_solve(prob, opts, b, x, ws)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        api.ac_ctx_set_profiling(ctx, True)
+        api.ac_ctx_reset_stats(ctx)
+        x.zero_()
+        api.ac_solve(prob, opts, b, x, ws)
+        st = api.ac_ctx_kernel_stats(ctx)
+        api.ac_ctx_set_profiling(ctx, False)
+        sd = st["saddle"]
+        rec = {"seconds": min(times), "outer_iters": info["outer_iters"], "converged": info["converged"],
+               "rel_residual": info["rel_residual_true"], "matvecs_A": info["matvecs_A"],
+               "prec_apply_ms": sd["ms"] / max(sd["launches"], 1)}
+        log(f"P_SP {iters} inner iterations: {rec}")
+        out[str(iters)] = rec
+        del ws
+    best = min(out.values(), key=lambda r: r["seconds"])
+    print(json.dumps({
+        "metric": "seconds per all-at-once solve to 1e-8, saddle-point preconditioner P_SP", "value": best["seconds"],
+        "unit": "s/solve", "n_gpus": 1, "steps": max(a.steps, 1), "warmup": 1,
+        "ms_per_step": 1000 * best["seconds"], "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{nx}x{ny} log-normal kappa, l {ell}, alpha {alpha}, FGMRES({a.restart}), P_SP"},
+        "multigrid_setup_s": t_setup, "inner_iterations": out,
+    }), flush=True)
+
+
 def kernels_only(a, api, prob, ell, n):
     """A few P_NC^{-1} applications in the solve's precision and launch shape, then a
     plain device copy of known size (reference for the FETCH_SIZE/WRITE_SIZE scale)."""
@@ -306,6 +365,9 @@ def main():
         return
     if a.mode == "exact":
         exact_mode(a)
+        return
+    if a.mode == "sp":
+        sp_mode(a)
         return
     import torch
     from paper_2506_03947_amd import api
