@@ -1281,6 +1281,7 @@ int ac_problem_create_multigrid(ac_problem* p) {
     if (!p) return fail(AC_ERR_ARG, "problem is NULL");
     if (p->mgmem) return AC_OK;
     if (p->g.periodic) return fail(AC_ERR_UNSUPPORTED, "the multigrid hierarchy needs Dirichlet boundaries");
+    if (p->g.n >= (1LL << 31)) return fail(AC_ERR_UNSUPPORTED, "the multigrid kernels index points with 32 bits");
     ac::MgHierarchy h{};
     h.nlev = ac::mg_plan(p->g.dim, p->g.nx, p->g.ny, h.lev);
     if (h.nlev < 1) return fail(AC_ERR_UNSUPPORTED, "grid too large for the multigrid hierarchy");

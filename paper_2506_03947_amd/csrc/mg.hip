@@ -15,6 +15,8 @@
 // cycle is a symmetric positive definite operator, as MINRES and CG need.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "ac_internal.h"
 
 namespace ac {
@@ -161,52 +163,153 @@ __global__ void diag_kernel(const MgLevel L) {
     L.diag[i] = d;
 }
 
-// ---- cycle kernels (grid: points x vectors) --------------------------------------------
+// ---- cycle kernels -----------------------------------------------------------------
+// The sweeps run one thread per point over every vector of the batch (the level's
+// coefficients are read once per point), two vectors at a time so that both vectors'
+// loads are issued before either store.  The transfers run one thread per (point,
+// vector) with the vector in blockIdx.y.
 
-// (A - c I) u at point i
-__device__ __forceinline__ double apply_at(const MgLevel& L, const double* __restrict__ u, long long i, int x, int y,
-                                           double c) {
-    double a = (L.diag[i] - c) * u[i];
-    if (x < L.nx - 1) a -= L.wx[i] * u[i + 1];
-    if (x > 0) a -= L.wx[i - 1] * u[i - 1];
-    if (L.dim == 2) {
-        if (y < L.ny - 1) a -= L.wy[i] * u[i + L.nx];
-        if (y > 0) a -= L.wy[i - L.nx] * u[i - L.nx];
-    }
-    return a;
+// Coefficients of point i: A u = d u_i - e u_{i+1} - w u_{i-1} - n u_{i+nx} - s u_{i-nx}
+// (a missing neighbour has coefficient 0 and is not read).
+struct Co {
+    double d, e, w, n, s;
+    bool he, hw, hn, hs;
+};
+__device__ __forceinline__ Co coef_at(const MgLevel& L, long long i, int x, int y) {
+    Co c;
+    c.d = L.diag[i];
+    c.he = x < L.nx - 1;
+    c.hw = x > 0;
+    c.hn = L.dim == 2 && y < L.ny - 1;
+    c.hs = L.dim == 2 && y > 0;
+    c.e = c.he ? L.wx[i] : 0.0;
+    c.w = c.hw ? L.wx[i - 1] : 0.0;
+    c.n = c.hn ? L.wy[i] : 0.0;
+    c.s = c.hs ? L.wy[i - L.nx] : 0.0;
+    return c;
+}
+// the five stencil values of an array at point i (0 for a missing neighbour)
+struct St {
+    double c, e, w, n, s;
+};
+__device__ __forceinline__ St stencil(const Co& k, const double* __restrict__ u, long long i, long long nx) {
+    St t;
+    t.c = u[i];
+    t.e = k.he ? u[i + 1] : 0.0;
+    t.w = k.hw ? u[i - 1] : 0.0;
+    t.n = k.hn ? u[i + nx] : 0.0;
+    t.s = k.hs ? u[i - nx] : 0.0;
+    return t;
+}
+__device__ __forceinline__ double apply_st(const Co& k, const St& u, double c) {
+    return (k.d - c) * u.c - k.e * u.e - k.w * u.w - k.n * u.n - k.s * u.s;
 }
 
-// FIRST: out = omega b / d (the sweep from zero); else out = in + omega (b - (A - cI) in) / d
-template <bool FIRST>
-__global__ void jacobi_kernel(const MgLevel L, const MgVecs v) {
+// out = in + omega (b - (A - cI) in) / (d - c)   (SWEEP)   or   out = b - (A - cI) in
+template <bool SWEEP>
+__global__ void sweep_kernel(const MgLevel L, const MgVecs v, int nv) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= L.n) return;
-    const int q = blockIdx.y;
-    const double c = v.c[q];
-    const double d = L.diag[i] - c;
-    if (FIRST) {
-        v.out[q][i] = kOmega * v.b[q][i] / d;
-        return;
+    const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
+    const Co k = coef_at(L, i, x, y);
+    for (int q = 0; q < nv; q += 2) {
+        const bool two = q + 1 < nv;
+        const St u0 = stencil(k, v.in[q], i, L.nx);
+        const double b0 = v.b[q][i];
+        St u1{};
+        double b1 = 0.0;
+        if (two) {
+            u1 = stencil(k, v.in[q + 1], i, L.nx);
+            b1 = v.b[q + 1][i];
+        }
+        const double r0 = b0 - apply_st(k, u0, v.c[q]);
+        v.out[q][i] = SWEEP ? u0.c + kOmega * r0 / (k.d - v.c[q]) : r0;
+        if (two) {
+            const double r1 = b1 - apply_st(k, u1, v.c[q + 1]);
+            v.out[q + 1][i] = SWEEP ? u1.c + kOmega * r1 / (k.d - v.c[q + 1]) : r1;
+        }
     }
-    const int x = static_cast<int>(i % L.nx), y = static_cast<int>(i / L.nx);
-    v.out[q][i] = v.in[q][i] + kOmega * (v.b[q][i] - apply_at(L, v.in[q], i, x, y, c)) / d;
 }
 
-__global__ void residual_kernel(const MgLevel L, const MgVecs v) {
+// Two sweeps from zero: u1 = omega b / (d - c) at every point, out = u1 + omega (b -
+// (A - cI) u1) / (d - c); u1 at the neighbours is formed from their b and diagonal.
+__global__ void sweep2_from_zero_kernel(const MgLevel L, const MgVecs v, int nv) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= L.n) return;
+    const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
+    const Co k = coef_at(L, i, x, y);
+    const St dg = stencil(k, L.diag, i, L.nx);
+    auto first = [&](const St& b, double c) {
+        St u;
+        u.c = kOmega * b.c / (dg.c - c);
+        u.e = k.he ? kOmega * b.e / (dg.e - c) : 0.0;
+        u.w = k.hw ? kOmega * b.w / (dg.w - c) : 0.0;
+        u.n = k.hn ? kOmega * b.n / (dg.n - c) : 0.0;
+        u.s = k.hs ? kOmega * b.s / (dg.s - c) : 0.0;
+        return u;
+    };
+    for (int q = 0; q < nv; q += 2) {
+        const bool two = q + 1 < nv;
+        const St b0 = stencil(k, v.b[q], i, L.nx);
+        St b1{};
+        if (two) b1 = stencil(k, v.b[q + 1], i, L.nx);
+        const St u0 = first(b0, v.c[q]);
+        v.out[q][i] = u0.c + kOmega * (b0.c - apply_st(k, u0, v.c[q])) / (k.d - v.c[q]);
+        if (two) {
+            const St u1 = first(b1, v.c[q + 1]);
+            v.out[q + 1][i] = u1.c + kOmega * (b1.c - apply_st(k, u1, v.c[q + 1])) / (k.d - v.c[q + 1]);
+        }
+    }
+}
+
+// Linear interpolation of fine index x from a coarse line of nc points (coarsened) or
+// the identity, as two (index, weight) pairs; an absent entry has weight 0 and a valid
+// (clamped) index, so the 2 x 2 sum below needs no branches or private arrays.
+struct Interp {
+    int j0, j1;
+    double w0, w1;
+};
+__device__ __forceinline__ Interp interp(int x, int nc, int coarsened) {
+    Interp t;
+    if (!coarsened) {
+        t.j0 = t.j1 = x;
+        t.w0 = 1.0;
+        t.w1 = 0.0;
+    } else if (x & 1) {
+        t.j0 = t.j1 = (x - 1) >> 1;
+        t.w0 = 1.0;
+        t.w1 = 0.0;
+    } else {
+        const int lo = (x >> 1) - 1, hi = x >> 1;
+        t.j0 = lo >= 0 ? lo : 0;
+        t.w0 = lo >= 0 ? 0.5 : 0.0;
+        t.j1 = hi < nc ? hi : nc - 1;
+        t.w1 = hi < nc ? 0.5 : 0.0;
+    }
+    return t;
+}
+
+// fine out += P coarse in; grid (point blocks, vectors)
+__global__ void prolong_add_kernel(const MgLevel F, const MgLevel C, const MgVecs v) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= F.n) return;
     const int q = blockIdx.y;
-    const int x = static_cast<int>(i % L.nx), y = static_cast<int>(i / L.nx);
-    v.out[q][i] = v.b[q][i] - apply_at(L, v.in[q], i, x, y, v.c[q]);
+    const int ii = static_cast<int>(i), x = ii % F.nx, y = ii / F.nx;
+    const Interp ix = interp(x, C.nx, C.cx), iy = interp(y, C.ny, C.cy);
+    const double* __restrict__ e = v.in[q];
+    const double* __restrict__ r0 = e + iy.j0 * C.nx;
+    const double* __restrict__ r1 = e + iy.j1 * C.nx;
+    const double acc = iy.w0 * (ix.w0 * r0[ix.j0] + ix.w1 * r0[ix.j1]) + iy.w1 * (ix.w0 * r1[ix.j0] + ix.w1 * r1[ix.j1]);
+    v.out[q][i] += acc;
 }
 
 // coarse out = R fine in: per coarsened dimension fine 2J (1/2), 2J+1 (1), 2J+2 (1/2),
-// divided by 2 per coarsened dimension
+// divided by 2 per coarsened dimension; grid (point blocks, vectors)
 __global__ void restrict_kernel(const MgLevel F, const MgLevel C, const MgVecs v) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= C.n) return;
     const int q = blockIdx.y;
-    const int X = static_cast<int>(i % C.nx), Y = static_cast<int>(i / C.nx);
+    const int ii = static_cast<int>(i), X = ii % C.nx, Y = ii / C.nx;
     const double* __restrict__ in = v.in[q];
     const double wd[3] = {0.5, 1.0, 0.5};
     double acc = 0.0;
@@ -222,58 +325,6 @@ __global__ void restrict_kernel(const MgLevel F, const MgLevel C, const MgVecs v
         }
     }
     v.out[q][i] = acc / static_cast<double>(1 << (C.cx + C.cy));
-}
-
-// fine out += P coarse in
-__global__ void prolong_add_kernel(const MgLevel F, const MgLevel C, const MgVecs v) {
-    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= F.n) return;
-    const int q = blockIdx.y;
-    const int x = static_cast<int>(i % F.nx), y = static_cast<int>(i / F.nx);
-    int jx[2], jy[2];
-    double wx[2], wy[2];
-    int nx = 0, ny = 0;
-    if (!C.cx) {
-        jx[0] = x;
-        wx[0] = 1.0;
-        nx = 1;
-    } else if (x % 2 == 1) {
-        jx[0] = (x - 1) / 2;
-        wx[0] = 1.0;
-        nx = 1;
-    } else {
-        if (x / 2 - 1 >= 0) {
-            jx[nx] = x / 2 - 1;
-            wx[nx++] = 0.5;
-        }
-        if (x / 2 < C.nx) {
-            jx[nx] = x / 2;
-            wx[nx++] = 0.5;
-        }
-    }
-    if (!C.cy) {
-        jy[0] = y;
-        wy[0] = 1.0;
-        ny = 1;
-    } else if (y % 2 == 1) {
-        jy[0] = (y - 1) / 2;
-        wy[0] = 1.0;
-        ny = 1;
-    } else {
-        if (y / 2 - 1 >= 0) {
-            jy[ny] = y / 2 - 1;
-            wy[ny++] = 0.5;
-        }
-        if (y / 2 < C.ny) {
-            jy[ny] = y / 2;
-            wy[ny++] = 0.5;
-        }
-    }
-    const double* __restrict__ e = v.in[q];
-    double acc = 0.0;
-    for (int b = 0; b < ny; ++b)
-        for (int a = 0; a < nx; ++a) acc += wy[b] * wx[a] * e[static_cast<long long>(jy[b]) * C.nx + jx[a]];
-    v.out[q][i] += acc;
 }
 
 // Exact solve on a level of at most 4 points: one thread per vector, Gaussian
@@ -393,26 +444,26 @@ hipError_t mg_vcycle(const MgHierarchy& h, int nv, const double* const* b, doubl
         (void)l;
         return v;
     };
-    // down the hierarchy
+    // down the hierarchy: two sweeps from zero, residual, restriction
     for (int l = 0; l < h.nlev - 1; ++l) {
         const MgLevel& L = h.lev[l];
-        const dim3 g(grid_of(L.n), nv);
-        hipLaunchKernelGGL(jacobi_kernel<true>, g, dim3(256), 0, s, L, vecs(l, nullptr, B[l], U[l]));
-        hipLaunchKernelGGL(jacobi_kernel<false>, g, dim3(256), 0, s, L, vecs(l, U[l], B[l], T[l]));
-        hipLaunchKernelGGL(residual_kernel, g, dim3(256), 0, s, L, vecs(l, T[l], B[l], U[l]));
+        const dim3 g(grid_of(L.n));
+        hipLaunchKernelGGL(sweep2_from_zero_kernel, g, dim3(256), 0, s, L, vecs(l, nullptr, B[l], T[l]), nv);
+        hipLaunchKernelGGL(sweep_kernel<false>, g, dim3(256), 0, s, L, vecs(l, T[l], B[l], U[l]), nv);
         double* const* Bn = const_cast<double* const*>(B[l + 1]);
         hipLaunchKernelGGL(restrict_kernel, dim3(grid_of(h.lev[l + 1].n), nv), dim3(256), 0, s, L, h.lev[l + 1],
                            vecs(l, U[l], nullptr, Bn));
     }
     const int last = h.nlev - 1;
     hipLaunchKernelGGL(coarsest_kernel, dim3(1), dim3(64), 0, s, h.lev[last], vecs(last, nullptr, B[last], T[last]), nv);
-    // and back up
+    // and back up: correction, two sweeps
     for (int l = h.nlev - 2; l >= 0; --l) {
         const MgLevel& L = h.lev[l];
-        const dim3 g(grid_of(L.n), nv);
-        hipLaunchKernelGGL(prolong_add_kernel, g, dim3(256), 0, s, L, h.lev[l + 1], vecs(l, T[l + 1], nullptr, T[l]));
-        hipLaunchKernelGGL(jacobi_kernel<false>, g, dim3(256), 0, s, L, vecs(l, T[l], B[l], U[l]));
-        hipLaunchKernelGGL(jacobi_kernel<false>, g, dim3(256), 0, s, L, vecs(l, U[l], B[l], T[l]));
+        const dim3 g(grid_of(L.n));
+        hipLaunchKernelGGL(prolong_add_kernel, dim3(grid_of(L.n), nv), dim3(256), 0, s, L, h.lev[l + 1],
+                           vecs(l, T[l + 1], nullptr, T[l]));
+        hipLaunchKernelGGL(sweep_kernel<true>, g, dim3(256), 0, s, L, vecs(l, T[l], B[l], U[l]), nv);
+        hipLaunchKernelGGL(sweep_kernel<true>, g, dim3(256), 0, s, L, vecs(l, U[l], B[l], T[l]), nv);
     }
     return hipGetLastError();
 }
