@@ -172,3 +172,42 @@ def test_sp_rejects():
     with pytest.raises(L.AlphacircError) as e:
         api.ac_problem_create_multigrid(per)
     assert e.value.status == L.AC_ERR_UNSUPPORTED
+
+
+GOLDEN_SP = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "sp_tables.json")
+
+
+def _outer_cheb_count(nx, ell, alpha, inner, iters):
+    kap = paper_operator_kappa(nx, ell)
+    lo, hi = ops.constant_interval(2, nx, nx, kap)
+    p = _problem(2, nx, nx, kap, ell, alpha, bounds=(lo, hi))
+    b = G.dev(first_block_rhs(nx * nx, ell, seed=0))
+    opts = api.Opts(precision=L.AC_PREC_FP64, inner=inner, p=iters, tol=1e-6, restart_m=1, max_outer=200,
+                    outer=L.AC_OUTER_CHEBYSHEV)
+    x = torch.zeros_like(b)
+    info = api.ac_solve(p, opts, b, x, api.workspace(api.ac_solve_workspace_size(p, opts)))
+    assert info["converged"]
+    return info["outer_iters"]
+
+
+def test_sp_dimension_independent_counts_paper_table():
+    """The paper's n_x scaling table for P_SP (l = 10, eta = 0.2, outer Chebyshev to
+    1e-6): the counts do not grow with n_x.  Here the same holds with the geometric
+    multigrid; each count is within one of the exact P_alpha's on the same problem (the
+    best a preconditioner built on P_alpha can do) and within two (alpha = 0.01) or four
+    (alpha = 1) of the paper's AMG-based counts."""
+    import json
+    rows = json.load(open(GOLDEN_SP))["rows"]
+    ell = 10
+    got = {}
+    for r in rows:
+        nx, alpha = r["nx"], r["alpha"]
+        sp_it = _outer_cheb_count(nx, ell, alpha, L.AC_INNER_SP, int(round(0.2 * nx)))
+        ex_it = _outer_cheb_count(nx, ell, alpha, L.AC_INNER_EXACT, 1)
+        print(f"alpha {alpha} n_x {nx}: P_SP {sp_it}, exact P_alpha {ex_it}, paper {r['iterations']}", flush=True)
+        got[(alpha, nx)] = sp_it
+        assert ex_it <= sp_it <= ex_it + 1
+        assert sp_it - r["iterations"] <= (2 if alpha < 0.1 else 4)
+    for alpha in (1.0, 0.01):
+        counts = [v for (a, _), v in got.items() if a == alpha]
+        assert max(counts) - min(counts) <= 1, counts
