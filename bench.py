@@ -2,7 +2,7 @@
 mixed precision against float64 inner solves, with the shifted-stencil roofline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium]
-                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact|sp]
+                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact|sp|blocks]
 
 One step = one FGMRES(30) solve of calA x = b (b = (b_1, 0, ..., 0)) from x = 0
 on resident device inputs, preconditioned by the nested-Chebyshev block
@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp", "blocks"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
                          "(the launch set used for hardware-counter runs); batch: many uneven problems "
                          "solved one by one and as one batch")
@@ -275,6 +275,64 @@ def sp_mode(a):
     }), flush=True)
 
 
+def blocks_mode(a):
+    """Varying diagonal blocks A_1..A_l (the representative block A(mean kappa) in the
+    preconditioner): the default grid, l = 10, alpha = 1e-2, kappa_k = 50 exp(g + d (k/l) h)
+    for drifts d in {0, 0.5, 1}; FGMRES(restart) to 1e-8 with the nested-Chebyshev P
+    (p inner steps, complex64 / bf16 kappa) and with P_SP (8 steps, float64).  Reports
+    seconds and iterations per solve and the block-varying calA kernel's bandwidth."""
+    import torch
+    from paper_2506_03947_amd import api
+    from synth import drifting_kappa_blocks, first_block_rhs
+    L = api.L
+    dev = torch.device("cuda:0")
+    w = WORKLOADS[a.workload]
+    nx, ny, ell, alpha = w["nx"], w["ny"], w["ell"], w["alpha"]
+    n = nx * ny
+    ctx = api.ac_ctx_create(0)
+    b = torch.from_numpy(first_block_rhs(n, ell, seed=a.seed)).to(dev)
+    out = {}
+    for drift in (0.0, 0.5, 1.0):
+        kb = drifting_kappa_blocks(nx, ny, ell, w["kappa0"], w["corr"], w["std"], drift, seed=a.seed)
+        prob = api.ac_problem_create_blocks(ctx, 2, nx, ny, torch.from_numpy(kb.reshape(-1)).to(dev), ell, alpha)
+        api.ac_problem_create_multigrid(prob)
+        del kb
+        # the nested-Chebyshev P(A_hat) stalls for strongly drifting blocks: cap its iterations
+        cases = {"nested_cheb": api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=a.p, tol=a.tol, restart_m=a.restart,
+                                         max_outer=1000),
+                 "saddle_sp8": api.Opts(precision=L.AC_PREC_FP64, inner=L.AC_INNER_SP, p=8, tol=a.tol,
+                                        restart_m=a.restart, max_outer=3000)}
+        for name, opts in cases.items():
+            ws = api.workspace(api.ac_solve_workspace_size(prob, opts))
+            x = torch.zeros_like(b)
+            api.ac_ctx_set_profiling(ctx, True)
+            api.ac_ctx_reset_stats(ctx)
+            api.ac_solve(prob, opts, b, x, ws)  # warm-up, profiled
+            st = api.ac_ctx_kernel_stats(ctx)["apply_calA"]
+            api.ac_ctx_set_profiling(ctx, False)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = api.ac_solve(prob, opts, b, x, ws)
+            torch.cuda.synchronize()
+            rec = {"seconds": time.perf_counter() - t0, "outer_iters": info["outer_iters"],
+                   "converged": info["converged"], "rel_residual": info["rel_residual_true"],
+                   "calA_GBps": st["bytes"] / st["ms"] / 1e6 if st["ms"] > 0 else None}
+            log(f"drift {drift} {name}: {rec}")
+            out[f"drift{drift}_{name}"] = rec
+            del ws
+        del prob
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "seconds per all-at-once solve to 1e-8, varying diagonal blocks (drift 0.5)", "value":
+            out["drift0.5_nested_cheb"]["seconds"], "unit": "s/solve", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000 * out["drift0.5_nested_cheb"]["seconds"], "higher_is_better": False,
+        "dtype": "c64+bf16 (inner), f64 (outer)", "data": "synthetic",
+        "config": {"workload": f"{nx}x{ny}, l {ell} drifting log-normal blocks, alpha {alpha}, FGMRES({a.restart})"},
+        "cases": out,
+    }), flush=True)
+
+
 def kernels_only(a, api, prob, ell, n):
     """A few P_NC^{-1} applications in the solve's precision and launch shape, then a
     plain device copy of known size (reference for the FETCH_SIZE/WRITE_SIZE scale)."""
@@ -368,6 +426,9 @@ def main():
         return
     if a.mode == "sp":
         sp_mode(a)
+        return
+    if a.mode == "blocks":
+        blocks_mode(a)
         return
     import torch
     from paper_2506_03947_amd import api

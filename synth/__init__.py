@@ -9,6 +9,7 @@ sharing any computational code.
 from .inputs import (  # noqa: F401
     gaussian_random_field,
     lognormal_kappa,
+    drifting_kappa_blocks,
     first_block_rhs,
     random_block_vector,
     batched_problem_specs,

@@ -50,6 +50,16 @@ def lognormal_kappa(nx: int, ny: int, kappa0: float, corr_len: float, std: float
     return np.ascontiguousarray((kappa0 * np.exp(g)).reshape(-1))
 
 
+def drifting_kappa_blocks(nx: int, ny: int, ell: int, kappa0: float, corr_len: float, std: float, drift: float,
+                          seed: int) -> np.ndarray:
+    """l coefficient fields kappa_k = kappa0 exp(g + drift (k / l) h), k = 0..l-1, with g, h
+    independent Gaussian random fields: a log-normal field whose pattern drifts through
+    the time window (drift 0 gives l equal blocks).  Shape (l, nx*ny)."""
+    g = gaussian_random_field(nx, ny, corr_len, std, seed).reshape(-1)
+    h = gaussian_random_field(nx, ny, corr_len, std, seed + 1).reshape(-1)
+    return np.stack([kappa0 * np.exp(g + drift * (k / ell) * h) for k in range(ell)])
+
+
 def first_block_rhs(n: int, ell: int, seed: int) -> np.ndarray:
     """b = (b_1, 0, ..., 0), b_1 = default_rng(seed).standard_normal(n)."""
     b = np.zeros(ell * n)
