@@ -2,7 +2,7 @@
 mixed precision against float64 inner solves, with the shifted-stencil roofline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium]
-                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact|sp|blocks]
+                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact|sp|blocks|paper]
 
 One step = one FGMRES(30) solve of calA x = b (b = (b_1, 0, ..., 0)) from x = 0
 on resident device inputs, preconditioned by the nested-Chebyshev block
@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp", "blocks"],
+    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp", "blocks", "paper"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
                          "(the launch set used for hardware-counter runs); batch: many uneven problems "
                          "solved one by one and as one batch")
@@ -333,6 +333,69 @@ def blocks_mode(a):
     }), flush=True)
 
 
+def paper_mode(a):
+    """The paper's high-dimension comparison (Section 5): the paper operator
+    A = I - (nu/h^2) L on n_x^2 grids, n_x in {500, 750, 1000, 1250, 1500}, l = 10,
+    alpha = 0.01, b = (b_1, 0, ...), outer Chebyshev with the Corollary 1 interval to 1e-6;
+    P_NC2 with the Algorithm 1 allocation of the budget l n_x eta, eta = 0.2 (float64 and
+    complex64 with float32 kappa), and P_SP with 14 MINRES / CG steps per shift (the paper's matvec counts imply
+    about 14).  Times, outer iterations and matvecs next to the paper's table."""
+    import torch
+    from paper_2506_03947_amd import api
+    from synth import first_block_rhs
+    L = api.L
+    dev = torch.device("cuda:0")
+    ell, alpha, eta, D = 10, 0.01, 0.2, 0.2
+    paper = {500: (7, 7035, 2, 532), 750: (7, 10535, 2, 516), 1000: (7, 14056, 2, 516), 1250: (7, 17535, 2, 532),
+             1500: (6, 18030, 2, 516)}
+    ctx = api.ac_ctx_create(0)
+    out = {}
+    for nx in sorted(paper):
+        n = nx * nx
+        h = 1.0 / (nx + 1)
+        kap = D * D / (2 * ell - 4) / (h * h)
+        # exact constant-coefficient interval (Appendix A)
+        lo = 1.0 + kap * 2.0 * 4.0 * np.sin(np.pi / (2 * (nx + 1))) ** 2
+        hi = 1.0 + kap * 2.0 * 4.0 * np.cos(np.pi / (2 * (nx + 1))) ** 2
+        prob = api.ac_problem_create(ctx, 2, nx, nx, torch.full((n,), kap, dtype=torch.float64, device=dev), ell,
+                                     alpha, bounds=(lo, hi))
+        api.ac_problem_create_multigrid(prob)
+        b = torch.from_numpy(first_block_rhs(n, ell, seed=0)).to(dev)
+        pm = api.ac_alloc_nc2(prob, ell * nx * eta)
+        cases = {"nc2_f64": api.Opts(precision=L.AC_PREC_FP64, p=pm, tol=1e-6, restart_m=1, max_outer=200,
+                                     outer=L.AC_OUTER_CHEBYSHEV),
+                 # the outer Chebyshev iteration refuses bf16 kappa (its interval is too narrow)
+                 "nc2_mixed": api.Opts(precision=L.AC_PREC_MIXED_FP32K, p=pm, tol=1e-6, restart_m=1, max_outer=200,
+                                       outer=L.AC_OUTER_CHEBYSHEV),
+                 "sp14": api.Opts(precision=L.AC_PREC_FP64, inner=L.AC_INNER_SP, p=14, tol=1e-6, restart_m=1,
+                                  max_outer=200, outer=L.AC_OUTER_CHEBYSHEV)}
+        row = {}
+        for name, opts in cases.items():
+            ws = api.workspace(api.ac_solve_workspace_size(prob, opts))
+            x = torch.zeros_like(b)
+            api.ac_solve(prob, opts, b, x, ws)
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = api.ac_solve(prob, opts, b, x, ws)
+            torch.cuda.synchronize()
+            row[name] = {"seconds": time.perf_counter() - t0, "outer_iters": info["outer_iters"],
+                         "matvecs_A": info["matvecs_A"], "converged": info["converged"]}
+            del ws
+        row["paper"] = {"nc2_iters": paper[nx][0], "nc2_matvecs": paper[nx][1], "sp_iters": paper[nx][2],
+                        "sp_matvecs": paper[nx][3]}
+        log(f"n_x {nx}: {row}")
+        out[str(nx)] = row
+        del prob
+        torch.cuda.empty_cache()
+    print(json.dumps({
+        "metric": "seconds per outer-Chebyshev solve to 1e-6, paper operator, n_x = 1500 (P_SP)",
+        "value": out["1500"]["sp14"]["seconds"], "unit": "s/solve", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": 1000 * out["1500"]["sp14"]["seconds"], "higher_is_better": False, "dtype": "f64",
+        "data": "synthetic", "config": {"workload": "paper operator, n_x 500..1500, l 10, alpha 0.01, eta 0.2"},
+        "rows": out}), flush=True)
+
+
 def kernels_only(a, api, prob, ell, n):
     """A few P_NC^{-1} applications in the solve's precision and launch shape, then a
     plain device copy of known size (reference for the FETCH_SIZE/WRITE_SIZE scale)."""
@@ -429,6 +492,9 @@ def main():
         return
     if a.mode == "blocks":
         blocks_mode(a)
+        return
+    if a.mode == "paper":
+        paper_mode(a)
         return
     import torch
     from paper_2506_03947_amd import api

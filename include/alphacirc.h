@@ -125,7 +125,10 @@ typedef struct {
  *                       [1, mu_lo^l / (mu_lo^l - alpha)], mu_lo the lower spectral bound
  *                       of A; valid for a linear preconditioner (AC_INNER_CHEB,
  *                       AC_INNER_EXACT); also run with AC_INNER_SP, whose inner
- *                       MINRES / CG make it nonlinear (the paper's setting). */
+ *                       MINRES / CG make it nonlinear (the paper's setting).  Not with
+ *                       AC_PREC_MIXED_BF16K (AC_ERR_UNSUPPORTED): bf16 rounding of kappa
+ *                       moves the eigenvalues of P^{-1} calA out of that interval, whose
+ *                       width is about alpha / mu_lo^l. */
 typedef enum { AC_OUTER_FGMRES = 0, AC_OUTER_CHEBYSHEV = 1 } ac_outer;
 
 typedef struct {

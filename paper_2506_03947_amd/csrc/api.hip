@@ -1572,6 +1572,10 @@ int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
                                         "inner solves");
     if (p->kblocks)
         return fail(AC_ERR_UNSUPPORTED, "no eigenvalue interval is known for varying diagonal blocks (use FGMRES)");
+    // bf16 rounding of kappa (relative 2^-9) moves the eigenvalues of P^{-1} calA by more
+    // than the width of the Corollary 1 interval at small alpha, and the iteration diverges
+    if (o->precision == AC_PREC_MIXED_BF16K)
+        return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration needs float32 or float64 kappa in the inner solve");
     ac_ctx* c = p->ctx;
     hipStream_t st = c->stream;
     const long long len = static_cast<long long>(p->ell) * p->g.n;

@@ -104,3 +104,18 @@ def test_paper_counts_alpha_001(eta, below, above):
         d = info["outer_iters"] - r["iterations"]
         print(f"{r['source']} nx={nx} eta={eta}: paper {r['iterations']} ours {info['outer_iters']}")
         assert info["converged"] and -below <= d <= above, (r, info["outer_iters"])
+
+
+def test_outer_chebyshev_rejects_bf16_kappa():
+    """The Corollary 1 interval is about alpha / mu_lo^l wide; bf16 rounding of kappa
+    perturbs P^{-1} calA by more than that, so the library refuses the combination
+    (float32 kappa is accepted, see test_outer_chebyshev_variable_kappa_mixed)."""
+    nx, ell = 32, 4
+    p = G.problem(2, nx, nx, 2.0, ell, 1e-2)
+    opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=5, tol=1e-6, restart_m=1, max_outer=10,
+                    outer=L.AC_OUTER_CHEBYSHEV)
+    b = G.dev(first_block_rhs(nx * nx, ell, seed=0))
+    x = torch.zeros_like(b)
+    with pytest.raises(L.AlphacircError) as e:
+        api.ac_solve(p, opts, b, x, api.workspace(api.ac_solve_workspace_size(p, opts)))
+    assert e.value.status == L.AC_ERR_UNSUPPORTED
