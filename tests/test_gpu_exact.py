@@ -45,6 +45,10 @@ def _exact(p, precision, r):
     (2, 40, 1, 3, 0.5, 5.0),
     (1, 57, 1, 7, 1e-2, 11.0),
     (2, 70, 66, 10, 1e-2, 25.0),
+    (2, 17, 15, 2, 0.3, 4.0),      # only real shifts
+    (2, 12, 19, 3, 1e-2, 6.0),     # one real, one complex shift
+    (2, 20, 18, 16, 1e-3, 9.0),    # the largest l
+    (1, 1, 1, 4, 0.5, 2.0),        # a single point
 ])
 def test_exact_prec_matches_oracle(dim, nx, ny, ell, alpha, kappa):
     A = ops.build_A(dim, nx, ny, kappa)

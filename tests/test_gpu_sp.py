@@ -53,6 +53,10 @@ def test_vcycle_matches_oracle(dim, nx, ny):
     (2, 13, 11, 5, 1.0, 3),
     (1, 40, 1, 8, 0.05, 6),
     (2, 24, 20, 10, 0.01, 8),
+    (2, 15, 9, 2, 0.2, 5),         # only real shifts (CG)
+    (2, 11, 14, 3, 0.01, 5),       # one complex shift (MINRES) and one real
+    (2, 18, 16, 16, 1e-3, 4),      # the largest l: 7 complex + 2 real shifts, 16 V-cycle vectors
+    (2, 2, 2, 4, 0.3, 3),          # a grid that is its own coarsest level
 ])
 def test_sp_prec_matches_oracle(dim, nx, ny, ell, alpha, iters):
     n = nx * ny
