@@ -96,7 +96,8 @@ typedef enum { AC_PREC_FP64 = 0, AC_PREC_MIXED_BF16K = 1, AC_PREC_MIXED_FP32K = 
  * P_D and the CG preconditioner applied by one geometric multigrid V-cycle (built by
  * ac_problem_create_multigrid; the paper uses a black-box algebraic multigrid there).
  * p_uniform (or equal p_per_shift entries) iterations per shift from a zero guess;
- * float64 only; nonlinear (use FGMRES, or the outer Chebyshev iteration as the paper
+ * float64 (AC_PREC_FP64) or float32 vectors and multigrid coefficients with float64
+ * inner products and recurrence scalars (AC_PREC_MIXED_FP32K; bf16 is refused); nonlinear (use FGMRES, or the outer Chebyshev iteration as the paper
  * does); two products with A per MINRES step and one per CG step are counted. */
 typedef enum {
     AC_INNER_CHEB = 0,

@@ -261,6 +261,7 @@ struct MgLevel {
     // wx / wy: face to the x+1 / y+1 neighbour (0 past the last point); bx0/bx1 (per
     // row) and by0/by1 (per column): Dirichlet faces; diag = 1 + all faces of a point
     double *diag, *wx, *wy, *bx0, *bx1, *by0, *by1;
+    float *diag_f, *wx_f, *wy_f;  // float32 copies for the float32 cycle
 };
 struct MgHierarchy {
     int nlev;
@@ -268,16 +269,19 @@ struct MgHierarchy {
 };
 // Level sizes of the hierarchy of a dim-dimensional nx x ny grid; returns the count.
 int mg_plan(int dim, int nx, int ny, MgLevel* out);
-// doubles of one level's arrays
+// doubles of one level's arrays (the float32 copies included)
 size_t mg_level_doubles(const MgLevel& L);
 // Fills every level's arrays from the fine coefficient (pointers assigned by the caller).
 hipError_t mg_build(const MgHierarchy& h, const double* kappa, hipStream_t s);
-// scratch doubles of a V-cycle over nv vectors
-size_t mg_scratch_doubles(const MgHierarchy& h, int nv);
+// scratch elements (of the vector type) of a V-cycle over nv vectors
+size_t mg_scratch_elems(const MgHierarchy& h, int nv);
 // u[v] = V-cycle applied to b[v] for the operator A - c[v] I (host arrays of nv <=
-// kMgMaxVec device pointers / shifts); u may not alias b.
+// kMgMaxVec device pointers / shifts); u may not alias b.  The float overload runs on
+// the float32 copies of the level arrays (the coarsest solve stays float64).
 hipError_t mg_vcycle(const MgHierarchy& h, int nv, const double* const* b, double* const* u, const double* c,
                      double* scratch, hipStream_t s);
+hipError_t mg_vcycle(const MgHierarchy& h, int nv, const float* const* b, float* const* u, const double* c,
+                     float* scratch, hipStream_t s);
 
 // ---- saddle-point inner solves of P_SP (sp.hip) ---------------------------------
 // nc complex shifts (MINRES on the real saddle form, P_D by V-cycles) and nr real
@@ -289,13 +293,15 @@ struct SpProblem {
     double sigma[kMaxShift], rho[kMaxShift];  // complex: |Im lambda|, Re lambda
     int im_pos[kMaxShift];                    // complex: Im lambda > 0
     double lam[kMaxShift];                    // real shifts
-    const double* bc[kMaxShift];              // complex right-hand sides (interleaved, n points)
-    double* yc[kMaxShift];                    // complex solutions (interleaved)
-    const double* br[kMaxShift];              // real right-hand sides (n)
-    double* yr[kMaxShift];                    // real solutions
+    // slot data of the vector type (float64 or float32)
+    const void* bc[kMaxShift];                // complex right-hand sides (interleaved, n points)
+    void* yc[kMaxShift];                      // complex solutions (interleaved)
+    const void* br[kMaxShift];                // real right-hand sides (n)
+    void* yr[kMaxShift];                      // real solutions
 };
-size_t sp_ws_doubles(const MgHierarchy& h, long long n, int nc, int nr);
-hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s);
+// f32: float32 vectors and multigrid coefficients (inner products and scalars float64)
+size_t sp_ws_bytes(const MgHierarchy& h, long long n, int nc, int nr, bool f32);
+hipError_t sp_solve(const SpProblem& P, int iters, bool f32, void* ws, hipStream_t s);
 
 // ---- setup kernels (setup.hip) -----------------------------------------------
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,

@@ -312,7 +312,8 @@ int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>&
     pm.assign(p->ell, 0);
     if (o->inner == AC_INNER_SP) {
         if (!p->mgmem) return fail(AC_ERR_ARG, "no multigrid hierarchy (ac_problem_create_multigrid)");
-        if (o->precision != AC_PREC_FP64) return fail(AC_ERR_UNSUPPORTED, "P_SP runs in float64");
+        if (o->precision == AC_PREC_MIXED_BF16K)
+            return fail(AC_ERR_UNSUPPORTED, "P_SP runs in float64 or float32 (AC_PREC_MIXED_FP32K)");
         for (int m = 0; m < p->ell; ++m) {
             const int v = o->p_per_shift ? o->p_per_shift[m] : o->p_uniform;
             if (v < 1 || v > 100000) return fail(AC_ERR_ARG, "inner iteration counts must be in [1, 100000]");
@@ -354,9 +355,9 @@ size_t exact_extra_bytes(const ac_problem* p, int prec) {
            align_up(ac::exact_carry_bytes(p->g.nx, p->g.ny, p->ns), 256) + kBlasWs;
 }
 
-size_t sp_extra_bytes(const ac_problem* p) {
+size_t sp_extra_bytes(const ac_problem* p, int prec) {
     if (!p->mgmem) return 0;
-    return ac::sp_ws_doubles(p->mg, p->g.n, p->nsc, p->nsr) * sizeof(double) + 256;
+    return ac::sp_ws_bytes(p->mg, p->g.n, p->nsc, p->nsr, prec != AC_PREC_FP64) + 256;
 }
 
 size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
@@ -364,7 +365,7 @@ size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
     spectral_offsets(p, off);
     size_t b = 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
     if (inner == AC_INNER_EXACT) b += exact_extra_bytes(p, prec);
-    else if (inner == AC_INNER_SP) b += sp_extra_bytes(p);
+    else if (inner == AC_INNER_SP) b += sp_extra_bytes(p, prec);
     else if (inner != AC_INNER_CHEB) b += cnn_ws_bytes(p);
     return b;
 }
@@ -933,35 +934,36 @@ int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
 }
 
 // P_SP: every shifted solve by saddle-point MINRES (complex shifts) or CG (real shifts)
-// with multigrid preconditioners, pm[0] iterations each, then the inverse time-DFT.
-int sp_inner(ac_problem* p, int iters, const PrecBufs& b, double* z) {
+// with multigrid preconditioners, pm[0] iterations each, then the inverse time-DFT; in
+// float32 (vectors and multigrid coefficients) for AC_PREC_MIXED_FP32K.
+int sp_inner(ac_problem* p, int prec, int iters, const PrecBufs& b, double* z) {
     ac::SpProblem P{};
     P.h = &p->mg;
     P.n = p->g.n;
     for (int s = 0; s < p->ns; ++s) {
         const cplx lam = shift_of(p, slot_to_m(p, s));
-        char* in = slot_ptr(p, AC_PREC_FP64, b.rhat, s);
-        char* out = slot_ptr(p, AC_PREC_FP64, b.buf[0], s);
+        char* in = slot_ptr(p, prec, b.rhat, s);
+        char* out = slot_ptr(p, prec, b.buf[0], s);
         if (slot_is_real(p, s)) {
             P.lam[P.nr] = lam.real();
-            P.br[P.nr] = reinterpret_cast<const double*>(in);
-            P.yr[P.nr++] = reinterpret_cast<double*>(out);
+            P.br[P.nr] = in;
+            P.yr[P.nr++] = out;
         } else {
             P.sigma[P.nc] = std::abs(lam.imag());
             P.rho[P.nc] = lam.real();
             P.im_pos[P.nc] = lam.imag() > 0.0 ? 1 : 0;
-            P.bc[P.nc] = reinterpret_cast<const double*>(in);
-            P.yc[P.nc++] = reinterpret_cast<double*>(out);
+            P.bc[P.nc] = in;
+            P.yc[P.nc++] = out;
         }
     }
     char* ws = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(b.cnn), 256));
     // per iteration: the saddle / CG operators (2 resp. 1 products with A), a V-cycle per
     // vector, the Lanczos / CG vector updates and two inner products
-    const double n8 = 8.0 * p->g.n;
-    const double bytes = iters * n8 * (p->nsc * 2.0 * 12.0 + p->nsr * 10.0);
+    const double ne = static_cast<double>(inner_elem(prec)) * p->g.n;
+    const double bytes = iters * ne * (p->nsc * 2.0 * 12.0 + p->nsr * 10.0);
     ProfScope ps(p->ctx, AC_K_SADDLE, bytes);
-    AC_HIP(ac::sp_solve(P, iters, reinterpret_cast<double*>(ws), p->ctx->stream));
-    AC_HIP(ac::launch_tdft_inv(p->ell, AC_PREC_FP64, inv_args(p, AC_PREC_FP64, b.buf[0], z), p->ctx->stream));
+    AC_HIP(ac::sp_solve(P, iters, prec != AC_PREC_FP64, ws, p->ctx->stream));
+    AC_HIP(ac::launch_tdft_inv(p->ell, prec, inv_args(p, prec, b.buf[0], z), p->ctx->stream));
     return AC_OK;
 }
 
@@ -970,7 +972,7 @@ int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
     const PrecBufs b = carve_prec(p, o->precision, ws);
     AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
     if (o->inner == AC_INNER_SP) {
-        AC_TRY(sp_inner(p, pm[0], b, z));
+        AC_TRY(sp_inner(p, o->precision, pm[0], b, z));
     } else if (o->inner == AC_INNER_EXACT) {
         AC_TRY(exact_inner(p, o->precision, b, z));
     } else if (o->inner != AC_INNER_CHEB) {
@@ -1301,6 +1303,9 @@ int ac_problem_create_multigrid(ac_problem* p) {
         L.bx1 = L.bx0 + L.ny;
         L.by0 = L.bx1 + L.ny;
         L.by1 = L.by0 + L.nx;
+        L.diag_f = reinterpret_cast<float*>(L.by1 + L.nx);
+        L.wx_f = L.diag_f + L.n;
+        L.wy_f = L.wx_f + L.n;
         q += align_up(ac::mg_level_doubles(L), 32);
     }
     hipError_t e = ac::mg_build(h, p->k64, p->ctx->stream);
@@ -1318,7 +1323,7 @@ int ac_mg_workspace_size(const ac_problem* p, int nvec, size_t* bytes) {
     if (!p || !bytes) return fail(AC_ERR_ARG, "NULL argument");
     if (!p->mgmem) return fail(AC_ERR_ARG, "no multigrid hierarchy (ac_problem_create_multigrid)");
     if (nvec < 1 || nvec > ac::kMgMaxVec) return fail(AC_ERR_ARG, "nvec out of range");
-    *bytes = ac::mg_scratch_doubles(p->mg, nvec) * sizeof(double) + 256;
+    *bytes = ac::mg_scratch_elems(p->mg, nvec) * sizeof(double) + 256;
     return AC_OK;
 }
 
@@ -1328,7 +1333,7 @@ int ac_mg_vcycle(ac_problem* p, int nvec, const double* shifts, const double* b,
     if (nvec < 1 || nvec > ac::kMgMaxVec) return fail(AC_ERR_ARG, "nvec out of range");
     for (int q = 0; q < nvec; ++q)
         if (!(shifts[q] < p->bounds[AC_PREC_FP64][0])) return fail(AC_ERR_ARG, "every shift must be below mu_lo");
-    if (!ws || ws_bytes < ac::mg_scratch_doubles(p->mg, nvec) * sizeof(double) + 256)
+    if (!ws || ws_bytes < ac::mg_scratch_elems(p->mg, nvec) * sizeof(double) + 256)
         return fail(AC_ERR_WORKSPACE, "workspace too small");
     AC_HIP(hipSetDevice(p->ctx->device));
     const double* bs[ac::kMgMaxVec];

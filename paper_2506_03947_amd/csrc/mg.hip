@@ -24,13 +24,6 @@ namespace {
 
 constexpr double kOmega = 0.8;
 
-struct MgVecs {
-    const double* in[kMgMaxVec];  // iterate
-    const double* b[kMgMaxVec];   // right-hand side
-    double* out[kMgMaxVec];
-    double c[kMgMaxVec];
-};
-
 __device__ __forceinline__ double harm4(double a, double b) { return a * b / (2.0 * (a + b)); }
 
 int grid_of(long long n) { return static_cast<int>((n + 255) / 256); }
@@ -164,100 +157,134 @@ __global__ void diag_kernel(const MgLevel L) {
 }
 
 // ---- cycle kernels -----------------------------------------------------------------
-// The sweeps run one thread per point over every vector of the batch (the level's
-// coefficients are read once per point), two vectors at a time so that both vectors'
-// loads are issued before either store.  The transfers run one thread per (point,
-// vector) with the vector in blockIdx.y.
+// T = double (float64 vectors and coefficients) or float (the float32 copies of the
+// level arrays).  The sweeps run one thread per point over every vector of the batch
+// (the level's coefficients are read once per point), two vectors at a time so that
+// both vectors' loads are issued before either store.  The transfers run one thread per
+// (point, vector) with the vector in blockIdx.y.
+
+template <typename T>
+struct MgVecsT {
+    const T* in[kMgMaxVec];  // iterate
+    const T* b[kMgMaxVec];   // right-hand side
+    T* out[kMgMaxVec];
+    double c[kMgMaxVec];
+};
+
+template <typename T> __device__ __forceinline__ const T* diag_of(const MgLevel& L);
+template <> __device__ __forceinline__ const double* diag_of<double>(const MgLevel& L) { return L.diag; }
+template <> __device__ __forceinline__ const float* diag_of<float>(const MgLevel& L) { return L.diag_f; }
+template <typename T> __device__ __forceinline__ const T* wx_of(const MgLevel& L);
+template <> __device__ __forceinline__ const double* wx_of<double>(const MgLevel& L) { return L.wx; }
+template <> __device__ __forceinline__ const float* wx_of<float>(const MgLevel& L) { return L.wx_f; }
+template <typename T> __device__ __forceinline__ const T* wy_of(const MgLevel& L);
+template <> __device__ __forceinline__ const double* wy_of<double>(const MgLevel& L) { return L.wy; }
+template <> __device__ __forceinline__ const float* wy_of<float>(const MgLevel& L) { return L.wy_f; }
 
 // Coefficients of point i: A u = d u_i - e u_{i+1} - w u_{i-1} - n u_{i+nx} - s u_{i-nx}
 // (a missing neighbour has coefficient 0 and is not read).
+template <typename T>
 struct Co {
-    double d, e, w, n, s;
+    T d, e, w, n, s;
     bool he, hw, hn, hs;
 };
-__device__ __forceinline__ Co coef_at(const MgLevel& L, long long i, int x, int y) {
-    Co c;
-    c.d = L.diag[i];
+template <typename T>
+__device__ __forceinline__ Co<T> coef_at(const MgLevel& L, long long i, int x, int y) {
+    const T* dg = diag_of<T>(L);
+    const T* wx = wx_of<T>(L);
+    const T* wy = wy_of<T>(L);
+    Co<T> c;
+    c.d = dg[i];
     c.he = x < L.nx - 1;
     c.hw = x > 0;
     c.hn = L.dim == 2 && y < L.ny - 1;
     c.hs = L.dim == 2 && y > 0;
-    c.e = c.he ? L.wx[i] : 0.0;
-    c.w = c.hw ? L.wx[i - 1] : 0.0;
-    c.n = c.hn ? L.wy[i] : 0.0;
-    c.s = c.hs ? L.wy[i - L.nx] : 0.0;
+    c.e = c.he ? wx[i] : T(0);
+    c.w = c.hw ? wx[i - 1] : T(0);
+    c.n = c.hn ? wy[i] : T(0);
+    c.s = c.hs ? wy[i - L.nx] : T(0);
     return c;
 }
 // the five stencil values of an array at point i (0 for a missing neighbour)
+template <typename T>
 struct St {
-    double c, e, w, n, s;
+    T c, e, w, n, s;
 };
-__device__ __forceinline__ St stencil(const Co& k, const double* __restrict__ u, long long i, long long nx) {
-    St t;
+template <typename T>
+__device__ __forceinline__ St<T> stencil(const Co<T>& k, const T* __restrict__ u, long long i, long long nx) {
+    St<T> t;
     t.c = u[i];
-    t.e = k.he ? u[i + 1] : 0.0;
-    t.w = k.hw ? u[i - 1] : 0.0;
-    t.n = k.hn ? u[i + nx] : 0.0;
-    t.s = k.hs ? u[i - nx] : 0.0;
+    t.e = k.he ? u[i + 1] : T(0);
+    t.w = k.hw ? u[i - 1] : T(0);
+    t.n = k.hn ? u[i + nx] : T(0);
+    t.s = k.hs ? u[i - nx] : T(0);
     return t;
 }
-__device__ __forceinline__ double apply_st(const Co& k, const St& u, double c) {
+template <typename T>
+__device__ __forceinline__ T apply_st(const Co<T>& k, const St<T>& u, T c) {
     return (k.d - c) * u.c - k.e * u.e - k.w * u.w - k.n * u.n - k.s * u.s;
 }
 
 // out = in + omega (b - (A - cI) in) / (d - c)   (SWEEP)   or   out = b - (A - cI) in
-template <bool SWEEP>
-__global__ void sweep_kernel(const MgLevel L, const MgVecs v, int nv) {
+template <typename T, bool SWEEP>
+__global__ void sweep_kernel(const MgLevel L, const MgVecsT<T> v, int nv) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= L.n) return;
     const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
-    const Co k = coef_at(L, i, x, y);
+    const Co<T> k = coef_at<T>(L, i, x, y);
+    const T om = static_cast<T>(kOmega);
     for (int q = 0; q < nv; q += 2) {
         const bool two = q + 1 < nv;
-        const St u0 = stencil(k, v.in[q], i, L.nx);
-        const double b0 = v.b[q][i];
-        St u1{};
-        double b1 = 0.0;
+        const St<T> u0 = stencil(k, v.in[q], i, L.nx);
+        const T b0 = v.b[q][i];
+        St<T> u1{};
+        T b1 = T(0);
         if (two) {
             u1 = stencil(k, v.in[q + 1], i, L.nx);
             b1 = v.b[q + 1][i];
         }
-        const double r0 = b0 - apply_st(k, u0, v.c[q]);
-        v.out[q][i] = SWEEP ? u0.c + kOmega * r0 / (k.d - v.c[q]) : r0;
+        const T c0 = static_cast<T>(v.c[q]);
+        const T r0 = b0 - apply_st(k, u0, c0);
+        v.out[q][i] = SWEEP ? u0.c + om * r0 / (k.d - c0) : r0;
         if (two) {
-            const double r1 = b1 - apply_st(k, u1, v.c[q + 1]);
-            v.out[q + 1][i] = SWEEP ? u1.c + kOmega * r1 / (k.d - v.c[q + 1]) : r1;
+            const T c1 = static_cast<T>(v.c[q + 1]);
+            const T r1 = b1 - apply_st(k, u1, c1);
+            v.out[q + 1][i] = SWEEP ? u1.c + om * r1 / (k.d - c1) : r1;
         }
     }
 }
 
 // Two sweeps from zero: u1 = omega b / (d - c) at every point, out = u1 + omega (b -
 // (A - cI) u1) / (d - c); u1 at the neighbours is formed from their b and diagonal.
-__global__ void sweep2_from_zero_kernel(const MgLevel L, const MgVecs v, int nv) {
+template <typename T>
+__global__ void sweep2_from_zero_kernel(const MgLevel L, const MgVecsT<T> v, int nv) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= L.n) return;
     const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
-    const Co k = coef_at(L, i, x, y);
-    const St dg = stencil(k, L.diag, i, L.nx);
-    auto first = [&](const St& b, double c) {
-        St u;
-        u.c = kOmega * b.c / (dg.c - c);
-        u.e = k.he ? kOmega * b.e / (dg.e - c) : 0.0;
-        u.w = k.hw ? kOmega * b.w / (dg.w - c) : 0.0;
-        u.n = k.hn ? kOmega * b.n / (dg.n - c) : 0.0;
-        u.s = k.hs ? kOmega * b.s / (dg.s - c) : 0.0;
+    const Co<T> k = coef_at<T>(L, i, x, y);
+    const St<T> dg = stencil(k, diag_of<T>(L), i, L.nx);
+    const T om = static_cast<T>(kOmega);
+    auto first = [&](const St<T>& b, T c) {
+        St<T> u;
+        u.c = om * b.c / (dg.c - c);
+        u.e = k.he ? om * b.e / (dg.e - c) : T(0);
+        u.w = k.hw ? om * b.w / (dg.w - c) : T(0);
+        u.n = k.hn ? om * b.n / (dg.n - c) : T(0);
+        u.s = k.hs ? om * b.s / (dg.s - c) : T(0);
         return u;
     };
     for (int q = 0; q < nv; q += 2) {
         const bool two = q + 1 < nv;
-        const St b0 = stencil(k, v.b[q], i, L.nx);
-        St b1{};
+        const St<T> b0 = stencil(k, v.b[q], i, L.nx);
+        St<T> b1{};
         if (two) b1 = stencil(k, v.b[q + 1], i, L.nx);
-        const St u0 = first(b0, v.c[q]);
-        v.out[q][i] = u0.c + kOmega * (b0.c - apply_st(k, u0, v.c[q])) / (k.d - v.c[q]);
+        const T c0 = static_cast<T>(v.c[q]);
+        const St<T> u0 = first(b0, c0);
+        v.out[q][i] = u0.c + om * (b0.c - apply_st(k, u0, c0)) / (k.d - c0);
         if (two) {
-            const St u1 = first(b1, v.c[q + 1]);
-            v.out[q + 1][i] = u1.c + kOmega * (b1.c - apply_st(k, u1, v.c[q + 1])) / (k.d - v.c[q + 1]);
+            const T c1 = static_cast<T>(v.c[q + 1]);
+            const St<T> u1 = first(b1, c1);
+            v.out[q + 1][i] = u1.c + om * (b1.c - apply_st(k, u1, c1)) / (k.d - c1);
         }
     }
 }
@@ -290,53 +317,58 @@ __device__ __forceinline__ Interp interp(int x, int nc, int coarsened) {
 }
 
 // fine out += P coarse in; grid (point blocks, vectors)
-__global__ void prolong_add_kernel(const MgLevel F, const MgLevel C, const MgVecs v) {
+template <typename T>
+__global__ void prolong_add_kernel(const MgLevel F, const MgLevel C, const MgVecsT<T> v) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= F.n) return;
     const int q = blockIdx.y;
     const int ii = static_cast<int>(i), x = ii % F.nx, y = ii / F.nx;
     const Interp ix = interp(x, C.nx, C.cx), iy = interp(y, C.ny, C.cy);
-    const double* __restrict__ e = v.in[q];
-    const double* __restrict__ r0 = e + iy.j0 * C.nx;
-    const double* __restrict__ r1 = e + iy.j1 * C.nx;
-    const double acc = iy.w0 * (ix.w0 * r0[ix.j0] + ix.w1 * r0[ix.j1]) + iy.w1 * (ix.w0 * r1[ix.j0] + ix.w1 * r1[ix.j1]);
+    const T* __restrict__ e = v.in[q];
+    const T* __restrict__ r0 = e + iy.j0 * C.nx;
+    const T* __restrict__ r1 = e + iy.j1 * C.nx;
+    const T wx0 = static_cast<T>(ix.w0), wx1 = static_cast<T>(ix.w1);
+    const T acc = static_cast<T>(iy.w0) * (wx0 * r0[ix.j0] + wx1 * r0[ix.j1]) +
+                  static_cast<T>(iy.w1) * (wx0 * r1[ix.j0] + wx1 * r1[ix.j1]);
     v.out[q][i] += acc;
 }
 
 // coarse out = R fine in: per coarsened dimension fine 2J (1/2), 2J+1 (1), 2J+2 (1/2),
 // divided by 2 per coarsened dimension; grid (point blocks, vectors)
-__global__ void restrict_kernel(const MgLevel F, const MgLevel C, const MgVecs v) {
+template <typename T>
+__global__ void restrict_kernel(const MgLevel F, const MgLevel C, const MgVecsT<T> v) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i >= C.n) return;
     const int q = blockIdx.y;
     const int ii = static_cast<int>(i), X = ii % C.nx, Y = ii / C.nx;
-    const double* __restrict__ in = v.in[q];
-    const double wd[3] = {0.5, 1.0, 0.5};
-    double acc = 0.0;
+    const T* __restrict__ in = v.in[q];
+    const T wd[3] = {T(0.5), T(1), T(0.5)};
+    T acc = T(0);
     for (int dy = 0; dy < (C.cy ? 3 : 1); ++dy) {
         const int y = C.cy ? 2 * Y + dy : Y;
         if (y >= F.ny) continue;
-        const double wy = C.cy ? wd[dy] : 1.0;
+        const T wy = C.cy ? wd[dy] : T(1);
         for (int dx = 0; dx < (C.cx ? 3 : 1); ++dx) {
             const int x = C.cx ? 2 * X + dx : X;
             if (x >= F.nx) continue;
-            const double wx = C.cx ? wd[dx] : 1.0;
+            const T wx = C.cx ? wd[dx] : T(1);
             acc += wy * wx * in[static_cast<long long>(y) * F.nx + x];
         }
     }
-    v.out[q][i] = acc / static_cast<double>(1 << (C.cx + C.cy));
+    v.out[q][i] = acc / static_cast<T>(1 << (C.cx + C.cy));
 }
 
 // Exact solve on a level of at most 4 points: one thread per vector, Gaussian
-// elimination (A - c I is symmetric positive definite).
-__global__ void coarsest_kernel(const MgLevel L, const MgVecs v, int nv) {
+// elimination in float64 (A - c I is symmetric positive definite).
+template <typename T>
+__global__ void coarsest_kernel(const MgLevel L, const MgVecsT<T> v, int nv) {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= nv) return;
     const int n = static_cast<int>(L.n);
     double M[4][4], r[4];
     for (int a = 0; a < n; ++a) {
         for (int b = 0; b < n; ++b) M[a][b] = 0.0;
-        r[a] = v.b[q][a];
+        r[a] = static_cast<double>(v.b[q][a]);
     }
     for (int a = 0; a < n; ++a) {
         const int x = a % L.nx, y = a / L.nx;
@@ -361,7 +393,74 @@ __global__ void coarsest_kernel(const MgLevel L, const MgVecs v, int nv) {
         for (int b = a + 1; b < n; ++b) t -= M[a][b] * r[b];
         r[a] = t / M[a][a];
     }
-    for (int a = 0; a < n; ++a) v.out[q][a] = r[a];
+    for (int a = 0; a < n; ++a) v.out[q][a] = static_cast<T>(r[a]);
+}
+
+// float32 copies of a level's diagonal and face arrays
+__global__ void to_float_kernel(const MgLevel L) {
+    const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= L.n) return;
+    L.diag_f[i] = static_cast<float>(L.diag[i]);
+    L.wx_f[i] = static_cast<float>(L.wx[i]);
+    L.wy_f[i] = static_cast<float>(L.wy[i]);
+}
+
+template <typename T>
+hipError_t vcycle_t(const MgHierarchy& h, int nv, const T* const* b, T* const* u, const double* c, T* scratch,
+                    hipStream_t s) {
+    if (nv < 1 || nv > kMgMaxVec || h.nlev < 1) return hipErrorInvalidValue;
+    // per level: B (right-hand sides), U (work), T (result)
+    const T* B[kMgMaxLevels][kMgMaxVec];
+    T* U[kMgMaxLevels][kMgMaxVec];
+    T* R[kMgMaxLevels][kMgMaxVec];
+    T* p = scratch;
+    for (int q = 0; q < nv; ++q) {
+        B[0][q] = b[q];
+        R[0][q] = u[q];
+        U[0][q] = p + static_cast<size_t>(q) * h.lev[0].n;
+    }
+    p += static_cast<size_t>(nv) * h.lev[0].n;
+    for (int l = 1; l < h.nlev; ++l) {
+        const size_t n = h.lev[l].n;
+        for (int q = 0; q < nv; ++q) {
+            B[l][q] = p + q * n;
+            U[l][q] = p + (nv + q) * n;
+            R[l][q] = p + (2 * nv + q) * n;
+        }
+        p += 3 * nv * n;
+    }
+    auto vecs = [&](T* const* in, const T* const* rhs, T* const* out) {
+        MgVecsT<T> v{};
+        for (int q = 0; q < nv; ++q) {
+            v.in[q] = in ? in[q] : nullptr;
+            v.b[q] = rhs ? rhs[q] : nullptr;
+            v.out[q] = out[q];
+            v.c[q] = c[q];
+        }
+        return v;
+    };
+    // down the hierarchy: two sweeps from zero, residual, restriction
+    for (int l = 0; l < h.nlev - 1; ++l) {
+        const MgLevel& L = h.lev[l];
+        const dim3 g(grid_of(L.n));
+        hipLaunchKernelGGL(sweep2_from_zero_kernel<T>, g, dim3(256), 0, s, L, vecs(nullptr, B[l], R[l]), nv);
+        hipLaunchKernelGGL((sweep_kernel<T, false>), g, dim3(256), 0, s, L, vecs(R[l], B[l], U[l]), nv);
+        T* const* Bn = const_cast<T* const*>(B[l + 1]);
+        hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid_of(h.lev[l + 1].n), nv), dim3(256), 0, s, L, h.lev[l + 1],
+                           vecs(U[l], nullptr, Bn));
+    }
+    const int last = h.nlev - 1;
+    hipLaunchKernelGGL(coarsest_kernel<T>, dim3(1), dim3(64), 0, s, h.lev[last], vecs(nullptr, B[last], R[last]), nv);
+    // and back up: correction, two sweeps
+    for (int l = h.nlev - 2; l >= 0; --l) {
+        const MgLevel& L = h.lev[l];
+        const dim3 g(grid_of(L.n));
+        hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(grid_of(L.n), nv), dim3(256), 0, s, L, h.lev[l + 1],
+                           vecs(R[l + 1], nullptr, R[l]));
+        hipLaunchKernelGGL((sweep_kernel<T, true>), g, dim3(256), 0, s, L, vecs(R[l], B[l], U[l]), nv);
+        hipLaunchKernelGGL((sweep_kernel<T, true>), g, dim3(256), 0, s, L, vecs(U[l], B[l], R[l]), nv);
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
@@ -390,7 +489,9 @@ int mg_plan(int dim, int nx, int ny, MgLevel* out) {
 }
 
 size_t mg_level_doubles(const MgLevel& L) {
-    return 3 * static_cast<size_t>(L.n) + 2 * static_cast<size_t>(L.nx) + 2 * static_cast<size_t>(L.ny);
+    // float64 diagonal and faces, Dirichlet faces, and the float32 copies (3n floats)
+    return 3 * static_cast<size_t>(L.n) + 2 * static_cast<size_t>(L.nx) + 2 * static_cast<size_t>(L.ny) +
+           (3 * static_cast<size_t>(L.n) + 1) / 2;
 }
 
 hipError_t mg_build(const MgHierarchy& h, const double* kappa, hipStream_t s) {
@@ -400,10 +501,12 @@ hipError_t mg_build(const MgHierarchy& h, const double* kappa, hipStream_t s) {
         hipLaunchKernelGGL(coarsen_faces_kernel, dim3(grid_of(h.lev[l].n)), dim3(256), 0, s, h.lev[l - 1], h.lev[l]);
         hipLaunchKernelGGL(diag_kernel, dim3(grid_of(h.lev[l].n)), dim3(256), 0, s, h.lev[l]);
     }
+    for (int l = 0; l < h.nlev; ++l)
+        hipLaunchKernelGGL(to_float_kernel, dim3(grid_of(h.lev[l].n)), dim3(256), 0, s, h.lev[l]);
     return hipGetLastError();
 }
 
-size_t mg_scratch_doubles(const MgHierarchy& h, int nv) {
+size_t mg_scratch_elems(const MgHierarchy& h, int nv) {
     // level 0: one work vector per right-hand side; coarser levels: b, u, t
     size_t d = static_cast<size_t>(nv) * h.lev[0].n;
     for (int l = 1; l < h.nlev; ++l) d += 3 * static_cast<size_t>(nv) * h.lev[l].n;
@@ -412,60 +515,12 @@ size_t mg_scratch_doubles(const MgHierarchy& h, int nv) {
 
 hipError_t mg_vcycle(const MgHierarchy& h, int nv, const double* const* b, double* const* u, const double* c,
                      double* scratch, hipStream_t s) {
-    if (nv < 1 || nv > kMgMaxVec || h.nlev < 1) return hipErrorInvalidValue;
-    // per level: B (right-hand sides), U (work), T (result)
-    const double* B[kMgMaxLevels][kMgMaxVec];
-    double* U[kMgMaxLevels][kMgMaxVec];
-    double* T[kMgMaxLevels][kMgMaxVec];
-    double* p = scratch;
-    for (int q = 0; q < nv; ++q) {
-        B[0][q] = b[q];
-        T[0][q] = u[q];
-        U[0][q] = p + static_cast<size_t>(q) * h.lev[0].n;
-    }
-    p += static_cast<size_t>(nv) * h.lev[0].n;
-    for (int l = 1; l < h.nlev; ++l) {
-        const size_t n = h.lev[l].n;
-        for (int q = 0; q < nv; ++q) {
-            B[l][q] = p + q * n;
-            U[l][q] = p + (nv + q) * n;
-            T[l][q] = p + (2 * nv + q) * n;
-        }
-        p += 3 * nv * n;
-    }
-    auto vecs = [&](int l, double* const* in, const double* const* rhs, double* const* out) {
-        MgVecs v{};
-        for (int q = 0; q < nv; ++q) {
-            v.in[q] = in ? in[q] : nullptr;
-            v.b[q] = rhs ? rhs[q] : nullptr;
-            v.out[q] = out[q];
-            v.c[q] = c[q];
-        }
-        (void)l;
-        return v;
-    };
-    // down the hierarchy: two sweeps from zero, residual, restriction
-    for (int l = 0; l < h.nlev - 1; ++l) {
-        const MgLevel& L = h.lev[l];
-        const dim3 g(grid_of(L.n));
-        hipLaunchKernelGGL(sweep2_from_zero_kernel, g, dim3(256), 0, s, L, vecs(l, nullptr, B[l], T[l]), nv);
-        hipLaunchKernelGGL(sweep_kernel<false>, g, dim3(256), 0, s, L, vecs(l, T[l], B[l], U[l]), nv);
-        double* const* Bn = const_cast<double* const*>(B[l + 1]);
-        hipLaunchKernelGGL(restrict_kernel, dim3(grid_of(h.lev[l + 1].n), nv), dim3(256), 0, s, L, h.lev[l + 1],
-                           vecs(l, U[l], nullptr, Bn));
-    }
-    const int last = h.nlev - 1;
-    hipLaunchKernelGGL(coarsest_kernel, dim3(1), dim3(64), 0, s, h.lev[last], vecs(last, nullptr, B[last], T[last]), nv);
-    // and back up: correction, two sweeps
-    for (int l = h.nlev - 2; l >= 0; --l) {
-        const MgLevel& L = h.lev[l];
-        const dim3 g(grid_of(L.n));
-        hipLaunchKernelGGL(prolong_add_kernel, dim3(grid_of(L.n), nv), dim3(256), 0, s, L, h.lev[l + 1],
-                           vecs(l, T[l + 1], nullptr, T[l]));
-        hipLaunchKernelGGL(sweep_kernel<true>, g, dim3(256), 0, s, L, vecs(l, T[l], B[l], U[l]), nv);
-        hipLaunchKernelGGL(sweep_kernel<true>, g, dim3(256), 0, s, L, vecs(l, U[l], B[l], T[l]), nv);
-    }
-    return hipGetLastError();
+    return vcycle_t<double>(h, nv, b, u, c, scratch, s);
+}
+
+hipError_t mg_vcycle(const MgHierarchy& h, int nv, const float* const* b, float* const* u, const double* c,
+                     float* scratch, hipStream_t s) {
+    return vcycle_t<float>(h, nv, b, u, c, scratch, s);
 }
 
 }  // namespace ac

@@ -10,7 +10,8 @@
 // same number of iterations from a zero guess, all in lockstep so that one batched
 // V-cycle serves every shift.  The MINRES and CG scalars live on the device (a
 // single-block kernel updates them from the reduced inner products), so an application
-// needs no host synchronisation.
+// needs no host synchronisation.  Vectors are float64, or float32 with the multigrid's
+// float32 coefficient copies (the inner products and the scalars stay float64).
 //
 // MINRES (Paige-Saunders, Lanczos form with an SPD preconditioner): from v_1 = f,
 // z_1 = M^{-1} v_1, gamma_1 = sqrt(v_1 . z_1), eta = gamma_1, c_0 = c_1 = 1,
@@ -23,6 +24,9 @@
 // x += c_{j+1} eta w_{j+1}; eta = -s_{j+1} eta.  A step that finds gamma_{j+1} = 0 (the
 // exact solution) is the last one.
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <type_traits>
 
 #include "ac_internal.h"
 
@@ -38,11 +42,13 @@ enum { G = 0, GP, ETA, C, CP, S, SP, DONE, A1, A2, A3, XC, GINV, SKIP };
 // real-slot state
 enum { RHO = 0, RDONE = 1, ALPHA = 2, BETA = 3 };
 
+template <typename T>
 struct Vec9 {
-    double* p[kMaxShift];
+    T* p[kMaxShift];
 };
+template <typename T>
 struct CVec9 {
-    const double* p[kMaxShift];
+    const T* p[kMaxShift];
 };
 
 __device__ __forceinline__ double block_sum(double v) {
@@ -57,22 +63,37 @@ __device__ __forceinline__ double block_sum(double v) {
     return t;
 }
 
-// (A - c I) u at point i on the fine level
-__device__ __forceinline__ double op_at(const MgLevel& L, const double* __restrict__ u, long long i, double c) {
-    const int x = static_cast<int>(i % L.nx), y = static_cast<int>(i / L.nx);
-    double a = (L.diag[i] - c) * u[i];
-    if (x < L.nx - 1) a -= L.wx[i] * u[i + 1];
-    if (x > 0) a -= L.wx[i - 1] * u[i - 1];
-    if (L.dim == 2) {
-        if (y < L.ny - 1) a -= L.wy[i] * u[i + L.nx];
-        if (y > 0) a -= L.wy[i - L.nx] * u[i - L.nx];
+// (A - c I) u at point i on the fine level (float64 arithmetic on the vector's and the
+// coefficients' stored type)
+template <typename T>
+__device__ __forceinline__ double op_at(const MgLevel& L, const T* __restrict__ u, long long i, double c) {
+    const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
+    double d, e = 0.0, w = 0.0, nn = 0.0, ss = 0.0;
+    if constexpr (std::is_same<T, float>::value) {
+        d = L.diag_f[i];
+        if (x < L.nx - 1) e = L.wx_f[i];
+        if (x > 0) w = L.wx_f[i - 1];
+        if (L.dim == 2 && y < L.ny - 1) nn = L.wy_f[i];
+        if (L.dim == 2 && y > 0) ss = L.wy_f[i - L.nx];
+    } else {
+        d = L.diag[i];
+        if (x < L.nx - 1) e = L.wx[i];
+        if (x > 0) w = L.wx[i - 1];
+        if (L.dim == 2 && y < L.ny - 1) nn = L.wy[i];
+        if (L.dim == 2 && y > 0) ss = L.wy[i - L.nx];
     }
+    double a = (d - c) * static_cast<double>(u[i]);
+    if (x < L.nx - 1) a -= e * static_cast<double>(u[i + 1]);
+    if (x > 0) a -= w * static_cast<double>(u[i - 1]);
+    if (L.dim == 2 && y < L.ny - 1) a -= nn * static_cast<double>(u[i + L.nx]);
+    if (L.dim == 2 && y > 0) a -= ss * static_cast<double>(u[i - L.nx]);
     return a;
 }
 
 // Sz = S (z / gamma) per complex slot (blockIdx.y), partial[blk * ns + q] of
 // (S z/gamma) . (z/gamma).  A finished slot writes zeros.
-__global__ __launch_bounds__(kThr) void saddle_apply_kernel(const MgLevel L, long long n, CVec9 z, Vec9 sz,
+template <typename T>
+__global__ __launch_bounds__(kThr) void saddle_apply_kernel(const MgLevel L, long long n, CVec9<T> z, Vec9<T> sz,
                                                             const double* __restrict__ st, SpProblem P,
                                                             double* __restrict__ partial, int ns) {
     const int q = blockIdx.y;
@@ -80,63 +101,67 @@ __global__ __launch_bounds__(kThr) void saddle_apply_kernel(const MgLevel L, lon
     const bool done = sq[DONE] != 0.0;
     const double ginv = done ? 0.0 : 1.0 / sq[G];
     const double sig = P.sigma[q], rho = P.rho[q];
-    const double* __restrict__ z1 = z.p[q];
-    const double* __restrict__ z2 = z1 + n;
-    double* __restrict__ o1 = sz.p[q];
-    double* __restrict__ o2 = o1 + n;
+    const T* __restrict__ z1 = z.p[q];
+    const T* __restrict__ z2 = z1 + n;
+    T* __restrict__ o1 = sz.p[q];
+    T* __restrict__ o2 = o1 + n;
     double acc = 0.0;
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * kThr) {
         if (done) {
-            o1[i] = 0.0;
-            o2[i] = 0.0;
+            o1[i] = T(0);
+            o2[i] = T(0);
             continue;
         }
-        const double t1 = (sig * z1[i] + op_at(L, z2, i, rho)) * ginv;
-        const double t2 = (op_at(L, z1, i, rho) - sig * z2[i]) * ginv;
-        o1[i] = t1;
-        o2[i] = t2;
-        acc += (t1 * z1[i] + t2 * z2[i]) * ginv;
+        const double a1 = z1[i], a2 = z2[i];
+        const double t1 = (sig * a1 + op_at(L, z2, i, rho)) * ginv;
+        const double t2 = (op_at(L, z1, i, rho) - sig * a2) * ginv;
+        o1[i] = static_cast<T>(t1);
+        o2[i] = static_cast<T>(t2);
+        acc += (t1 * a1 + t2 * a2) * ginv;
     }
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[static_cast<long long>(blockIdx.x) * ns + q] = t;
 }
 
 // q = (A - lambda I) p per real slot, partial of p . q (slot index nc + r)
-__global__ __launch_bounds__(kThr) void cg_apply_kernel(const MgLevel L, long long n, CVec9 pv, Vec9 qv,
+template <typename T>
+__global__ __launch_bounds__(kThr) void cg_apply_kernel(const MgLevel L, long long n, CVec9<T> pv, Vec9<T> qv,
                                                         SpProblem P, double* __restrict__ partial, int ns) {
     const int r = blockIdx.y;
-    const double* __restrict__ p = pv.p[r];
-    double* __restrict__ q = qv.p[r];
+    const T* __restrict__ p = pv.p[r];
+    T* __restrict__ q = qv.p[r];
     double acc = 0.0;
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * kThr) {
         const double a = op_at(L, p, i, P.lam[r]);
-        q[i] = a;
-        acc += p[i] * a;
+        q[i] = static_cast<T>(a);
+        acc += static_cast<double>(p[i]) * a;
     }
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[static_cast<long long>(blockIdx.x) * ns + P.nc + r] = t;
 }
 
 // v_{j+1} = Sz - (delta/gamma) v - (gamma/gamma_prev) v_prev, written over v_prev
-__global__ __launch_bounds__(kThr) void lanczos_kernel(long long len, CVec9 sz, CVec9 v, Vec9 vp,
+template <typename T>
+__global__ __launch_bounds__(kThr) void lanczos_kernel(long long len, CVec9<T> sz, CVec9<T> v, Vec9<T> vp,
                                                        const double* __restrict__ st, const double* __restrict__ sums) {
     const int q = blockIdx.y;
     const double* sq = st + q * kSt;
     if (sq[DONE] != 0.0) return;
     const double a = sums[q] / sq[G], b = sq[G] / sq[GP];
-    const double* __restrict__ s = sz.p[q];
-    const double* __restrict__ vv = v.p[q];
-    double* __restrict__ o = vp.p[q];
+    const T* __restrict__ s = sz.p[q];
+    const T* __restrict__ vv = v.p[q];
+    T* __restrict__ o = vp.p[q];
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < len;
          i += static_cast<long long>(gridDim.x) * kThr)
-        o[i] = s[i] - a * vv[i] - b * o[i];
+        o[i] = static_cast<T>(static_cast<double>(s[i]) - a * static_cast<double>(vv[i]) - b * static_cast<double>(o[i]));
 }
 
 // CG: x += a p, r -= a q with a = rho / (p . q)
-__global__ __launch_bounds__(kThr) void cg_update1_kernel(long long n, CVec9 pv, CVec9 qv, Vec9 xv, Vec9 rv,
-                                                          const double* __restrict__ st,
+template <typename T>
+__global__ __launch_bounds__(kThr) void cg_update1_kernel(long long n, CVec9<T> pv, CVec9<T> qv, Vec9<T> xv,
+                                                          Vec9<T> rv, const double* __restrict__ st,
                                                           const double* __restrict__ sums, int nc) {
     const int r = blockIdx.y;
     const double* sr = st + (nc + r) * kSt;
@@ -144,29 +169,30 @@ __global__ __launch_bounds__(kThr) void cg_update1_kernel(long long n, CVec9 pv,
     const double a = sr[RHO] / sums[nc + r];
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * kThr) {
-        xv.p[r][i] += a * pv.p[r][i];
-        rv.p[r][i] -= a * qv.p[r][i];
+        xv.p[r][i] = static_cast<T>(static_cast<double>(xv.p[r][i]) + a * static_cast<double>(pv.p[r][i]));
+        rv.p[r][i] = static_cast<T>(static_cast<double>(rv.p[r][i]) - a * static_cast<double>(qv.p[r][i]));
     }
 }
 
 // partial[blk * ns + k] of a_k . b_k over len_k entries
+template <typename T>
 struct DotArgs {
-    const double* a[2 * kMaxShift];
-    const double* b[2 * kMaxShift];
+    const T* a[2 * kMaxShift];
+    const T* b[2 * kMaxShift];
     long long len[2 * kMaxShift];
 };
-__global__ __launch_bounds__(kThr) void dot_kernel(DotArgs d, double* __restrict__ partial, int ns) {
+template <typename T>
+__global__ __launch_bounds__(kThr) void dot_kernel(DotArgs<T> d, double* __restrict__ partial, int ns) {
     const int k = blockIdx.y;
-    const double* __restrict__ a = d.a[k];
-    const double* __restrict__ b = d.b[k];
+    const T* __restrict__ a = d.a[k];
+    const T* __restrict__ b = d.b[k];
     double acc = 0.0;
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < d.len[k];
          i += static_cast<long long>(gridDim.x) * kThr)
-        acc += a[i] * b[i];
+        acc += static_cast<double>(a[i]) * static_cast<double>(b[i]);
     const double t = block_sum(acc);
     if (threadIdx.x == 0) partial[static_cast<long long>(blockIdx.x) * ns + k] = t;
 }
-
 // Scalars after the preconditioner step (one thread per slot).  init: start values from
 // gamma_1^2 / rho_0 in sums; else the MINRES rotation (sumsA: delta, sumsB: gamma_{j+1}^2)
 // and the CG beta.
@@ -228,99 +254,118 @@ __global__ void coef_kernel(double* __restrict__ st, const double* __restrict__ 
 }
 
 // w_{j+1} = (z_j / gamma_j - a3 w_{j-1} - a2 w_j) / a1 over w_{j-1}; x += c eta w_{j+1}
-__global__ __launch_bounds__(kThr) void minres_update_kernel(long long len, CVec9 z, CVec9 w, Vec9 wp, Vec9 x,
-                                                             const double* __restrict__ st) {
+template <typename T>
+__global__ __launch_bounds__(kThr) void minres_update_kernel(long long len, CVec9<T> z, CVec9<T> w, Vec9<T> wp,
+                                                             Vec9<T> x, const double* __restrict__ st) {
     const int q = blockIdx.y;
     const double* s = st + q * kSt;
     if (s[SKIP] != 0.0) return;
     const double gi = s[GINV], a1 = s[A1], a2 = s[A2], a3 = s[A3], xc = s[XC];
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < len;
          i += static_cast<long long>(gridDim.x) * kThr) {
-        const double wn = (z.p[q][i] * gi - a3 * wp.p[q][i] - a2 * w.p[q][i]) / a1;
-        wp.p[q][i] = wn;
-        x.p[q][i] += xc * wn;
+        const double wn = (static_cast<double>(z.p[q][i]) * gi - a3 * static_cast<double>(wp.p[q][i]) -
+                           a2 * static_cast<double>(w.p[q][i])) / a1;
+        wp.p[q][i] = static_cast<T>(wn);
+        x.p[q][i] = static_cast<T>(static_cast<double>(x.p[q][i]) + xc * wn);
     }
 }
 
 // CG: p = z + beta p (init: p = z)
-__global__ __launch_bounds__(kThr) void cg_update2_kernel(long long n, CVec9 z, Vec9 p, const double* __restrict__ st,
-                                                          int nc, int init) {
+template <typename T>
+__global__ __launch_bounds__(kThr) void cg_update2_kernel(long long n, CVec9<T> z, Vec9<T> p,
+                                                          const double* __restrict__ st, int nc, int init) {
     const int r = blockIdx.y;
     const double* s = st + (nc + r) * kSt;
     if (!init && s[RDONE] != 0.0 && s[BETA] == 0.0) return;
     const double b = init ? 0.0 : s[BETA];
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * kThr)
-        p.p[r][i] = init ? z.p[r][i] : z.p[r][i] + b * p.p[r][i];
+        p.p[r][i] = init ? z.p[r][i]
+                         : static_cast<T>(static_cast<double>(z.p[r][i]) + b * static_cast<double>(p.p[r][i]));
 }
 
 // Start vectors: complex slots f from the interleaved right-hand side, zero v_prev, w, w_prev
 // and x; real slots r = b, x = 0.  blockIdx.y = slot (complex first).
+template <typename T>
 struct InitArgs {
-    CVec9 bc, br;
-    Vec9 v, vp, w, wp, xc, r, xr;
+    CVec9<T> bc, br;
+    Vec9<T> v, vp, w, wp, xc, r, xr;
 };
-__global__ __launch_bounds__(kThr) void init_kernel(long long n, InitArgs a, SpProblem P) {
+template <typename T>
+__global__ __launch_bounds__(kThr) void init_kernel(long long n, InitArgs<T> a, SpProblem P) {
     const int q = blockIdx.y;
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * kThr) {
         if (q < P.nc) {
-            const double br = a.bc.p[q][2 * i], bi = a.bc.p[q][2 * i + 1];
+            const T br = a.bc.p[q][2 * i], bi = a.bc.p[q][2 * i + 1];
             a.v.p[q][i] = P.im_pos[q] ? -bi : bi;
             a.v.p[q][n + i] = br;
-            a.vp.p[q][i] = a.vp.p[q][n + i] = 0.0;
-            a.w.p[q][i] = a.w.p[q][n + i] = 0.0;
-            a.wp.p[q][i] = a.wp.p[q][n + i] = 0.0;
-            a.xc.p[q][i] = a.xc.p[q][n + i] = 0.0;
+            a.vp.p[q][i] = a.vp.p[q][n + i] = T(0);
+            a.w.p[q][i] = a.w.p[q][n + i] = T(0);
+            a.wp.p[q][i] = a.wp.p[q][n + i] = T(0);
+            a.xc.p[q][i] = a.xc.p[q][n + i] = T(0);
         } else {
             const int r = q - P.nc;
             a.r.p[r][i] = a.br.p[r][i];
-            a.xr.p[r][i] = 0.0;
+            a.xr.p[r][i] = T(0);
         }
     }
 }
 
 // Solutions back to the spectral slots: x = u1 -+ i u2 (complex), x (real)
-__global__ __launch_bounds__(kThr) void final_kernel(long long n, CVec9 xc, CVec9 xr, SpProblem P) {
+template <typename T>
+__global__ __launch_bounds__(kThr) void final_kernel(long long n, CVec9<T> xc, CVec9<T> xr, SpProblem P) {
     const int q = blockIdx.y;
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * kThr) {
         if (q < P.nc) {
-            const double u1 = xc.p[q][i], u2 = xc.p[q][n + i];
-            P.yc[q][2 * i] = u1;
-            P.yc[q][2 * i + 1] = P.im_pos[q] ? -u2 : u2;
+            const T u1 = xc.p[q][i], u2 = xc.p[q][n + i];
+            T* y = static_cast<T*>(P.yc[q]);
+            y[2 * i] = u1;
+            y[2 * i + 1] = P.im_pos[q] ? -u2 : u2;
         } else {
             const int r = q - P.nc;
-            P.yr[r][i] = xr.p[r][i];
+            static_cast<T*>(P.yr[r])[i] = xr.p[r][i];
         }
     }
 }
 
-size_t al(size_t d) { return (d + 31) / 32 * 32; }
+size_t al(size_t d) { return (d + 63) / 64 * 64; }  // elements: 256-byte multiples for either type
 
-}  // namespace
-
-size_t sp_ws_doubles(const MgHierarchy& h, long long n, int nc, int nr) {
+template <typename T>
+size_t ws_bytes_t(const MgHierarchy& h, long long n, int nc, int nr) {
     const int ns = nc + nr;
-    size_t d = 0;
-    d += static_cast<size_t>(nc) * 8 * al(2 * n);  // z_a, z_b, Sz, v_prev, v, w_prev, w, x
-    d += static_cast<size_t>(nr) * 5 * al(n);      // x, r, z, p, q
-    d += al(mg_scratch_doubles(h, 2 * nc + nr));
-    d += 2 * al(static_cast<size_t>(kBlk) * ns) + 2 * al(ns) + al(static_cast<size_t>(kSt) * ns);
-    return d;
+    size_t e = 0;
+    e += static_cast<size_t>(nc) * 8 * al(2 * n);  // z_a, z_b, Sz, v_prev, v, w_prev, w, x
+    e += static_cast<size_t>(nr) * 5 * al(n);      // x, r, z, p, q
+    e += al(mg_scratch_elems(h, 2 * nc + nr));
+    const size_t d = 2 * al(static_cast<size_t>(kBlk) * ns) + 2 * al(ns) + al(static_cast<size_t>(kSt) * ns);
+    return e * sizeof(T) + d * sizeof(double);
 }
 
-hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s) {
+template <typename T>
+hipError_t solve_t(const SpProblem& P, int iters, char* ws, hipStream_t s) {
     const int nc = P.nc, nr = P.nr, ns = nc + nr;
     const long long n = P.n;
     if (ns < 1 || ns > kMaxShift || 2 * nc + nr > kMgMaxVec) return hipErrorInvalidValue;
-    double* p = ws;
+    double* dp = reinterpret_cast<double*>(ws);
+    double* partA = dp;
+    dp += al(static_cast<size_t>(kBlk) * ns);
+    double* partB = dp;
+    dp += al(static_cast<size_t>(kBlk) * ns);
+    double* sumsA = dp;
+    dp += al(ns);
+    double* sumsB = dp;
+    dp += al(ns);
+    double* st = dp;
+    dp += al(static_cast<size_t>(kSt) * ns);
+    T* p = reinterpret_cast<T*>(dp);
     auto take = [&](size_t d) {
-        double* r = p;
+        T* r = p;
         p += al(d);
         return r;
     };
-    double *za[kMaxShift], *zb[kMaxShift], *szb[kMaxShift], *vpb[kMaxShift], *vb[kMaxShift], *wpb[kMaxShift],
+    T *za[kMaxShift], *zb[kMaxShift], *szb[kMaxShift], *vpb[kMaxShift], *vb[kMaxShift], *wpb[kMaxShift],
         *wb[kMaxShift], *xcb[kMaxShift];
     for (int q = 0; q < nc; ++q) {
         za[q] = take(2 * n);
@@ -332,7 +377,7 @@ hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s) {
         wb[q] = take(2 * n);
         xcb[q] = take(2 * n);
     }
-    double *xr[kMaxShift], *rr[kMaxShift], *zr[kMaxShift], *pr[kMaxShift], *qr[kMaxShift];
+    T *xr[kMaxShift], *rr[kMaxShift], *zr[kMaxShift], *pr[kMaxShift], *qr[kMaxShift];
     for (int r = 0; r < nr; ++r) {
         xr[r] = take(n);
         rr[r] = take(n);
@@ -340,29 +385,24 @@ hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s) {
         pr[r] = take(n);
         qr[r] = take(n);
     }
-    double* mgs = take(mg_scratch_doubles(*P.h, 2 * nc + nr));
-    double* partA = take(static_cast<size_t>(kBlk) * ns);
-    double* partB = take(static_cast<size_t>(kBlk) * ns);
-    double* sumsA = take(ns);
-    double* sumsB = take(ns);
-    double* st = take(static_cast<size_t>(kSt) * ns);
+    T* mgs = take(mg_scratch_elems(*P.h, 2 * nc + nr));
     const MgLevel& L0 = P.h->lev[0];
     const int nb = static_cast<int>(std::min<long long>(kBlk, (2 * n + kThr - 1) / kThr));
 
-    auto cv = [&](double* const* a, int cnt) {
-        CVec9 v{};
+    auto cv = [&](T* const* a, int cnt) {
+        CVec9<T> v{};
         for (int i = 0; i < cnt; ++i) v.p[i] = a[i];
         return v;
     };
-    auto mv = [&](double* const* a, int cnt) {
-        Vec9 v{};
+    auto mv = [&](T* const* a, int cnt) {
+        Vec9<T> v{};
         for (int i = 0; i < cnt; ++i) v.p[i] = a[i];
         return v;
     };
     // V-cycles: complex halves of src_c (2 each, shift rho - sigma) then real src_r
-    auto vcycle = [&](double* const* src_c, double* const* dst_c, double* const* src_r, double* const* dst_r) {
-        const double* b[kMgMaxVec];
-        double* u[kMgMaxVec];
+    auto vcycle = [&](T* const* src_c, T* const* dst_c, T* const* src_r, T* const* dst_r) {
+        const T* b[kMgMaxVec];
+        T* u[kMgMaxVec];
         double c[kMgMaxVec];
         int k = 0;
         for (int q = 0; q < nc; ++q)
@@ -379,8 +419,8 @@ hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s) {
         return mg_vcycle(*P.h, k, b, u, c, mgs, s);
     };
     // dots: complex v . z (2n), real r . z (n) -> sumsB
-    auto dots = [&](double* const* vc, double* const* zc) -> hipError_t {
-        DotArgs d{};
+    auto dots = [&](T* const* vc, T* const* zc) -> hipError_t {
+        DotArgs<T> d{};
         for (int q = 0; q < nc; ++q) {
             d.a[q] = vc[q];
             d.b[q] = zc[q];
@@ -391,15 +431,15 @@ hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s) {
             d.b[nc + r] = zr[r];
             d.len[nc + r] = n;
         }
-        hipLaunchKernelGGL(dot_kernel, dim3(nb, ns), dim3(kThr), 0, s, d, partB, ns);
+        hipLaunchKernelGGL(dot_kernel<T>, dim3(nb, ns), dim3(kThr), 0, s, d, partB, ns);
         return launch_reduce(partB, nb, ns, ns, sumsB, s);
     };
 
     // start: v_1 = f, z_1 = M^{-1} v_1, gamma_1; r_0 = b, z_0, p_0 = z_0, rho_0
     {
-        InitArgs a{};
+        InitArgs<T> a{};
         for (int q = 0; q < nc; ++q) {
-            a.bc.p[q] = P.bc[q];
+            a.bc.p[q] = static_cast<const T*>(P.bc[q]);
             a.v.p[q] = vb[q];
             a.vp.p[q] = vpb[q];
             a.w.p[q] = wb[q];
@@ -407,47 +447,66 @@ hipError_t sp_solve(const SpProblem& P, int iters, double* ws, hipStream_t s) {
             a.xc.p[q] = xcb[q];
         }
         for (int r = 0; r < nr; ++r) {
-            a.br.p[r] = P.br[r];
+            a.br.p[r] = static_cast<const T*>(P.br[r]);
             a.r.p[r] = rr[r];
             a.xr.p[r] = xr[r];
         }
-        hipLaunchKernelGGL(init_kernel, dim3(nb, ns), dim3(kThr), 0, s, n, a, P);
+        hipLaunchKernelGGL(init_kernel<T>, dim3(nb, ns), dim3(kThr), 0, s, n, a, P);
     }
     hipError_t e = vcycle(vb, za, rr, zr);
     if (e != hipSuccess) return e;
     if ((e = dots(vb, za)) != hipSuccess) return e;
     hipLaunchKernelGGL(coef_kernel, dim3(1), dim3(64), 0, s, st, sumsA, sumsB, nc, nr, 1);
-    if (nr) hipLaunchKernelGGL(cg_update2_kernel, dim3(nb, nr), dim3(kThr), 0, s, n, cv(zr, nr), mv(pr, nr), st, nc, 1);
+    if (nr)
+        hipLaunchKernelGGL(cg_update2_kernel<T>, dim3(nb, nr), dim3(kThr), 0, s, n, cv(zr, nr), mv(pr, nr), st, nc, 1);
 
-    double** z = za;
-    double** zn = zb;
-    double** v = vb;
-    double** vp = vpb;
-    double** w = wb;
-    double** wp = wpb;
+    T** z = za;
+    T** zn = zb;
+    T** v = vb;
+    T** vp = vpb;
+    T** w = wb;
+    T** wp = wpb;
     for (int it = 0; it < iters; ++it) {
-        if (nc) hipLaunchKernelGGL(saddle_apply_kernel, dim3(nb, nc), dim3(kThr), 0, s, L0, n, cv(z, nc), mv(szb, nc), st, P,
-                                   partA, ns);
-        if (nr) hipLaunchKernelGGL(cg_apply_kernel, dim3(nb, nr), dim3(kThr), 0, s, L0, n, cv(pr, nr), mv(qr, nr), P, partA,
-                                   ns);
+        if (nc)
+            hipLaunchKernelGGL(saddle_apply_kernel<T>, dim3(nb, nc), dim3(kThr), 0, s, L0, n, cv(z, nc), mv(szb, nc),
+                               st, P, partA, ns);
+        if (nr)
+            hipLaunchKernelGGL(cg_apply_kernel<T>, dim3(nb, nr), dim3(kThr), 0, s, L0, n, cv(pr, nr), mv(qr, nr), P,
+                               partA, ns);
         if ((e = launch_reduce(partA, nb, ns, ns, sumsA, s)) != hipSuccess) return e;
-        if (nc) hipLaunchKernelGGL(lanczos_kernel, dim3(nb, nc), dim3(kThr), 0, s, 2 * n, cv(szb, nc), cv(v, nc), mv(vp, nc),
-                                   st, sumsA);
-        if (nr) hipLaunchKernelGGL(cg_update1_kernel, dim3(nb, nr), dim3(kThr), 0, s, n, cv(pr, nr), cv(qr, nr), mv(xr, nr),
-                                   mv(rr, nr), st, sumsA, nc);
+        if (nc)
+            hipLaunchKernelGGL(lanczos_kernel<T>, dim3(nb, nc), dim3(kThr), 0, s, 2 * n, cv(szb, nc), cv(v, nc),
+                               mv(vp, nc), st, sumsA);
+        if (nr)
+            hipLaunchKernelGGL(cg_update1_kernel<T>, dim3(nb, nr), dim3(kThr), 0, s, n, cv(pr, nr), cv(qr, nr),
+                               mv(xr, nr), mv(rr, nr), st, sumsA, nc);
         // vp now holds v_{j+1}
         if ((e = vcycle(vp, zn, rr, zr)) != hipSuccess) return e;
         if ((e = dots(vp, zn)) != hipSuccess) return e;
         hipLaunchKernelGGL(coef_kernel, dim3(1), dim3(64), 0, s, st, sumsA, sumsB, nc, nr, 0);
-        if (nc) hipLaunchKernelGGL(minres_update_kernel, dim3(nb, nc), dim3(kThr), 0, s, 2 * n, cv(z, nc), cv(w, nc), mv(wp, nc),
-                                   mv(xcb, nc), st);
-        if (nr) hipLaunchKernelGGL(cg_update2_kernel, dim3(nb, nr), dim3(kThr), 0, s, n, cv(zr, nr), mv(pr, nr), st, nc, 0);
-        std::swap(v, vp);   // v_prev <- v, v <- v_{j+1}
-        std::swap(w, wp);   // w_prev <- w, w <- w_{j+1}
+        if (nc)
+            hipLaunchKernelGGL(minres_update_kernel<T>, dim3(nb, nc), dim3(kThr), 0, s, 2 * n, cv(z, nc), cv(w, nc),
+                               mv(wp, nc), mv(xcb, nc), st);
+        if (nr)
+            hipLaunchKernelGGL(cg_update2_kernel<T>, dim3(nb, nr), dim3(kThr), 0, s, n, cv(zr, nr), mv(pr, nr), st, nc,
+                               0);
+        std::swap(v, vp);  // v_prev <- v, v <- v_{j+1}
+        std::swap(w, wp);  // w_prev <- w, w <- w_{j+1}
         std::swap(z, zn);
     }
-    hipLaunchKernelGGL(final_kernel, dim3(nb, ns), dim3(kThr), 0, s, n, cv(xcb, nc), cv(xr, nr), P);
+    hipLaunchKernelGGL(final_kernel<T>, dim3(nb, ns), dim3(kThr), 0, s, n, cv(xcb, nc), cv(xr, nr), P);
     return hipGetLastError();
+}
+
+}  // namespace
+
+size_t sp_ws_bytes(const MgHierarchy& h, long long n, int nc, int nr, bool f32) {
+    return f32 ? ws_bytes_t<float>(h, n, nc, nr) : ws_bytes_t<double>(h, n, nc, nr);
+}
+
+hipError_t sp_solve(const SpProblem& P, int iters, bool f32, void* ws, hipStream_t s) {
+    char* w = static_cast<char*>(ws);
+    return f32 ? solve_t<float>(P, iters, w, s) : solve_t<double>(P, iters, w, s);
 }
 
 }  // namespace ac

@@ -167,7 +167,7 @@ def test_sp_rejects():
     assert e.value.status == L.AC_ERR_ARG
     api.ac_problem_create_multigrid(p)
     with pytest.raises(L.AlphacircError) as e:
-        api.ac_apply_prec(p, api.Opts(precision=L.AC_PREC_MIXED_FP32K, inner=L.AC_INNER_SP, p=3), r, z, ws)
+        api.ac_apply_prec(p, api.Opts(precision=L.AC_PREC_MIXED_BF16K, inner=L.AC_INNER_SP, p=3), r, z, ws)
     assert e.value.status == L.AC_ERR_UNSUPPORTED
     with pytest.raises(L.AlphacircError) as e:
         api.ac_apply_prec(p, api.Opts(inner=L.AC_INNER_SP, p=[3, 4, 3, 4]), r, z, ws)
@@ -215,3 +215,49 @@ def test_sp_dimension_independent_counts_paper_table():
     for alpha in (1.0, 0.01):
         counts = [v for (a, _), v in got.items() if a == alpha]
         assert max(counts) - min(counts) <= 1, counts
+
+
+@pytest.mark.parametrize("dim,nx,ny,ell,alpha,iters", [
+    (2, 16, 12, 4, 0.3, 3),
+    (2, 24, 20, 10, 0.01, 8),
+    (1, 40, 1, 8, 0.05, 6),
+    (2, 64, 48, 6, 1.0, 5),
+])
+def test_sp_prec_float32_matches_oracle(dim, nx, ny, ell, alpha, iters):
+    """float32 vectors and multigrid coefficients against the float64 oracle."""
+    n = nx * ny
+    kap = lognormal_kappa(nx, max(ny, 1), 10.0, 3.0, 0.8, seed=ell)[:n]
+    A = ops.build_A(dim, nx, ny, kap)
+    levels = mg.hierarchy(dim, nx, ny, kap)
+    r = random_block_vector(n, ell, seed=iters)
+    ref = sd.apply_prec_sp(A, r, ell, alpha, iters, levels)
+    p = _problem(dim, nx, ny, kap, ell, alpha)
+    opts = api.Opts(precision=L.AC_PREC_MIXED_FP32K, inner=L.AC_INNER_SP, p=iters)
+    z = torch.empty(ell * n, dtype=torch.float64, device="cuda:0")
+    api.ac_apply_prec(p, opts, G.dev(r), z, api.workspace(api.ac_prec_workspace_size(p, opts)))
+    err = G.rel(G.host(z), ref)
+    print(f"P_SP float32 vs float64 oracle ({dim}, {nx}x{ny}, l={ell}, alpha={alpha}, {iters} steps): {err:.3e}",
+          flush=True)
+    # float32 rounding (2^-24) per step of the inner solve, amplified by the inverse time
+    # transform's alpha^{-(l-1)/l} (measured: 1e-7 .. 8e-7)
+    assert err < 2.0 ** -24 * 4 * iters * max(1.0, alpha ** (-(ell - 1) / ell)) * 16, err
+
+
+def test_sp_fgmres_float32_inner():
+    """FGMRES stays float64, so float32 inner solves still reach 1e-8, in about the float64
+    iteration count."""
+    nx, ell, iters, alpha = 64, 10, 6, 1e-2
+    kap = lognormal_kappa(nx, nx, 50.0, 10.0, 1.0, seed=5)
+    A = ops.build_A(2, nx, nx, kap)
+    b = first_block_rhs(nx * nx, ell, seed=1)
+    p = _problem(2, nx, nx, kap, ell, alpha)
+    its = {}
+    for prec in (L.AC_PREC_FP64, L.AC_PREC_MIXED_FP32K):
+        opts = api.Opts(precision=prec, inner=L.AC_INNER_SP, p=iters, tol=1e-8, restart_m=8, max_outer=200)
+        x = G.dev(np.zeros_like(b))
+        info = api.ac_solve(p, opts, G.dev(b), x, api.workspace(api.ac_solve_workspace_size(p, opts)))
+        assert info["converged"] and info["rel_residual_true"] < 1e-8
+        assert G.rel(G.host(x), ops.sequential_solve(A, b, ell)) < 1e-6
+        its[prec] = info["outer_iters"]
+    print(f"P_SP FGMRES iterations float64 {its[L.AC_PREC_FP64]}, float32 {its[L.AC_PREC_MIXED_FP32K]}", flush=True)
+    assert its[L.AC_PREC_MIXED_FP32K] <= its[L.AC_PREC_FP64] + 2
