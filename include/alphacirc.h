@@ -181,6 +181,11 @@ const char* ac_last_error(void);
 int ac_ctx_create(int device, void* hip_stream, ac_ctx** out);
 int ac_ctx_destroy(ac_ctx* ctx);
 int ac_ctx_set_stream(ac_ctx* ctx, void* hip_stream);
+/* Graph replay of launch-bound inner solves (default on): the AC_INNER_SP inner solve
+ * (hundreds of small launches per application) is captured once per problem, workspace,
+ * step count and precision on a stream the context owns and replayed as one hipGraph on
+ * the context stream; off runs the same kernels directly.  Results are identical. */
+int ac_ctx_set_graphs(ac_ctx* ctx, int on);
 /* Profiling: when on, every launch of the classes above is bracketed by HIP events
  * on the context stream and its algorithmic bytes are accumulated. */
 int ac_ctx_set_profiling(ac_ctx* ctx, int on);

@@ -104,6 +104,7 @@ SIGNATURES = {
     "ac_problem_create_blocks": (_I, [_VP, C.POINTER(ac_grid), _VP, _I, _D, C.POINTER(ac_bounds), C.POINTER(_VP)]),
     "ac_problem_destroy": (_I, [_VP]),
     "ac_problem_create_multigrid": (_I, [_VP]),
+    "ac_ctx_set_graphs": (_I, [_VP, _I]),
     "ac_mg_workspace_size": (_I, [_VP, _I, C.POINTER(_SZ)]),
     "ac_mg_vcycle": (_I, [_VP, _I, C.POINTER(_D), _VP, _VP, _VP, _SZ]),
     "ac_spectral_bounds": (_I, [_VP, C.POINTER(_D), C.POINTER(_D)]),

@@ -464,6 +464,10 @@ def ac_cnn_make_inputs(p: Problem, cnn: Cnn, precision: int, rhat: torch.Tensor,
     return sc
 
 
+def ac_ctx_set_graphs(ctx: Ctx, on: bool) -> None:
+    check(L.load().ac_ctx_set_graphs(ctx.h, 1 if on else 0), "ac_ctx_set_graphs")
+
+
 def ac_problem_create_multigrid(p: Problem) -> None:
     """Build the multigrid hierarchy of A used by AC_INNER_SP (owned by the problem)."""
     check(L.load().ac_problem_create_multigrid(p.h), "ac_problem_create_multigrid")

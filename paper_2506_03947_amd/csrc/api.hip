@@ -95,6 +95,9 @@ struct ac_ctx {
     int shift_groups = -1;
     // dense sine transforms of the exact inner solve (workspace set per call)
     rocblas_handle blas = nullptr;
+    // launch-bound inner solves (P_SP) are captured on this stream and replayed as graphs
+    hipStream_t cap = nullptr;
+    bool graphs = true;
 };
 
 constexpr int kResidBlocks = 512;  // blocks of the warm-start residual-statistics kernel
@@ -121,6 +124,12 @@ struct ac_problem {
     // multigrid hierarchy of A (AC_INNER_SP), built by ac_problem_create_multigrid
     ac::MgHierarchy mg{};
     double* mgmem = nullptr;
+    // captured P_SP inner solve, valid for this workspace, step count and precision
+    struct SpGraph {
+        hipGraphExec_t exec = nullptr;
+        const void* ws = nullptr;
+        int iters = 0, prec = -1;
+    } spg;
 };
 
 struct ac_cnn {
@@ -962,7 +971,36 @@ int sp_inner(ac_problem* p, int prec, int iters, const PrecBufs& b, double* z) {
     const double ne = static_cast<double>(inner_elem(prec)) * p->g.n;
     const double bytes = iters * ne * (p->nsc * 2.0 * 12.0 + p->nsr * 10.0);
     ProfScope ps(p->ctx, AC_K_SADDLE, bytes);
-    AC_HIP(ac::sp_solve(P, iters, prec != AC_PREC_FP64, ws, p->ctx->stream));
+    ac_ctx* c = p->ctx;
+    if (!c->graphs) {
+        AC_HIP(ac::sp_solve(P, iters, prec != AC_PREC_FP64, ws, c->stream));
+    } else {
+        // Every argument of the inner solve is fixed by the problem, the workspace, the
+        // step count and the precision, so one capture serves every later application.
+        ac_problem::SpGraph& gr = p->spg;
+        if (!(gr.exec && gr.ws == ws && gr.iters == iters && gr.prec == prec)) {
+            if (gr.exec) (void)hipGraphExecDestroy(gr.exec);
+            gr = ac_problem::SpGraph{};
+            AC_HIP(hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal));
+            const hipError_t le = ac::sp_solve(P, iters, prec != AC_PREC_FP64, ws, c->cap);
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(c->cap, &graph);
+            if (le != hipSuccess || ee != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(AC_ERR_HIP, std::string("P_SP graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ee));
+            }
+            const hipError_t ie = hipGraphInstantiate(&gr.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) {
+                gr.exec = nullptr;
+                return fail(AC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+            }
+            gr.ws = ws;
+            gr.iters = iters;
+            gr.prec = prec;
+        }
+        AC_HIP(hipGraphLaunch(gr.exec, c->stream));
+    }
     AC_HIP(ac::launch_tdft_inv(p->ell, prec, inv_args(p, prec, b.buf[0], z), p->ctx->stream));
     return AC_OK;
 }
@@ -1054,6 +1092,13 @@ int ac_ctx_create(int device, void* stream, ac_ctx** out) {
         delete c;
         return fail(AC_ERR_HIP, std::string("rocblas_create_handle: ") + rocblas_status_to_string(bs));
     }
+    e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        (void)rocblas_destroy_handle(c->blas);
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return fail(AC_ERR_HIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+    }
     *out = c;
     return AC_OK;
 }
@@ -1071,8 +1116,15 @@ int ac_ctx_destroy(ac_ctx* c) {
         (void)hipEventDestroy(p.second);
     }
     if (c->blas) (void)rocblas_destroy_handle(c->blas);
+    if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;
+    return AC_OK;
+}
+
+int ac_ctx_set_graphs(ac_ctx* c, int on) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    c->graphs = on != 0;
     return AC_OK;
 }
 
@@ -1275,6 +1327,7 @@ int ac_problem_destroy(ac_problem* p) {
     (void)hipFree(p->rpart);
     if (p->kblocks) (void)hipFree(p->kblocks);
     if (p->mgmem) (void)hipFree(p->mgmem);
+    if (p->spg.exec) (void)hipGraphExecDestroy(p->spg.exec);
     delete p;
     return AC_OK;
 }

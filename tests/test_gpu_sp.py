@@ -261,3 +261,44 @@ def test_sp_fgmres_float32_inner():
         its[prec] = info["outer_iters"]
     print(f"P_SP FGMRES iterations float64 {its[L.AC_PREC_FP64]}, float32 {its[L.AC_PREC_MIXED_FP32K]}", flush=True)
     assert its[L.AC_PREC_MIXED_FP32K] <= its[L.AC_PREC_FP64] + 2
+
+
+@pytest.mark.parametrize("precision", [L.AC_PREC_FP64, L.AC_PREC_MIXED_FP32K])
+def test_sp_graph_replay_matches_eager(precision):
+    """The captured inner solve, replayed several times with other eager work and
+    synchronisations in between, gives exactly the directly launched result; a full
+    FGMRES solve too."""
+    nx, ny, ell, alpha, iters = 64, 48, 6, 1e-2, 5
+    n = nx * ny
+    kap = lognormal_kappa(nx, ny, 20.0, 4.0, 1.0, seed=11)
+    p = _problem(2, nx, ny, kap, ell, alpha)
+    ctx = G.ctx()
+    opts = api.Opts(precision=precision, inner=L.AC_INNER_SP, p=iters)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    r = G.dev(random_block_vector(n, ell, seed=3))
+    try:
+        api.ac_ctx_set_graphs(ctx, False)
+        z_ref = torch.empty_like(r)
+        api.ac_apply_prec(p, opts, r, z_ref, ws)
+        torch.cuda.synchronize()
+        z_ref = z_ref.clone()
+        api.ac_ctx_set_graphs(ctx, True)
+        y = torch.empty_like(r)
+        for rep in range(3):
+            z = torch.full_like(r, float("nan"))
+            api.ac_apply_prec(p, opts, r, z, ws)
+            api.ac_apply_A(p, z, y)  # eager work between replays
+            torch.cuda.synchronize()
+            assert torch.equal(z, z_ref), rep
+        b = G.dev(first_block_rhs(n, ell, seed=2))
+        sopts = api.Opts(precision=precision, inner=L.AC_INNER_SP, p=iters, tol=1e-8, restart_m=8, max_outer=100)
+        sws = api.workspace(api.ac_solve_workspace_size(p, sopts))
+        res = {}
+        for on in (False, True):
+            api.ac_ctx_set_graphs(ctx, on)
+            x = torch.zeros_like(b)
+            info = api.ac_solve(p, sopts, b, x, sws)
+            res[on] = (info["outer_iters"], x.clone())
+        assert res[True][0] == res[False][0] and torch.equal(res[True][1], res[False][1])
+    finally:
+        api.ac_ctx_set_graphs(ctx, True)
