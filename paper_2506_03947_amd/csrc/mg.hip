@@ -12,7 +12,8 @@
 // 2J, 2J+1, 2J+2 with weights 1/4, 1/2, 1/4.  Linear interpolation P, full weighting
 // R = P^T / 2^d.  Cycle: two damped-Jacobi sweeps (omega = 0.8) from zero, coarse
 // correction, two sweeps; the last level (at most 4 points) is solved exactly.  The
-// cycle is a symmetric positive definite operator, as MINRES and CG need.
+// cycle is a symmetric positive definite operator, as MINRES and CG need.  The levels of
+// at most 4096 points run as one kernel (one workgroup per vector).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -358,21 +359,102 @@ __global__ void restrict_kernel(const MgLevel F, const MgLevel C, const MgVecsT<
     v.out[q][i] = acc / static_cast<T>(1 << (C.cx + C.cy));
 }
 
-// Exact solve on a level of at most 4 points: one thread per vector, Gaussian
-// elimination in float64 (A - c I is symmetric positive definite).
+// ---- the coarse tail of the cycle in one kernel ------------------------------------
+// Levels of at most kTailN points cost a few microseconds per launch whatever their
+// size, so the part of the cycle from the first such level down to the coarsest and back
+// up runs in one kernel: one workgroup per vector, each phase a strided loop over the
+// level's points followed by a workgroup barrier (which orders the phases' global
+// writes and reads).  Same arithmetic as the per-level kernels.
+constexpr long long kTailN = 4096;
+constexpr int kTailMax = 13;  // levels from 4096 points down to at most 4 (1D: 11)
+constexpr int kTailThreads = 256;
+
 template <typename T>
-__global__ void coarsest_kernel(const MgLevel L, const MgVecsT<T> v, int nv) {
-    const int q = blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nv) return;
+struct TailArgs {
+    int lt, nl;                  // first tail level, number of tail levels
+    MgLevel lev[kTailMax + 1];   // lev[0]: the level above the tail (unused when lt == 0)
+    const T* b0[kMgMaxVec];      // right-hand sides of the first tail level
+    T* r0[kMgMaxVec];            // its results
+    T* u0[kMgMaxVec];            // its work vectors
+    T* base[kTailMax];           // levels below the first: B | U | R blocks of nv vectors
+    double c[kMgMaxVec];
+    int nv;
+};
+
+template <typename T>
+__device__ void tail_sweep2(const MgLevel& L, const T* __restrict__ b, T* __restrict__ o, T c) {
+    const T om = static_cast<T>(kOmega);
+    const T* dgp = diag_of<T>(L);
+    for (long long i = threadIdx.x; i < L.n; i += blockDim.x) {
+        const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
+        const Co<T> k = coef_at<T>(L, i, x, y);
+        const St<T> dg = stencil(k, dgp, i, L.nx);
+        const St<T> bb = stencil(k, b, i, L.nx);
+        St<T> u;
+        u.c = om * bb.c / (dg.c - c);
+        u.e = k.he ? om * bb.e / (dg.e - c) : T(0);
+        u.w = k.hw ? om * bb.w / (dg.w - c) : T(0);
+        u.n = k.hn ? om * bb.n / (dg.n - c) : T(0);
+        u.s = k.hs ? om * bb.s / (dg.s - c) : T(0);
+        o[i] = u.c + om * (bb.c - apply_st(k, u, c)) / (k.d - c);
+    }
+}
+template <typename T, bool SWEEP>
+__device__ void tail_sweep(const MgLevel& L, const T* __restrict__ u, const T* __restrict__ b, T* __restrict__ o,
+                           T c) {
+    const T om = static_cast<T>(kOmega);
+    for (long long i = threadIdx.x; i < L.n; i += blockDim.x) {
+        const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
+        const Co<T> k = coef_at<T>(L, i, x, y);
+        const St<T> uu = stencil(k, u, i, L.nx);
+        const T r = b[i] - apply_st(k, uu, c);
+        o[i] = SWEEP ? uu.c + om * r / (k.d - c) : r;
+    }
+}
+template <typename T>
+__device__ void tail_restrict(const MgLevel& F, const MgLevel& C, const T* __restrict__ in, T* __restrict__ o) {
+    const T wd[3] = {T(0.5), T(1), T(0.5)};
+    for (long long i = threadIdx.x; i < C.n; i += blockDim.x) {
+        const int ii = static_cast<int>(i), X = ii % C.nx, Y = ii / C.nx;
+        T acc = T(0);
+        for (int dy = 0; dy < (C.cy ? 3 : 1); ++dy) {
+            const int y = C.cy ? 2 * Y + dy : Y;
+            if (y >= F.ny) continue;
+            const T wy = C.cy ? wd[dy] : T(1);
+            for (int dx = 0; dx < (C.cx ? 3 : 1); ++dx) {
+                const int x = C.cx ? 2 * X + dx : X;
+                if (x >= F.nx) continue;
+                const T wx = C.cx ? wd[dx] : T(1);
+                acc += wy * wx * in[static_cast<long long>(y) * F.nx + x];
+            }
+        }
+        o[i] = acc / static_cast<T>(1 << (C.cx + C.cy));
+    }
+}
+template <typename T>
+__device__ void tail_prolong_add(const MgLevel& F, const MgLevel& C, const T* __restrict__ e, T* __restrict__ o) {
+    for (long long i = threadIdx.x; i < F.n; i += blockDim.x) {
+        const int ii = static_cast<int>(i), x = ii % F.nx, y = ii / F.nx;
+        const Interp ix = interp(x, C.nx, C.cx), iy = interp(y, C.ny, C.cy);
+        const T* r0 = e + iy.j0 * C.nx;
+        const T* r1 = e + iy.j1 * C.nx;
+        const T wx0 = static_cast<T>(ix.w0), wx1 = static_cast<T>(ix.w1);
+        o[i] += static_cast<T>(iy.w0) * (wx0 * r0[ix.j0] + wx1 * r0[ix.j1]) +
+                static_cast<T>(iy.w1) * (wx0 * r1[ix.j0] + wx1 * r1[ix.j1]);
+    }
+}
+template <typename T>
+__device__ void tail_coarsest(const MgLevel& L, const T* __restrict__ b, T* __restrict__ o, double c) {
+    if (threadIdx.x != 0) return;
     const int n = static_cast<int>(L.n);
     double M[4][4], r[4];
     for (int a = 0; a < n; ++a) {
-        for (int b = 0; b < n; ++b) M[a][b] = 0.0;
-        r[a] = static_cast<double>(v.b[q][a]);
+        for (int bb = 0; bb < n; ++bb) M[a][bb] = 0.0;
+        r[a] = static_cast<double>(b[a]);
     }
     for (int a = 0; a < n; ++a) {
         const int x = a % L.nx, y = a / L.nx;
-        M[a][a] = L.diag[a] - v.c[q];
+        M[a][a] = L.diag[a] - c;
         if (x < L.nx - 1) {
             M[a][a + 1] = -L.wx[a];
             M[a + 1][a] = -L.wx[a];
@@ -385,15 +467,50 @@ __global__ void coarsest_kernel(const MgLevel L, const MgVecsT<T> v, int nv) {
     for (int k = 0; k < n; ++k)
         for (int a = k + 1; a < n; ++a) {
             const double f = M[a][k] / M[k][k];
-            for (int b = k; b < n; ++b) M[a][b] -= f * M[k][b];
+            for (int bb = k; bb < n; ++bb) M[a][bb] -= f * M[k][bb];
             r[a] -= f * r[k];
         }
     for (int a = n - 1; a >= 0; --a) {
         double t = r[a];
-        for (int b = a + 1; b < n; ++b) t -= M[a][b] * r[b];
+        for (int bb = a + 1; bb < n; ++bb) t -= M[a][bb] * r[bb];
         r[a] = t / M[a][a];
     }
-    for (int a = 0; a < n; ++a) v.out[q][a] = static_cast<T>(r[a]);
+    for (int a = 0; a < n; ++a) o[a] = static_cast<T>(r[a]);
+}
+
+// One workgroup per vector q: the V-cycle from tail level 0 (= hierarchy level lt) down
+// and back up; the result lands in r0[q].
+template <typename T>
+__global__ __launch_bounds__(kTailThreads) void tail_kernel(const TailArgs<T> a) {
+    const int q = blockIdx.x;
+    const T c = static_cast<T>(a.c[q]);
+    const MgLevel* lv = a.lev + 1;  // lv[k] = hierarchy level lt + k
+    auto B = [&](int k) -> T* { return k == 0 ? const_cast<T*>(a.b0[q]) : a.base[k] + static_cast<long long>(q) * lv[k].n; };
+    auto U = [&](int k) -> T* {
+        return k == 0 ? a.u0[q] : a.base[k] + static_cast<long long>(a.nv + q) * lv[k].n;
+    };
+    auto R = [&](int k) -> T* {
+        return k == 0 ? a.r0[q] : a.base[k] + static_cast<long long>(2 * a.nv + q) * lv[k].n;
+    };
+    const int last = a.nl - 1;
+    for (int k = 0; k < last; ++k) {
+        tail_sweep2(lv[k], B(k), R(k), c);
+        __syncthreads();
+        tail_sweep<T, false>(lv[k], R(k), B(k), U(k), c);
+        __syncthreads();
+        tail_restrict(lv[k], lv[k + 1], U(k), B(k + 1));
+        __syncthreads();
+    }
+    tail_coarsest(lv[last], B(last), R(last), a.c[q]);
+    __syncthreads();
+    for (int k = last - 1; k >= 0; --k) {
+        tail_prolong_add(lv[k], lv[k + 1], R(k + 1), R(k));
+        __syncthreads();
+        tail_sweep<T, true>(lv[k], R(k), B(k), U(k), c);
+        __syncthreads();
+        tail_sweep<T, true>(lv[k], U(k), B(k), R(k), c);
+        __syncthreads();
+    }
 }
 
 // float32 copies of a level's diagonal and face arrays
@@ -439,8 +556,12 @@ hipError_t vcycle_t(const MgHierarchy& h, int nv, const T* const* b, T* const* u
         }
         return v;
     };
-    // down the hierarchy: two sweeps from zero, residual, restriction
-    for (int l = 0; l < h.nlev - 1; ++l) {
+    // the first level of the fused coarse tail
+    int lt = 0;
+    while (lt < h.nlev - 1 && h.lev[lt].n > kTailN) ++lt;
+    if (h.nlev - lt > kTailMax) return hipErrorInvalidValue;
+    // down the hierarchy to the tail: two sweeps from zero, residual, restriction
+    for (int l = 0; l < lt; ++l) {
         const MgLevel& L = h.lev[l];
         const dim3 g(grid_of(L.n));
         hipLaunchKernelGGL(sweep2_from_zero_kernel<T>, g, dim3(256), 0, s, L, vecs(nullptr, B[l], R[l]), nv);
@@ -449,10 +570,25 @@ hipError_t vcycle_t(const MgHierarchy& h, int nv, const T* const* b, T* const* u
         hipLaunchKernelGGL(restrict_kernel<T>, dim3(grid_of(h.lev[l + 1].n), nv), dim3(256), 0, s, L, h.lev[l + 1],
                            vecs(U[l], nullptr, Bn));
     }
-    const int last = h.nlev - 1;
-    hipLaunchKernelGGL(coarsest_kernel<T>, dim3(1), dim3(64), 0, s, h.lev[last], vecs(nullptr, B[last], R[last]), nv);
-    // and back up: correction, two sweeps
-    for (int l = h.nlev - 2; l >= 0; --l) {
+    // the tail: levels lt .. nlev-1 in one kernel, one workgroup per vector
+    {
+        TailArgs<T> ta{};
+        ta.lt = lt;
+        ta.nl = h.nlev - lt;
+        ta.nv = nv;
+        for (int k = 0; k < ta.nl; ++k) ta.lev[k + 1] = h.lev[lt + k];
+        for (int q = 0; q < nv; ++q) {
+            ta.b0[q] = B[lt][q];
+            ta.r0[q] = R[lt][q];
+            ta.u0[q] = U[lt][q];
+            ta.c[q] = c[q];
+        }
+        // levels below lt keep the B | U | R layout of the scratch (base = B of vector 0)
+        for (int k = 1; k < ta.nl; ++k) ta.base[k] = const_cast<T*>(B[lt + k][0]);
+        hipLaunchKernelGGL(tail_kernel<T>, dim3(nv), dim3(kTailThreads), 0, s, ta);
+    }
+    // and back up from the tail: correction, two sweeps
+    for (int l = lt - 1; l >= 0; --l) {
         const MgLevel& L = h.lev[l];
         const dim3 g(grid_of(L.n));
         hipLaunchKernelGGL(prolong_add_kernel<T>, dim3(grid_of(L.n), nv), dim3(256), 0, s, L, h.lev[l + 1],
