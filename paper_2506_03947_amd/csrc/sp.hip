@@ -33,7 +33,7 @@
 namespace ac {
 namespace {
 
-constexpr int kBlk = 512;   // blocks of the reducing kernels (grid-stride)
+constexpr int kBlk = 2048;  // blocks of the reducing kernels (grid-stride)
 constexpr int kThr = 256;
 constexpr int kSt = 16;     // state doubles per shift
 
@@ -63,30 +63,46 @@ __device__ __forceinline__ double block_sum(double v) {
     return t;
 }
 
-// (A - c I) u at point i on the fine level (float64 arithmetic on the vector's and the
-// coefficients' stored type)
+// Coefficients of the fine level at point i (float64 arithmetic on the stored type: the
+// float64 arrays, or their float32 copies for float32 vectors); a missing neighbour has
+// coefficient 0 and its value is not read.
+struct Fine {
+    double d, e, w, n, s;
+    bool he, hw, hn, hs;
+    long long nx;
+};
 template <typename T>
-__device__ __forceinline__ double op_at(const MgLevel& L, const T* __restrict__ u, long long i, double c) {
+__device__ __forceinline__ Fine fine_at(const MgLevel& L, long long i) {
     const int ii = static_cast<int>(i), x = ii % L.nx, y = ii / L.nx;
-    double d, e = 0.0, w = 0.0, nn = 0.0, ss = 0.0;
+    Fine f;
+    f.nx = L.nx;
+    f.he = x < L.nx - 1;
+    f.hw = x > 0;
+    f.hn = L.dim == 2 && y < L.ny - 1;
+    f.hs = L.dim == 2 && y > 0;
     if constexpr (std::is_same<T, float>::value) {
-        d = L.diag_f[i];
-        if (x < L.nx - 1) e = L.wx_f[i];
-        if (x > 0) w = L.wx_f[i - 1];
-        if (L.dim == 2 && y < L.ny - 1) nn = L.wy_f[i];
-        if (L.dim == 2 && y > 0) ss = L.wy_f[i - L.nx];
+        f.d = L.diag_f[i];
+        f.e = f.he ? L.wx_f[i] : 0.0;
+        f.w = f.hw ? L.wx_f[i - 1] : 0.0;
+        f.n = f.hn ? L.wy_f[i] : 0.0;
+        f.s = f.hs ? L.wy_f[i - L.nx] : 0.0;
     } else {
-        d = L.diag[i];
-        if (x < L.nx - 1) e = L.wx[i];
-        if (x > 0) w = L.wx[i - 1];
-        if (L.dim == 2 && y < L.ny - 1) nn = L.wy[i];
-        if (L.dim == 2 && y > 0) ss = L.wy[i - L.nx];
+        f.d = L.diag[i];
+        f.e = f.he ? L.wx[i] : 0.0;
+        f.w = f.hw ? L.wx[i - 1] : 0.0;
+        f.n = f.hn ? L.wy[i] : 0.0;
+        f.s = f.hs ? L.wy[i - L.nx] : 0.0;
     }
-    double a = (d - c) * static_cast<double>(u[i]);
-    if (x < L.nx - 1) a -= e * static_cast<double>(u[i + 1]);
-    if (x > 0) a -= w * static_cast<double>(u[i - 1]);
-    if (L.dim == 2 && y < L.ny - 1) a -= nn * static_cast<double>(u[i + L.nx]);
-    if (L.dim == 2 && y > 0) a -= ss * static_cast<double>(u[i - L.nx]);
+    return f;
+}
+// (A - c I) u at point i
+template <typename T>
+__device__ __forceinline__ double op_at(const Fine& f, const T* __restrict__ u, long long i, double c) {
+    double a = (f.d - c) * static_cast<double>(u[i]);
+    if (f.he) a -= f.e * static_cast<double>(u[i + 1]);
+    if (f.hw) a -= f.w * static_cast<double>(u[i - 1]);
+    if (f.hn) a -= f.n * static_cast<double>(u[i + f.nx]);
+    if (f.hs) a -= f.s * static_cast<double>(u[i - f.nx]);
     return a;
 }
 
@@ -113,9 +129,10 @@ __global__ __launch_bounds__(kThr) void saddle_apply_kernel(const MgLevel L, lon
             o2[i] = T(0);
             continue;
         }
+        const Fine f = fine_at<T>(L, i);
         const double a1 = z1[i], a2 = z2[i];
-        const double t1 = (sig * a1 + op_at(L, z2, i, rho)) * ginv;
-        const double t2 = (op_at(L, z1, i, rho) - sig * a2) * ginv;
+        const double t1 = (sig * a1 + op_at(f, z2, i, rho)) * ginv;
+        const double t2 = (op_at(f, z1, i, rho) - sig * a2) * ginv;
         o1[i] = static_cast<T>(t1);
         o2[i] = static_cast<T>(t2);
         acc += (t1 * a1 + t2 * a2) * ginv;
@@ -134,7 +151,7 @@ __global__ __launch_bounds__(kThr) void cg_apply_kernel(const MgLevel L, long lo
     double acc = 0.0;
     for (long long i = static_cast<long long>(blockIdx.x) * kThr + threadIdx.x; i < n;
          i += static_cast<long long>(gridDim.x) * kThr) {
-        const double a = op_at(L, p, i, P.lam[r]);
+        const double a = op_at(fine_at<T>(L, i), p, i, P.lam[r]);
         q[i] = static_cast<T>(a);
         acc += static_cast<double>(p[i]) * a;
     }
