@@ -302,3 +302,18 @@ def test_sp_graph_replay_matches_eager(precision):
         assert res[True][0] == res[False][0] and torch.equal(res[True][1], res[False][1])
     finally:
         api.ac_ctx_set_graphs(ctx, True)
+
+
+def test_sp_l_scaling_paper_table():
+    """The paper's l scaling table for P_SP at n_x = 100 (eta = 0.2, rows with l <= 16):
+    every count within one of the exact P_alpha's on the same problem and close to the
+    paper's AMG-based counts."""
+    import json
+    rows = json.load(open(GOLDEN_SP))["l_rows"]
+    for r in rows:
+        nx, ell, alpha = r["nx"], r["ell"], r["alpha"]
+        sp_it = _outer_cheb_count(nx, ell, alpha, L.AC_INNER_SP, int(round(0.2 * nx)))
+        ex_it = _outer_cheb_count(nx, ell, alpha, L.AC_INNER_EXACT, 1)
+        print(f"alpha {alpha} l {ell}: P_SP {sp_it}, exact P_alpha {ex_it}, paper {r['iterations']}", flush=True)
+        assert ex_it <= sp_it <= ex_it + 1
+        assert sp_it - r["iterations"] <= (2 if alpha < 0.1 else 4)
