@@ -296,7 +296,9 @@ int ac_tdft_inverse(ac_problem* p, int precision, const void* yhat, double* z);
 
 /* rel[m] = ||rhat_m - (A - lambda_m I) yhat_m|| / ||rhat_m||, m = 0..l_s-1 (host output),
  * the inner residual of shifted solutions in the spectral layout (float64 sums).
- * Synchronises. */
+ * Meant for judging warm-start guesses: lambda is taken in float32 and the norm is
+ * formed from |rhat|^2, <B yhat, rhat> and |B yhat|^2, so values below about 1e-7 are
+ * not resolved.  Synchronises. */
 int ac_shifted_residual(ac_problem* p, int precision, const void* rhat, const void* yhat, double* rel);
 
 /* ---- outer solve ---------------------------------------------------------- */
