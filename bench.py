@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--step-pairs", type=int, default=1, choices=[0, 1],
+                    help="fuse two steady Chebyshev steps per sweep (1) or run single steps (0)")
+    ap.add_argument("--pair-tiling", type=int, nargs=3, default=[0, 0, 0], metavar=("ROWS", "WPB", "VX"),
+                    help="tiling of the paired sweep (0 = automatic)")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp", "blocks", "paper"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
                          "(the launch set used for hardware-counter runs); batch: many uneven problems "
@@ -416,40 +420,42 @@ def kernels_only(a, api, prob, ell, n):
     api.ac_ctx_reset_stats(ctx)
     for _ in range(max(a.steps, 1)):
         api.ac_apply_prec(prob, opts, r, z, ws)
-    st = api.ac_ctx_kernel_stats(ctx)["cheb_step"]
+    stats = api.ac_ctx_kernel_stats(ctx)
     api.ac_ctx_set_profiling(ctx, False)
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)  # 512 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    avg_ms = st["ms"] / st["launches"]
-    per = st["bytes"] / st["launches"]
-    print(json.dumps({"mode": "kernels", "cheb_step_avg_ms": avg_ms, "cheb_step_bytes_per_launch": per,
-                      "cheb_step_GBps": per / avg_ms / 1e6, "launches": st["launches"],
-                      "copy_bytes_each_way": src.numel() * 8}), flush=True)
+    out = {"mode": "kernels", "copy_bytes_each_way": src.numel() * 8}
+    for name in ("cheb_step", "cheb_pair"):
+        st = stats[name]
+        if st["launches"]:
+            avg_ms = st["ms"] / st["launches"]
+            per = st["bytes"] / st["launches"]
+            out[name] = {"avg_ms": avg_ms, "bytes_per_launch": per, "GBps": per / avg_ms / 1e6,
+                         "launches": st["launches"]}
+    print(json.dumps(out), flush=True)
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def measured_traffic(a):
-    """HBM bytes per launch of the steady-state sweep from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE record (scaled by a copy of known size), or None when the
-    record does not cover this workload or the kernel source changed since."""
+def measured_traffic(a, name, sources):
+    """HBM bytes per launch of the roofline kernel from a committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE record (scaled by a copy of known size), or None when the record does not
+    cover this workload or a kernel source changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "cheb_sweep_group_2048x2048_l10_traffic.json")
-    if a.workload != "large" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", name)
+    if a.workload != "large" or a.p != 20 or not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, "paper_2506_03947_amd", "csrc", "stencil_kernels.h"), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["kernel_source_sha256"] or a.p < 4:
+    h = hashlib.sha256()
+    for f in sources:
+        h.update(open(os.path.join(ROOT, "paper_2506_03947_amd", "csrc", f), "rb").read())
+    if h.hexdigest() != rec["kernel_source_sha256"]:
         return None
-    # steady-state steps per application: k = 2..p-2, the k = 2 one reads x_1 = rhat/theta;
-    # every step is two group launches of equal size
-    v = rec["variants"]
-    n = a.p - 3
-    return ((n - 1) * v["steady_prev_buffer"]["bytes"] + v["steady_prev_rhat"]["bytes"]) / n
+    return rec["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(w, kappa, b, p, gpu_outer_iters):
@@ -516,6 +522,7 @@ def main():
     bd = torch.from_numpy(b).to(dev)
     x = torch.zeros(ell * n, dtype=torch.float64, device=dev)
     ctx = api.ac_ctx_create(0)
+    api.ac_ctx_set_step_pairs(ctx, a.step_pairs, *a.pair_tiling)
     prob = api.ac_problem_create(ctx, 2, nx, ny, kd, ell, alpha)
     mu_lo, mu_hi = api.ac_spectral_bounds(prob)
     if a.mode == "kernels":
@@ -561,17 +568,37 @@ def main():
                     "speedup_mixed_vs_fp64": t64 / t_mixed,
                     "mixed_vs_fp64_solution_rel_diff": diff}
 
-    st = stats_mixed["cheb_step"]
+    # Dominant kernel: the paired steady sweep (two Chebyshev steps per launch, one launch
+    # per shift group), else the single steady sweep.  `achieved` counts the unfused
+    # algorithmic bytes of the steps a launch performs (4 vector streams per shift and
+    # step, kappa once per step); the paired sweep itself moves 5 of every 8 of those
+    # vector streams, which `own_min_bytes_per_launch` and `traffic` show.
+    pair = stats_mixed.get("cheb_pair", {"launches": 0})
+    if pair["launches"]:
+        st = pair
+        kname = ("cheb_pair_kernel<float, unsigned short, 2>: two steady shifted-Chebyshev steps fused in one "
+                 "sweep over a shift group (one real + two complex shifts; two launches per pair of steps at l = 10)")
+        traffic = measured_traffic(a, "cheb_pair_2048x2048_l10_traffic.json", ["stencil_pair.hip", "stencil_kernels.h"])
+    else:
+        st = stats_mixed["cheb_step"]
+        kname = ("cheb_sweep_kernel<float, unsigned short, 5, 2, false, false, false>: steady-state shifted "
+                 "Chebyshev sweep over one shift group (two launches per step at l = 10)")
+        traffic = None
     avg_ms = st["ms"] / max(st["launches"], 1)
     bytes_per_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"kernel": ("cheb_sweep_kernel<float, unsigned short, 5, 2, false, false, false>: steady-state "
-                           "shifted Chebyshev sweep over one shift group (one real + two complex shifts; "
-                           "two launches per step at l = 10)"),
-                "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(a),
+    roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
                 "launches": st["launches"]}
+    if pair["launches"]:
+        kap_b = 2.0  # bf16 kappa
+        per_shift = (bytes_per_launch / n - 2 * kap_b) / 8.0  # bytes of one stream, summed over the group
+        own = n * (5 * per_shift + kap_b)
+        roofline["own_min_bytes_per_launch"] = own
+        roofline["own_min_GBps"] = own / (avg_ms * 1e-3) / 1e9
+        if traffic:
+            roofline["traffic_GBps"] = traffic / (avg_ms * 1e-3) / 1e9
 
     cpu = None
     if not a.no_cpu_baseline:

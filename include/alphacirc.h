@@ -167,7 +167,8 @@ typedef enum {
     AC_K_CHEB_FIRST = 6, /* the first sweep from a zero guess (x_2 from x_1 = rhat/theta) */
     AC_K_EXACT = 7,      /* AC_INNER_EXACT: sine transforms, tridiagonal solves, inverse time-DFT */
     AC_K_SADDLE = 8,     /* AC_INNER_SP: MINRES / CG with multigrid V-cycles (whole inner solve) */
-    AC_K_COUNT = 9
+    AC_K_CHEB_PAIR = 9,  /* two steady Chebyshev sweeps fused into one (per shift group) */
+    AC_K_COUNT = 10
 } ac_kernel_class;
 
 /* ---- status ------------------------------------------------------------- */
@@ -324,6 +325,19 @@ int ac_solve_record(ac_problem* p, const ac_solve_opts* opts, const double* b, d
  * complex shifts and runs as its own launch; results are those of the all-shift
  * sweep.  Problems with grouped sweeps default to 8 rows per wave. */
 int ac_ctx_set_shift_groups(ac_ctx* ctx, int mode);
+
+/* Two steady Chebyshev steps per sweep (temporal blocking of the three-term recurrence
+ * of Section 3): mode 1 (default) fuses every two consecutive steady steps in which the
+ * same shifts compute, on Dirichlet grids, into one sweep per shift group (one real,
+ * two complex shifts) that reads x_k, x_{k-1} and rhat once and writes x_{k+1} and
+ * x_{k+2}; mode 0 runs single steps.  The iterates are those of single steps (float64:
+ * identical; float32: up to contraction).  rows_per_wave, waves_per_block (1..4) and
+ * points_per_lane (1..2) set the paired sweep's tiling, 0 = automatic (8 rows, 1
+ * wave, 2 points per lane in float32 on even grids at least 128 wide, else 1).  Pairs
+ * are used while every spectral buffer is below 2^31 bytes.  Profiling (AC_K_CHEB_PAIR)
+ * counts the two steps' unfused algorithmic bytes.
+ * Batched solves (ac_batch_solve) run single steps. */
+int ac_ctx_set_step_pairs(ac_ctx* ctx, int mode, int rows_per_wave, int waves_per_block, int points_per_lane);
 
 /* ---- tiling ----------------------------------------------------------------
  * Sweep tiling of one problem (overrides the context's ac_ctx_set_tiling; 0 keeps

@@ -57,19 +57,38 @@ struct SweepArgs {
     const void* kappa;  // storage type depends on the precision
     ShiftCoef<R> cf;
     int src[kMaxShift];        // SRC_COMPUTE, or (final sweep) SRC_RHAT / SRC_BUF for finished shifts
-    int fbuf[kMaxShift];       // final sweep, SRC_BUF: finished iterate in buf0 (0) or buf1 (1)
+    int fbuf[kMaxShift];       // final sweep, SRC_BUF: finished iterate in bufs[fbuf]
     unsigned soff[kMaxShift];  // slot offset (elements of R) inside every spectral buffer
     int prevk;                 // kind of x_{k-1}: SRC_ZERO / SRC_RHAT / SRC_BUF
     const R* rhat;             // spectral buffers (identical layouts)
     const R* cur;              // x_k
-    R* out;                    // step: holds x_{k-1} on entry (if a buffer), x_{k+1} on exit
-    const R* prev;             // final: x_{k-1}
-    const R* buf0;
-    const R* buf1;
+    R* out;                    // x_{k+1} (may be the buffer of x_{k-1}: each lane reads before it writes)
+    const R* prev;             // x_{k-1} (when a buffer)
+    const R* bufs[4];          // iterate buffers (final sweep: finished iterates)
     // inverse transform (final sweep only)
     double ginv[kMaxEll];             // 1 / (l * alpha^{k/l})
     double cw[kMaxEll], sw[kMaxEll];  // cos / sin (2 pi j / l)
     double* z;
+};
+
+// Two consecutive steady Chebyshev steps (x_{k+1} and x_{k+2}) in one sweep, for one
+// group of shift slots: slot 0 real, slots 1 and 2 complex (as the l = 5 sweep).
+// Tiling: strips of 64*vx computed columns at a stride of 64*vx - 2 (the two edge
+// columns of a strip only feed the second step of its inner columns).
+template <typename R>
+struct PairArgs {
+    Geom g;
+    Tiling t;
+    const void* kappa;
+    ShiftCoef<R> cf[2];  // steps k and k+1
+    int comp[3];         // slot computes (else skipped)
+    unsigned soff[3];    // slot offset (elements of R) inside every spectral buffer
+    const R* rhat;
+    const R* cur;        // x_k
+    const R* prev;       // x_{k-1}
+    R* out1;             // x_{k+1}
+    R* out2;             // x_{k+2}
+    unsigned bytes;      // bytes of each spectral buffer (below 2^31)
 };
 
 struct FwdArgs {
@@ -129,6 +148,8 @@ inline void fwd_geometry(long long n, int& vx, int& blocks) {
 // the kind of x_{k-1} travels in SweepArgs::prevk.
 hipError_t launch_cheb_step(int ell, int prec, int curk, const void* args, hipStream_t s);
 hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipStream_t s);
+// Two steady steps per sweep (PairArgs<double> for prec 0, else PairArgs<float>).
+hipError_t launch_cheb_pair(int prec, const void* args, hipStream_t s);
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);

@@ -93,6 +93,9 @@ struct ac_ctx {
     std::vector<ac_launch_rec>* rec = nullptr;
     // steady sweeps in shift groups: -1 automatic (5 or more unique shifts), 0 off, 1 on
     int shift_groups = -1;
+    // two steady Chebyshev steps per sweep: 0 off, 1 on (Dirichlet grids); rows per
+    // wave, points per lane, waves per block of the paired sweep (0 = automatic)
+    int pairs = 1, pair_h = 0, pair_vx = 0, pair_wpb = 0;
     // dense sine transforms of the exact inner solve (workspace set per call)
     rocblas_handle blas = nullptr;
     // launch-bound inner solves (P_SP) are captured on this stream and replayed as graphs
@@ -258,6 +261,27 @@ Tiling sweep_tiling(const ac_problem* p) {
                        p->tile_wpb ? p->tile_wpb : p->ctx->tile_wpb);
 }
 
+// Paired sweep (two steps): strips of 64*vx computed columns at a stride of
+// 64*vx - 2; two points per lane on even grids at least 128 wide in float32, one in
+// float64 (register budget).
+Tiling pair_tiling(const ac_problem* p, int prec) {
+    const ac_ctx* c = p->ctx;
+    const Geom& g = p->g;
+    Tiling t{};
+    int vx = c->pair_vx > 0 ? c->pair_vx : (prec == AC_PREC_FP64 ? 1 : 2);
+    if (g.nx % 2 != 0 || g.nx < 128) vx = 1;
+    t.vx = vx;
+    t.h = c->pair_h > 0 ? c->pair_h : 8;
+    if (t.h > g.ny) t.h = g.ny;
+    t.wpb = c->pair_wpb > 0 ? c->pair_wpb : 1;
+    const int stride = ac::kWave * vx - 2;
+    t.nsx = (g.nx - 1 + stride - 1) / stride;
+    t.ncy = (g.ny + t.h - 1) / t.h;
+    t.tiles = static_cast<long long>(t.nsx) * t.ncy;
+    t.blocks = static_cast<int>((t.tiles + t.wpb - 1) / t.wpb);
+    return t;
+}
+
 template <class A>
 void record_launch(ac_ctx* c, int op, int ell, int prec, int curk, int vx, int wpb, int blocks, const A& a) {
     ac_launch_rec r{op, ell, prec, curk, vx, wpb, blocks, std::vector<char>(sizeof(A))};
@@ -369,10 +393,15 @@ size_t sp_extra_bytes(const ac_problem* p, int prec) {
     return ac::sp_ws_bytes(p->mg, p->g.n, p->nsc, p->nsr, prec != AC_PREC_FP64) + 256;
 }
 
+// Iterate buffers of the inner solve: four for the Chebyshev solves (x_q lives in
+// buffer q mod 4, so that a sweep fusing two steps never writes a buffer another wave
+// reads), two for the exact and saddle-point solves.
+int iter_bufs(int inner) { return (inner == AC_INNER_EXACT || inner == AC_INNER_SP) ? 2 : 4; }
+
 size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
-    size_t b = 3 * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
+    size_t b = (1 + iter_bufs(inner)) * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
     if (inner == AC_INNER_EXACT) b += exact_extra_bytes(p, prec);
     else if (inner == AC_INNER_SP) b += sp_extra_bytes(p, prec);
     else if (inner != AC_INNER_CHEB) b += cnn_ws_bytes(p);
@@ -381,16 +410,22 @@ size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
 
 struct PrecBufs {
     char* rhat;
-    char* buf[2];
-    char* cnn;  // start of the CNN buffers or of the exact solve's extra buffers
+    char* buf[4];  // iterate buffers (the last two null for the exact and saddle-point solves)
+    char* cnn;     // start of the CNN buffers or of the exact / saddle-point solve's extra buffers
 };
 
-PrecBufs carve_prec(const ac_problem* p, int prec, void* ws) {
+PrecBufs carve_prec(const ac_problem* p, int prec, void* ws, int inner = AC_INNER_CHEB) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     const size_t sz = align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256);
     char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
-    return {base, {base + sz, base + 2 * sz}, base + 3 * sz};
+    const int nb = iter_bufs(inner);
+    PrecBufs b{base, {base + sz, base + 2 * sz, nullptr, nullptr}, base + (1 + nb) * sz};
+    if (nb == 4) {
+        b.buf[2] = base + 3 * sz;
+        b.buf[3] = base + 4 * sz;
+    }
+    return b;
 }
 
 // slot pointer into a spectral buffer
@@ -429,16 +464,21 @@ int run_fwd(ac_problem* p, int prec, const double* r, char* rhat, double in_scal
 }
 
 template <typename R>
-void fill_coef(ac::SweepArgs<R>& a, int slot, const ChebShift& cs, int k) {
-    a.cf.lam_re[slot] = static_cast<R>(cs.lam.real());
-    a.cf.lam_im[slot] = static_cast<R>(cs.lam.imag());
-    a.cf.a_re[slot] = static_cast<R>(cs.a[k].real());
-    a.cf.a_im[slot] = static_cast<R>(cs.a[k].imag());
-    a.cf.c_re[slot] = static_cast<R>(cs.c[k].real());
-    a.cf.c_im[slot] = static_cast<R>(cs.c[k].imag());
+void fill_cf(ac::ShiftCoef<R>& cf, int slot, const ChebShift& cs, int k) {
+    cf.lam_re[slot] = static_cast<R>(cs.lam.real());
+    cf.lam_im[slot] = static_cast<R>(cs.lam.imag());
+    cf.a_re[slot] = static_cast<R>(cs.a[k].real());
+    cf.a_im[slot] = static_cast<R>(cs.a[k].imag());
+    cf.c_re[slot] = static_cast<R>(cs.c[k].real());
+    cf.c_im[slot] = static_cast<R>(cs.c[k].imag());
     const cplx s = 1.0 / cs.theta;
-    a.cf.s_re[slot] = static_cast<R>(s.real());
-    a.cf.s_im[slot] = static_cast<R>(s.imag());
+    cf.s_re[slot] = static_cast<R>(s.real());
+    cf.s_im[slot] = static_cast<R>(s.imag());
+}
+
+template <typename R>
+void fill_coef(ac::SweepArgs<R>& a, int slot, const ChebShift& cs, int k) {
+    fill_cf(a.cf, slot, cs, k);
 }
 
 // Bytes a sweep moves, per point, for one computing shift of element size esz.
@@ -450,11 +490,13 @@ double sweep_bytes_per_point(int curk, int prevk, bool final, double esz) {
     return n * esz;
 }
 
-// Nested Chebyshev over all unique shifts.  warm: x_0 is in buf[0].
+// Nested Chebyshev over all unique shifts.  warm: x_0 is in buf[0].  x_q lives in
+// buf[q mod nb], nb = 4 when buf[2] and buf[3] are given (then runs of steady steps
+// are fused in pairs), else 2.
 // If z != nullptr the last sweep is fused with the inverse transform into z;
 // otherwise the finished iterates are left in place and `where` reports them.
 template <typename R>
-int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[2], bool warm,
+int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[4], bool warm,
                double* z, std::vector<std::pair<int, char*>>* where) {
     const int ns = p->ns;
     int pmax = 0;
@@ -484,14 +526,16 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             prevk = (k == 1) ? ac::SRC_ZERO : (k == 2) ? ac::SRC_RHAT : ac::SRC_BUF;
         }
     };
+    const int nb = (buf[2] && buf[3]) ? 4 : 2;
+    auto bidx = [&](int q) { return ((q % nb) + nb) % nb; };
     // location of a finished iterate x_q
-    auto fin_src = [&](int q, int& kind, char*& b) {
+    auto fin_src = [&](int q, int& kind, int& bi) {
         if (!warm && q == 1) {
             kind = ac::SRC_RHAT;
-            b = rhat;
+            bi = -1;
         } else {
             kind = ac::SRC_BUF;
-            b = buf[q % 2];
+            bi = bidx(q);
         }
     };
 
@@ -504,8 +548,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         a.t = t;
         a.kappa = kap;
         a.rhat = reinterpret_cast<const R*>(rhat);
-        a.buf0 = reinterpret_cast<const R*>(buf[0]);
-        a.buf1 = reinterpret_cast<const R*>(buf[1]);
+        for (int i = 0; i < 4; ++i) a.bufs[i] = reinterpret_cast<const R*>(buf[i]);
         for (int s = 0; s < ns; ++s) a.soff[s] = static_cast<unsigned>(off[slot_to_m(p, s)]);
     };
     auto fill_final = [&](ac::SweepArgs<R>& a) {
@@ -572,18 +615,88 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         }
         return ac::launch_cheb_step(p->ell, prec, curk, &a, p->ctx->stream);
     };
-    // consecutive steady-state sweeps share one event pair (no per-launch event cost)
-    std::unique_ptr<ProfScope> steady;
+    // Steady step k (x_k and x_{k-1} in buffers, not the fused last sweep).  Two
+    // consecutive steady steps in which the same shifts compute run as one paired
+    // sweep per shift group when four iterate buffers are available.
+    // (the paired sweep addresses its buffers with 32-bit byte offsets below 2^31)
+    const double spec_bytes = static_cast<double>(off[ns]) * sizeof(R);
+    const bool can_pair = nb == 4 && p->ctx->pairs == 1 && !p->ctx->rec && !p->g.periodic && p->g.nx >= 3 &&
+                          spec_bytes < 2147483648.0 && static_cast<double>(p->g.n) * ksz < 2147483648.0;
+    auto steady_step = [&](int k) {
+        if (k > k_last || (fuse && k == k_last)) return false;
+        int ck, pk;
+        kinds(k, ck, pk);
+        return ck == ac::SRC_BUF && pk == ac::SRC_BUF;
+    };
+    auto launch_pair = [&](int k, double& bytes) -> hipError_t {
+        ac::PairArgs<R> pa{};
+        pa.g = p->g;
+        pa.t = pair_tiling(p, prec);
+        pa.kappa = kap;
+        pa.rhat = reinterpret_cast<const R*>(rhat);
+        pa.cur = reinterpret_cast<const R*>(buf[bidx(k)]);
+        pa.prev = reinterpret_cast<const R*>(buf[bidx(k - 1)]);
+        pa.out1 = reinterpret_cast<R*>(buf[bidx(k + 1)]);
+        pa.out2 = reinterpret_cast<R*>(buf[bidx(k + 2)]);
+        pa.bytes = static_cast<unsigned>(spec_bytes);
+        bytes = 0.0;
+        const int ngroups = std::max(p->nsr, (p->nsc + 1) / 2);
+        for (int grp = 0; grp < ngroups; ++grp) {
+            const int map[3] = {grp < p->nsr ? grp : -1, 2 * grp < p->nsc ? p->nsr + 2 * grp : -1,
+                                2 * grp + 1 < p->nsc ? p->nsr + 2 * grp + 1 : -1};
+            bool anyc = false;
+            for (int j = 0; j < 3; ++j) {
+                const int sl = map[j];
+                pa.comp[j] = 0;
+                pa.soff[j] = 0;
+                if (sl < 0 || ps[sl] < k + 1) continue;
+                pa.comp[j] = 1;
+                pa.soff[j] = static_cast<unsigned>(off[slot_to_m(p, sl)]);
+                fill_cf(pa.cf[0], j, cs[sl], k);
+                fill_cf(pa.cf[1], j, cs[sl], k + 1);
+                bytes += 8.0 * (slot_is_real(p, sl) ? esz_r : esz_c);  // two steps of 4 streams
+                anyc = true;
+            }
+            if (!anyc) continue;
+            const hipError_t e = ac::launch_cheb_pair(prec, &pa, p->ctx->stream);
+            if (e != hipSuccess) return e;
+            ++launched;
+        }
+        // algorithmic bytes of the two steps as unfused sweeps (kappa once per step), the
+        // unit every steady sweep is measured in; the pair itself moves 5 of the 8 streams
+        bytes = (bytes + 2.0 * ksz) * static_cast<double>(p->g.n);
+        return hipSuccess;
+    };
+    // consecutive steady-state sweeps (single or paired) share one event pair
+    std::unique_ptr<ProfScope> steady, paired;
     for (int k = k_first; k <= k_last; ++k) {
+        bool pair = can_pair && steady_step(k) && steady_step(k + 1);
+        for (int s = 0; pair && s < ns; ++s)
+            if ((ps[s] >= k + 1) != (ps[s] >= k + 2)) pair = false;
+        if (pair) {
+            steady.reset();
+            if (!paired) {
+                paired = std::make_unique<ProfScope>(p->ctx, AC_K_CHEB_PAIR, 0.0);
+                paired->launches = 0;
+            }
+            launched = 0;
+            double bytes = 0.0;
+            AC_HIP(launch_pair(k, bytes));
+            paired->bytes += bytes;
+            paired->launches += launched;
+            ++k;  // x_{k+2} done
+            continue;
+        }
+        paired.reset();
         const bool final = fuse && (k == k_last);
         ac::SweepArgs<R> a{};
         base_args(a);
         int curk, prevk;
         kinds(k, curk, prevk);
         a.prevk = prevk;
-        a.cur = reinterpret_cast<const R*>(buf[k % 2]);
-        a.out = reinterpret_cast<R*>(buf[(k + 1) % 2]);
-        a.prev = reinterpret_cast<const R*>(buf[(k + 1) % 2]);
+        a.cur = reinterpret_cast<const R*>(buf[bidx(k)]);
+        a.out = reinterpret_cast<R*>(buf[bidx(k + 1)]);
+        a.prev = reinterpret_cast<const R*>(buf[bidx(k - 1)]);
         double bytes = 0.0;
         bool anyc = false;
         for (int s = 0; s < ns; ++s) {
@@ -594,11 +707,10 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 anyc = true;
                 bytes += sweep_bytes_per_point(curk, prevk, final, esz);
             } else {
-                int kind;
-                char* b;
-                fin_src(ps[s], kind, b);
+                int kind, bi;
+                fin_src(ps[s], kind, bi);
                 a.src[s] = kind;
-                a.fbuf[s] = (b == buf[1]) ? 1 : 0;
+                a.fbuf[s] = bi < 0 ? 0 : bi;
                 if (final) bytes += esz;
             }
         }
@@ -623,6 +735,8 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         }
         if (steady && (k + 1 > k_last || (fuse && k + 1 == k_last))) steady.reset();
     }
+    steady.reset();
+    paired.reset();
     if (fuse && k_last < k_first) {
         // nothing to iterate (cold start, every p = 1): x_1 = rhat/theta everywhere
         ac::SweepArgs<R> a{};
@@ -642,16 +756,15 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     if (where) {
         where->clear();
         for (int s = 0; s < ns; ++s) {
-            int kind;
-            char* b;
-            fin_src(ps[s], kind, b);
-            where->emplace_back(kind, b);
+            int kind, bi;
+            fin_src(ps[s], kind, bi);
+            where->emplace_back(kind, bi < 0 ? rhat : buf[bi]);
         }
     }
     return AC_OK;
 }
 
-int run_cheb(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[2], bool warm, double* z,
+int run_cheb(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[4], bool warm, double* z,
              std::vector<std::pair<int, char*>>* where) {
     if (prec == AC_PREC_FP64) return run_cheb_t<double>(p, prec, pm, rhat, buf, warm, z, where);
     return run_cheb_t<float>(p, prec, pm, rhat, buf, warm, z, where);
@@ -1007,7 +1120,7 @@ int sp_inner(ac_problem* p, int prec, int iters, const PrecBufs& b, double* z) {
 
 int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* r, double* z,
                     void* ws, double in_scale, int* fallbacks = nullptr) {
-    const PrecBufs b = carve_prec(p, o->precision, ws);
+    const PrecBufs b = carve_prec(p, o->precision, ws, o->inner);
     AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
     if (o->inner == AC_INNER_SP) {
         AC_TRY(sp_inner(p, o->precision, pm[0], b, z));
@@ -2318,6 +2431,19 @@ int ac_ctx_set_shift_groups(ac_ctx* c, int mode) {
     if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
     if (mode < -1 || mode > 1) return fail(AC_ERR_ARG, "mode must be -1, 0 or 1");
     c->shift_groups = mode;
+    return AC_OK;
+}
+
+int ac_ctx_set_step_pairs(ac_ctx* c, int mode, int rows_per_wave, int waves_per_block, int points_per_lane) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    if (mode < 0 || mode > 1) return fail(AC_ERR_ARG, "mode must be 0 or 1");
+    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
+    if (waves_per_block < 0 || waves_per_block > 4) return fail(AC_ERR_ARG, "waves_per_block must be 0..4");
+    if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
+    c->pairs = mode;
+    c->pair_h = rows_per_wave;
+    c->pair_wpb = waves_per_block;
+    c->pair_vx = points_per_lane;
     return AC_OK;
 }
 

@@ -119,6 +119,45 @@ __device__ __forceinline__ void kloadv(const double* p, long long i, double (&o)
     ldv<double, V>(p + i, o);
 }
 
+// kappa storage value -> compute type (bf16: the high half of a float32)
+__device__ __forceinline__ float kconv(uint16_t v) { return __uint_as_float(static_cast<uint32_t>(v) << 16); }
+__device__ __forceinline__ float kconv(float v) { return v; }
+__device__ __forceinline__ double kconv(double v) { return v; }
+
+// Raw buffer loads (buffer resource with a byte range): a lane whose byte offset lies
+// past the range reads zeros and touches no memory, which gives ghost values without a
+// lane-divergent branch.  kOob is such an offset for every range below 2^31 bytes.
+constexpr unsigned kOob = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), 0x00020000);
+}
+
+// V values of type T at byte offset off; AUX 2 = non-temporal
+template <int AUX, typename T, int V>
+__device__ __forceinline__ void bld(__amdgpu_buffer_rsrc_t r, unsigned off, T (&out)[V]) {
+    constexpr int B = static_cast<int>(sizeof(T)) * V;
+    if constexpr (B == 2) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b16(r, off, 0, AUX);
+        __builtin_memcpy(out, &u, 2);
+    } else if constexpr (B == 4) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, AUX);
+        __builtin_memcpy(out, &u, 4);
+    } else if constexpr (B == 8) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, AUX);
+        __builtin_memcpy(out, &u, 8);
+    } else if constexpr (B == 16) {
+        const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+        __builtin_memcpy(out, &u, 16);
+    } else {
+        static_assert(B == 32, "buffer load of 2, 4, 8, 16 or 32 bytes");
+        const auto u0 = __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, AUX);
+        const auto u1 = __builtin_amdgcn_raw_buffer_load_b128(r, off + 16u, 0, AUX);
+        __builtin_memcpy(out, &u0, 16);
+        __builtin_memcpy(reinterpret_cast<char*>(out) + 16, &u1, 16);
+    }
+}
+
 __device__ __forceinline__ float shfl_up1(float v) { return __shfl_up(v, 1, kWave); }
 __device__ __forceinline__ float shfl_dn1(float v) { return __shfl_down(v, 1, kWave); }
 __device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, kWave); }
@@ -373,7 +412,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
     R hr[NSR][VX], hc[NSCA][2 * VX];  // rhat centre
     R pr[NSR][VX], pc[NSCA][2 * VX];  // x_{k-1} centre, or finished iterate
     const int prevk = a.prevk;
-    const R* __restrict__ pbase = FINAL ? a.prev : a.out;
+    const R* __restrict__ pbase = a.prev;
 
     auto load_centre = [&](int y) {
         const unsigned pt = static_cast<unsigned>(y) * static_cast<unsigned>(nx) + static_cast<unsigned>(xb);
@@ -388,7 +427,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
                 if (prevk == SRC_BUF && ok) ldc<R, VX>(pbase + o, pr[s]);
                 if (prevk == SRC_RHAT && ok) ldc<R, VX>(a.rhat + o, pr[s]);
             } else if (FINAL && ok) {
-                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : (a.fbuf[s] ? a.buf1 : a.buf0);
+                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : a.bufs[a.fbuf[s]];
                 ldc<R, VX>(f + o, pr[s]);
             }
         }
@@ -403,7 +442,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
                 if (prevk == SRC_BUF && ok) ldc<R, 2 * VX>(pbase + o, pc[c]);
                 if (prevk == SRC_RHAT && ok) ldc<R, 2 * VX>(a.rhat + o, pc[c]);
             } else if (FINAL && ok) {
-                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : (a.fbuf[s] ? a.buf1 : a.buf0);
+                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : a.bufs[a.fbuf[s]];
                 ldc<R, 2 * VX>(f + o, pc[c]);
             }
         }

@@ -28,6 +28,7 @@ def test_grouped_sweeps_equal_all_shift_sweeps(ell, precision, nc2):
     ws = api.workspace(api.ac_prec_workspace_size(p, opts))
     r = G.dev(np.random.default_rng(ell).standard_normal(ell * nx * ny))
     out = []
+    api.ac_ctx_set_step_pairs(G.ctx(), 0)  # single steady steps: grouped or all-shift
     try:
         for mode in (0, 1):
             api.ac_ctx_set_shift_groups(G.ctx(), mode)
@@ -36,6 +37,7 @@ def test_grouped_sweeps_equal_all_shift_sweeps(ell, precision, nc2):
             out.append(G.host(z))
     finally:
         api.ac_ctx_set_shift_groups(G.ctx(), -1)
+        api.ac_ctx_set_step_pairs(G.ctx(), 1)
     # float32: another kernel variant may contract operations differently; a few
     # roundings (2^-24) per step, amplified by cond(U* Gamma) = alpha^{-(l-1)/l}
     tol = 1e-14 if precision == L.AC_PREC_FP64 else 8 * 7 * 1e-2 ** (-(ell - 1) / ell) * 2.0 ** -24

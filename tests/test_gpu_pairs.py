@@ -1,0 +1,115 @@
+"""Two steady Chebyshev steps fused into one sweep (temporal blocking of the three-term
+recurrence of Section 3) compute what two single sweeps compute: P_NC^{-1} and the
+shifted solves with and without pairing, on grids whose strips (126 or 62 inner
+columns) and row chunks end ragged, in 1D and 2D, uniform and NC2 budgets (shifts
+finishing at different steps), cold and warm starts, every precision and several
+tilings of the paired sweep; plus the oracle."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import operators as ops
+from oracle import precond as pc
+from paper_2506_03947_amd import api
+from synth import lognormal_kappa
+from tests import gpu_util as G
+
+L = api.L
+pytestmark = pytest.mark.gpu
+
+# (dim, nx, ny, l, p): two strips with a ragged second one; odd nx (one point per lane,
+# seven strips); exactly one 128-column strip; ny below the chunk height; 1D; l = 16
+CASES = [
+    (2, 254, 37, 10, 8),
+    (2, 381, 19, 5, 7),
+    (2, 128, 128, 4, 9),
+    (2, 500, 3, 8, 8),
+    (1, 300, 1, 6, 10),
+    (2, 130, 70, 16, 6),
+]
+# (rows per wave, waves per block, points per lane); 0 = automatic
+TILINGS = [(0, 0, 0), (1, 1, 1), (5, 3, 2), (64, 4, 0)]
+
+
+def _tol(precision, ell, steps):
+    if precision == L.AC_PREC_FP64:
+        return 1e-14
+    # float32: the paired kernel may contract operations differently; a few roundings
+    # (2^-24) per step, amplified by cond(U* Gamma) = alpha^{-(l-1)/l}
+    return 8 * steps * 1e-2 ** (-(ell - 1) / ell) * 2.0 ** -24
+
+
+def _apply(p, opts, r, ws, pairs, tiling=(0, 0, 0)):
+    api.ac_ctx_set_step_pairs(G.ctx(), pairs, *tiling)
+    try:
+        z = G.dev(np.zeros(p.ell * p.n))
+        api.ac_apply_prec(p, opts, r, z, ws)
+        return G.host(z)
+    finally:
+        api.ac_ctx_set_step_pairs(G.ctx(), 1)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}d-{c[1]}x{c[2]}-l{c[3]}" for c in CASES])
+@pytest.mark.parametrize("precision", [L.AC_PREC_FP64, L.AC_PREC_MIXED_FP32K, L.AC_PREC_MIXED_BF16K])
+@pytest.mark.parametrize("nc2", [False, True])
+def test_paired_sweeps_equal_single_sweeps(case, precision, nc2):
+    dim, nx, ny, ell, steps = case
+    kap = lognormal_kappa(nx, ny, 20.0, 6.0, 1.0, seed=nx + ell)
+    p = G.problem(dim, nx, ny, kap, ell, 1e-2)
+    pm = api.ac_alloc_nc2(p, float(steps * ell)) if nc2 else steps
+    opts = api.Opts(precision=precision, p=pm)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    r = G.dev(np.random.default_rng(ell).standard_normal(ell * nx * ny))
+    single = _apply(p, opts, r, ws, 0)
+    tol = _tol(precision, ell, max(np.atleast_1d(pm)))
+    for tiling in TILINGS:
+        paired = _apply(p, opts, r, ws, 1, tiling)
+        assert G.max_rel(paired, single) <= tol, tiling
+    if precision == L.AC_PREC_FP64 and not nc2:
+        A = ops.build_A(dim, nx, ny, kap)
+        lo, hi = api.ac_spectral_bounds(p)
+        ref = pc.apply_prec_nc(A, G.host(r), ell, 1e-2, lo, hi, pm)
+        assert G.rel(paired, ref) < 1e-12
+
+
+@pytest.mark.parametrize("warm", [False, True])
+@pytest.mark.parametrize("steps", [5, 6])
+def test_paired_shifted_solves_in_place(warm, steps):
+    """ac_shifted_cheb leaves the finished iterates in the iterate buffers (x_q in buffer
+    q mod 4) and gathers them: the last steps may be a pair; warm starts pair from the
+    second step on."""
+    nx, ny, ell = 258, 41, 10
+    kap = lognormal_kappa(nx, ny, 20.0, 6.0, 1.0, seed=3)
+    p = G.problem(2, nx, ny, kap, ell, 1e-2)
+    opts = api.Opts(precision=L.AC_PREC_FP64, p=steps)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    rng = np.random.default_rng(steps)
+    cplx = lambda: G.dev(rng.standard_normal(p.n) + 1j * rng.standard_normal(p.n))
+    rhat = api.complex_to_spectral(p, 0, [cplx() for _ in range(p.ns)])
+    x0 = api.complex_to_spectral(p, 0, [cplx() for _ in range(p.ns)]) if warm else None
+    out = []
+    for mode in (0, 1):
+        api.ac_ctx_set_step_pairs(G.ctx(), mode)
+        try:
+            y = torch.zeros_like(rhat)
+            api.ac_shifted_cheb(p, opts, rhat, x0, y, ws)
+            out.append(G.host(y))
+        finally:
+            api.ac_ctx_set_step_pairs(G.ctx(), 1)
+    assert G.max_rel(out[1], out[0]) <= 1e-14
+
+
+def test_paired_sweeps_full_size():
+    """The benchmark's inner solve (2048^2, l = 10, p = 20, complex64 with bf16 kappa):
+    P_NC^{-1} with paired steady sweeps against single sweeps, every element."""
+    nx = ny = 2048
+    ell = 10
+    kap = lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=0)
+    p = G.problem(2, nx, ny, kap, ell, 1e-2)
+    opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=20)
+    ws = api.workspace(api.ac_prec_workspace_size(p, opts))
+    r = G.dev(np.random.default_rng(5).standard_normal(ell * nx * ny))
+    single = _apply(p, opts, r, ws, 0)
+    paired = _apply(p, opts, r, ws, 1)
+    assert G.max_rel(paired, single) <= _tol(L.AC_PREC_MIXED_BF16K, ell, 20)
