@@ -52,6 +52,10 @@ def parse():
                     help="fuse two steady Chebyshev steps per sweep (1) or run single steps (0)")
     ap.add_argument("--pair-tiling", type=int, nargs=3, default=[0, 0, 0], metavar=("ROWS", "WPB", "VX"),
                     help="tiling of the paired sweep (0 = automatic)")
+    ap.add_argument("--step-triples", type=int, default=1, choices=[0, 1],
+                    help="fuse three steady Chebyshev steps per sweep (1) or at most two (0)")
+    ap.add_argument("--triple-tiling", type=int, nargs=3, default=[0, 0, 0], metavar=("ROWS", "WPB", "VX"),
+                    help="tiling of the three-step sweep (0 = automatic)")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp", "blocks", "paper"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
                          "(the launch set used for hardware-counter runs); batch: many uneven problems "
@@ -427,7 +431,7 @@ def kernels_only(a, api, prob, ell, n):
     dst.copy_(src)
     torch.cuda.synchronize()
     out = {"mode": "kernels", "copy_bytes_each_way": src.numel() * 8}
-    for name in ("cheb_step", "cheb_pair"):
+    for name in ("cheb_step", "cheb_pair", "cheb_triple"):
         st = stats[name]
         if st["launches"]:
             avg_ms = st["ms"] / st["launches"]
@@ -523,6 +527,7 @@ def main():
     x = torch.zeros(ell * n, dtype=torch.float64, device=dev)
     ctx = api.ac_ctx_create(0)
     api.ac_ctx_set_step_pairs(ctx, a.step_pairs, *a.pair_tiling)
+    api.ac_ctx_set_step_triples(ctx, a.step_triples, *a.triple_tiling)
     prob = api.ac_problem_create(ctx, 2, nx, ny, kd, ell, alpha)
     mu_lo, mu_hi = api.ac_spectral_bounds(prob)
     if a.mode == "kernels":
@@ -568,37 +573,49 @@ def main():
                     "speedup_mixed_vs_fp64": t64 / t_mixed,
                     "mixed_vs_fp64_solution_rel_diff": diff}
 
-    # Dominant kernel: the paired steady sweep (two Chebyshev steps per launch, one launch
-    # per shift group), else the single steady sweep.  `achieved` counts the unfused
-    # algorithmic bytes of the steps a launch performs (4 vector streams per shift and
-    # step, kappa once per step); the paired sweep itself moves 5 of every 8 of those
-    # vector streams, which `own_min_bytes_per_launch` and `traffic` show.
-    pair = stats_mixed.get("cheb_pair", {"launches": 0})
-    if pair["launches"]:
-        st = pair
-        kname = ("cheb_pair_kernel<float, unsigned short, 2>: two steady shifted-Chebyshev steps fused in one "
-                 "sweep over a shift group (one real + two complex shifts; two launches per pair of steps at l = 10)")
-        traffic = measured_traffic(a, "cheb_pair_2048x2048_l10_traffic.json", ["stencil_pair.hip", "stencil_kernels.h"])
-    else:
-        st = stats_mixed["cheb_step"]
-        kname = ("cheb_sweep_kernel<float, unsigned short, 5, 2, false, false, false>: steady-state shifted "
-                 "Chebyshev sweep over one shift group (two launches per step at l = 10)")
-        traffic = None
+    # Dominant kernel: the steady-sweep class with the most time per solve (fused blocks of
+    # three steps, pairs, or single sweeps).  `achieved` counts the unfused algorithmic
+    # bytes of the steps a launch performs (4 vector streams per shift and step, kappa
+    # once per step); a fused block of d steps itself moves 5 of every 4d of those vector
+    # streams, which `own_min_bytes_per_launch` and `traffic` show.
+    kinds = {
+        "cheb_triple": (3, "cheb_triple_kernel<float, unsigned short, 2, {1,2}, {2,1}>: three steady shifted-Chebyshev "
+                           "steps fused in one sweep, one launch per complex shift and per two real shifts (five "
+                           "launches per block at l = 10)", "cheb_triple_2048x2048_l10_traffic.json",
+                        ["stencil_triple.hip", "stencil_kernels.h"]),
+        "cheb_pair": (2, "cheb_pair_kernel<float, unsigned short, 2>: two steady shifted-Chebyshev steps fused in one "
+                         "sweep over a shift group (one real + two complex shifts)", None, None),
+        "cheb_step": (1, "cheb_sweep_kernel<float, unsigned short, 5, 2, false, false, false>: steady-state shifted "
+                         "Chebyshev sweep over one shift group", None, None),
+    }
+    dom = max((k for k in kinds if stats_mixed[k]["launches"]), key=lambda k: stats_mixed[k]["ms"])
+    depth, kname, tfile, tsrc = kinds[dom]
+    st = stats_mixed[dom]
+    traffic = measured_traffic(a, tfile, tsrc) if tfile else None
     avg_ms = st["ms"] / max(st["launches"], 1)
     bytes_per_launch = st["bytes"] / max(st["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     roofline = {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": bytes_per_launch,
-                "launches": st["launches"]}
-    if pair["launches"]:
-        kap_b = 2.0  # bf16 kappa
-        per_shift = (bytes_per_launch / n - 2 * kap_b) / 8.0  # bytes of one stream, summed over the group
-        own = n * (5 * per_shift + kap_b)
+                "launches": st["launches"], "steps_per_launch": depth}
+    if depth > 1:
+        # the block's own minimum: 5 vector streams of every computing shift once (complex64
+        # 8 B, real 4 B per point) and kappa (bf16) once per launch, averaged over the
+        # block's launches (pairs: one per group of one real + two complex shifts; triples:
+        # one per complex shift and per two real shifts)
+        nsr = 2 if ell % 2 == 0 else 1
+        nsc = (ell - nsr) // 2
+        per_stream = 4.0 * nsr + 8.0 * nsc
+        nl = max(nsr, (nsc + 1) // 2) if depth == 2 else nsc + (nsr + 1) // 2
+        own = n * (5 * per_stream + nl * 2.0) / nl
         roofline["own_min_bytes_per_launch"] = own
         roofline["own_min_GBps"] = own / (avg_ms * 1e-3) / 1e9
         if traffic:
             roofline["traffic_GBps"] = traffic / (avg_ms * 1e-3) / 1e9
+        roofline["note"] = (f"a launch performs {depth} steps while moving 5 of their {4 * depth} unfused vector "
+                            "streams, so achieved (unfused algorithmic bytes / time) can exceed the HBM peak; "
+                            "traffic / traffic_GBps are the measured HBM bytes and rate")
 
     cpu = None
     if not a.no_cpu_baseline:

@@ -168,7 +168,8 @@ typedef enum {
     AC_K_EXACT = 7,      /* AC_INNER_EXACT: sine transforms, tridiagonal solves, inverse time-DFT */
     AC_K_SADDLE = 8,     /* AC_INNER_SP: MINRES / CG with multigrid V-cycles (whole inner solve) */
     AC_K_CHEB_PAIR = 9,  /* two steady Chebyshev sweeps fused into one (per shift group) */
-    AC_K_COUNT = 10
+    AC_K_CHEB_TRIPLE = 10, /* three steady Chebyshev sweeps fused into one (per shift group) */
+    AC_K_COUNT = 11
 } ac_kernel_class;
 
 /* ---- status ------------------------------------------------------------- */
@@ -332,12 +333,24 @@ int ac_ctx_set_shift_groups(ac_ctx* ctx, int mode);
  * two complex shifts) that reads x_k, x_{k-1} and rhat once and writes x_{k+1} and
  * x_{k+2}; mode 0 runs single steps.  The iterates are those of single steps (float64:
  * identical; float32: up to contraction).  rows_per_wave, waves_per_block (1..4) and
- * points_per_lane (1..2) set the paired sweep's tiling, 0 = automatic (8 rows, 1
- * wave, 2 points per lane in float32 on even grids at least 128 wide, else 1).  Pairs
+ * points_per_lane (1..2) set the paired sweep's tiling, 0 = automatic (rows for about
+ * one round of waves, 4..32; 4 waves; 2 points per lane in float32 on even grids at
+ * least 128 wide, else 1).  Pairs
  * are used while every spectral buffer is below 2^31 bytes.  Profiling (AC_K_CHEB_PAIR)
  * counts the two steps' unfused algorithmic bytes.
  * Batched solves (ac_batch_solve) run single steps. */
 int ac_ctx_set_step_pairs(ac_ctx* ctx, int mode, int rows_per_wave, int waves_per_block, int points_per_lane);
+
+/* Three steady Chebyshev steps per sweep: mode 1 (default) fuses runs of steady steps
+ * in which the same shifts compute into blocks of three (a remainder of two as a pair,
+ * of one as a single step), where pairs are allowed (mode 1 of ac_ctx_set_step_pairs,
+ * Dirichlet grids, buffers below 2^31 bytes).  A block reads x_k, x_{k-1} and rhat
+ * once and writes x_{k+2} and x_{k+3} (x_{k+1} stays in registers), one launch per
+ * complex shift and per two real shifts.  The iterates are those of single steps
+ * (float64: identical; float32: up to contraction).  Tiling arguments as for pairs
+ * (automatic: rows for about one round of waves, 4 waves per block).  Profiling
+ * (AC_K_CHEB_TRIPLE) counts the three steps' unfused algorithmic bytes. */
+int ac_ctx_set_step_triples(ac_ctx* ctx, int mode, int rows_per_wave, int waves_per_block, int points_per_lane);
 
 /* ---- tiling ----------------------------------------------------------------
  * Sweep tiling of one problem (overrides the context's ac_ctx_set_tiling; 0 keeps

@@ -47,9 +47,10 @@ AC_K_CHEB_FIRST = 6
 AC_K_EXACT = 7
 AC_K_SADDLE = 8
 AC_K_CHEB_PAIR = 9
-AC_K_COUNT = 10
+AC_K_CHEB_TRIPLE = 10
+AC_K_COUNT = 11
 KERNEL_CLASS_NAMES = ["tdft_fwd", "cheb_step", "cheb_final", "apply_calA", "krylov", "cnn", "cheb_first", "exact",
-                      "saddle", "cheb_pair"]
+                      "saddle", "cheb_pair", "cheb_triple"]
 
 
 class ac_grid(C.Structure):
@@ -140,6 +141,7 @@ SIGNATURES = {
     "ac_problem_set_tiling": (_I, [_VP, _I, _I, _I]),
     "ac_ctx_set_shift_groups": (_I, [_VP, _I]),
     "ac_ctx_set_step_pairs": (_I, [_VP, _I, _I, _I, _I]),
+    "ac_ctx_set_step_triples": (_I, [_VP, _I, _I, _I, _I]),
     "ac_tune_tiling": (_I, [_VP, _I, C.c_char_p, _VP, _SZ, C.POINTER(C.c_int), C.POINTER(_D)]),
     "ac_cnn_adam_step": (_I, [_VP, _D, _D, _D, _D]),
     "ac_cnn_make_inputs": (_I, [_VP, _VP, _I, _VP, _VP, C.POINTER(_D)]),

@@ -275,6 +275,12 @@ def ac_ctx_set_shift_groups(ctx: Ctx, mode: int) -> None:
     check(L.load().ac_ctx_set_shift_groups(ctx.h, int(mode)), "ac_ctx_set_shift_groups")
 
 
+def ac_ctx_set_step_triples(ctx: Ctx, mode: int, rows_per_wave: int = 0, waves_per_block: int = 0,
+                            points_per_lane: int = 0) -> None:
+    check(L.load().ac_ctx_set_step_triples(ctx.h, int(mode), int(rows_per_wave), int(waves_per_block),
+                                           int(points_per_lane)), "ac_ctx_set_step_triples")
+
+
 def ac_ctx_set_step_pairs(ctx: Ctx, mode: int, rows_per_wave: int = 0, waves_per_block: int = 0,
                           points_per_lane: int = 0) -> None:
     check(L.load().ac_ctx_set_step_pairs(ctx.h, int(mode), int(rows_per_wave), int(waves_per_block),

@@ -91,6 +91,26 @@ struct PairArgs {
     unsigned bytes;      // bytes of each spectral buffer (below 2^31)
 };
 
+// Three consecutive steady Chebyshev steps (x_{k+1} kept in registers, x_{k+2} and
+// x_{k+3} written) in one sweep, for one group: up to two real shift slots (kind 0) or
+// one complex slot (kind 1).  Strips of 64*vx computed columns advance by 64*vx - 4.
+template <typename R>
+struct TripleArgs {
+    Geom g;
+    Tiling t;
+    const void* kappa;
+    ShiftCoef<R> cf[3];  // steps k, k+1, k+2 (slots 0, 1)
+    int comp[2];         // slot computes (else skipped)
+    unsigned soff[2];    // slot offset (elements of R) inside every spectral buffer
+    const R* rhat;
+    const R* cur;        // x_k
+    const R* prev;       // x_{k-1}
+    R* outz;             // x_{k+2}
+    R* outw;             // x_{k+3}
+    unsigned bytes;      // bytes of each spectral buffer (below 2^31)
+    int kind;            // 0: real slots, 1: one complex slot
+};
+
 struct FwdArgs {
     long long n;
     double gam[kMaxEll];              // input scale * alpha^{k/l}
@@ -150,6 +170,8 @@ hipError_t launch_cheb_step(int ell, int prec, int curk, const void* args, hipSt
 hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipStream_t s);
 // Two steady steps per sweep (PairArgs<double> for prec 0, else PairArgs<float>).
 hipError_t launch_cheb_pair(int prec, const void* args, hipStream_t s);
+// Three steady steps per sweep (TripleArgs<double> for prec 0, else TripleArgs<float>).
+hipError_t launch_cheb_triple(int prec, const void* args, hipStream_t s);
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);

@@ -96,6 +96,8 @@ struct ac_ctx {
     // two steady Chebyshev steps per sweep: 0 off, 1 on (Dirichlet grids); rows per
     // wave, points per lane, waves per block of the paired sweep (0 = automatic)
     int pairs = 1, pair_h = 0, pair_vx = 0, pair_wpb = 0;
+    // three steady steps per sweep: 0 off, 1 on (where pairs are allowed); tiling as pairs
+    int triples = 1, triple_h = 0, triple_vx = 0, triple_wpb = 0;
     // dense sine transforms of the exact inner solve (workspace set per call)
     rocblas_handle blas = nullptr;
     // launch-bound inner solves (P_SP) are captured on this stream and replayed as graphs
@@ -261,25 +263,43 @@ Tiling sweep_tiling(const ac_problem* p) {
                        p->tile_wpb ? p->tile_wpb : p->ctx->tile_wpb);
 }
 
-// Paired sweep (two steps): strips of 64*vx computed columns at a stride of
-// 64*vx - 2; two points per lane on even grids at least 128 wide in float32, one in
-// float64 (register budget).
-Tiling pair_tiling(const ac_problem* p, int prec) {
-    const ac_ctx* c = p->ctx;
+// Tiling of a fused block of `depth` steps (2 or 3): strips of 64*vx computed columns at
+// a stride of 64*vx - 2*(depth-1); two points per lane on even grids at least 128 wide
+// in float32, one in float64 (register budget); automatic height for about one round of
+// waves at `occ` waves per SIMD.
+Tiling block_tiling(const ac_problem* p, int prec, int depth, int h_pref, int wpb_pref, int vx_pref, int occ) {
     const Geom& g = p->g;
     Tiling t{};
-    int vx = c->pair_vx > 0 ? c->pair_vx : (prec == AC_PREC_FP64 ? 1 : 2);
+    int vx = vx_pref > 0 ? vx_pref : (prec == AC_PREC_FP64 ? 1 : 2);
     if (g.nx % 2 != 0 || g.nx < 128) vx = 1;
     t.vx = vx;
-    t.h = c->pair_h > 0 ? c->pair_h : 8;
+    t.wpb = wpb_pref > 0 ? wpb_pref : 4;
+    const int stride = ac::kWave * vx - 2 * (depth - 1);
+    const int inner = g.nx - (depth - 1);  // columns past the first strip's low ghost edge
+    t.nsx = (inner + stride - 1) / stride;
+    const long long slots = static_cast<long long>(occ) * 1024;
+    const int h = static_cast<int>((static_cast<long long>(t.nsx) * g.ny + slots - 1) / slots);
+    t.h = h_pref > 0 ? h_pref : std::min(32, std::max(4, h));
     if (t.h > g.ny) t.h = g.ny;
-    t.wpb = c->pair_wpb > 0 ? c->pair_wpb : 1;
-    const int stride = ac::kWave * vx - 2;
-    t.nsx = (g.nx - 1 + stride - 1) / stride;
     t.ncy = (g.ny + t.h - 1) / t.h;
     t.tiles = static_cast<long long>(t.nsx) * t.ncy;
     t.blocks = static_cast<int>((t.tiles + t.wpb - 1) / t.wpb);
     return t;
+}
+
+Tiling triple_tiling(const ac_problem* p, int prec) {
+    const ac_ctx* c = p->ctx;
+    // (automatic height as for pairs: 12 rows at 2048^2, 42 us per launch against 44 us
+    // at 9 rows and 47-54 us at 6, 8 or 16 rows)
+    return block_tiling(p, prec, 3, c->triple_h, c->triple_wpb, c->triple_vx, 3);
+}
+
+// (the automatic height of the paired sweep, about one round of waves at three per
+// SIMD, measured best at 2048^2: 12 rows, 96 us per launch against 100-103 us at 8 rows
+// and 110 us at 16)
+Tiling pair_tiling(const ac_problem* p, int prec) {
+    const ac_ctx* c = p->ctx;
+    return block_tiling(p, prec, 2, c->pair_h, c->pair_wpb, c->pair_vx, 3);
 }
 
 template <class A>
@@ -527,7 +547,25 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         }
     };
     const int nb = (buf[2] && buf[3]) ? 4 : 2;
-    auto bidx = [&](int q) { return ((q % nb) + nb) % nb; };
+    // bq[q]: buffer holding x_q (-1: not stored).  A single step writes x_{k+1} over
+    // x_{k-1} when that is in a buffer (each lane reads its points before writing them),
+    // else into a buffer not holding x_k; a fused block writes its two outputs into the
+    // two buffers it does not read (neighbouring waves read x_k and x_{k-1} on halos).
+    std::vector<int> bq(static_cast<size_t>(std::max(pmax, 1)) + 4, -1);
+    if (warm) bq[0] = 0;
+    auto free_bufs = [&](int k, int* out, int want) {
+        int got = 0;
+        const int b0 = k >= 0 ? bq[k] : -1, b1 = k >= 1 ? bq[k - 1] : -1;
+        for (int i = 0; i < nb && got < want; ++i)
+            if (i != b0 && i != b1) out[got++] = i;
+        return got == want;
+    };
+    auto single_out = [&](int k) {
+        if (k >= 1 && bq[k - 1] >= 0) return bq[k - 1];
+        int f[1];
+        free_bufs(k, f, 1);
+        return f[0];
+    };
     // location of a finished iterate x_q
     auto fin_src = [&](int q, int& kind, int& bi) {
         if (!warm && q == 1) {
@@ -535,7 +573,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             bi = -1;
         } else {
             kind = ac::SRC_BUF;
-            bi = bidx(q);
+            bi = bq[q];
         }
     };
 
@@ -634,10 +672,14 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         pa.t = pair_tiling(p, prec);
         pa.kappa = kap;
         pa.rhat = reinterpret_cast<const R*>(rhat);
-        pa.cur = reinterpret_cast<const R*>(buf[bidx(k)]);
-        pa.prev = reinterpret_cast<const R*>(buf[bidx(k - 1)]);
-        pa.out1 = reinterpret_cast<R*>(buf[bidx(k + 1)]);
-        pa.out2 = reinterpret_cast<R*>(buf[bidx(k + 2)]);
+        int f[2];
+        if (!free_bufs(k, f, 2)) return hipErrorInvalidValue;
+        bq[k + 1] = f[0];
+        bq[k + 2] = f[1];
+        pa.cur = reinterpret_cast<const R*>(buf[bq[k]]);
+        pa.prev = reinterpret_cast<const R*>(buf[bq[k - 1]]);
+        pa.out1 = reinterpret_cast<R*>(buf[bq[k + 1]]);
+        pa.out2 = reinterpret_cast<R*>(buf[bq[k + 2]]);
         pa.bytes = static_cast<unsigned>(spec_bytes);
         bytes = 0.0;
         const int ngroups = std::max(p->nsr, (p->nsc + 1) / 2);
@@ -667,18 +709,102 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         bytes = (bytes + 2.0 * ksz) * static_cast<double>(p->g.n);
         return hipSuccess;
     };
-    // consecutive steady-state sweeps (single or paired) share one event pair
-    std::unique_ptr<ProfScope> steady, paired;
-    for (int k = k_first; k <= k_last; ++k) {
-        bool pair = can_pair && steady_step(k) && steady_step(k + 1);
-        for (int s = 0; pair && s < ns; ++s)
-            if ((ps[s] >= k + 1) != (ps[s] >= k + 2)) pair = false;
-        if (pair) {
-            steady.reset();
-            if (!paired) {
-                paired = std::make_unique<ProfScope>(p->ctx, AC_K_CHEB_PAIR, 0.0);
-                paired->launches = 0;
+    // Three steps per sweep: one launch per complex shift, one per (up to) two real shifts.
+    const bool can_triple = can_pair && p->ctx->triples == 1 && p->g.nx >= 4;
+    auto launch_triple = [&](int k, double& bytes) -> hipError_t {
+        ac::TripleArgs<R> ta{};
+        ta.g = p->g;
+        ta.t = triple_tiling(p, prec);
+        ta.kappa = kap;
+        ta.rhat = reinterpret_cast<const R*>(rhat);
+        int f[2];
+        if (!free_bufs(k, f, 2)) return hipErrorInvalidValue;
+        bq[k + 1] = -1;  // x_{k+1} stays in registers
+        bq[k + 2] = f[0];
+        bq[k + 3] = f[1];
+        ta.cur = reinterpret_cast<const R*>(buf[bq[k]]);
+        ta.prev = reinterpret_cast<const R*>(buf[bq[k - 1]]);
+        ta.outz = reinterpret_cast<R*>(buf[bq[k + 2]]);
+        ta.outw = reinterpret_cast<R*>(buf[bq[k + 3]]);
+        ta.bytes = static_cast<unsigned>(spec_bytes);
+        bytes = 0.0;
+        auto go = [&](int kind, const int* slots, int count) -> hipError_t {
+            ac::TripleArgs<R> g = ta;
+            g.kind = kind;
+            bool anyc = false;
+            for (int j = 0; j < 2; ++j) {
+                g.comp[j] = 0;
+                g.soff[j] = 0;
+                const int sl = j < count ? slots[j] : -1;
+                if (sl < 0 || ps[sl] < k + 1) continue;
+                g.comp[j] = 1;
+                g.soff[j] = static_cast<unsigned>(off[slot_to_m(p, sl)]);
+                for (int t = 0; t < 3; ++t) fill_cf(g.cf[t], j, cs[sl], k + t);
+                bytes += 12.0 * (slot_is_real(p, sl) ? esz_r : esz_c);  // three steps of 4 streams
+                anyc = true;
             }
+            if (!anyc) return hipSuccess;
+            const hipError_t e = ac::launch_cheb_triple(prec, &g, p->ctx->stream);
+            if (e == hipSuccess) ++launched;
+            return e;
+        };
+        for (int r = 0; r < p->nsr; r += 2) {
+            const int sl[2] = {r, r + 1 < p->nsr ? r + 1 : -1};
+            const hipError_t e = go(0, sl, 2);
+            if (e != hipSuccess) return e;
+        }
+        for (int c = 0; c < p->nsc; ++c) {
+            const int sl[1] = {p->nsr + c};
+            const hipError_t e = go(1, sl, 1);
+            if (e != hipSuccess) return e;
+        }
+        // unfused algorithmic bytes of the three steps (kappa once per step); the block
+        // itself moves 5 of the 12 vector streams
+        bytes = (bytes + 3.0 * ksz) * static_cast<double>(p->g.n);
+        return hipSuccess;
+    };
+    // length of the run of steady steps from k in which the same shifts compute
+    auto steady_run = [&](int k) {
+        int n = 0;
+        while (steady_step(k + n)) {
+            bool same = true;
+            for (int s = 0; s < ns; ++s)
+                if ((ps[s] >= k + 1) != (ps[s] >= k + n + 1)) same = false;
+            if (!same) break;
+            ++n;
+        }
+        return n;
+    };
+    // consecutive steady-state sweeps of one kind share one event pair
+    std::unique_ptr<ProfScope> steady, paired, tripled;
+    auto block_scope = [&](std::unique_ptr<ProfScope>& sc, int cls) {
+        if (!sc) {
+            sc = std::make_unique<ProfScope>(p->ctx, cls, 0.0);
+            sc->launches = 0;
+        }
+    };
+    for (int k = k_first; k <= k_last; ++k) {
+        // block size: greedy triples, then a pair or a single step (at 2048^2, l = 10 per
+        // application: triple 211 us, pair 193 us, single 116 us, so a remainder of one
+        // step is cheaper as a single than as two pairs replacing a triple)
+        const int run = (can_pair && steady_step(k)) ? steady_run(k) : 0;
+        const int blk = (can_triple && run >= 3) ? 3 : (run >= 2 ? 2 : 1);
+        if (blk == 3) {
+            steady.reset();
+            paired.reset();
+            block_scope(tripled, AC_K_CHEB_TRIPLE);
+            launched = 0;
+            double bytes = 0.0;
+            AC_HIP(launch_triple(k, bytes));
+            tripled->bytes += bytes;
+            tripled->launches += launched;
+            k += 2;  // x_{k+3} done
+            continue;
+        }
+        if (blk == 2) {
+            steady.reset();
+            tripled.reset();
+            block_scope(paired, AC_K_CHEB_PAIR);
             launched = 0;
             double bytes = 0.0;
             AC_HIP(launch_pair(k, bytes));
@@ -688,15 +814,18 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             continue;
         }
         paired.reset();
+        tripled.reset();
         const bool final = fuse && (k == k_last);
         ac::SweepArgs<R> a{};
         base_args(a);
         int curk, prevk;
         kinds(k, curk, prevk);
         a.prevk = prevk;
-        a.cur = reinterpret_cast<const R*>(buf[bidx(k)]);
-        a.out = reinterpret_cast<R*>(buf[bidx(k + 1)]);
-        a.prev = reinterpret_cast<const R*>(buf[bidx(k - 1)]);
+        if (curk == ac::SRC_BUF && bq[k] < 0) return fail(AC_ERR_UNSUPPORTED, "internal: iterate x_k not stored");
+        bq[k + 1] = single_out(k);
+        a.cur = reinterpret_cast<const R*>(buf[bq[k] >= 0 ? bq[k] : 0]);
+        a.out = reinterpret_cast<R*>(buf[bq[k + 1]]);
+        a.prev = reinterpret_cast<const R*>(buf[k >= 1 && bq[k - 1] >= 0 ? bq[k - 1] : bq[k + 1]]);
         double bytes = 0.0;
         bool anyc = false;
         for (int s = 0; s < ns; ++s) {
@@ -737,6 +866,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     }
     steady.reset();
     paired.reset();
+    tripled.reset();
     if (fuse && k_last < k_first) {
         // nothing to iterate (cold start, every p = 1): x_1 = rhat/theta everywhere
         ac::SweepArgs<R> a{};
@@ -2431,6 +2561,19 @@ int ac_ctx_set_shift_groups(ac_ctx* c, int mode) {
     if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
     if (mode < -1 || mode > 1) return fail(AC_ERR_ARG, "mode must be -1, 0 or 1");
     c->shift_groups = mode;
+    return AC_OK;
+}
+
+int ac_ctx_set_step_triples(ac_ctx* c, int mode, int rows_per_wave, int waves_per_block, int points_per_lane) {
+    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
+    if (mode < 0 || mode > 1) return fail(AC_ERR_ARG, "mode must be 0 or 1");
+    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
+    if (waves_per_block < 0 || waves_per_block > 4) return fail(AC_ERR_ARG, "waves_per_block must be 0..4");
+    if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
+    c->triples = mode;
+    c->triple_h = rows_per_wave;
+    c->triple_wpb = waves_per_block;
+    c->triple_vx = points_per_lane;
     return AC_OK;
 }
 

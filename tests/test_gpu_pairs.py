@@ -1,9 +1,9 @@
-"""Two steady Chebyshev steps fused into one sweep (temporal blocking of the three-term
-recurrence of Section 3) compute what two single sweeps compute: P_NC^{-1} and the
-shifted solves with and without pairing, on grids whose strips (126 or 62 inner
-columns) and row chunks end ragged, in 1D and 2D, uniform and NC2 budgets (shifts
-finishing at different steps), cold and warm starts, every precision and several
-tilings of the paired sweep; plus the oracle."""
+"""Steady Chebyshev steps fused into blocks of two or three per sweep (temporal blocking
+of the three-term recurrence of Section 3) compute what single sweeps compute: P_NC^{-1}
+and the shifted solves with blocks of three and two, of two only, and single steps, on
+grids whose strips (126/124 or 62/60 inner columns) and row chunks end ragged, in 1D and
+2D, uniform and NC2 budgets (shifts finishing at different steps), cold and warm starts,
+every precision and several tilings of the fused sweeps; plus the oracle."""
 
 import numpy as np
 import pytest
@@ -40,14 +40,16 @@ def _tol(precision, ell, steps):
     return 8 * steps * 1e-2 ** (-(ell - 1) / ell) * 2.0 ** -24
 
 
-def _apply(p, opts, r, ws, pairs, tiling=(0, 0, 0)):
+def _apply(p, opts, r, ws, pairs, triples=1, tiling=(0, 0, 0)):
     api.ac_ctx_set_step_pairs(G.ctx(), pairs, *tiling)
+    api.ac_ctx_set_step_triples(G.ctx(), triples, *tiling)
     try:
         z = G.dev(np.zeros(p.ell * p.n))
         api.ac_apply_prec(p, opts, r, z, ws)
         return G.host(z)
     finally:
         api.ac_ctx_set_step_pairs(G.ctx(), 1)
+        api.ac_ctx_set_step_triples(G.ctx(), 1)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[f"{c[0]}d-{c[1]}x{c[2]}-l{c[3]}" for c in CASES])
@@ -63,8 +65,10 @@ def test_paired_sweeps_equal_single_sweeps(case, precision, nc2):
     r = G.dev(np.random.default_rng(ell).standard_normal(ell * nx * ny))
     single = _apply(p, opts, r, ws, 0)
     tol = _tol(precision, ell, max(np.atleast_1d(pm)))
+    pairs_only = _apply(p, opts, r, ws, 1, 0)
+    assert G.max_rel(pairs_only, single) <= tol
     for tiling in TILINGS:
-        paired = _apply(p, opts, r, ws, 1, tiling)
+        paired = _apply(p, opts, r, ws, 1, 1, tiling)
         assert G.max_rel(paired, single) <= tol, tiling
     if precision == L.AC_PREC_FP64 and not nc2:
         A = ops.build_A(dim, nx, ny, kap)
@@ -74,11 +78,10 @@ def test_paired_sweeps_equal_single_sweeps(case, precision, nc2):
 
 
 @pytest.mark.parametrize("warm", [False, True])
-@pytest.mark.parametrize("steps", [5, 6])
+@pytest.mark.parametrize("steps", [5, 6, 7, 9])
 def test_paired_shifted_solves_in_place(warm, steps):
-    """ac_shifted_cheb leaves the finished iterates in the iterate buffers (x_q in buffer
-    q mod 4) and gathers them: the last steps may be a pair; warm starts pair from the
-    second step on."""
+    """ac_shifted_cheb leaves the finished iterates in the iterate buffers and gathers
+    them: the last steps may be a fused block; warm starts fuse from the second step on."""
     nx, ny, ell = 258, 41, 10
     kap = lognormal_kappa(nx, ny, 20.0, 6.0, 1.0, seed=3)
     p = G.problem(2, nx, ny, kap, ell, 1e-2)
@@ -89,20 +92,24 @@ def test_paired_shifted_solves_in_place(warm, steps):
     rhat = api.complex_to_spectral(p, 0, [cplx() for _ in range(p.ns)])
     x0 = api.complex_to_spectral(p, 0, [cplx() for _ in range(p.ns)]) if warm else None
     out = []
-    for mode in (0, 1):
-        api.ac_ctx_set_step_pairs(G.ctx(), mode)
+    for pairs, triples in ((0, 0), (1, 0), (1, 1)):
+        api.ac_ctx_set_step_pairs(G.ctx(), pairs)
+        api.ac_ctx_set_step_triples(G.ctx(), triples)
         try:
             y = torch.zeros_like(rhat)
             api.ac_shifted_cheb(p, opts, rhat, x0, y, ws)
             out.append(G.host(y))
         finally:
             api.ac_ctx_set_step_pairs(G.ctx(), 1)
+            api.ac_ctx_set_step_triples(G.ctx(), 1)
     assert G.max_rel(out[1], out[0]) <= 1e-14
+    assert G.max_rel(out[2], out[0]) <= 1e-14
 
 
 def test_paired_sweeps_full_size():
     """The benchmark's inner solve (2048^2, l = 10, p = 20, complex64 with bf16 kappa):
-    P_NC^{-1} with paired steady sweeps against single sweeps, every element."""
+    P_NC^{-1} with fused steady sweeps (pairs only; triples and pairs) against single
+    sweeps, every element."""
     nx = ny = 2048
     ell = 10
     kap = lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=0)
@@ -111,5 +118,6 @@ def test_paired_sweeps_full_size():
     ws = api.workspace(api.ac_prec_workspace_size(p, opts))
     r = G.dev(np.random.default_rng(5).standard_normal(ell * nx * ny))
     single = _apply(p, opts, r, ws, 0)
-    paired = _apply(p, opts, r, ws, 1)
-    assert G.max_rel(paired, single) <= _tol(L.AC_PREC_MIXED_BF16K, ell, 20)
+    for triples in (0, 1):
+        fused = _apply(p, opts, r, ws, 1, triples)
+        assert G.max_rel(fused, single) <= _tol(L.AC_PREC_MIXED_BF16K, ell, 20), triples
