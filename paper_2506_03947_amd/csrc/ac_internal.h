@@ -109,6 +109,7 @@ struct TripleArgs {
     R* outw;             // x_{k+3}
     unsigned bytes;      // bytes of each spectral buffer (below 2^31)
     int kind;            // 0: real slots, 1: one complex slot
+    int first;           // steps 1..3 from a zero guess: x_1 = rhat / theta (never stored), x_0 = 0
 };
 
 struct FwdArgs {

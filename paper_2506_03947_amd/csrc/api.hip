@@ -711,19 +711,22 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     };
     // Three steps per sweep: one launch per complex shift, one per (up to) two real shifts.
     const bool can_triple = can_pair && p->ctx->triples == 1 && p->g.nx >= 4;
-    auto launch_triple = [&](int k, double& bytes) -> hipError_t {
+    // first: steps 1..3 from a zero guess (x_1 = rhat/theta and x_0 = 0 never stored)
+    auto launch_triple = [&](int k, double& bytes, bool first) -> hipError_t {
         ac::TripleArgs<R> ta{};
         ta.g = p->g;
         ta.t = triple_tiling(p, prec);
         ta.kappa = kap;
         ta.rhat = reinterpret_cast<const R*>(rhat);
+        ta.first = first ? 1 : 0;
         int f[2];
         if (!free_bufs(k, f, 2)) return hipErrorInvalidValue;
         bq[k + 1] = -1;  // x_{k+1} stays in registers
         bq[k + 2] = f[0];
         bq[k + 3] = f[1];
-        ta.cur = reinterpret_cast<const R*>(buf[bq[k]]);
-        ta.prev = reinterpret_cast<const R*>(buf[bq[k - 1]]);
+        // (first: neither is read; any valid pointer)
+        ta.cur = reinterpret_cast<const R*>(buf[first ? f[0] : bq[k]]);
+        ta.prev = reinterpret_cast<const R*>(buf[first ? f[0] : bq[k - 1]]);
         ta.outz = reinterpret_cast<R*>(buf[bq[k + 2]]);
         ta.outw = reinterpret_cast<R*>(buf[bq[k + 3]]);
         ta.bytes = static_cast<unsigned>(spec_bytes);
@@ -740,7 +743,8 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 g.comp[j] = 1;
                 g.soff[j] = static_cast<unsigned>(off[slot_to_m(p, sl)]);
                 for (int t = 0; t < 3; ++t) fill_cf(g.cf[t], j, cs[sl], k + t);
-                bytes += 12.0 * (slot_is_real(p, sl) ? esz_r : esz_c);  // three steps of 4 streams
+                // unfused streams of the three steps: 4 each; from a zero guess 2 + 3 + 4
+                bytes += (first ? 9.0 : 12.0) * (slot_is_real(p, sl) ? esz_r : esz_c);
                 anyc = true;
             }
             if (!anyc) return hipSuccess;
@@ -784,6 +788,23 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         }
     };
     for (int k = k_first; k <= k_last; ++k) {
+        // the first three steps from a zero guess as one block, if the same shifts compute
+        // in all three and none of them is the fused last sweep
+        if (can_triple && !warm && k == 1 && 3 <= k_last && !(fuse && 3 == k_last)) {
+            bool same = true;
+            for (int s = 0; s < ns; ++s)
+                if ((ps[s] >= 2) != (ps[s] >= 4)) same = false;
+            if (same) {
+                launched = 0;
+                double bytes = 0.0;
+                ProfScope ps_(p->ctx, AC_K_CHEB_FIRST, 0.0);
+                AC_HIP(launch_triple(k, bytes, true));
+                ps_.bytes = bytes;
+                ps_.launches = launched;
+                k += 2;  // x_4 done
+                continue;
+            }
+        }
         // block size: greedy triples, then a pair or a single step (at 2048^2, l = 10 per
         // application: triple 211 us, pair 193 us, single 116 us, so a remainder of one
         // step is cheaper as a single than as two pairs replacing a triple)
@@ -795,7 +816,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             block_scope(tripled, AC_K_CHEB_TRIPLE);
             launched = 0;
             double bytes = 0.0;
-            AC_HIP(launch_triple(k, bytes));
+            AC_HIP(launch_triple(k, bytes, false));
             tripled->bytes += bytes;
             tripled->launches += launched;
             k += 2;  // x_{k+3} done

@@ -37,6 +37,21 @@ __device__ __forceinline__ D2 load2(const double* p, long long e, long long len)
     }
     return r;
 }
+// Same, zero past the end (the second element of an unrolled pair of iterations).
+__device__ __forceinline__ D2 load2z(const double* p, long long e, long long len) {
+    if (e < len) return load2(p, e, len);
+    return D2{0.0, 0.0};
+}
+// Cached load for an operand that every wave of a block reads (the multi-dot's target
+// and newest basis vector): the block's other waves then hit L2 instead of HBM.
+__device__ __forceinline__ D2 load2c(const double* p, long long e, long long len) {
+    if (e + 1 < len) {
+        const D2v t = *reinterpret_cast<const D2v*>(p + e);
+        return D2{t[0], t[1]};
+    }
+    if (e < len) return D2{p[e], 0.0};
+    return D2{0.0, 0.0};
+}
 __device__ __forceinline__ void store2(double* p, long long e, long long len, D2 v) {
     if (e + 1 < len) {
         D2v t;
@@ -160,17 +175,38 @@ __global__ __launch_bounds__(kThreads) void mdot_vp_kernel(const double* __restr
     double nrm = 0.0;
     const double* __restrict__ vl = v0 + static_cast<long long>(nv - 1) * vstride;
     const long long step = 2LL * kWave * gridDim.x;
-    for (long long e = 2LL * (static_cast<long long>(blockIdx.x) * kWave + lane); e < len; e += step) {
-        const D2 wv = load2(w, e, len);
-        D2 lv{0.0, 0.0};
-        if (TWO) lv = load2(vl, e, len);
-        if (wid == 0) nrm += wv.x * wv.x + wv.y * wv.y;
+    // two iterations per trip (G <= 4; more would cost occupancy): all their loads are
+    // issued before the first product, and the sums are taken in the plain loop's order
+    constexpr int U = G <= 4 ? 2 : 1;
+    for (long long e = 2LL * (static_cast<long long>(blockIdx.x) * kWave + lane); e < len; e += U * step) {
+        const long long e2 = U == 2 ? e + step : len;
+        const D2 wv = load2c(w, e, len);
+        const D2 wv2 = load2c(w, e2, len);
+        D2 lv{0.0, 0.0}, lv2{0.0, 0.0};
+        if (TWO) {
+            lv = load2c(vl, e, len);
+            lv2 = load2c(vl, e2, len);
+        }
+        D2 v[G], v2[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            v[g] = v2[g] = D2{0.0, 0.0};
+            if (i0 + g < nv) {
+                v[g] = load2(v0 + static_cast<long long>(i0 + g) * vstride, e, len);
+                v2[g] = load2z(v0 + static_cast<long long>(i0 + g) * vstride, e2, len);
+            }
+        }
+        if (wid == 0) {
+            nrm += wv.x * wv.x + wv.y * wv.y;
+            nrm += wv2.x * wv2.x + wv2.y * wv2.y;
+        }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (i0 + g < nv) {
-                const D2 v = load2(v0 + static_cast<long long>(i0 + g) * vstride, e, len);
-                acc[g] += v.x * wv.x + v.y * wv.y;
-                if (TWO) acc2[g] += v.x * lv.x + v.y * lv.y;
+                acc[g] += v[g].x * wv.x + v[g].y * wv.y;
+                if (TWO) acc2[g] += v[g].x * lv.x + v[g].y * lv.y;
+                acc[g] += v2[g].x * wv2.x + v2[g].y * wv2.y;
+                if (TWO) acc2[g] += v2[g].x * lv2.x + v2[g].y * lv2.y;
             }
         }
     }

@@ -16,12 +16,17 @@
 //
 // Arithmetic per point is the single-step sweep's, term for term (float64 iterates
 // identical to three single steps; float32 up to contraction).
+//
+// FIRST: steps 1..3 from a zero initial guess.  x_1 = rhat / theta is never stored: the
+// x_k window holds rhat itself (the scale is applied after the linear stencil, as in the
+// single first sweep), x_0 = 0, and step 2 takes x_1 = rhat / theta as its x_{k-1}; the
+// block reads only rhat and kappa.
 #include "stencil_kernels.h"
 
 namespace ac {
 namespace {
 
-template <typename R, typename KS, int VX, int NS, int NV>
+template <typename R, typename KS, int VX, int NS, int NV, bool FIRST>
 __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid, int nb) {
     using K = R;
     constexpr int W = kWave * VX;  // computed columns per strip
@@ -100,20 +105,26 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
         for (int s = 0; s < NS; ++s) {
             if (comp[s]) {
                 const unsigned o = a.soff[s];
-                bld<0>(rx, lane_ok ? (o + NV * pt) * nR : kOob, X[S][s]);
-                bld<0>(rx, hok ? (o + NV * hp) * nR : kOob, XH[S][s]);
+                const __amdgpu_buffer_rsrc_t r = FIRST ? rh : rx;  // FIRST: rhat (x_1 unscaled)
+                bld<0>(r, lane_ok ? (o + NV * pt) * nR : kOob, X[S][s]);
+                bld<0>(r, hok ? (o + NV * hp) * nR : kOob, XH[S][s]);
             }
         }
     };
 
     // rhat into HN and x_{k-1} into P for row y; non-temporal inside the chunk, plain on
-    // its halo rows (also read by the neighbouring chunk)
-    auto load_centre = [&](int y) {
+    // its halo rows (also read by the neighbouring chunk).  FIRST: rhat of row y is the
+    // x_k window's slot XS (already loaded) and x_0 = 0.
+    auto load_centre = [&](auto XS_, int y) {
+        constexpr int XS = decltype(XS_)::value;
 #pragma unroll
         for (int s = 0; s < NS; ++s)
 #pragma unroll
-            for (int e = 0; e < E; ++e) HN[s][e] = P[s][e] = R(0);
-        if (y < 0 || y >= ny) return;
+            for (int e = 0; e < E; ++e) {
+                HN[s][e] = FIRST ? X[XS][s][e] : R(0);
+                P[s][e] = R(0);
+            }
+        if (FIRST || y < 0 || y >= ny) return;
         const unsigned pt = static_cast<unsigned>(y) * static_cast<unsigned>(nx) + static_cast<unsigned>(xb);
         const bool inner = (y >= y0 && y < y1);
 #pragma unroll
@@ -194,6 +205,72 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
         }
     };
 
+    // FIRST, step 1: x_2 from x_1 = s rhat (s = 1/theta) and x_0 = 0, the stencil applied
+    // to rhat and scaled after (the single first sweep's arithmetic)
+    auto update_first = [&](const Faces<K> (&fc)[VX], const ShiftCoef<R>& cf, int s, const R (&u)[E],
+                            const R (&us)[E], const R (&un)[E], const R (&hw)[NV], const R (&he)[NV], R (&out)[E]) {
+        if constexpr (NV == 1) {
+            const R sc = cf.s_re[s];
+            const R wv = shfl_up1(u[VX - 1]);
+            const R ev = shfl_dn1(u[0]);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const R uw = (v > 0) ? u[v - 1] : (lane == 0 ? hw[0] : wv);
+                const R ue = (v < VX - 1) ? u[v + 1] : (lane == kWave - 1 ? he[0] : ev);
+                const R uc = u[v];
+                R bu = (fc[v].diag - cf.lam_re[s]) * uc;
+                bu -= fc[v].w * uw + fc[v].e * ue + fc[v].s * us[v] + fc[v].n * un[v];
+                const R xc = sc * uc;
+                const R bx = sc * bu;
+                const R xp = R(0);
+                out[v] = xc + cf.a_re[s] * (xc - xp) + cf.c_re[s] * (uc - bx);
+            }
+        } else {
+            const R sr = cf.s_re[s], si = cf.s_im[s];
+            const R wre = shfl_up1(u[2 * VX - 2]);
+            const R wim = shfl_up1(u[2 * VX - 1]);
+            const R ere = shfl_dn1(u[0]);
+            const R eim = shfl_dn1(u[1]);
+            const R lr = cf.lam_re[s], li = cf.lam_im[s];
+            const R ar = cf.a_re[s], ai = cf.a_im[s];
+            const R kr = cf.c_re[s], ki = cf.c_im[s];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const R uwr = (v > 0) ? u[2 * v - 2] : (lane == 0 ? hw[0] : wre);
+                const R uwi = (v > 0) ? u[2 * v - 1] : (lane == 0 ? hw[1] : wim);
+                const R uer = (v < VX - 1) ? u[2 * v + 2] : (lane == kWave - 1 ? he[0] : ere);
+                const R uei = (v < VX - 1) ? u[2 * v + 3] : (lane == kWave - 1 ? he[1] : eim);
+                const R ucr = u[2 * v], uci = u[2 * v + 1];
+                const R dl = fc[v].diag - lr;
+                R bur = dl * ucr + li * uci;
+                R bui = dl * uci - li * ucr;
+                bur -= fc[v].w * uwr + fc[v].e * uer + fc[v].s * us[2 * v] + fc[v].n * un[2 * v];
+                bui -= fc[v].w * uwi + fc[v].e * uei + fc[v].s * us[2 * v + 1] + fc[v].n * un[2 * v + 1];
+                const R xr = sr * ucr - si * uci, xi = sr * uci + si * ucr;
+                const R bxr = sr * bur - si * bui, bxi = sr * bui + si * bur;
+                const R xpr = R(0), xpi = R(0);
+                const R dr = xr - xpr, di = xi - xpi;
+                const R qr = ucr - bxr, qi = uci - bxi;
+                out[2 * v] = xr + (ar * dr - ai * di) + (kr * qr - ki * qi);
+                out[2 * v + 1] = xi + (ar * di + ai * dr) + (kr * qi + ki * qr);
+            }
+        }
+    };
+    // FIRST, step 2: its x_{k-1} is x_1 = s rhat, scaled as the single sweep scales it
+    auto scaled_rhat = [&](const ShiftCoef<R>& cf, int s, const R (&u)[E], R (&out)[E]) {
+        if constexpr (NV == 1) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) out[v] = cf.s_re[s] * u[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const R xpr = u[2 * v], xpi = u[2 * v + 1];
+                out[2 * v] = cf.s_re[s] * xpr - cf.s_im[s] * xpi;
+                out[2 * v + 1] = cf.s_re[s] * xpi + cf.s_im[s] * xpr;
+            }
+        }
+    };
+
     auto store_row = [&](R* base, unsigned off, int y, const R (&vals)[E]) {
         if (!own_any) return;
         const unsigned pt = static_cast<unsigned>(y) * static_cast<unsigned>(nx) + static_cast<unsigned>(xb);
@@ -230,7 +307,8 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
         for (int s = 0; s < NS; ++s) {
             if (comp[s]) {
                 R o[E];
-                update(fc, a.cf[0], s, X[CS][s], X[PS][s], X[NN][s], XH[CS][s], XH[CS][s], P[s], HN[s], o);
+                if constexpr (FIRST) update_first(fc, a.cf[0], s, X[CS][s], X[PS][s], X[NN][s], XH[CS][s], XH[CS][s], o);
+                else update(fc, a.cf[0], s, X[CS][s], X[PS][s], X[NN][s], XH[CS][s], XH[CS][s], P[s], HN[s], o);
 #pragma unroll
                 for (int e = 0; e < E; ++e) Y[YS][s][e] = (live && lane_ok) ? o[e] : R(0);
             } else {
@@ -255,7 +333,13 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
         for (int s = 0; s < NS; ++s) {
             if (comp[s]) {
                 R o[E];
-                update(fc, a.cf[1], s, Y[CS][s], Y[PS][s], Y[NN][s], zh, zh, X[XC][s], rh[s], o);
+                if constexpr (FIRST) {
+                    R xp[E];
+                    scaled_rhat(a.cf[1], s, X[XC][s], xp);
+                    update(fc, a.cf[1], s, Y[CS][s], Y[PS][s], Y[NN][s], zh, zh, xp, rh[s], o);
+                } else {
+                    update(fc, a.cf[1], s, Y[CS][s], Y[PS][s], Y[NN][s], zh, zh, X[XC][s], rh[s], o);
+                }
 #pragma unroll
                 for (int e = 0; e < E; ++e) Z[ZS][s][e] = (live && lane_ok) ? o[e] : R(0);
                 if (st) store_row(a.outz, a.soff[s], y, Z[ZS][s]);
@@ -311,16 +395,16 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
     load_row(I0{}, y0 - 3);
     load_row(I1{}, y0 - 2);
     load_row(I2{}, y0 - 1);
-    load_centre(y0 - 2);
+    load_centre(I1{}, y0 - 2);
     step1(I0{}, I1{}, I2{}, I0{}, y0 - 2);             // x_{k+1}(y0-2) -> Y slot 0
     load_row(I0{}, y0);
-    load_centre(y0 - 1);
+    load_centre(I2{}, y0 - 1);
     step1(I1{}, I2{}, I0{}, I1{}, y0 - 1);             // x_{k+1}(y0-1) -> Y slot 1
     copy_rows(HA, HN);
 #pragma unroll
     for (int v = 0; v < VX; ++v) KS2[v] = KW[1][v];  // kappa(y0-2) before its slot is reused
     load_row(I1{}, y0 + 1);
-    load_centre(y0);
+    load_centre(I0{}, y0);
     step1(I2{}, I0{}, I1{}, I2{}, y0);                 // x_{k+1}(y0) -> Y slot 2
     copy_rows(HB, HN);
     step2(I0{}, I1{}, I2{}, I2{}, I0{}, KW[2], KH[2], KS2, KW[0], HA, y0 - 1);  // x_{k+2}(y0-1) -> Z slot 0
@@ -328,7 +412,7 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
     for (int v = 0; v < VX; ++v) KF[v] = KW[2][v];   // kappa(y0-1) with its halo
     KFH = KH[2];
     load_row(I2{}, y0 + 2);
-    load_centre(y0 + 1);
+    load_centre(I1{}, y0 + 1);
     step1(I0{}, I1{}, I2{}, I0{}, y0 + 1);             // x_{k+1}(y0+1) -> Y slot 0
     step2(I1{}, I2{}, I0{}, I0{}, I1{}, KW[0], KH[0], KF, KW[1], HB, y0);  // x_{k+2}(y0) -> Z slot 1
     copy_rows(H0, HB);
@@ -342,7 +426,7 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
         // in 2, 0, 1; x_{k+2} rows y-1, y, y+1 in 0, 1, 2
         keep_kappa(I0{});
         load_row(I0{}, y + 3);
-        load_centre(y + 2);
+        load_centre(I2{}, y + 2);
         step1(I1{}, I2{}, I0{}, I1{}, y + 2);
         step2(I2{}, I0{}, I1{}, I1{}, I2{}, KW[1], KH[1], KF, KW[2], H1, y + 1);
         step3(I0{}, I1{}, I2{}, I2{}, I1{}, y);
@@ -353,7 +437,7 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
         // rows y-1..y+1 in 1, 2, 0
         keep_kappa(I1{});
         load_row(I1{}, y + 3);
-        load_centre(y + 2);
+        load_centre(I0{}, y + 2);
         step1(I2{}, I0{}, I1{}, I2{}, y + 2);
         step2(I0{}, I1{}, I2{}, I2{}, I0{}, KW[2], KH[2], KF, KW[0], H1, y + 1);
         step3(I1{}, I2{}, I0{}, I0{}, I2{}, y);
@@ -364,7 +448,7 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
         // rows y-1..y+1 in 2, 0, 1
         keep_kappa(I2{});
         load_row(I2{}, y + 3);
-        load_centre(y + 2);
+        load_centre(I1{}, y + 2);
         step1(I0{}, I1{}, I2{}, I0{}, y + 2);
         step2(I1{}, I2{}, I0{}, I0{}, I1{}, KW[0], KH[0], KF, KW[1], H1, y + 1);
         step3(I2{}, I0{}, I1{}, I1{}, I0{}, y);
@@ -374,16 +458,16 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, int bid
     }
 }
 
-template <typename R, typename KS, int VX, int NS, int NV>
+template <typename R, typename KS, int VX, int NS, int NV, bool FIRST>
 __global__ __launch_bounds__(256) void cheb_triple_kernel(const TripleArgs<R> a) {
-    cheb_triple_body<R, KS, VX, NS, NV>(a, blockIdx.x, gridDim.x);
+    cheb_triple_body<R, KS, VX, NS, NV, FIRST>(a, blockIdx.x, gridDim.x);
 }
 
-template <typename R, typename KS, int VX>
+template <typename R, typename KS, int VX, bool FIRST>
 hipError_t triple_by_kind(const TripleArgs<R>& a, hipStream_t s) {
     const dim3 grid(a.t.blocks), block(a.t.wpb * kWave);
-    if (a.kind == 0) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, VX, 2, 1>), grid, block, 0, s, a);
-    else if (a.kind == 1) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, VX, 1, 2>), grid, block, 0, s, a);
+    if (a.kind == 0) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, VX, 2, 1, FIRST>), grid, block, 0, s, a);
+    else if (a.kind == 1) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, VX, 1, 2, FIRST>), grid, block, 0, s, a);
     else return hipErrorInvalidValue;
     return hipGetLastError();
 }
@@ -393,8 +477,8 @@ hipError_t triple_launch_t(const void* args, hipStream_t s) {
     const TripleArgs<R>& a = *static_cast<const TripleArgs<R>*>(args);
     if (a.g.periodic || a.t.blocks <= 0 || a.t.wpb < 1 || a.t.wpb > 4 || a.g.nx < 4) return hipErrorInvalidValue;
     if (a.t.vx == 2 && a.g.nx % 2 != 0) return hipErrorInvalidValue;
-    if (a.t.vx == 2) return triple_by_kind<R, KS, 2>(a, s);
-    if (a.t.vx == 1) return triple_by_kind<R, KS, 1>(a, s);
+    if (a.t.vx == 2) return a.first ? triple_by_kind<R, KS, 2, true>(a, s) : triple_by_kind<R, KS, 2, false>(a, s);
+    if (a.t.vx == 1) return a.first ? triple_by_kind<R, KS, 1, true>(a, s) : triple_by_kind<R, KS, 1, false>(a, s);
     return hipErrorInvalidValue;
 }
 
