@@ -84,6 +84,8 @@ def batch_mode(a):
     dev = torch.device("cuda:0")
     specs = batched_problem_specs(a.batch_count, seed=2026)
     ctx = api.ac_ctx_create(0)
+    api.ac_ctx_set_step_pairs(ctx, a.step_pairs, *a.pair_tiling)
+    api.ac_ctx_set_step_triples(ctx, a.step_triples, *a.triple_tiling)
     probs, bs = [], []
     for i, sp in enumerate(specs):
         kap = lognormal_kappa(sp["nx"], sp["ny"], 50.0, 10.0, sp["std"], seed=sp["seed"])
@@ -582,7 +584,7 @@ def main():
         "cheb_triple": (3, "cheb_triple_kernel<float, unsigned short, 2, {1,2}, {2,1}>: three steady shifted-Chebyshev "
                            "steps fused in one sweep, one launch per complex shift and per two real shifts (five "
                            "launches per block at l = 10)", "cheb_triple_2048x2048_l10_traffic.json",
-                        ["stencil_triple.hip", "stencil_kernels.h"]),
+                        ["stencil_triple.h", "stencil_kernels.h"]),
         "cheb_pair": (2, "cheb_pair_kernel<float, unsigned short, 2>: two steady shifted-Chebyshev steps fused in one "
                          "sweep over a shift group (one real + two complex shifts)", None, None),
         "cheb_step": (1, "cheb_sweep_kernel<float, unsigned short, 5, 2, false, false, false>: steady-state shifted "

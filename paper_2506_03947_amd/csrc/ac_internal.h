@@ -154,7 +154,7 @@ struct BatchList {
     int wpb;            // waves per block, equal for every entry
 };
 
-enum BatchOp : int { BOP_FWD = 0, BOP_STEP = 1, BOP_FINAL = 2, BOP_CALA = 3 };
+enum BatchOp : int { BOP_FWD = 0, BOP_STEP = 1, BOP_FINAL = 2, BOP_CALA = 3, BOP_TRIPLE = 4 };
 
 // Grid of the forward transform for n points: vx points per thread, 256 threads.
 inline void fwd_geometry(long long n, int& vx, int& blocks) {
@@ -173,6 +173,8 @@ hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipS
 hipError_t launch_cheb_pair(int prec, const void* args, hipStream_t s);
 // Three steady steps per sweep (TripleArgs<double> for prec 0, else TripleArgs<float>).
 hipError_t launch_cheb_triple(int prec, const void* args, hipStream_t s);
+// Batched three-step sweeps (args TripleArgs per problem); code = kind | 2 * first.
+hipError_t launch_batch_triple(int prec, int code, int vx, const BatchList& L, hipStream_t s);
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);

@@ -658,8 +658,9 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     // sweep per shift group when four iterate buffers are available.
     // (the paired sweep addresses its buffers with 32-bit byte offsets below 2^31)
     const double spec_bytes = static_cast<double>(off[ns]) * sizeof(R);
-    const bool can_pair = nb == 4 && p->ctx->pairs == 1 && !p->ctx->rec && !p->g.periodic && p->g.nx >= 3 &&
-                          spec_bytes < 2147483648.0 && static_cast<double>(p->g.n) * ksz < 2147483648.0;
+    const bool fuse_ok = nb == 4 && p->ctx->pairs == 1 && !p->g.periodic && p->g.nx >= 3 &&
+                         spec_bytes < 2147483648.0 && static_cast<double>(p->g.n) * ksz < 2147483648.0;
+    const bool can_pair = fuse_ok && !p->ctx->rec;
     auto steady_step = [&](int k) {
         if (k > k_last || (fuse && k == k_last)) return false;
         int ck, pk;
@@ -710,7 +711,11 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         return hipSuccess;
     };
     // Three steps per sweep: one launch per complex shift, one per (up to) two real shifts.
-    const bool can_triple = can_pair && p->ctx->triples == 1 && p->g.nx >= 4;
+    // Recorded for a batch only with one budget for every shift, so that every problem
+    // of the batch cuts its steps into the same blocks (aligned launch sequences).
+    bool uniform = true;
+    for (int s = 1; s < ns; ++s) uniform = uniform && ps[s] == ps[0];
+    const bool can_triple = fuse_ok && p->ctx->triples == 1 && p->g.nx >= 4 && (!p->ctx->rec || uniform);
     // first: steps 1..3 from a zero guess (x_1 = rhat/theta and x_0 = 0 never stored)
     auto launch_triple = [&](int k, double& bytes, bool first) -> hipError_t {
         ac::TripleArgs<R> ta{};
@@ -734,6 +739,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         auto go = [&](int kind, const int* slots, int count) -> hipError_t {
             ac::TripleArgs<R> g = ta;
             g.kind = kind;
+            g.comp[0] = g.comp[1] = 0;
             bool anyc = false;
             for (int j = 0; j < 2; ++j) {
                 g.comp[j] = 0;
@@ -747,18 +753,26 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 bytes += (first ? 9.0 : 12.0) * (slot_is_real(p, sl) ? esz_r : esz_c);
                 anyc = true;
             }
+            if (p->ctx->rec) {
+                // batched: a fixed number of positions per block (empty ones with no
+                // blocks) so that problems with different l record aligned sequences
+                record_launch(p->ctx, ac::BOP_TRIPLE, 3, prec, kind | (first ? 2 : 0), g.t.vx, g.t.wpb,
+                              anyc ? g.t.blocks : 0, g);
+                return hipSuccess;
+            }
             if (!anyc) return hipSuccess;
             const hipError_t e = ac::launch_cheb_triple(prec, &g, p->ctx->stream);
             if (e == hipSuccess) ++launched;
             return e;
         };
-        for (int r = 0; r < p->nsr; r += 2) {
-            const int sl[2] = {r, r + 1 < p->nsr ? r + 1 : -1};
+        // position 0: the real shifts (at most two); positions 1..: one complex shift each
+        {
+            const int sl[2] = {p->nsr > 0 ? 0 : -1, p->nsr > 1 ? 1 : -1};
             const hipError_t e = go(0, sl, 2);
             if (e != hipSuccess) return e;
         }
-        for (int c = 0; c < p->nsc; ++c) {
-            const int sl[1] = {p->nsr + c};
+        for (int c = 0; c < (p->ctx->rec ? kMaxShift - 2 : p->nsc); ++c) {
+            const int sl[1] = {c < p->nsc ? p->nsr + c : -1};
             const hipError_t e = go(1, sl, 1);
             if (e != hipSuccess) return e;
         }
@@ -808,8 +822,8 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         // block size: greedy triples, then a pair or a single step (at 2048^2, l = 10 per
         // application: triple 211 us, pair 193 us, single 116 us, so a remainder of one
         // step is cheaper as a single than as two pairs replacing a triple)
-        const int run = (can_pair && steady_step(k)) ? steady_run(k) : 0;
-        const int blk = (can_triple && run >= 3) ? 3 : (run >= 2 ? 2 : 1);
+        const int run = ((can_pair || can_triple) && steady_step(k)) ? steady_run(k) : 0;
+        const int blk = (can_triple && run >= 3) ? 3 : (can_pair && run >= 2 ? 2 : 1);
         if (blk == 3) {
             steady.reset();
             paired.reset();
@@ -2177,8 +2191,9 @@ struct BatchLaunch {
 };
 
 size_t max_args_bytes() {
-    return std::max(std::max(sizeof(ac::SweepArgs<double>), sizeof(ac::SweepArgs<float>)),
-                    std::max(sizeof(ac::FwdArgs), sizeof(ac::CalAArgs)));
+    return std::max(std::max(std::max(sizeof(ac::SweepArgs<double>), sizeof(ac::SweepArgs<float>)),
+                             std::max(sizeof(ac::FwdArgs), sizeof(ac::CalAArgs))),
+                    std::max(sizeof(ac::TripleArgs<double>), sizeof(ac::TripleArgs<float>)));
 }
 
 // Device bytes for the work lists: per j at most 4p + 3 launch positions (a sweep step

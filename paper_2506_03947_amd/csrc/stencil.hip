@@ -74,6 +74,7 @@ hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t
 }
 
 hipError_t launch_batch(int op, int ell, int prec, int curk, int vx, const BatchList& b, hipStream_t s) {
+    if (op == BOP_TRIPLE) return launch_batch_triple(prec, curk, vx, b, s);  // not specialised by l
 #define AC_X(L) batch_ell_##L(op, prec, curk, vx, b, s)
     AC_SWITCH(AC_X)
 #undef AC_X
