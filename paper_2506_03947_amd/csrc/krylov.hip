@@ -231,6 +231,53 @@ __global__ __launch_bounds__(kThreads) void mdot_vp_kernel(const double* __restr
 
 // w -= sum_i c_i V_i with c_i = s2_i dcoef_i (dcoef on the device) or c_i = s2_i
 // (dcoef == nullptr);  partial[0] = ||w||^2 afterwards
+// Few basis vectors (nv <= NVB = 4, contiguous at a stride): every thread streams its
+// own elements of w and of all nv vectors (no wave re-reads w), two iterations per trip;
+// the dots with the newest vector come from the same loads.  Partial layout as above.
+template <int NVB, bool TWO>
+__global__ __launch_bounds__(kThreads) void mdot_es_kernel(const double* __restrict__ v0, long long vstride, int nv,
+                                                           const double* __restrict__ w, long long len,
+                                                           double* partial, int stride) {
+    constexpr int NQ = 2 * NVB + 1;
+    double acc[NQ];  // [0, NVB): V_i . w; NVB: w . w; NVB + 1 + i: V_i . V_{nv-1}
+#pragma unroll
+    for (int i = 0; i < NQ; ++i) acc[i] = 0.0;
+    const long long step = 2LL * gridDim.x * blockDim.x;
+    for (long long e = 2LL * (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x); e < len; e += 2 * step) {
+        const long long e2 = e + step;
+        const D2 wv = load2(w, e, len);
+        const D2 wv2 = load2z(w, e2, len);
+        D2 v[NVB], v2[NVB];
+#pragma unroll
+        for (int i = 0; i < NVB; ++i) {
+            v[i] = v2[i] = D2{0.0, 0.0};
+            if (i < nv) {
+                v[i] = load2(v0 + static_cast<long long>(i) * vstride, e, len);
+                v2[i] = load2z(v0 + static_cast<long long>(i) * vstride, e2, len);
+            }
+        }
+        D2 lv = v[0], lv2 = v2[0];
+#pragma unroll
+        for (int i = 1; i < NVB; ++i)
+            if (i == nv - 1) {
+                lv = v[i];
+                lv2 = v2[i];
+            }
+        acc[NVB] += wv.x * wv.x + wv.y * wv.y;
+        acc[NVB] += wv2.x * wv2.x + wv2.y * wv2.y;
+#pragma unroll
+        for (int i = 0; i < NVB; ++i) {
+            if (i < nv) {
+                acc[i] += v[i].x * wv.x + v[i].y * wv.y;
+                if (TWO) acc[NVB + 1 + i] += v[i].x * lv.x + v[i].y * lv.y;
+                acc[i] += v2[i].x * wv2.x + v2[i].y * wv2.y;
+                if (TWO) acc[NVB + 1 + i] += v2[i].x * lv2.x + v2[i].y * lv2.y;
+            }
+        }
+    }
+    block_sums_mdot<NQ, NVB, TWO>(acc, nv, partial + static_cast<long long>(blockIdx.x) * stride);
+}
+
 template <int NVB>
 __global__ __launch_bounds__(kThreads) void axpy_norm_kernel(const VecSet V, int nv, const double* __restrict__ dcoef,
                                                              double* w, long long len, double* partial, int stride) {
@@ -320,6 +367,11 @@ hipError_t launch_mdot_strided(const double* v0, long long vstride, int nv, bool
     if (nv < 1 || nv > 32) return hipErrorInvalidValue;
     const int per_wave = (nv + kThreads / kWave - 1) / (kThreads / kWave);
     const dim3 g(kBlocks), b(kThreads);
+    if (nv <= 4) {  // few vectors: split the elements, not the vectors, over the waves
+        if (with_last) hipLaunchKernelGGL((mdot_es_kernel<4, true>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
+        else hipLaunchKernelGGL((mdot_es_kernel<4, false>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
+        return hipGetLastError();
+    }
 #define AC_MV(GG)                                                                                             \
     if (with_last) hipLaunchKernelGGL((mdot_vp_kernel<GG, true>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride); \
     else hipLaunchKernelGGL((mdot_vp_kernel<GG, false>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
