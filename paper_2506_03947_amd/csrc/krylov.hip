@@ -231,7 +231,7 @@ __global__ __launch_bounds__(kThreads) void mdot_vp_kernel(const double* __restr
 
 // w -= sum_i c_i V_i with c_i = s2_i dcoef_i (dcoef on the device) or c_i = s2_i
 // (dcoef == nullptr);  partial[0] = ||w||^2 afterwards
-// Few basis vectors (nv <= NVB = 4, contiguous at a stride): every thread streams its
+// Few basis vectors (nv <= NVB, 4 or 8, contiguous at a stride): every thread streams its
 // own elements of w and of all nv vectors (no wave re-reads w), two iterations per trip;
 // the dots with the newest vector come from the same loads.  Partial layout as above.
 template <int NVB, bool TWO>
@@ -370,6 +370,11 @@ hipError_t launch_mdot_strided(const double* v0, long long vstride, int nv, bool
     if (nv <= 4) {  // few vectors: split the elements, not the vectors, over the waves
         if (with_last) hipLaunchKernelGGL((mdot_es_kernel<4, true>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
         else hipLaunchKernelGGL((mdot_es_kernel<4, false>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
+        return hipGetLastError();
+    }
+    if (nv <= 8) {
+        if (with_last) hipLaunchKernelGGL((mdot_es_kernel<8, true>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
+        else hipLaunchKernelGGL((mdot_es_kernel<8, false>), g, b, 0, s, v0, vstride, nv, w, len, partial, stride);
         return hipGetLastError();
     }
 #define AC_MV(GG)                                                                                             \
