@@ -331,8 +331,8 @@ int ac_ctx_set_shift_groups(ac_ctx* ctx, int mode);
  * of Section 3): mode 1 (default) fuses every two consecutive steady steps in which the
  * same shifts compute, on Dirichlet grids, into one sweep per shift group (one real,
  * two complex shifts) that reads x_k, x_{k-1} and rhat once and writes x_{k+1} and
- * x_{k+2}; mode 0 runs single steps.  The iterates are those of single steps (float64:
- * identical; float32: up to contraction).  rows_per_wave, waves_per_block (1..4) and
+ * x_{k+2}; mode 0 runs single steps.  The iterates are those of single steps up to
+ * rounding (operations may be contracted differently: a few ulps per step).  rows_per_wave, waves_per_block (1..4) and
  * points_per_lane (1..2) set the paired sweep's tiling, 0 = automatic (rows for about
  * one round of waves, 4..32; 4 waves; 2 points per lane in float32 on even grids at
  * least 128 wide, else 1).  Pairs
@@ -346,8 +346,8 @@ int ac_ctx_set_step_pairs(ac_ctx* ctx, int mode, int rows_per_wave, int waves_pe
  * of one as a single step), where pairs are allowed (mode 1 of ac_ctx_set_step_pairs,
  * Dirichlet grids, buffers below 2^31 bytes).  A block reads x_k, x_{k-1} and rhat
  * once and writes x_{k+2} and x_{k+3} (x_{k+1} stays in registers), one launch per
- * complex shift and per two real shifts.  The iterates are those of single steps
- * (float64: identical; float32: up to contraction).  Tiling arguments as for pairs
+ * complex shift and per two real shifts.  The iterates are those of single steps up to
+ * rounding (a few ulps per step).  Tiling arguments as for pairs
  * (automatic: rows for about one round of waves, 4 waves per block).  Profiling
  * (AC_K_CHEB_TRIPLE) counts the three steps' unfused algorithmic bytes. */
 int ac_ctx_set_step_triples(ac_ctx* ctx, int mode, int rows_per_wave, int waves_per_block, int points_per_lane);

@@ -16,7 +16,8 @@
 // written by exactly one wave.  Dirichlet grids only.
 //
 // Arithmetic per point is the single-step sweep's, term for term, so the iterates
-// agree with two single steps (float64: identical; float32: up to contraction).
+// agree with two single steps up to rounding (the compiler may contract the same
+// expressions differently in another kernel: a few ulps).
 #include "stencil_kernels.h"
 
 namespace ac {

@@ -15,8 +15,9 @@
 // Dirichlet grids only.  Loads are raw buffer loads: lanes past the grid edge, non-halo
 // lanes and halo values outside the grid read zeros (the ghosts) without a branch.
 //
-// Arithmetic per point is the single-step sweep's, term for term (float64 iterates
-// identical to three single steps; float32 up to contraction).
+// Arithmetic per point is the single-step sweep's, term for term: the iterates agree with
+// three single steps up to rounding (the compiler may contract the same expressions
+// differently in another kernel: a few ulps).
 //
 // FIRST: steps 1..3 from a zero initial guess.  x_1 = rhat / theta is never stored: the
 // x_k window holds rhat itself (the scale is applied after the linear stencil, as in the

@@ -33,11 +33,11 @@ TILINGS = [(0, 0, 0), (1, 1, 1), (5, 3, 2), (64, 4, 0)]
 
 
 def _tol(precision, ell, steps):
-    if precision == L.AC_PREC_FP64:
-        return 1e-14
-    # float32: the paired kernel may contract operations differently; a few roundings
-    # (2^-24) per step, amplified by cond(U* Gamma) = alpha^{-(l-1)/l}
-    return 8 * steps * 1e-2 ** (-(ell - 1) / ell) * 2.0 ** -24
+    # a fused kernel may contract the same expressions differently (measured: a few ulps,
+    # float64 up to 9e-15 relative after 20 steps): a few roundings per step, amplified by
+    # cond(U* Gamma) = alpha^{-(l-1)/l}
+    eps = 2.0 ** -53 if precision == L.AC_PREC_FP64 else 2.0 ** -24
+    return 8 * steps * 1e-2 ** (-(ell - 1) / ell) * eps
 
 
 def _apply(p, opts, r, ws, pairs, triples=1, tiling=(0, 0, 0)):
@@ -102,8 +102,8 @@ def test_paired_shifted_solves_in_place(warm, steps):
         finally:
             api.ac_ctx_set_step_pairs(G.ctx(), 1)
             api.ac_ctx_set_step_triples(G.ctx(), 1)
-    assert G.max_rel(out[1], out[0]) <= 1e-14
-    assert G.max_rel(out[2], out[0]) <= 1e-14
+    assert G.max_rel(out[1], out[0]) <= _tol(L.AC_PREC_FP64, ell, steps)
+    assert G.max_rel(out[2], out[0]) <= _tol(L.AC_PREC_FP64, ell, steps)
 
 
 def test_paired_sweeps_full_size():
