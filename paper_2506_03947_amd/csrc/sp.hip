@@ -141,6 +141,158 @@ __global__ __launch_bounds__(kThr) void saddle_apply_kernel(const MgLevel L, lon
     if (threadIdx.x == 0) partial[static_cast<long long>(blockIdx.x) * ns + q] = t;
 }
 
+// VX consecutive points of one grid row per thread (nx % VX == 0, so a vector never
+// crosses a row): vector loads of the centre values and of the rows above and below,
+// clamped addresses for neighbours past the grid (their coefficients are zero there, so
+// they subtract nothing), no branch around a load.  The memory instructions per point
+// drop about VX-fold; the arithmetic per point is op_at's, term for term.
+template <typename T, int V>
+__device__ __forceinline__ void ldvec(const T* p, T (&o)[V]) {
+    typedef T TV __attribute__((ext_vector_type(V)));
+    const TV t = *reinterpret_cast<const TV*>(p);
+#pragma unroll
+    for (int v = 0; v < V; ++v) o[v] = t[v];
+}
+template <typename T, int V>
+__device__ __forceinline__ void stvec(T* p, const T (&in)[V]) {
+    typedef T TV __attribute__((ext_vector_type(V)));
+    TV t;
+#pragma unroll
+    for (int v = 0; v < V; ++v) t[v] = in[v];
+    *reinterpret_cast<TV*>(p) = t;
+}
+
+template <int VX>
+struct FineV {
+    double d[VX], e[VX], w[VX], n[VX], s[VX];
+    int x0;
+    bool hn, hs;
+};
+template <typename T, int VX>
+__device__ __forceinline__ FineV<VX> fine_v(const MgLevel& L, long long i0) {
+    const int ii = static_cast<int>(i0), x0 = ii % L.nx, y = ii / L.nx;
+    const long long nx = L.nx;
+    FineV<VX> f;
+    f.x0 = x0;
+    f.hn = L.dim == 2 && y < L.ny - 1;
+    f.hs = L.dim == 2 && y > 0;
+    T dv[VX], wxv[VX], wyn[VX], wys[VX];
+    const T* __restrict__ dg = std::is_same<T, float>::value ? reinterpret_cast<const T*>(L.diag_f)
+                                                             : reinterpret_cast<const T*>(L.diag);
+    const T* __restrict__ wx = std::is_same<T, float>::value ? reinterpret_cast<const T*>(L.wx_f)
+                                                             : reinterpret_cast<const T*>(L.wx);
+    const T* __restrict__ wy = std::is_same<T, float>::value ? reinterpret_cast<const T*>(L.wy_f)
+                                                             : reinterpret_cast<const T*>(L.wy);
+    ldvec<T, VX>(dg + i0, dv);
+    ldvec<T, VX>(wx + i0, wxv);
+    ldvec<T, VX>(wy + i0, wyn);
+    ldvec<T, VX>(wy + (f.hs ? i0 - nx : i0), wys);
+    const T wxw = wx[x0 > 0 ? i0 - 1 : i0];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        f.d[v] = dv[v];
+        f.e[v] = (x0 + v < L.nx - 1) ? static_cast<double>(wxv[v]) : 0.0;
+        f.w[v] = (x0 + v > 0) ? static_cast<double>(v > 0 ? wxv[v - 1] : wxw) : 0.0;
+        f.n[v] = f.hn ? static_cast<double>(wyn[v]) : 0.0;
+        f.s[v] = f.hs ? static_cast<double>(wys[v]) : 0.0;
+    }
+    return f;
+}
+template <typename T, int VX>
+__device__ __forceinline__ void op_v(const FineV<VX>& f, const T* __restrict__ u, long long i0, long long nx, int gnx,
+                                     double c, double (&out)[VX]) {
+    T uc[VX], un[VX], us[VX];
+    ldvec<T, VX>(u + i0, uc);
+    ldvec<T, VX>(u + (f.hn ? i0 + nx : i0), un);
+    ldvec<T, VX>(u + (f.hs ? i0 - nx : i0), us);
+    const T uwe = u[f.x0 > 0 ? i0 - 1 : i0];
+    const T uee = u[f.x0 + VX < gnx ? i0 + VX : i0];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        const T ue = v < VX - 1 ? uc[v + 1] : uee;
+        const T uw = v > 0 ? uc[v - 1] : uwe;
+        double a = (f.d[v] - c) * static_cast<double>(uc[v]);
+        a -= f.e[v] * static_cast<double>(ue);
+        a -= f.w[v] * static_cast<double>(uw);
+        a -= f.n[v] * static_cast<double>(un[v]);
+        a -= f.s[v] * static_cast<double>(us[v]);
+        out[v] = a;
+    }
+}
+
+template <typename T, int VX>
+__global__ __launch_bounds__(kThr) void saddle_apply_v_kernel(const MgLevel L, long long n, CVec9<T> z, Vec9<T> sz,
+                                                              const double* __restrict__ st, SpProblem P,
+                                                              double* __restrict__ partial, int ns) {
+    const int q = blockIdx.y;
+    const double* sq = st + q * kSt;
+    const bool done = sq[DONE] != 0.0;
+    const double ginv = done ? 0.0 : 1.0 / sq[G];
+    const double sig = P.sigma[q], rho = P.rho[q];
+    const T* __restrict__ z1 = z.p[q];
+    const T* __restrict__ z2 = z1 + n;
+    T* __restrict__ o1 = sz.p[q];
+    T* __restrict__ o2 = o1 + n;
+    const long long nx = L.nx;
+    double acc = 0.0;
+    for (long long i0 = (static_cast<long long>(blockIdx.x) * kThr + threadIdx.x) * VX; i0 < n;
+         i0 += static_cast<long long>(gridDim.x) * kThr * VX) {
+        T r1[VX], r2[VX];
+        if (done) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) r1[v] = r2[v] = T(0);
+            stvec<T, VX>(o1 + i0, r1);
+            stvec<T, VX>(o2 + i0, r2);
+            continue;
+        }
+        const FineV<VX> f = fine_v<T, VX>(L, i0);
+        T a1v[VX], a2v[VX];
+        ldvec<T, VX>(z1 + i0, a1v);
+        ldvec<T, VX>(z2 + i0, a2v);
+        double op1[VX], op2[VX];
+        op_v<T, VX>(f, z2, i0, nx, L.nx, rho, op2);
+        op_v<T, VX>(f, z1, i0, nx, L.nx, rho, op1);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            const double a1 = a1v[v], a2 = a2v[v];
+            const double t1 = (sig * a1 + op2[v]) * ginv;
+            const double t2 = (op1[v] - sig * a2) * ginv;
+            r1[v] = static_cast<T>(t1);
+            r2[v] = static_cast<T>(t2);
+            acc += (t1 * a1 + t2 * a2) * ginv;
+        }
+        stvec<T, VX>(o1 + i0, r1);
+        stvec<T, VX>(o2 + i0, r2);
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[static_cast<long long>(blockIdx.x) * ns + q] = t;
+}
+
+template <typename T, int VX>
+__global__ __launch_bounds__(kThr) void cg_apply_v_kernel(const MgLevel L, long long n, CVec9<T> pv, Vec9<T> qv,
+                                                          SpProblem P, double* __restrict__ partial, int ns) {
+    const int r = blockIdx.y;
+    const T* __restrict__ p = pv.p[r];
+    T* __restrict__ q = qv.p[r];
+    const long long nx = L.nx;
+    double acc = 0.0;
+    for (long long i0 = (static_cast<long long>(blockIdx.x) * kThr + threadIdx.x) * VX; i0 < n;
+         i0 += static_cast<long long>(gridDim.x) * kThr * VX) {
+        double a[VX];
+        op_v<T, VX>(fine_v<T, VX>(L, i0), p, i0, nx, L.nx, P.lam[r], a);
+        T pc[VX], qo[VX];
+        ldvec<T, VX>(p + i0, pc);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            qo[v] = static_cast<T>(a[v]);
+            acc += static_cast<double>(pc[v]) * a[v];
+        }
+        stvec<T, VX>(q + i0, qo);
+    }
+    const double t = block_sum(acc);
+    if (threadIdx.x == 0) partial[static_cast<long long>(blockIdx.x) * ns + P.nc + r] = t;
+}
+
 // q = (A - lambda I) p per real slot, partial of p . q (slot index nc + r)
 template <typename T>
 __global__ __launch_bounds__(kThr) void cg_apply_kernel(const MgLevel L, long long n, CVec9<T> pv, Vec9<T> qv,
@@ -484,12 +636,25 @@ hipError_t solve_t(const SpProblem& P, int iters, char* ws, hipStream_t s) {
     T** w = wb;
     T** wp = wpb;
     for (int it = 0; it < iters; ++it) {
-        if (nc)
-            hipLaunchKernelGGL(saddle_apply_kernel<T>, dim3(nb, nc), dim3(kThr), 0, s, L0, n, cv(z, nc), mv(szb, nc),
-                               st, P, partA, ns);
-        if (nr)
-            hipLaunchKernelGGL(cg_apply_kernel<T>, dim3(nb, nr), dim3(kThr), 0, s, L0, n, cv(pr, nr), mv(qr, nr), P,
-                               partA, ns);
+        // vector variants (16-byte loads) when rows split into whole vectors
+        constexpr int VX = sizeof(T) == 4 ? 4 : 2;
+        const bool vec = L0.nx % VX == 0;
+        if (nc) {
+            if (vec)
+                hipLaunchKernelGGL((saddle_apply_v_kernel<T, VX>), dim3(nb, nc), dim3(kThr), 0, s, L0, n, cv(z, nc),
+                                   mv(szb, nc), st, P, partA, ns);
+            else
+                hipLaunchKernelGGL(saddle_apply_kernel<T>, dim3(nb, nc), dim3(kThr), 0, s, L0, n, cv(z, nc),
+                                   mv(szb, nc), st, P, partA, ns);
+        }
+        if (nr) {
+            if (vec)
+                hipLaunchKernelGGL((cg_apply_v_kernel<T, VX>), dim3(nb, nr), dim3(kThr), 0, s, L0, n, cv(pr, nr),
+                                   mv(qr, nr), P, partA, ns);
+            else
+                hipLaunchKernelGGL(cg_apply_kernel<T>, dim3(nb, nr), dim3(kThr), 0, s, L0, n, cv(pr, nr), mv(qr, nr),
+                                   P, partA, ns);
+        }
         if ((e = launch_reduce(partA, nb, ns, ns, sumsA, s)) != hipSuccess) return e;
         if (nc)
             hipLaunchKernelGGL(lanczos_kernel<T>, dim3(nb, nc), dim3(kThr), 0, s, 2 * n, cv(szb, nc), cv(v, nc),
