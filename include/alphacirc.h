@@ -355,7 +355,9 @@ int ac_ctx_set_step_triples(ac_ctx* ctx, int mode, int rows_per_wave, int waves_
 /* ---- tiling ----------------------------------------------------------------
  * Sweep tiling of one problem (overrides the context's ac_ctx_set_tiling; 0 keeps
  * the context's value): rows per wave, waves per block (1..4), points per lane
- * (1 or 2; 1 is forced for odd or narrow grids). */
+ * (1 or 2; 1 is forced for odd or narrow grids).  It applies to single sweeps (the
+ * first and last ones, and steady steps not fused); fused blocks of steady steps take
+ * the tiling of ac_ctx_set_step_pairs / ac_ctx_set_step_triples. */
 int ac_problem_set_tiling(ac_problem* p, int rows_per_wave, int waves_per_block, int points_per_lane);
 /* Tile tuner: times the shifted Chebyshev sweeps of p at the given precision for
  * candidate tilings (points per lane 1 and 2, 4..64 rows per wave, 1, 2 or 4 waves
