@@ -106,18 +106,19 @@ def test_paired_shifted_solves_in_place(warm, steps):
     assert G.max_rel(out[2], out[0]) <= _tol(L.AC_PREC_FP64, ell, steps)
 
 
-def test_paired_sweeps_full_size():
-    """The benchmark's inner solve (2048^2, l = 10, p = 20, complex64 with bf16 kappa):
-    P_NC^{-1} with fused steady sweeps (pairs only; triples and pairs) against single
-    sweeps, every element."""
+@pytest.mark.parametrize("precision", [L.AC_PREC_MIXED_BF16K, L.AC_PREC_FP64])
+def test_paired_sweeps_full_size(precision):
+    """The benchmark's inner solve (2048^2, l = 10, p = 20; complex64 with bf16 kappa as
+    benchmarked, and float64): P_NC^{-1} with fused steady sweeps (pairs only; triples and
+    pairs) against single sweeps, every element."""
     nx = ny = 2048
     ell = 10
     kap = lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=0)
     p = G.problem(2, nx, ny, kap, ell, 1e-2)
-    opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, p=20)
+    opts = api.Opts(precision=precision, p=20)
     ws = api.workspace(api.ac_prec_workspace_size(p, opts))
     r = G.dev(np.random.default_rng(5).standard_normal(ell * nx * ny))
     single = _apply(p, opts, r, ws, 0)
     for triples in (0, 1):
         fused = _apply(p, opts, r, ws, 1, triples)
-        assert G.max_rel(fused, single) <= _tol(L.AC_PREC_MIXED_BF16K, ell, 20), triples
+        assert G.max_rel(fused, single) <= _tol(precision, ell, 20), triples
