@@ -501,7 +501,7 @@ def cpu_baseline(w, kappa, b, p, gpu_outer_iters):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is design-only)"}))
+        print(json.dumps({"error": "the library runs on one GPU; --gpus must be 1 (sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     if a.mode == "batch":
         batch_mode(a)
