@@ -309,8 +309,9 @@ int ac_shifted_residual(ac_problem* p, int precision, const void* rhat, const vo
  * the basis per step), all in float64; Givens
  * rotations on the host.  x holds the initial guess on entry and the solution on
  * return.  Converged when the TRUE relative residual ||b - calA x||/||b|| <= tol
- * (the paper's residual definition, Section 5).  Synchronises once per
- * iteration.  info may be NULL.  Returns AC_NOT_CONVERGED after max_outer. */
+ * (the paper's residual definition, Section 5).  A zero b gives x = 0 and zeroed
+ * info, with no iteration.  Synchronises once per iteration.  info may be NULL.
+ * Returns AC_NOT_CONVERGED after max_outer. */
 int ac_solve(ac_problem* p, const ac_solve_opts* opts, const double* b, double* x, void* ws, size_t ws_bytes,
              ac_solve_info* info);
 /* ac_solve that also copies the first rec_count vectors handed to the

@@ -1940,6 +1940,13 @@ int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
     AC_TRY(fetch1(bb));
     const double bnorm = std::sqrt(bb);
     if (!std::isfinite(bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
+    if (bnorm == 0.0) {  // the solution is x = 0, whatever the initial guess
+        hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((len + 255) / 256)), dim3(256), 0, st, x, len);
+        AC_HIP(hipGetLastError());
+        AC_HIP(hipStreamSynchronize(st));
+        if (info) *info = ac_solve_info{};
+        return AC_OK;
+    }
     long long matvecs = 0;
     int it = 0, status = AC_OK;
     double beta = 0.0, rho = delta / theta;
@@ -1951,7 +1958,7 @@ int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
         matvecs += p->ell;
         beta = std::sqrt(rr);
         if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
-        if (bnorm == 0.0 || beta / bnorm <= o->tol) break;
+        if (beta / bnorm <= o->tol) break;
         if (it >= o->max_outer) {
             status = AC_NOT_CONVERGED;
             break;

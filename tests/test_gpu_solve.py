@@ -152,9 +152,10 @@ def test_errors():
     with pytest.raises(api.L.AlphacircError) as e:
         G.problem(1, n, 1, kap, 4, 50.0)  # alpha >= mu_lo^l
     assert e.value.status == L.AC_ERR_ALPHA
-    with pytest.raises(api.L.AlphacircError) as e:
-        G.problem(1, n, 1, kap, 17, 1e-2)
-    assert e.value.status == L.AC_ERR_UNSUPPORTED
+    for ell in (1, 17):  # l outside [2, 16]
+        with pytest.raises(api.L.AlphacircError) as e:
+            G.problem(1, n, 1, kap, ell, 1e-2)
+        assert e.value.status == L.AC_ERR_UNSUPPORTED
     bad = kap.copy()
     bad[3] = -1.0
     with pytest.raises(api.L.AlphacircError) as e:
@@ -192,3 +193,26 @@ def test_errors():
     x = G.dev(np.ones(4 * n))
     info = api.ac_solve(p, opts, G.dev(np.zeros(4 * n)), x, sws)
     assert info["converged"] and not G.host(x).any()
+
+
+def test_zero_rhs_outer_chebyshev_and_batch():
+    """b = 0 has the unique solution x = 0: both outer solvers and the batched solve
+    return it without iterating, whatever the initial guess."""
+    nx, ell = 40, 4
+    kap = lognormal_kappa(nx, nx, 20.0, 5.0, 1.0, seed=3)
+    p = G.problem(2, nx, nx, kap, ell, 1e-2)
+    n = ell * nx * nx
+    opts = api.Opts(precision=L.AC_PREC_FP64, p=6, tol=1e-10, outer=L.AC_OUTER_CHEBYSHEV)
+    x = G.dev(np.ones(n))
+    info = api.ac_solve(p, opts, G.dev(np.zeros(n)), x, api.workspace(api.ac_solve_workspace_size(p, opts)))
+    assert info["converged"] and info["outer_iters"] == 0 and not G.host(x).any()
+    q = G.problem(2, nx, nx, kap, ell, 1e-2)
+    bopts = api.Opts(precision=L.AC_PREC_FP64, p=8, tol=1e-10, restart_m=12, max_outer=800)
+    b = first_block_rhs(nx * nx, ell, seed=4)
+    xs = [G.dev(np.ones(n)), G.dev(np.zeros(n))]
+    ws = api.workspace(api.ac_batch_workspace_size(G.ctx(), [p, q], bopts))
+    infos = api.ac_batch_solve(G.ctx(), [p, q], bopts, [G.dev(np.zeros(n)), G.dev(b)], xs, ws)
+    assert infos[0]["converged"] and infos[0]["outer_iters"] == 0 and not G.host(xs[0]).any()
+    assert infos[1]["converged"] and infos[1]["rel_residual_true"] <= 1e-10
+    A = ops.build_A(2, nx, nx, kap)
+    assert G.rel(G.host(xs[1]), ops.sequential_solve(A, b, ell)) < 1e-6  # cond(calA) * tol
