@@ -52,9 +52,11 @@ def _coverage(nx, ny, vx, h, wpb, depth):
 @pytest.mark.parametrize("depth", [2, 3])
 @pytest.mark.parametrize("vx", [1, 2])
 def test_every_point_written_once(depth, vx):
-    for nx in [4, 5, 63, 64, 65, 124, 125, 126, 127, 128, 130, 248, 250, 252, 254, 256, 372, 500]:
+    for nx in [3, 4, 5, 63, 64, 65, 124, 125, 126, 127, 128, 130, 248, 250, 252, 254, 256, 372, 500]:
         if vx == 2 and (nx % 2 or nx < 128):
             continue  # two points per lane only on even grids at least 128 wide
+        if nx < depth + 1:
+            continue  # pairs need nx >= 3, blocks of three nx >= 4
         for ny in [1, 2, 7, 17]:
             for h in [1, 4, 9, 12]:
                 for wpb in [1, 4]:

@@ -27,6 +27,10 @@ CASES = [
     (2, 500, 3, 8, 8),
     (1, 300, 1, 6, 10),
     (2, 130, 70, 16, 6),
+    (2, 3, 11, 5, 7),   # the narrowest grid with fused pairs (no blocks of three)
+    (2, 4, 9, 6, 8),    # the narrowest with blocks of three: one strip, first and last
+    (2, 5, 17, 4, 9),
+    (1, 7, 1, 3, 6),
 ]
 # (rows per wave, waves per block, points per lane); 0 = automatic
 TILINGS = [(0, 0, 0), (1, 1, 1), (5, 3, 2), (64, 4, 0)]
