@@ -65,7 +65,7 @@ typedef enum {
     AC_ERR_HIP = -4,         /* a HIP runtime call failed */
     AC_ERR_WORKSPACE = -5,   /* workspace pointer null or smaller than required */
     AC_ERR_NONFINITE = -6,   /* kappa not finite and positive, or a solve produced NaN/Inf */
-    AC_ERR_UNSUPPORTED = -7  /* e.g. l outside [2, 16], restart_m > 32 */
+    AC_ERR_UNSUPPORTED = -7  /* e.g. l outside [2, 16], l*N >= 2^31, restart_m > 32 */
 } ac_status;
 
 typedef enum { AC_BC_DIRICHLET = 0, AC_BC_PERIODIC = 1 } ac_bc;
@@ -212,7 +212,9 @@ int ac_ctx_set_tiling(ac_ctx* ctx, int rows_per_wave, int waves_per_block, int p
  * Gershgorin maximum over rows, mu_lo = 1 + min(kappa) * lambda_min(-Delta_h)
  * (lambda_min of the integer Dirichlet stencil; 0 for periodic).  The interval
  * feeds the Chebyshev centres (Proposition 1).  Checks 0 < alpha < mu_lo^l
- * (Corollary 1) and l in [2, 16].  Synchronises the stream. */
+ * (Corollary 1) and l in [2, 16].  AC_ERR_UNSUPPORTED when l*N (plus 64 values of
+ * padding per frequency) reaches 2^31: block vectors are addressed with 32-bit
+ * element offsets.  Synchronises the stream. */
 int ac_problem_create(ac_ctx* ctx, const ac_grid* grid, const double* kappa_dev, int ell, double alpha,
                       const ac_bounds* bounds, ac_problem** out);
 int ac_problem_destroy(ac_problem* p);
@@ -244,7 +246,8 @@ int ac_mg_vcycle(ac_problem* p, int nvec, const double* shifts, const double* b,
  * refer to that block.  Every ac_* call on the problem then applies the varying
  * blocks in calA (ac_apply_A, the residuals of ac_solve).  Corollary 1 no longer
  * bounds the spectrum, so the outer Chebyshev iteration and batched solves return
- * AC_ERR_UNSUPPORTED; FGMRES is the outer solver.  Synchronises. */
+ * AC_ERR_UNSUPPORTED; FGMRES is the outer solver.  The l*N limit of ac_problem_create
+ * applies.  Synchronises. */
 int ac_problem_create_blocks(ac_ctx* ctx, const ac_grid* grid, const double* kappa_blocks, int ell, double alpha,
                              const ac_bounds* bounds, ac_problem** out);
 /* Interval used for the FP64 inner solve (host outputs). */

@@ -218,6 +218,12 @@ long long slice_elems(const ac_problem* p, int m) {
     return (e + 63) / 64 * 64;
 }
 
+// Kernels address block vectors and spectral buffers (l*N values, each slice padded to
+// 64) with 32-bit element offsets: keep the padded total below 2^31.
+bool block_elems_too_large(long long n, int ell) {
+    return n * ell + 64LL * (ell / 2 + 1) > (1LL << 31) - 1;
+}
+
 // offsets by frequency m = 0..ns-1 (ABI order), last entry = total
 void spectral_offsets(const ac_problem* p, long long* off) {
     long long o = 0;
@@ -1452,6 +1458,8 @@ int ac_problem_create(ac_ctx* c, const ac_grid* grid, const double* kappa, int e
     if (ell < 2 || ell > kMaxEll) return fail(AC_ERR_UNSUPPORTED, "l must be in [2, 16]");
     if (!(alpha > 0.0) || !std::isfinite(alpha)) return fail(AC_ERR_ALPHA, "alpha must be positive and finite");
     if (static_cast<long long>(grid->nx) * grid->ny > (1LL << 31) - 1) return fail(AC_ERR_UNSUPPORTED, "N too large");
+    if (block_elems_too_large(static_cast<long long>(grid->nx) * grid->ny, ell))
+        return fail(AC_ERR_UNSUPPORTED, "l*N too large (block vectors use 32-bit element offsets)");
     AC_HIP(hipSetDevice(c->device));
 
     auto* p = new ac_problem();
@@ -1549,6 +1557,8 @@ int ac_problem_create_blocks(ac_ctx* c, const ac_grid* grid, const double* kappa
     if (ell < 2 || ell > kMaxEll) return fail(AC_ERR_UNSUPPORTED, "l must be in [2, 16]");
     if (grid->nx < 1 || grid->ny < 1) return fail(AC_ERR_ARG, "grid sizes must be positive");
     if (static_cast<long long>(grid->nx) * grid->ny > (1LL << 31) - 1) return fail(AC_ERR_UNSUPPORTED, "N too large");
+    if (block_elems_too_large(static_cast<long long>(grid->nx) * grid->ny, ell))
+        return fail(AC_ERR_UNSUPPORTED, "l*N too large (block vectors use 32-bit element offsets)");
     AC_HIP(hipSetDevice(c->device));
     const size_t n = static_cast<size_t>(grid->nx) * static_cast<size_t>(grid->ny);
     const int nblk = ac::setup_blocks();

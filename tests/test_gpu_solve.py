@@ -9,6 +9,7 @@ must match to 1e-6.
 
 import numpy as np
 import pytest
+import torch
 
 from oracle import operators as ops
 from oracle import precond as pc
@@ -156,6 +157,12 @@ def test_errors():
         with pytest.raises(api.L.AlphacircError) as e:
             G.problem(1, n, 1, kap, ell, 1e-2)
         assert e.value.status == L.AC_ERR_UNSUPPORTED
+    # l*N at 2^31 (block vectors use 32-bit element offsets): 16385 x 8192 points, l = 16
+    big = torch.full((16385 * 8192,), 5.0, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(api.L.AlphacircError) as e:
+        api.ac_problem_create(G.ctx(), 2, 16385, 8192, big, 16, 1e-2)
+    assert e.value.status == L.AC_ERR_UNSUPPORTED
+    del big
     bad = kap.copy()
     bad[3] = -1.0
     with pytest.raises(api.L.AlphacircError) as e:
