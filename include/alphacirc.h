@@ -274,12 +274,14 @@ int ac_prec_workspace_size(const ac_problem* p, const ac_solve_opts* opts, size_
 int ac_solve_workspace_size(const ac_problem* p, const ac_solve_opts* opts, size_t* bytes);
 
 /* ---- operators (Section 1 eq. (1); Section 2.2 eq. (4); Section 3) ------- */
-/* y = calA x: y_k = A x_k - x_{k-1}, x_0 := 0 (float64; x, y: l*N, must not overlap). */
+/* y = calA x: y_k = A x_k - x_{k-1}, x_0 := 0 (float64; x, y: l*N, must not overlap:
+ * AC_ERR_ARG). */
 int ac_apply_A(ac_problem* p, const double* x, double* y);
 
 /* z = P_NC^{-1} r (nested Chebyshev, opts->precision / p_per_shift / inner), the
  * three steps fused into first/last Chebyshev sweeps.  With p_m -> infinity this
- * tends to the exact P_alpha^{-1} r of eq. (4).  r, z: l*N float64, must not overlap. */
+ * tends to the exact P_alpha^{-1} r of eq. (4).  r, z: l*N float64, must not overlap
+ * (AC_ERR_ARG). */
 int ac_apply_prec(ac_problem* p, const ac_solve_opts* opts, const double* r, double* z, void* ws, size_t ws_bytes);
 
 /* Spectral buffers used by the three stages below: l_s shift slices, slice m of
@@ -311,7 +313,7 @@ int ac_shifted_residual(ac_problem* p, int precision, const void* rhat, const vo
  * Arnoldi by modified Gram-Schmidt in inverse compact WY form (two sweeps over
  * the basis per step), all in float64; Givens
  * rotations on the host.  x holds the initial guess on entry and the solution on
- * return.  Converged when the TRUE relative residual ||b - calA x||/||b|| <= tol
+ * return; b and x must not overlap (AC_ERR_ARG).  Converged when the TRUE relative residual ||b - calA x||/||b|| <= tol
  * (the paper's residual definition, Section 5).  A zero b gives x = 0 and zeroed
  * info, with no iteration.  Synchronises once per iteration.  info may be NULL.
  * Returns AC_NOT_CONVERGED after max_outer. */

@@ -218,6 +218,14 @@ long long slice_elems(const ac_problem* p, int m) {
     return (e + 63) / 64 * 64;
 }
 
+// True when the device ranges [a, a + bytes) and [b, b + bytes) intersect.
+bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+    const auto x = reinterpret_cast<uintptr_t>(a), y = reinterpret_cast<uintptr_t>(b);
+    return x < y + bytes && y < x + bytes;
+}
+
+size_t block_bytes(const ac_problem* p) { return static_cast<size_t>(p->ell) * p->g.n * sizeof(double); }
+
 // Kernels address block vectors and spectral buffers (l*N values, each slice padded to
 // 64) with 32-bit element offsets: keep the padded total below 2^31.
 bool block_elems_too_large(long long n, int ell) {
@@ -1796,12 +1804,14 @@ int ac_solve_workspace_size(const ac_problem* p, const ac_solve_opts* o, size_t*
 
 int ac_apply_A(ac_problem* p, const double* x, double* y) {
     if (!p || !x || !y) return fail(AC_ERR_ARG, "NULL argument");
+    if (ranges_overlap(x, y, block_bytes(p))) return fail(AC_ERR_ARG, "x and y overlap");
     AC_HIP(hipSetDevice(p->ctx->device));
     return calA_impl(p, x, y, nullptr, nullptr);
 }
 
 int ac_apply_prec(ac_problem* p, const ac_solve_opts* o, const double* r, double* z, void* ws, size_t ws_bytes) {
     if (!p || !r || !z) return fail(AC_ERR_ARG, "NULL argument");
+    if (ranges_overlap(r, z, block_bytes(p))) return fail(AC_ERR_ARG, "r and z overlap");
     std::vector<int> pm;
     AC_TRY(validate_opts(p, o, pm));
     if (!ws || ws_bytes < prec_ws_bytes(p, o->precision, o->inner)) return fail(AC_ERR_WORKSPACE, "workspace too small");
@@ -2003,6 +2013,7 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
                ac_solve_info* info, double* rec, int rec_count, int* rec_done) {
     const auto t0 = std::chrono::steady_clock::now();
     if (!p || !b || !x) return fail(AC_ERR_ARG, "NULL argument");
+    if (ranges_overlap(b, x, block_bytes(p))) return fail(AC_ERR_ARG, "b and x overlap");
     std::vector<int> pm;
     AC_TRY(validate_opts(p, o, pm));
     if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
@@ -2290,8 +2301,10 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
     const auto t0 = std::chrono::steady_clock::now();
     AC_TRY(validate_batch(c, count, probs, o));
     if (!b || !x) return fail(AC_ERR_ARG, "NULL argument");
-    for (int q = 0; q < count; ++q)
+    for (int q = 0; q < count; ++q) {
         if (!b[q] || !x[q]) return fail(AC_ERR_ARG, "NULL right-hand side or solution");
+        if (ranges_overlap(b[q], x[q], block_bytes(probs[q]))) return fail(AC_ERR_ARG, "b and x overlap");
+    }
     if (!ws || ws_bytes < batch_ws_bytes(count, probs, o)) return fail(AC_ERR_WORKSPACE, "workspace too small");
     AC_HIP(hipSetDevice(c->device));
     const int m = o->restart_m;

@@ -200,6 +200,19 @@ def test_errors():
     x = G.dev(np.ones(4 * n))
     info = api.ac_solve(p, opts, G.dev(np.zeros(4 * n)), x, sws)
     assert info["converged"] and not G.host(x).any()
+    # overlapping operands are rejected before any kernel runs; adjacent ones are not
+    w = G.dev(np.ones(8 * n))
+    lo_, hi_ = w[: 4 * n], w[n: 5 * n]
+    for call in (lambda: api.ac_apply_A(p, lo_, hi_), lambda: api.ac_apply_A(p, lo_, lo_),
+                 lambda: api.ac_apply_prec(p, api.Opts(p=3), lo_, hi_, ws),
+                 lambda: api.ac_solve(p, opts, hi_, lo_, sws)):
+        with pytest.raises(api.L.AlphacircError) as e:
+            call()
+        assert e.value.status == L.AC_ERR_ARG
+    api.ac_apply_A(p, w[: 4 * n], w[4 * n:])
+    y = G.dev(np.zeros(4 * n))
+    api.ac_apply_A(p, G.dev(np.ones(4 * n)), y)
+    assert np.array_equal(G.host(w[4 * n:]), G.host(y))
 
 
 def test_zero_rhs_outer_chebyshev_and_batch():
