@@ -13,13 +13,15 @@ Readings of the paper used here:
 
 Pins (tests/test_oracle_operators.py): the constant-coefficient spectrum and
 sine eigenvectors of Appendix A, the periodic DFT eigenvalues, the all-at-once
-solve against the sequential chain A x_{k+1} = x_k (Section 1), Gershgorin /
-Rayleigh bounds against eigsh.
+solve against the sequential chain A x_{k+1} = x_k (Section 1), the closed-form
+(sine-transform) chain against the sparse direct chain and against the assembled
+all-at-once matrix, Gershgorin / Rayleigh bounds against eigsh.
 """
 
 from __future__ import annotations
 
 import numpy as np
+import scipy.fft as sfft
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
@@ -103,6 +105,28 @@ def sequential_solve(A: sp.spmatrix, b: np.ndarray, ell: int) -> np.ndarray:
     for k in range(ell):
         X[k] = lu.solve(B[k] + prev)
         prev = X[k]
+    return X.reshape(-1)
+
+
+def sequential_solve_closed_form(dim: int, nx: int, ny: int, kappa: float, b: np.ndarray, ell: int) -> np.ndarray:
+    """The chain of sequential_solve for a constant coefficient on a Dirichlet grid, at
+    any size in O(l N log N): the orthonormal DST-I per axis diagonalises A (Appendix A:
+    sine eigenvectors, eigenvalues mu = 1 + 4 kappa sum_d sin^2(.)), so in mode space
+    every link of the chain A x_1 = b_1, A x_k = b_k + x_{k-1} (Section 1) is a division
+    by mu."""
+    if dim == 1:
+        ny = 1
+    n = nx * ny
+    shape = (nx,) if dim == 1 else (ny, nx)
+    axes = (0,) if dim == 1 else (0, 1)
+    mu = dirichlet_eigs(dim, nx, ny, float(kappa))
+    B = np.asarray(b, dtype=np.float64).reshape(ell, n)
+    X = np.empty((ell, n))
+    prev_hat = np.zeros(shape)
+    for k in range(ell):
+        rhs_hat = sfft.dstn(B[k].reshape(shape), type=1, axes=axes, norm="ortho") + prev_hat
+        prev_hat = rhs_hat / mu
+        X[k] = sfft.idstn(prev_hat, type=1, axes=axes, norm="ortho").reshape(-1)
     return X.reshape(-1)
 
 

@@ -711,7 +711,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 pa.soff[j] = static_cast<unsigned>(off[slot_to_m(p, sl)]);
                 fill_cf(pa.cf[0], j, cs[sl], k);
                 fill_cf(pa.cf[1], j, cs[sl], k + 1);
-                bytes += 8.0 * (slot_is_real(p, sl) ? esz_r : esz_c);  // two steps of 4 streams
+                bytes += 5.0 * (slot_is_real(p, sl) ? esz_r : esz_c);  // x_k, x_{k-1}, rhat in; two out
                 anyc = true;
             }
             if (!anyc) continue;
@@ -719,9 +719,9 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             if (e != hipSuccess) return e;
             ++launched;
         }
-        // algorithmic bytes of the two steps as unfused sweeps (kappa once per step), the
-        // unit every steady sweep is measured in; the pair itself moves 5 of the 8 streams
-        bytes = (bytes + 2.0 * ksz) * static_cast<double>(p->g.n);
+        // the pair's own minimum traffic: 5 vector streams per computing shift, kappa once
+        // per launch (two unfused steps would move 8 streams and kappa twice)
+        bytes = (bytes + static_cast<double>(launched) * ksz) * static_cast<double>(p->g.n);
         return hipSuccess;
     };
     // Three steps per sweep: one launch per complex shift, one per (up to) two real shifts.
@@ -763,8 +763,9 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 g.comp[j] = 1;
                 g.soff[j] = static_cast<unsigned>(off[slot_to_m(p, sl)]);
                 for (int t = 0; t < 3; ++t) fill_cf(g.cf[t], j, cs[sl], k + t);
-                // unfused streams of the three steps: 4 each; from a zero guess 2 + 3 + 4
-                bytes += (first ? 9.0 : 12.0) * (slot_is_real(p, sl) ? esz_r : esz_c);
+                // the block's own minimum: x_k, x_{k-1}, rhat in, x_{k+2}, x_{k+3} out; from a
+                // zero guess rhat in, two out
+                bytes += (first ? 3.0 : 5.0) * (slot_is_real(p, sl) ? esz_r : esz_c);
                 anyc = true;
             }
             if (p->ctx->rec) {
@@ -790,9 +791,9 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
             const hipError_t e = go(1, sl, 1);
             if (e != hipSuccess) return e;
         }
-        // unfused algorithmic bytes of the three steps (kappa once per step); the block
-        // itself moves 5 of the 12 vector streams
-        bytes = (bytes + 3.0 * ksz) * static_cast<double>(p->g.n);
+        // kappa once per launch (three unfused steps would move 12 vector streams per shift,
+        // from a zero guess 9, and kappa three times)
+        bytes = (bytes + static_cast<double>(launched) * ksz) * static_cast<double>(p->g.n);
         return hipSuccess;
     };
     // length of the run of steady steps from k in which the same shifts compute

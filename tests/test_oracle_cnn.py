@@ -177,3 +177,24 @@ def test_residual_loss_network_gradients_match_finite_differences():
             flat[i] = old
             fd = (Lp - Lm) / (2 * h)
             assert abs(fd - g[k].reshape(-1)[i]) <= 1e-6 * max(1.0, abs(fd)), (k, i)
+
+
+def test_make_inputs_hand_computed_planes():
+    """The five input planes of one shift on a 2 x 3 grid, written out by hand: channel
+    0/1 the real/imaginary part of rhat divided by the scale, 2/3 the real/imaginary part
+    of the shift (constant planes), 4 the normalised log-coefficient (ln kappa - c0)/c1.
+    A swapped channel, a missing scale or a wrong normalisation fails it."""
+    rhat = np.array([[2.0 + 4.0j, -6.0 + 0.0j, 0.0 + 1.0j],
+                     [1.0 - 2.0j, 0.0 + 0.0j, -3.0 - 3.0j]])
+    kappa = np.exp(np.array([1.0, 3.0, 5.0, 0.0, 2.0, 7.0]))  # ln kappa = 1, 3, 5, 0, 2, 7
+    X = cnn.make_inputs(rhat, 0.25 - 0.5j, kappa, c0=1.0, c1=2.0, scale=2.0)
+    assert X.shape == (2, 3, 5)
+    expect = {
+        0: [[1.0, -3.0, 0.0], [0.5, 0.0, -1.5]],
+        1: [[2.0, 0.0, 0.5], [-1.0, 0.0, -1.5]],
+        2: [[0.25] * 3, [0.25] * 3],
+        3: [[-0.5] * 3, [-0.5] * 3],
+        4: [[0.0, 1.0, 2.0], [-0.5, 0.5, 3.0]],
+    }
+    for c, plane in expect.items():
+        assert np.allclose(X[..., c], plane, rtol=0, atol=1e-15), c

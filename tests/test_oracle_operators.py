@@ -125,6 +125,33 @@ def test_all_at_once_equals_sequential(ell):
     assert np.allclose(x_seq[n:2 * n], x2, rtol=1e-13, atol=1e-15)
 
 
+@pytest.mark.parametrize("dim,nx,ny,ell,kappa", [(1, 31, 1, 4, 25.0), (2, 9, 7, 5, 3.0), (2, 16, 11, 10, 50.0)])
+def test_closed_form_chain_equals_direct_solves(dim, nx, ny, ell, kappa):
+    """Constant kappa, Dirichlet: the sine-transform chain equals the sparse LU chain and
+    the direct solve of the assembled all-at-once matrix of eq. (1), for a rhs with every
+    block nonzero (so the x_{k-1} coupling of every link is exercised)."""
+    n = nx * (ny if dim == 2 else 1)
+    b = random_block_vector(n, ell, seed=11)
+    A = ops.build_A(dim, nx, ny, kappa)
+    x_cf = ops.sequential_solve_closed_form(dim, nx, ny, kappa, b, ell)
+    x_seq = ops.sequential_solve(A, b, ell)
+    x_dir = spla.spsolve(ops.build_calA(A, ell).tocsc(), b)
+    assert np.linalg.norm(x_cf - x_seq) < 1e-13 * np.linalg.norm(x_seq)
+    assert np.linalg.norm(x_cf - x_dir) < 1e-13 * np.linalg.norm(x_dir)
+
+
+def test_closed_form_chain_single_mode():
+    """One sine eigenvector as b_1 (Appendix A): x_k = mu^{-k} V_j exactly."""
+    nx, ell, kappa, j = 20, 6, 7.0, 3
+    v = ops.sine_vector(nx, j)
+    mu = 1.0 + 4.0 * kappa * np.sin(j * np.pi / (2 * (nx + 1))) ** 2
+    b = np.zeros(ell * nx)
+    b[:nx] = v
+    x = ops.sequential_solve_closed_form(1, nx, 1, kappa, b, ell).reshape(ell, nx)
+    for k in range(ell):
+        assert np.allclose(x[k], v / mu ** (k + 1), rtol=1e-13, atol=1e-16)
+
+
 def test_varying_blocks_reduce_to_constant_blocks():
     rng = np.random.default_rng(21)
     nx, ny, ell = 6, 5, 4

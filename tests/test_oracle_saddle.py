@@ -182,3 +182,35 @@ def test_apply_prec_sp_conjugate_branches_agree():
     r = random_block_vector(nx * ny, ell, seed=3)
     y = sd.apply_prec_sp(A, r, ell, alpha, 5, L, return_complex=True)
     assert np.max(np.abs(y.imag)) < 1e-12 * np.max(np.abs(y.real))
+
+
+@pytest.mark.parametrize("nx", [15, 16, 9])
+def test_multigrid_coarse_faces_are_halved_schur_complement_1d(nx):
+    """1D coarse-face rule against exact elimination: removing the fine points that are
+    not coarse points (0, 2, 4, ...) from the pure-diffusion part A - I of the fine level
+    leaves a tridiagonal Schur complement on the coarse points; its off-diagonals are the
+    series conductances ab/(a + b) of the two fine faces between coarse neighbours, and
+    its Dirichlet terms those of a fine interior face in series with the boundary face.
+    The coarse level's faces (spacing 2h, full-weighting scale 1/2) are exactly half of
+    it, on odd and even sizes (the even size's high end keeps its own boundary face)."""
+    kap = np.exp(np.random.default_rng(nx).normal(0.0, 1.5, nx))
+    fine = mg.fine_level(1, nx, 1, kap)
+    coarse = mg.coarsen(fine)
+    Ld = (mg.level_matrix(fine) - sp.identity(nx)).toarray()
+    C = np.arange(1, nx, 2)
+    F = np.setdiff1d(np.arange(nx), C)
+    S = Ld[np.ix_(C, C)] - Ld[np.ix_(C, F)] @ np.linalg.solve(Ld[np.ix_(F, F)], Ld[np.ix_(F, C)])
+    Lc = (mg.level_matrix(coarse) - sp.identity(len(C))).toarray()
+    assert Lc.shape == S.shape
+    assert np.allclose(Lc, 0.5 * S, rtol=1e-13, atol=1e-13)
+
+
+def test_multigrid_constant_kappa_coarse_level_is_rediscretisation():
+    """Constant kappa on a 15 x 15 grid: the coarse level is I + (kappa/4)(-Delta) on the
+    7 x 7 coarse points, the textbook rediscretisation at twice the spacing (kappa =
+    nu/h^2 becomes nu/(2h)^2)."""
+    kappa = 12.0
+    levels = mg.hierarchy(2, 15, 15, kappa)
+    assert (levels[1].nx, levels[1].ny) == (7, 7)
+    ref = ops.build_A(2, 7, 7, kappa / 4.0)
+    assert np.allclose(mg.level_matrix(levels[1]).toarray(), ref.toarray(), rtol=1e-14, atol=1e-13)
