@@ -284,6 +284,21 @@ int ac_apply_A(ac_problem* p, const double* x, double* y);
  * (AC_ERR_ARG). */
 int ac_apply_prec(ac_problem* p, const ac_solve_opts* opts, const double* r, double* z, void* ws, size_t ws_bytes);
 
+/* z = P_NC^{-1} r exactly as ac_apply_prec (AC_INNER_CHEB only), for callers that
+ * cannot allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): no workspace argument, no allocation.  The
+ * workspace is a fixed array of AC_NOALLOC_SCRATCH_BYTES in device memory that every
+ * GPU the library runs on holds until the process ends (its address is looked up once
+ * per device by ac_ctx_create).  Problems whose ac_prec_workspace_size exceeds it
+ * return AC_ERR_WORKSPACE (e.g. 512 x 512 with l = 10 fits in complex64, not in
+ * float64); other inner modes AC_ERR_UNSUPPORTED.  All calls on one device share the
+ * array: calls that overlap in time on one device (several host threads or streams)
+ * race; serialise them.  r, z: l*N float64, must not overlap (AC_ERR_ARG).
+ * Asynchronous on the context's stream; with profiling off it calls no allocating
+ * runtime or library routine. */
+#define AC_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int ac_apply_prec_noalloc(ac_problem* p, const ac_solve_opts* opts, const double* r, double* z);
+
 /* Spectral buffers used by the three stages below: l_s shift slices, slice m of
  * ac_spectral_offsets()[m] elements of the inner real type (float64 for
  * AC_PREC_FP64, float32 otherwise), real shifts (m = 0, and m = l/2 for even l) as

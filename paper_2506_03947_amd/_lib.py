@@ -34,6 +34,8 @@ AC_INNER_CHEB_CNN = 1
 AC_INNER_CHEB_CNN_CYCLE = 2
 AC_INNER_EXACT = 3
 AC_INNER_SP = 4
+AC_NOALLOC_SCRATCH_BYTES = 64 << 20  # fixed device scratch of ac_apply_prec_noalloc
+
 AC_OUTER_FGMRES = 0
 AC_OUTER_CHEBYSHEV = 1
 
@@ -117,6 +119,7 @@ SIGNATURES = {
     "ac_solve_workspace_size": (_I, [_VP, C.POINTER(ac_solve_opts), C.POINTER(_SZ)]),
     "ac_apply_A": (_I, [_VP, _VP, _VP]),
     "ac_apply_prec": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _SZ]),
+    "ac_apply_prec_noalloc": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP]),
     "ac_spectral_offsets": (_I, [_VP, _I, C.POINTER(C.c_longlong)]),
     "ac_tdft_forward": (_I, [_VP, _I, _VP, _VP]),
     "ac_shifted_cheb": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _VP, _SZ]),

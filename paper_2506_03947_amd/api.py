@@ -215,6 +215,15 @@ def ac_apply_prec(p: Problem, opts: Opts, r: torch.Tensor, z: torch.Tensor, ws: 
           "ac_apply_prec")
 
 
+def ac_apply_prec_noalloc(p: Problem, opts: Opts, r: torch.Tensor, z: torch.Tensor) -> None:
+    """ac_apply_prec with the library's fixed device scratch as workspace (no allocation)."""
+    n = p.ell * p.n
+    o, keep = opts.to_c(p.ell)
+    check(L.load().ac_apply_prec_noalloc(p.h, C.byref(o), _f64(r, n, "r"), _f64(z, n, "z")),
+          "ac_apply_prec_noalloc")
+    del keep
+
+
 def ac_spectral_offsets(p: Problem, precision: int) -> list[int]:
     off = (C.c_longlong * (p.ns + 1))()
     check(L.load().ac_spectral_offsets(p.h, precision, off), "ac_spectral_offsets")

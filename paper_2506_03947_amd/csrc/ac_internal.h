@@ -5,6 +5,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <string>
+
+struct ac_problem;  // the ABI's opaque problem (alphacirc.h)
 
 namespace ac {
 
@@ -356,5 +359,14 @@ hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, ui
 // entries that are not finite and positive.
 hipError_t launch_kappa_mean(const double* kb, int ell, long long n, double* mean, double* bad, hipStream_t s);
 int setup_blocks();
+
+// ---- host plumbing shared across translation units ---------------------------------
+// Records msg as the calling thread's last error (ac_last_error) and returns status.
+int set_error(int status, const std::string& msg);
+// Device of a problem's context.
+int problem_device(const ::ac_problem* p);
+// Looks up, with that device current, the device address of the fixed scratch array of
+// ac_apply_prec_noalloc for the device (once per device; noalloc.hip).
+int noalloc_scratch_init(int device);
 
 }  // namespace ac

@@ -56,6 +56,11 @@ int fail(int status, const std::string& msg) {
     } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+}  // namespace
+
+int ac::set_error(int status, const std::string& msg) { return fail(status, msg); }
+
+namespace {
 
 constexpr double kPi = 3.14159265358979323846;
 
@@ -136,6 +141,8 @@ struct ac_problem {
         int iters = 0, prec = -1;
     } spg;
 };
+
+int ac::problem_device(const ac_problem* p) { return p->ctx->device; }
 
 struct ac_cnn {
     ac_ctx* ctx = nullptr;
@@ -1391,6 +1398,14 @@ int ac_ctx_create(int device, void* stream, ac_ctx** out) {
         (void)hipHostFree(c->pinned);
         delete c;
         return fail(AC_ERR_HIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+    }
+    const int ns = ac::noalloc_scratch_init(device);
+    if (ns < 0) {
+        (void)hipStreamDestroy(c->cap);
+        (void)rocblas_destroy_handle(c->blas);
+        (void)hipHostFree(c->pinned);
+        delete c;
+        return ns;
     }
     *out = c;
     return AC_OK;
