@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 # sources that decide the three-step sweep's traffic: its device body and launch files, and
 # the host code that picks its tiling
-TRIPLE_SOURCES = ["stencil_triple.h", "stencil_kernels.h", "stencil_triple.hip", "api.hip"]
+TRIPLE_SOURCES = ["stencil_triple.h", "stencil_kernels.h", "stencil_triple.hip", "tiling.h"]
 
 WORKLOADS = {
     "large": {"nx": 2048, "ny": 2048, "ell": 10, "alpha": 1e-2, "kappa0": 50.0, "std": 1.0, "corr": 10.0},
@@ -62,7 +62,7 @@ def parse():
                     help="tiling of the paired sweep (0 = automatic)")
     ap.add_argument("--step-triples", type=int, default=1, choices=[0, 1],
                     help="fuse three steady Chebyshev steps per sweep (1) or at most two (0)")
-    ap.add_argument("--triple-tiling", type=int, nargs=3, default=[0, 0, 0], metavar=("ROWS", "WPB", "VX"),
+    ap.add_argument("--triple-tiling", type=int, nargs=3, default=[0, 0, 0], metavar=("ROWS", "OCC", "VX"),
                     help="tiling of the three-step sweep (0 = automatic)")
     ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp", "blocks", "paper"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
@@ -441,11 +441,12 @@ def kernels_only(a, api, prob, ell, n):
         api.ac_apply_prec(prob, opts, r, z, ws)
     stats = api.ac_ctx_kernel_stats(ctx)
     api.ac_ctx_set_profiling(ctx, False)
+    out_ceil = stream_ceilings(api, ctx)
     src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)  # 512 MiB
     dst = torch.empty_like(src)
     dst.copy_(src)
     torch.cuda.synchronize()
-    out = {"mode": "kernels", "copy_bytes_each_way": src.numel() * 8}
+    out = {"mode": "kernels", "copy_bytes_each_way": src.numel() * 8, "stream_ceilings_GBps": out_ceil}
     for name in ("cheb_step", "cheb_pair", "cheb_triple"):
         st = stats[name]
         if st["launches"]:
@@ -454,6 +455,17 @@ def kernels_only(a, api, prob, ell, n):
             out[name] = {"avg_ms": avg_ms, "bytes_per_launch": per, "GBps": per / avg_ms / 1e6,
                          "launches": st["launches"]}
     print(json.dumps(out), flush=True)
+
+
+def stream_ceilings(api, ctx, bytes_total=5 * 512 * 1024 * 1024):
+    """GB/s of the library's pure streaming kernel for a few read / write mixes."""
+    ws = api.workspace(bytes_total)
+    out = {}
+    for name, (r, w) in (("read", (1, 0)), ("copy", (1, 1)), ("triad", (2, 1)), ("3R2W", (3, 2))):
+        out[name] = api.ac_stream_bandwidth(ctx, r, w, ws, reps=20)
+    del ws
+    log(f"stream ceilings GB/s: {out}")
+    return out
 
 
 def log(msg):
@@ -661,6 +673,13 @@ def main():
                             "traffic = rocprofv3 FETCH_SIZE + WRITE_SIZE per launch (scaled by a copy of known "
                             "size); effective_GBps = the unfused single-step bytes of the same steps / the same "
                             "time (not a bandwidth)")
+
+    # streaming ceilings of this GPU for the read / write mixes in question (a kernel that
+    # only moves its streams): read-only, copy, triad, and the fused block's 3 reads + 2
+    # writes
+    ceilings = stream_ceilings(api, ctx)
+    roofline["stream_ceilings_GBps"] = ceilings
+    roofline["frac_of_stream_ceiling"] = achieved / ceilings["3R2W"]
 
     # the other inner budgets of the workload (p = 5, 10): same solve, fewer steps per shift
     budgets = {}

@@ -362,16 +362,31 @@ int ac_ctx_set_shift_groups(ac_ctx* ctx, int mode);
  * Batched solves (ac_batch_solve) run single steps. */
 int ac_ctx_set_step_pairs(ac_ctx* ctx, int mode, int rows_per_wave, int waves_per_block, int points_per_lane);
 
-/* Three steady Chebyshev steps per sweep: mode 1 (default) fuses runs of steady steps
- * in which the same shifts compute into blocks of three (a remainder of two as a pair,
- * of one as a single step), where pairs are allowed (mode 1 of ac_ctx_set_step_pairs,
- * Dirichlet grids, buffers below 2^31 bytes).  A block reads x_k, x_{k-1} and rhat
- * once and writes x_{k+2} and x_{k+3} (x_{k+1} stays in registers), one launch per
- * complex shift and per two real shifts.  The iterates are those of single steps up to
- * rounding (a few ulps per step).  Tiling arguments as for pairs
- * (automatic: rows for about one round of waves, 4 waves per block).  Profiling
- * (AC_K_CHEB_TRIPLE) counts the three steps' unfused algorithmic bytes. */
-int ac_ctx_set_step_triples(ac_ctx* ctx, int mode, int rows_per_wave, int waves_per_block, int points_per_lane);
+/* Three steady Chebyshev steps per sweep (Section 3's recurrence, temporally blocked):
+ * mode 1 (default) fuses runs of steady steps in which the same shifts compute into
+ * blocks of three (a remainder of two as a pair, of one as a single step), where pairs
+ * are allowed (mode 1 of ac_ctx_set_step_pairs, Dirichlet grids, buffers below 2^31
+ * bytes); the first three steps from a zero guess form a block too.  A block reads
+ * x_k, x_{k-1} and rhat once and writes x_{k+2} and x_{k+3} (x_{k+1} stays in
+ * registers), in one launch over every shift: a workgroup per tile (a strip of grid
+ * columns by rows_per_wave rows) with one wave per shift group (the real shifts
+ * together, each complex shift alone).  The iterates are those of single steps up to
+ * rounding (a few ulps per step).  rows_per_wave 0 picks the height for about one round
+ * of workgroups at waves_per_simd waves per SIMD (0: 4); points_per_lane 0 picks 2 in
+ * float32 on even grids at least 128 wide, else 1.  Profiling (AC_K_CHEB_TRIPLE,
+ * AC_K_CHEB_FIRST) counts each launch's own minimum bytes: the vector streams it
+ * reads and writes once each and kappa once. */
+int ac_ctx_set_step_triples(ac_ctx* ctx, int mode, int rows_per_wave, int waves_per_simd, int points_per_lane);
+
+/* ---- measurement ------------------------------------------------------------
+ * Streaming-bandwidth calibration (not part of the method): times reps passes of one
+ * kernel that reads `reads` and writes `writes` contiguous streams (each 0..4, not both
+ * zero) of equal length carved from ws (16-byte aligned; ws_bytes / (16 (reads +
+ * writes)) float32x4 elements per stream, at least 1024), plain loads and non-temporal
+ * stores, on the context's stream.  gbps (host): bytes moved per second / 1e9, the
+ * ceiling for a memory-bound kernel with that read / write mix.  Overwrites ws (zeroes it
+ * first).  Synchronises. */
+int ac_stream_bandwidth(ac_ctx* ctx, int reads, int writes, void* ws, size_t ws_bytes, int reps, double* gbps);
 
 /* ---- tiling ----------------------------------------------------------------
  * Sweep tiling of one problem (overrides the context's ac_ctx_set_tiling; 0 keeps

@@ -120,6 +120,7 @@ SIGNATURES = {
     "ac_apply_A": (_I, [_VP, _VP, _VP]),
     "ac_apply_prec": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _SZ]),
     "ac_apply_prec_noalloc": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP]),
+    "ac_stream_bandwidth": (_I, [_VP, _I, _I, _VP, _SZ, _I, C.POINTER(_D)]),
     "ac_spectral_offsets": (_I, [_VP, _I, C.POINTER(C.c_longlong)]),
     "ac_tdft_forward": (_I, [_VP, _I, _VP, _VP]),
     "ac_shifted_cheb": (_I, [_VP, C.POINTER(ac_solve_opts), _VP, _VP, _VP, _VP, _SZ]),

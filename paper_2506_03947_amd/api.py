@@ -224,6 +224,14 @@ def ac_apply_prec_noalloc(p: Problem, opts: Opts, r: torch.Tensor, z: torch.Tens
     del keep
 
 
+def ac_stream_bandwidth(ctx: Ctx, reads: int, writes: int, ws: torch.Tensor, reps: int = 20) -> float:
+    """GB/s of a kernel that only streams `reads` inputs and `writes` outputs (calibration)."""
+    out = C.c_double()
+    check(L.load().ac_stream_bandwidth(ctx.h, int(reads), int(writes), _ptr(ws), ws.numel(), int(reps),
+                                       C.byref(out)), "ac_stream_bandwidth")
+    return out.value
+
+
 def ac_spectral_offsets(p: Problem, precision: int) -> list[int]:
     off = (C.c_longlong * (p.ns + 1))()
     check(L.load().ac_spectral_offsets(p.h, precision, off), "ac_spectral_offsets")
@@ -284,9 +292,9 @@ def ac_ctx_set_shift_groups(ctx: Ctx, mode: int) -> None:
     check(L.load().ac_ctx_set_shift_groups(ctx.h, int(mode)), "ac_ctx_set_shift_groups")
 
 
-def ac_ctx_set_step_triples(ctx: Ctx, mode: int, rows_per_wave: int = 0, waves_per_block: int = 0,
+def ac_ctx_set_step_triples(ctx: Ctx, mode: int, rows_per_wave: int = 0, waves_per_simd: int = 0,
                             points_per_lane: int = 0) -> None:
-    check(L.load().ac_ctx_set_step_triples(ctx.h, int(mode), int(rows_per_wave), int(waves_per_block),
+    check(L.load().ac_ctx_set_step_triples(ctx.h, int(mode), int(rows_per_wave), int(waves_per_simd),
                                            int(points_per_lane)), "ac_ctx_set_step_triples")
 
 

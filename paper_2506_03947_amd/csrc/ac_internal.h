@@ -7,7 +7,8 @@
 #include <cstdint>
 #include <string>
 
-struct ac_problem;  // the ABI's opaque problem (alphacirc.h)
+struct ac_problem;  // the ABI's opaque problem and context (alphacirc.h)
+struct ac_ctx;
 
 namespace ac {
 
@@ -97,22 +98,39 @@ struct PairArgs {
 // Three consecutive steady Chebyshev steps (x_{k+1} kept in registers, x_{k+2} and
 // x_{k+3} written) in one sweep, for one group: up to two real shift slots (kind 0) or
 // one complex slot (kind 1).  Strips of 64*vx computed columns advance by 64*vx - 4.
+// One shift group of a three-step block: one complex shift or up to two real shifts
+// (slots 0, 1), with the coefficients of steps k, k+1, k+2 (index t) in the folded form
+// x_{k+1} = g x_k - a x_{k-1} + c (rhat - A' x_k), A' = A without the shift,
+// g = 1 + a + c lambda (the first block of a zero-guess solve scales them for
+// x_1 = rhat / theta).
+template <typename R>
+struct TripleGroup {
+    int kind;            // 0: real slots, 1: one complex slot
+    int comp[2];         // slot computes (else skipped)
+    unsigned soff[2];    // slot offset (elements of R) inside every spectral buffer
+    R g_re[3][2], g_im[3][2];
+    R a_re[3][2], a_im[3][2];
+    R c_re[3][2], c_im[3][2];
+};
+
+// Real shifts share one group, every complex shift has its own: l <= 16 gives at most
+// one real group and seven complex ones.
+constexpr int kMaxTripleGroups = 8;
+
 template <typename R>
 struct TripleArgs {
     Geom g;
-    Tiling t;
+    Tiling t;            // one tile per workgroup, one wave per group (t.wpb = ngroups)
     const void* kappa;
-    ShiftCoef<R> cf[3];  // steps k, k+1, k+2 (slots 0, 1)
-    int comp[2];         // slot computes (else skipped)
-    unsigned soff[2];    // slot offset (elements of R) inside every spectral buffer
     const R* rhat;
     const R* cur;        // x_k
     const R* prev;       // x_{k-1}
     R* outz;             // x_{k+2}
     R* outw;             // x_{k+3}
     unsigned bytes;      // bytes of each spectral buffer (below 2^31)
-    int kind;            // 0: real slots, 1: one complex slot
     int first;           // steps 1..3 from a zero guess: x_1 = rhat / theta (never stored), x_0 = 0
+    int ngroups;
+    TripleGroup<R> grp[kMaxTripleGroups];
 };
 
 struct FwdArgs {
@@ -176,7 +194,8 @@ hipError_t launch_cheb_final(int ell, int prec, int curk, const void* args, hipS
 hipError_t launch_cheb_pair(int prec, const void* args, hipStream_t s);
 // Three steady steps per sweep (TripleArgs<double> for prec 0, else TripleArgs<float>).
 hipError_t launch_cheb_triple(int prec, const void* args, hipStream_t s);
-// Batched three-step sweeps (args TripleArgs per problem); code = kind | 2 * first.
+// Batched three-step sweeps (args TripleArgs per problem, L.wpb = their group count);
+// code = 2 * first.
 hipError_t launch_batch_triple(int prec, int code, int vx, const BatchList& L, hipStream_t s);
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
@@ -363,8 +382,10 @@ int setup_blocks();
 // ---- host plumbing shared across translation units ---------------------------------
 // Records msg as the calling thread's last error (ac_last_error) and returns status.
 int set_error(int status, const std::string& msg);
-// Device of a problem's context.
+// Device of a problem's context; a context's device and stream.
 int problem_device(const ::ac_problem* p);
+int ctx_device(const ::ac_ctx* c);
+hipStream_t ctx_stream(const ::ac_ctx* c);
 // Looks up, with that device current, the device address of the fixed scratch array of
 // ac_apply_prec_noalloc for the device (once per device; noalloc.hip).
 int noalloc_scratch_init(int device);

@@ -17,6 +17,7 @@
 
 #include "alphacirc.h"
 #include "ac_internal.h"
+#include "tiling.h"
 
 using ac::Geom;
 using ac::kMaxEll;
@@ -102,7 +103,7 @@ struct ac_ctx {
     // wave, points per lane, waves per block of the paired sweep (0 = automatic)
     int pairs = 1, pair_h = 0, pair_vx = 0, pair_wpb = 0;
     // three steady steps per sweep: 0 off, 1 on (where pairs are allowed); tiling as pairs
-    int triples = 1, triple_h = 0, triple_vx = 0, triple_wpb = 0;
+    int triples = 1, triple_h = 0, triple_vx = 0, triple_occ = 4;
     // dense sine transforms of the exact inner solve (workspace set per call)
     rocblas_handle blas = nullptr;
     // launch-bound inner solves (P_SP) are captured on this stream and replayed as graphs
@@ -143,6 +144,8 @@ struct ac_problem {
 };
 
 int ac::problem_device(const ac_problem* p) { return p->ctx->device; }
+int ac::ctx_device(const ac_ctx* c) { return c->device; }
+hipStream_t ac::ctx_stream(const ac_ctx* c) { return c->stream; }
 
 struct ac_cnn {
     ac_ctx* ctx = nullptr;
@@ -308,11 +311,9 @@ Tiling block_tiling(const ac_problem* p, int prec, int depth, int h_pref, int wp
     return t;
 }
 
-Tiling triple_tiling(const ac_problem* p, int prec) {
+Tiling triple_tiling(const ac_problem* p, int prec, int groups) {
     const ac_ctx* c = p->ctx;
-    // (automatic height as for pairs: 12 rows at 2048^2, 42 us per launch against 44 us
-    // at 9 rows and 47-54 us at 6, 8 or 16 rows)
-    return block_tiling(p, prec, 3, c->triple_h, c->triple_wpb, c->triple_vx, 3);
+    return ac::triple_tiling(p->g, prec == AC_PREC_FP64, groups, c->triple_h, c->triple_vx, c->triple_occ);
 }
 
 // (the automatic height of the paired sweep, about one round of waves at three per
@@ -731,7 +732,8 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         bytes = (bytes + static_cast<double>(launched) * ksz) * static_cast<double>(p->g.n);
         return hipSuccess;
     };
-    // Three steps per sweep: one launch per complex shift, one per (up to) two real shifts.
+    // Three steps per sweep: one launch per block over every shift group (the real shifts
+    // together, each complex shift alone), a workgroup per tile, a wave per group.
     // Recorded for a batch only with one budget for every shift, so that every problem
     // of the batch cuts its steps into the same blocks (aligned launch sequences).
     bool uniform = true;
@@ -741,7 +743,6 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     auto launch_triple = [&](int k, double& bytes, bool first) -> hipError_t {
         ac::TripleArgs<R> ta{};
         ta.g = p->g;
-        ta.t = triple_tiling(p, prec);
         ta.kappa = kap;
         ta.rhat = reinterpret_cast<const R*>(rhat);
         ta.first = first ? 1 : 0;
@@ -757,51 +758,66 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         ta.outw = reinterpret_cast<R*>(buf[bq[k + 3]]);
         ta.bytes = static_cast<unsigned>(spec_bytes);
         bytes = 0.0;
-        auto go = [&](int kind, const int* slots, int count) -> hipError_t {
-            ac::TripleArgs<R> g = ta;
+        auto add_group = [&](int kind, const int* slots, int count) {
+            ac::TripleGroup<R> g{};
             g.kind = kind;
-            g.comp[0] = g.comp[1] = 0;
             bool anyc = false;
             for (int j = 0; j < 2; ++j) {
-                g.comp[j] = 0;
-                g.soff[j] = 0;
                 const int sl = j < count ? slots[j] : -1;
                 if (sl < 0 || ps[sl] < k + 1) continue;
                 g.comp[j] = 1;
                 g.soff[j] = static_cast<unsigned>(off[slot_to_m(p, sl)]);
-                for (int t = 0; t < 3; ++t) fill_cf(g.cf[t], j, cs[sl], k + t);
+                const ChebShift& c = cs[sl];
+                const cplx sc = 1.0 / c.theta;  // x_1 = rhat / theta
+                for (int t = 0; t < 3; ++t) {
+                    const cplx at = c.a[k + t], ct = c.c[k + t];
+                    cplx gt = 1.0 + at + ct * c.lam, ax = at, cx = ct;
+                    if (first && t == 0) {
+                        // x_2 from x_1 = s rhat, x_0 = 0, the window holding rhat:
+                        // g x_1 + c (rhat - A' x_1) = (s g + c) rhat - (c s) A' rhat
+                        gt = sc * gt + ct;
+                        cx = ct * sc;
+                        ax = 0.0;
+                    } else if (first && t == 1) {
+                        ax = at * sc;  // x_{k-1} = x_1 = s rhat, passed as rhat
+                    }
+                    g.g_re[t][j] = static_cast<R>(gt.real());
+                    g.g_im[t][j] = static_cast<R>(gt.imag());
+                    g.a_re[t][j] = static_cast<R>(ax.real());
+                    g.a_im[t][j] = static_cast<R>(ax.imag());
+                    g.c_re[t][j] = static_cast<R>(cx.real());
+                    g.c_im[t][j] = static_cast<R>(cx.imag());
+                }
                 // the block's own minimum: x_k, x_{k-1}, rhat in, x_{k+2}, x_{k+3} out; from a
                 // zero guess rhat in, two out
                 bytes += (first ? 3.0 : 5.0) * (slot_is_real(p, sl) ? esz_r : esz_c);
                 anyc = true;
             }
-            if (p->ctx->rec) {
-                // batched: a fixed number of positions per block (empty ones with no
-                // blocks) so that problems with different l record aligned sequences
-                record_launch(p->ctx, ac::BOP_TRIPLE, 3, prec, kind | (first ? 2 : 0), g.t.vx, g.t.wpb,
-                              anyc ? g.t.blocks : 0, g);
-                return hipSuccess;
-            }
-            if (!anyc) return hipSuccess;
-            const hipError_t e = ac::launch_cheb_triple(prec, &g, p->ctx->stream);
-            if (e == hipSuccess) ++launched;
-            return e;
+            if (anyc) ta.grp[ta.ngroups++] = g;
         };
-        // position 0: the real shifts (at most two); positions 1..: one complex shift each
         {
             const int sl[2] = {p->nsr > 0 ? 0 : -1, p->nsr > 1 ? 1 : -1};
-            const hipError_t e = go(0, sl, 2);
-            if (e != hipSuccess) return e;
+            add_group(0, sl, 2);
         }
-        for (int c = 0; c < (p->ctx->rec ? kMaxShift - 2 : p->nsc); ++c) {
-            const int sl[1] = {c < p->nsc ? p->nsr + c : -1};
-            const hipError_t e = go(1, sl, 1);
-            if (e != hipSuccess) return e;
+        for (int c = 0; c < p->nsc; ++c) {
+            const int sl[1] = {p->nsr + c};
+            add_group(1, sl, 1);
         }
+        ta.t = triple_tiling(p, prec, std::max(ta.ngroups, 1));
+        if (p->ctx->rec) {
+            // batched: one record per block (its work list groups problems with equal group
+            // counts; a problem with no computing shift records no blocks)
+            record_launch(p->ctx, ac::BOP_TRIPLE, 3, prec, first ? 2 : 0, ta.t.vx, ta.t.wpb,
+                          ta.ngroups > 0 ? ta.t.blocks : 0, ta);
+            return hipSuccess;
+        }
+        if (ta.ngroups == 0) return hipSuccess;
+        const hipError_t e = ac::launch_cheb_triple(prec, &ta, p->ctx->stream);
+        if (e == hipSuccess) ++launched;
         // kappa once per launch (three unfused steps would move 12 vector streams per shift,
         // from a zero guess 9, and kappa three times)
         bytes = (bytes + static_cast<double>(launched) * ksz) * static_cast<double>(p->g.n);
-        return hipSuccess;
+        return e;
     };
     // length of the run of steady steps from k in which the same shifts compute
     auto steady_run = [&](int k) {
@@ -2646,15 +2662,15 @@ int ac_ctx_set_shift_groups(ac_ctx* c, int mode) {
     return AC_OK;
 }
 
-int ac_ctx_set_step_triples(ac_ctx* c, int mode, int rows_per_wave, int waves_per_block, int points_per_lane) {
+int ac_ctx_set_step_triples(ac_ctx* c, int mode, int rows_per_wave, int waves_per_simd, int points_per_lane) {
     if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
     if (mode < 0 || mode > 1) return fail(AC_ERR_ARG, "mode must be 0 or 1");
     if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
-    if (waves_per_block < 0 || waves_per_block > 4) return fail(AC_ERR_ARG, "waves_per_block must be 0..4");
+    if (waves_per_simd < 0 || waves_per_simd > 8) return fail(AC_ERR_ARG, "waves_per_simd must be 0..8");
     if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
     c->triples = mode;
     c->triple_h = rows_per_wave;
-    c->triple_wpb = waves_per_block;
+    c->triple_occ = waves_per_simd > 0 ? waves_per_simd : 4;
     c->triple_vx = points_per_lane;
     return AC_OK;
 }

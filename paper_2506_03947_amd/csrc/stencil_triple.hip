@@ -1,27 +1,29 @@
 // Launches of the three-step shifted-Chebyshev sweep for one problem (the device body
-// is in stencil_triple.h).
+// is in stencil_triple.h): one launch per block of three steps over every shift group,
+// a workgroup per tile with one wave per group.
 #include "stencil_triple.h"
 
 namespace ac {
 namespace {
 
-template <typename R, typename KS, int VX, bool FIRST>
-hipError_t triple_by_kind(const TripleArgs<R>& a, hipStream_t s) {
-    const dim3 grid(a.t.blocks), block(a.t.wpb * kWave);
-    if (a.kind == 0) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, VX, 2, 1, FIRST>), grid, block, 0, s, a);
-    else if (a.kind == 1) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, VX, 1, 2, FIRST>), grid, block, 0, s, a);
-    else return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
 template <typename R, typename KS>
 hipError_t triple_launch_t(const void* args, hipStream_t s) {
     const TripleArgs<R>& a = *static_cast<const TripleArgs<R>*>(args);
-    if (a.g.periodic || a.t.blocks <= 0 || a.t.wpb < 1 || a.t.wpb > 4 || a.g.nx < 4) return hipErrorInvalidValue;
+    if (a.g.periodic || a.t.blocks <= 0 || a.g.nx < 4) return hipErrorInvalidValue;
+    if (a.ngroups < 1 || a.ngroups > kMaxTripleGroups || a.t.wpb != a.ngroups) return hipErrorInvalidValue;
+    if (a.t.tiles != a.t.blocks) return hipErrorInvalidValue;
     if (a.t.vx == 2 && a.g.nx % 2 != 0) return hipErrorInvalidValue;
-    if (a.t.vx == 2) return a.first ? triple_by_kind<R, KS, 2, true>(a, s) : triple_by_kind<R, KS, 2, false>(a, s);
-    if (a.t.vx == 1) return a.first ? triple_by_kind<R, KS, 1, true>(a, s) : triple_by_kind<R, KS, 1, false>(a, s);
-    return hipErrorInvalidValue;
+    const dim3 grid(a.t.blocks), block(a.ngroups * kWave);
+    if (a.t.vx == 2) {
+        if (a.first) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, 2, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cheb_triple_kernel<R, KS, 2, false>), grid, block, 0, s, a);
+    } else if (a.t.vx == 1) {
+        if (a.first) hipLaunchKernelGGL((cheb_triple_kernel<R, KS, 1, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((cheb_triple_kernel<R, KS, 1, false>), grid, block, 0, s, a);
+    } else {
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace
