@@ -2,7 +2,7 @@
 mixed precision against float64 inner solves, with the shifted-stencil roofline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large|medium]
-                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact|sp|blocks|paper]
+                    [--p 20] [--no-cpu-baseline] [--mode solve|kernels|batch|exact|sp|blocks|paper|warmstart]
 
 One step = one FGMRES(7) solve of calA x = b (b = (b_1, 0, ..., 0)) from x = 0
 on resident device inputs, preconditioned by the nested-Chebyshev block
@@ -53,6 +53,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-budgets", action="store_true", help="skip the p = 5 and p = 10 solves")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip training and timing the learned warm start")
     ap.add_argument("--no-const-check", action="store_true",
                     help="skip the constant-coefficient solves checked against the oracle's closed form")
     ap.add_argument("--seed", type=int, default=0)
@@ -64,12 +65,16 @@ def parse():
                     help="fuse three steady Chebyshev steps per sweep (1) or at most two (0)")
     ap.add_argument("--triple-tiling", type=int, nargs=3, default=[0, 0, 0], metavar=("ROWS", "OCC", "VX"),
                     help="tiling of the three-step sweep (0 = automatic)")
-    ap.add_argument("--mode", default="solve", choices=["solve", "kernels", "batch", "exact", "sp", "blocks", "paper"],
+    ap.add_argument("--mode", default="solve",
+                    choices=["solve", "kernels", "batch", "exact", "sp", "blocks", "paper", "warmstart"],
                     help="kernels: only a few preconditioner applications plus a 512 MiB device copy "
                          "(the launch set used for hardware-counter runs); batch: many uneven problems "
                          "solved one by one and as one batch")
     ap.add_argument("--sp-iters", type=int, nargs="*", default=None,
                     help="sp mode: inner MINRES / CG iteration counts to time")
+    ap.add_argument("--ws-nx", type=int, default=1024, help="warmstart mode: grid side")
+    ap.add_argument("--ws-pairs", type=int, default=20000, help="warmstart mode: training crops")
+    ap.add_argument("--ws-steps", type=int, default=4000, help="warmstart mode: Adam steps")
     ap.add_argument("--batch-count", type=int, default=64)
     ap.add_argument("--batch-restart", type=int, default=30,
                     help="FGMRES restart of the batch mode (p = 10: restart 8 leaves one of the 64 problems unconverged)")
@@ -77,8 +82,8 @@ def parse():
     a = ap.parse_args()
     if a.restart is None:
         # FGMRES(7) is the fastest restart for the default solve with fused Chebyshev
-        # steps; the other modes were measured with FGMRES(8)
-        a.restart = 7 if a.mode == "solve" else 8
+        # steps and for the warm-started one; the other modes were measured with FGMRES(8)
+        a.restart = {"solve": 7, "warmstart": 7}.get(a.mode, 8)
     return a
 
 
@@ -423,6 +428,89 @@ def paper_mode(a):
         "rows": out}), flush=True)
 
 
+def train_warm_start(api, ctx, restart, p_in, n_target, steps, nx=1024, ell=10, alpha=1e-2):
+    """Trains the warm-start network on the GPU with the library's kernels, on pairs the
+    plain method generates: the first 60 vectors FGMRES(restart) hands to the
+    preconditioner on coefficient fields 0..8 of the nx x nx log-normal workload (two
+    right-hand sides each), every 4th, their scaled transforms cut into 64 x 64 crops of
+    every shift (about n_target crops); Adam on the residual loss, then one round more
+    on pairs from solves warm-started by the network.  Field 9 is held out."""
+    import torch
+    from paper_2506_03947_amd import warmstart as W
+    from synth import first_block_rhs, lognormal_kappa
+    ny = nx
+    kfn = lambda s: lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=1000 + s)  # noqa: E731
+    rfn = lambda s: first_block_rhs(nx * ny, ell, seed=s)  # noqa: E731
+    train_seeds, test_seed, b_seeds = list(range(9)), 9, (1, 2)
+    lk = np.log(np.concatenate([kfn(s) for s in train_seeds[:2]]))
+    c0, c1 = float(lk.mean()), float(lk.std())
+    n_record, pick, crop = 60, 4, 64
+    per_plane = max(1, n_target // (len(train_seeds) * len(b_seeds) * (n_record // pick) * (ell // 2 + 1)))
+    t0 = time.perf_counter()
+    train = W.generate_pairs(ctx, nx, ny, ell, alpha, kfn, train_seeds, rfn, b_seeds, n_record, pick, p_in, crop,
+                             per_plane, c0, c1, restart=restart, log=None)
+    held = W.generate_pairs(ctx, nx, ny, ell, alpha, kfn, [test_seed], rfn, b_seeds, n_record, pick, p_in, crop,
+                            per_plane, c0, c1, seed=1, restart=restart, log=None)
+    torch.cuda.synchronize()
+    t_gen = time.perf_counter() - t0
+    n_pairs = len(train)
+    t0 = time.perf_counter()
+    cnn, hist = W.train_network(ctx, train, steps, 64, 2e-3, 3, c0, c1, log=log, log_every=1000)
+    more = W.generate_pairs(ctx, nx, ny, ell, alpha, kfn, train_seeds, rfn, b_seeds[:1], n_record, pick, p_in, crop,
+                            per_plane, c0, c1, seed=10, net=cnn, restart=restart, log=None)
+    train = train.join(more)
+    cnn, hist2 = W.train_network(ctx, train, steps // 3, 64, 1e-3, 3, c0, c1, cnn=cnn, log=None)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    held_loss = W.eval_loss(ctx, cnn, held, 3)
+    log(f"warm start: {n_pairs} + {len(more)} pairs in {t_gen:.1f} s, training {t_train:.1f} s, "
+        f"held-out loss {held_loss:.3f}")
+    record = {"grid": [nx, ny], "pairs": n_pairs, "second_round_pairs": len(more), "gen_s": t_gen,
+              "train_s": t_train, "adam_steps": steps + steps // 3, "first_loss": float(np.mean(hist[:20])),
+              "final_loss": float(np.mean(hist2[-100:])), "held_out_loss": held_loss, "held_out_field": test_seed}
+    return cnn, record, kfn, rfn, test_seed
+
+
+def warmstart_mode(a):
+    """The learned warm start on its workload: 1024 x 1024, l = 10, alpha = 1e-2,
+    kappa = 50 exp(g) (std 1, correlation 10 cells), p inner Chebyshev steps per shift,
+    complex64 + bf16 kappa inner; the network trained by train_warm_start.  On the
+    held-out field: solves to 1e-8 by FGMRES(restart) with the plain method in float64
+    and in mixed precision, the network on every preconditioner input (cnn), on the first
+    vector of each cycle (cnn_cycle), and as a minimal-residual correction before each
+    cycle (cnn_mr, the headline value); and the plain mixed solve with FGMRES(7)."""
+    from paper_2506_03947_amd import api
+    from paper_2506_03947_amd import warmstart as W
+    nx = ny = a.ws_nx
+    ell, alpha, p_in = 10, 1e-2, a.p
+    ctx = api.ac_ctx_create(0)
+    cnn, trec, kfn, rfn, test_seed = train_warm_start(api, ctx, a.restart, p_in, a.ws_pairs, a.ws_steps, nx=nx)
+    res = W.compare_solves(ctx, cnn, nx, ny, ell, alpha, kfn(test_seed), rfn(7), p_in, tol=a.tol, restart=a.restart,
+                           reps=max(a.steps, 1), fp64_plain=True, modes=("plain", "cnn", "cnn_cycle", "cnn_mr"))
+    r7 = W.compare_solves(ctx, cnn, nx, ny, ell, alpha, kfn(test_seed), rfn(7), p_in, tol=a.tol, restart=7,
+                          reps=max(a.steps, 1), modes=("plain",))
+    keep = ("outer_iters", "converged", "rel_residual_true", "cnn_fallbacks", "wall_s", "rel_diff_vs_fp64_plain")
+    solves = {k: {f: v[f] for f in keep if f in v} for k, v in res.items() if k not in ("inner", "x")}
+    solves["plain_restart7"] = {f: r7["plain"][f] for f in keep if f in r7["plain"]}
+    for k, v in solves.items():
+        log(f"{k}: {v}")
+    t_ws = solves["cnn_mr"]["wall_s"]
+    best_plain = min(solves["plain"]["wall_s"], solves["plain_restart7"]["wall_s"])
+    print(json.dumps({
+        "metric": "s per all-at-once solve to 1e-8 with the learned warm start (1024^2, l=10)", "value": t_ws,
+        "warm_start_mode": "cnn_mr: minimal-residual correction along the warm-started P^-1 r before each cycle",
+        "unit": "s/solve", "n_gpus": 1, "steps": max(a.steps, 1), "warmup": 1, "ms_per_step": 1000 * t_ws,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c64+bf16 (inner), f64 (outer)",
+        "data": "synthetic",
+        "config": {"workload": f"{nx}x{ny} log-normal kappa (kappa0 50, std 1, corr 10), l {ell}, alpha {alpha}, "
+                               f"p {p_in}, FGMRES({a.restart}) to {a.tol}; network 5-16-16-2 3x3, bf16 weights"},
+        "speedup_vs_plain_fp64": solves["plain_fp64"]["wall_s"] / t_ws,
+        "speedup_vs_plain_mixed_same_restart": solves["plain"]["wall_s"] / t_ws,
+        "speedup_vs_best_plain_mixed": best_plain / t_ws,
+        "solves": solves, "inner_residual_per_shift": res["inner"], "training": trec,
+    }), flush=True)
+
+
 def kernels_only(a, api, prob, ell, n):
     """A few P_NC^{-1} applications in the solve's precision and launch shape, then a
     plain device copy of known size (reference for the FETCH_SIZE/WRITE_SIZE scale)."""
@@ -563,6 +651,9 @@ def main():
         return
     if a.mode == "paper":
         paper_mode(a)
+        return
+    if a.mode == "warmstart":
+        warmstart_mode(a)
         return
     import torch
     from paper_2506_03947_amd import api
@@ -737,6 +828,41 @@ def main():
             del ws
         del pc_, kc, x_ref
 
+    # the learned warm start on the same problem: the network trained on the 1024^2
+    # workload (train_warm_start), applied as a minimal-residual correction before each
+    # FGMRES cycle (AC_INNER_CHEB_CNN_MR), mixed precision; against the plain method in
+    # float64 and mixed precision above
+    warm = None
+    if not a.no_warm_start:
+        net, trec, _, _, _ = train_warm_start(api, ctx, a.restart, a.p, a.ws_pairs, a.ws_steps)
+        api.ac_problem_attach_cnn(prob, net)
+        opts = api.Opts(precision=prec_mixed, inner=L.AC_INNER_CHEB_CNN_MR, p=a.p, tol=a.tol, restart_m=a.restart,
+                        max_outer=3000)
+        ws = api.workspace(api.ac_solve_workspace_size(prob, opts))
+        x.zero_()
+        api.ac_solve(prob, opts, bd, x, ws)
+        ts = []
+        for _ in range(max(2, a.steps // 4)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            inf = api.ac_solve(prob, opts, bd, x, ws)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        t_w = sum(ts) / len(ts)
+        warm = {"mode": "minimal-residual correction along the warm-started P^-1 r before each FGMRES cycle",
+                "s_per_solve": t_w, "outer_iters": inf["outer_iters"], "restarts": inf["restarts"],
+                "matvecs_A": inf["matvecs_A"], "cnn_fallbacks": inf["cnn_fallbacks"],
+                "rel_residual_true": inf["rel_residual_true"],
+                "speedup_vs_plain_mixed": t_mixed / t_w,
+                "speedup_vs_plain_fp64": (out_fp64["s_per_solve"] / t_w) if out_fp64 else None,
+                "rel_diff_vs_fp64_solution": (float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))
+                                              if out_fp64 else None),
+                "training": trec}
+        log(f"warm start: {warm['s_per_solve']:.3f} s, {warm['outer_iters']} iterations")
+        del ws
+        api.ac_problem_attach_cnn(prob, None)
+
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
@@ -773,6 +899,7 @@ def main():
         "fp64": out_fp64,
         "budgets": budgets,
         "constant_kappa_check": const,
+        "warm_start": warm,
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,

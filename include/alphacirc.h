@@ -81,8 +81,12 @@ typedef enum { AC_PREC_FP64 = 0, AC_PREC_MIXED_BF16K = 1, AC_PREC_MIXED_FP32K = 
  * from the learned warm start attached with ac_problem_attach_cnn (makes the
  * preconditioner nonlinear): for every preconditioner application
  * (AC_INNER_CHEB_CNN), or only for the first vector of each FGMRES cycle, the true
- * residual, with zero guesses inside the cycle (AC_INNER_CHEB_CNN_CYCLE; ac_apply_prec
- * treats it as AC_INNER_CHEB_CNN).
+ * residual, with zero guesses inside the cycle (AC_INNER_CHEB_CNN_CYCLE), or as a
+ * minimal-residual correction before each FGMRES cycle: z = the warm-started P^{-1}
+ * of the true residual r, x += gamma z with gamma = <calA z, r> / |calA z|^2 (the
+ * residual cannot grow), then a plain cycle (AC_INNER_CHEB_CNN_MR; one extra
+ * preconditioner application and calA product per cycle).  ac_apply_prec treats both
+ * cycle modes as AC_INNER_CHEB_CNN.
  * AC_INNER_EXACT applies P_alpha^{-1} itself (eq. (4) with direct shifted solves; the
  * paper's reference preconditioner, Section 2 and Fig. 2): only for a constant
  * coefficient on a Dirichlet grid, where the sine transform of Appendix A diagonalises
@@ -104,7 +108,8 @@ typedef enum {
     AC_INNER_CHEB_CNN = 1,
     AC_INNER_CHEB_CNN_CYCLE = 2,
     AC_INNER_EXACT = 3,
-    AC_INNER_SP = 4
+    AC_INNER_SP = 4,
+    AC_INNER_CHEB_CNN_MR = 5
 } ac_inner;
 
 typedef struct {
@@ -475,10 +480,13 @@ int ac_cnn_grad_residual(ac_cnn* cnn, const uint16_t* x, const float* rhat, cons
 /* One Adam step (bias-corrected) with the last gradient. */
 int ac_cnn_adam_step(ac_cnn* cnn, double lr, double beta1, double beta2, double eps);
 /* Network inputs x (device bf16 [l_s][N][16]) for every shift slot of a spectral
- * buffer rhat (layout of ac_spectral_offsets); slot order m = 0, then m = l/2 (even
- * l), then m = 1, 2, ...; scales: host, l_s RMS values in slot order (or NULL). */
+ * buffer rhat (layout of ac_spectral_offsets): channels Re rhat_m / s_m, Im rhat_m / s_m,
+ * Re lambda_m, Im lambda_m, (ln kappa - c0) / c1, the rest zero, s_m the RMS of rhat_m;
+ * slot order m = 0, then m = l/2 (even l), then m = 1, 2, ...; scales: host, l_s RMS
+ * values in slot order (or NULL); rscaled: device float32 [l_s][N][2], (Re, Im) of
+ * rhat_m / s_m in float32 (the training target's right-hand side), or NULL. */
 int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* cnn, int precision, const void* rhat, uint16_t* x,
-                       double* scales);
+                       double* scales, float* rscaled);
 /* The attached network's initial guesses x0hat (spectral layout) for every shift of
  * rhat, exactly as AC_INNER_CHEB_CNN forms them (scaling and fallback included);
  * rejected (host, may be NULL) receives the number of slots reset to zero.  Workspace

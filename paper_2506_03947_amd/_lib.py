@@ -34,6 +34,7 @@ AC_INNER_CHEB_CNN = 1
 AC_INNER_CHEB_CNN_CYCLE = 2
 AC_INNER_EXACT = 3
 AC_INNER_SP = 4
+AC_INNER_CHEB_CNN_MR = 5
 AC_NOALLOC_SCRATCH_BYTES = 64 << 20  # fixed device scratch of ac_apply_prec_noalloc
 
 AC_OUTER_FGMRES = 0
@@ -148,7 +149,7 @@ SIGNATURES = {
     "ac_ctx_set_step_triples": (_I, [_VP, _I, _I, _I, _I]),
     "ac_tune_tiling": (_I, [_VP, _I, C.c_char_p, _VP, _SZ, C.POINTER(C.c_int), C.POINTER(_D)]),
     "ac_cnn_adam_step": (_I, [_VP, _D, _D, _D, _D]),
-    "ac_cnn_make_inputs": (_I, [_VP, _VP, _I, _VP, _VP, C.POINTER(_D)]),
+    "ac_cnn_make_inputs": (_I, [_VP, _VP, _I, _VP, _VP, C.POINTER(_D), _VP]),
     "ac_problem_attach_cnn": (_I, [_VP, _VP]),
     "ac_shifted_residual": (_I, [_VP, _I, _VP, _VP, C.POINTER(_D)]),
     "ac_cnn_guess_workspace_size": (_I, [_VP, C.POINTER(_SZ)]),

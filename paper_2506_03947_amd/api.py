@@ -485,11 +485,15 @@ def ac_cnn_adam_step(cnn: Cnn, lr: float, beta1: float = 0.9, beta2: float = 0.9
     check(L.load().ac_cnn_adam_step(cnn.h, lr, beta1, beta2, eps), "ac_cnn_adam_step")
 
 
-def ac_cnn_make_inputs(p: Problem, cnn: Cnn, precision: int, rhat: torch.Tensor, x: torch.Tensor):
+def ac_cnn_make_inputs(p: Problem, cnn: Cnn, precision: int, rhat: torch.Tensor, x: torch.Tensor,
+                       rscaled: torch.Tensor | None = None):
+    """Network inputs x (bf16 bits) and, optionally, rhat_m / s_m in float32 (rscaled,
+    [l_s][N][2]); returns the RMS scales s_m in slot order."""
     import numpy as np
     sc = np.empty(p.ns, dtype=np.float64)
+    rs = None if rscaled is None else _f32(rscaled, p.ns * p.n * 2, "rscaled")
     check(L.load().ac_cnn_make_inputs(p.h, cnn.h, precision, _ptr(rhat), _u16(x, p.ns * p.n * 16, "x"),
-                                      sc.ctypes.data_as(C.POINTER(C.c_double))), "ac_cnn_make_inputs")
+                                      sc.ctypes.data_as(C.POINTER(C.c_double)), rs), "ac_cnn_make_inputs")
     return sc
 
 

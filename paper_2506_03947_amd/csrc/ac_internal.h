@@ -268,6 +268,7 @@ struct CnnPrepArgs {
     const double* kappa;
     double c0, c1;                     // input normalisation of ln kappa
     uint16_t* x;                       // bf16 [ns][N][16]
+    float* rs;                         // optional: rhat / s per slot, float32 [ns][N][2] (re, im)
 };
 
 int cnn_wgrad_waves(long long ntiles);

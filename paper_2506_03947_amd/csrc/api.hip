@@ -382,7 +382,7 @@ int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>&
     if (!o) return fail(AC_ERR_ARG, "opts is NULL");
     if (o->precision < 0 || o->precision > 2) return fail(AC_ERR_ARG, "unknown precision");
     if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_CHEB_CNN && o->inner != AC_INNER_CHEB_CNN_CYCLE &&
-        o->inner != AC_INNER_EXACT && o->inner != AC_INNER_SP)
+        o->inner != AC_INNER_CHEB_CNN_MR && o->inner != AC_INNER_EXACT && o->inner != AC_INNER_SP)
         return fail(AC_ERR_ARG, "unknown inner mode");
     pm.assign(p->ell, 0);
     if (o->inner == AC_INNER_SP) {
@@ -2112,6 +2112,46 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
             status = AC_NOT_CONVERGED;
             break;
         }
+        if (o->inner == AC_INNER_CHEB_CNN_MR) {
+            // warm-started correction before the cycle: zw = P_warm(r) (the network's guesses
+            // corrected by the Chebyshev steps), then the one-dimensional minimal-residual
+            // step x += gamma zw, r -= gamma calA zw, gamma = <calA zw, r> / |calA zw|^2:
+            // the residual never grows, and the cycle that follows is the plain method's
+            ac_solve_opts ow = *o;
+            ow.inner = AC_INNER_CHEB_CNN;
+            AC_TRY(apply_prec_impl(p, &ow, pm, w.V[0], w.Z[0], w.prec, 1.0 / beta, &fallbacks));
+            AC_TRY(calA_impl(p, w.Z[0], w.V[1], nullptr, nullptr));
+            matvecs += p->ell + psum;
+            {
+                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * 2);
+                AC_HIP(ac::launch_mdot_strided(w.V[0], static_cast<long long>(vec_bytes(p) / sizeof(double)), 1,
+                                               false, w.V[1], len, w.partial, 72, st));
+                AC_HIP(ac::launch_reduce(w.partial, kb, 2, 72, w.red, st));
+            }
+            AC_TRY(fetch(2));
+            const double wr = c->pinned[0], ww = c->pinned[1];
+            if (ww > 0.0 && std::isfinite(wr) && std::isfinite(ww)) {
+                const double gam = wr / ww;
+                ac::VecSet zs{}, ws1{};
+                zs.v[0] = w.Z[0];
+                zs.s2[0] = gam;
+                ws1.v[0] = w.V[1];
+                ws1.s2[0] = gam;
+                {
+                    ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * 3);
+                    AC_HIP(ac::launch_maxpy(zs, 1, nullptr, x, len, st));
+                }
+                {
+                    ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * 3);
+                    AC_HIP(ac::launch_axpy_norm(ws1, 1, nullptr, w.V[0], len, w.partial, 72, st));
+                    AC_HIP(ac::launch_reduce(w.partial, kb, 1, 72, w.red, st));
+                }
+                AC_TRY(fetch(1));
+                beta = std::sqrt(c->pinned[0]);
+                if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
+                if (beta / bnorm <= o->tol) break;
+            }
+        }
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
@@ -2126,7 +2166,8 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
             // z_j = P^{-1} v_j with v_j = scale_j * V_j (scale folded into the transform);
             // AC_INNER_CHEB_CNN_CYCLE warm-starts only the cycle's first vector
             ac_solve_opts oj = *o;
-            if (o->inner == AC_INNER_CHEB_CNN_CYCLE && j > 0) oj.inner = AC_INNER_CHEB;
+            if ((o->inner == AC_INNER_CHEB_CNN_CYCLE && j > 0) || o->inner == AC_INNER_CHEB_CNN_MR)
+                oj.inner = AC_INNER_CHEB;
             AC_TRY(apply_prec_impl(p, &oj, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
             AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
             matvecs += p->ell + psum;
@@ -3102,7 +3143,8 @@ int ac_cnn_adam_step(ac_cnn* n, double lr, double beta1, double beta2, double ep
     return AC_OK;
 }
 
-int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* n, int prec, const void* rhat, uint16_t* x, double* scales) {
+int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* n, int prec, const void* rhat, uint16_t* x, double* scales,
+                       float* rscaled) {
     if (!p || !n || !rhat || !x) return fail(AC_ERR_ARG, "NULL argument");
     if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
     AC_HIP(hipSetDevice(p->ctx->device));
@@ -3113,6 +3155,7 @@ int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* n, int prec, const void* rha
     AC_TRY(slot_residuals(p, prec, a, nullptr, st));
     set_rms_scales(p, st, a, scales);
     a.x = x;
+    a.rs = rscaled;
     AC_HIP(ac::launch_cnn_prep(prec, a, p->ctx->stream));
     return AC_OK;
 }

@@ -365,6 +365,12 @@ __global__ __launch_bounds__(256) void prep_kernel(const CnnPrepArgs a) {
         h[3] = f2bf(a.lam_im[s]);
         h[4] = f2bf(lk);
         store16(a.x + (static_cast<long long>(s) * a.n + p) * kC, h);
+        if (a.rs) {
+            float2 t;
+            t.x = re * a.inv_scale[s];
+            t.y = im * a.inv_scale[s];
+            reinterpret_cast<float2*>(a.rs)[static_cast<long long>(s) * a.n + p] = t;
+        }
     }
 }
 

@@ -10,15 +10,14 @@ residual of the guess under the shifted operator of the crop, which is the quant
 the inner Chebyshev steps contract and the fallback test checks; training runs the
 library's forward, residual-loss, backward and Adam kernels.
 
-    python -m paper_2506_03947_amd.warmstart --nx 1024 --pairs 20000 --out warmstart.json
-
 Checkpoints are JSON: the parameter vector, the ln-kappa normalisation and the
-training record.
+training record.  The coefficient fields and right-hand sides come from the caller
+(callables returning host arrays); `bench.py --mode warmstart` runs the whole
+generate / train / compare sequence on the 1024 x 1024 workload.
 """
 
 from __future__ import annotations
 
-import argparse
 import json
 import math
 import time
@@ -61,21 +60,16 @@ def preconditioner_inputs(prob, b, p_inner, count, bufs, restart=8, warm=False):
 
 def field_pairs(prob, cnn, r):
     """For one block residual r: network inputs [l_s, N, 16] (bf16 bits), the scaled
-    transformed residual [l_s, N, 2] (float) and the shifts [l_s, 2], in slot order."""
+    transformed residual [l_s, N, 2] (float) and the shifts [l_s, 2], in slot order
+    (all formed by the library's transform and input kernels)."""
     off = api.ac_spectral_offsets(prob, PAIR_PREC)
     rhat = torch.zeros(off[-1], dtype=torch.float32, device="cuda:0")
     api.ac_tdft_forward(prob, PAIR_PREC, r, rhat)
     X = torch.zeros(prob.ns * prob.n * 16, dtype=torch.int16, device="cuda:0")
-    scales = api.ac_cnn_make_inputs(prob, cnn, PAIR_PREC, rhat, X)
-    planes = api.spectral_to_complex(prob, PAIR_PREC, rhat)
-    lam_all = api.ac_problem_shifts(prob)
     R = torch.empty((prob.ns, prob.n, 2), dtype=torch.float32, device="cuda:0")
-    lam = torch.empty((prob.ns, 2), dtype=torch.float32)
-    for s, m in enumerate(api.slot_order(prob)):
-        sc = float(scales[s]) if scales[s] > 0 else 1.0
-        R[s, :, 0] = planes[m].real / sc
-        R[s, :, 1] = planes[m].imag / sc
-        lam[s, 0], lam[s, 1] = lam_all[m].real, lam_all[m].imag
+    api.ac_cnn_make_inputs(prob, cnn, PAIR_PREC, rhat, X, R)
+    lam_all = api.ac_problem_shifts(prob)
+    lam = torch.tensor([[lam_all[m].real, lam_all[m].imag] for m in api.slot_order(prob)], dtype=torch.float32)
     return X.view(prob.ns, -1, 16), R, lam
 
 
@@ -98,12 +92,12 @@ class PairSet:
         return self.R[:, border:H - border, border:W - border].pow(2).sum((1, 2, 3)).contiguous()
 
 
-def generate_pairs(ctx, nx, ny, ell, alpha, kappa_fn, kappa_seeds, b_seeds, n_record, pick_every, p_inner, crop,
-                   crops_per_plane, c0, c1, seed=0, log=print, net=None, restart=8):
+def generate_pairs(ctx, nx, ny, ell, alpha, kappa_fn, kappa_seeds, rhs_fn, b_seeds, n_record, pick_every, p_inner,
+                   crop, crops_per_plane, c0, c1, seed=0, log=print, net=None, restart=8):
     """Crops from every `pick_every`-th of the first `n_record` preconditioner inputs
-    of solves for each coefficient seed and right-hand-side seed: plain solves, or
+    of solves for each coefficient field kappa_fn(seed) and right-hand side
+    rhs_fn(seed) (host arrays from the caller's input generators): plain solves, or
     solves warm-started by `net` when given."""
-    from synth import first_block_rhs
     rng = np.random.default_rng(seed)
     Xs, Rs, Ks, Ls = [], [], [], []
     for ks in kappa_seeds:
@@ -116,7 +110,7 @@ def generate_pairs(ctx, nx, ny, ell, alpha, kappa_fn, kappa_seeds, b_seeds, n_re
         if net is not None:
             api.ac_problem_attach_cnn(prob, net)
         for bs in b_seeds:
-            b = torch.as_tensor(first_block_rhs(nx * ny, ell, seed=bs), device="cuda:0")
+            b = torch.as_tensor(rhs_fn(bs), device="cuda:0")
             inputs = preconditioner_inputs(prob, b, p_inner, n_record, bufs, restart=restart, warm=net is not None)
             for v in inputs[::pick_every]:
                 X, R, lam = field_pairs(prob, cnn, v.contiguous())
@@ -216,35 +210,53 @@ def inner_gain(prob, cnn, r, p_inner, bufs):
             "warm": api.ac_shifted_residual(prob, prec, rhat, y_warm).tolist()}
 
 
-def compare_solves(ctx, cnn, nx, ny, ell, alpha, kappa, b_seed, p_inner, tol=1e-8, restart=8):
-    """Plain and warm-started FGMRES (network on every preconditioner input, and on the
-    first vector of each cycle only) on one problem: outer iterations, wall time,
-    fallbacks, plus the mean inner residuals per shift on inputs the plain method's
-    preconditioner receives."""
-    from synth import first_block_rhs
+def compare_solves(ctx, cnn, nx, ny, ell, alpha, kappa, b, p_inner, tol=1e-8, restart=8, reps=1,
+                   modes=("plain", "cnn", "cnn_cycle"), fp64_plain=False):
+    """Plain and warm-started FGMRES on one problem (b: host right-hand side): the plain
+    method (complex64 + bf16 kappa inner; with fp64_plain also float64 inner), the network
+    on every preconditioner input (cnn) and on the first vector of each cycle only
+    (cnn_cycle), and as a minimal-residual correction before each cycle (cnn_mr): outer iterations, best wall time of `reps`, fallbacks, the solutions'
+    difference to the float64 plain solution when it was run, plus the mean inner residuals per
+    shift on inputs the plain method's preconditioner receives; out["x"] holds each
+    solution (device tensors)."""
     prob = make_problem(ctx, nx, ny, ell, alpha, kappa)
     api.ac_problem_attach_cnn(prob, cnn)
-    b = torch.as_tensor(first_block_rhs(nx * ny, ell, seed=b_seed), device="cuda:0")
+    bd = torch.as_tensor(b, device="cuda:0")
     out = {}
     bufs = _Buffers()
-    for name, inner in (("plain", L.AC_INNER_CHEB), ("cnn", L.AC_INNER_CHEB_CNN),
-                        ("cnn_cycle", L.AC_INNER_CHEB_CNN_CYCLE)):
-        opts = api.Opts(precision=L.AC_PREC_MIXED_BF16K, inner=inner, p=p_inner, tol=tol, restart_m=restart,
-                        max_outer=3000)
+    runs = [(m, L.AC_PREC_MIXED_BF16K) for m in modes]
+    if fp64_plain:
+        runs = [("plain_fp64", L.AC_PREC_FP64)] + runs
+    inner_of = {"plain": L.AC_INNER_CHEB, "plain_fp64": L.AC_INNER_CHEB, "cnn": L.AC_INNER_CHEB_CNN,
+                "cnn_cycle": L.AC_INNER_CHEB_CNN_CYCLE, "cnn_mr": L.AC_INNER_CHEB_CNN_MR}
+    xref = None
+    xs = {}
+    for name, prec in runs:
+        opts = api.Opts(precision=prec, inner=inner_of[name], p=p_inner, tol=tol, restart_m=restart, max_outer=3000)
         ws = bufs.get("solve" + name, api.ac_solve_workspace_size(prob, opts))
         x = torch.zeros(ell * nx * ny, dtype=torch.float64, device="cuda:0")
-        api.ac_solve(prob, opts, b, x, ws)  # warm-up
-        x.zero_()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info = api.ac_solve(prob, opts, b, x, ws)
-        torch.cuda.synchronize()
-        info["wall_s"] = time.perf_counter() - t0
+        api.ac_solve(prob, opts, bd, x, ws)  # warm-up
+        best = None
+        for _ in range(max(reps, 1)):
+            x.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = api.ac_solve(prob, opts, bd, x, ws)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        info["wall_s"] = best
+        xs[name] = x.clone()
+        if name == "plain_fp64":
+            xref = xs[name]
+        elif xref is not None:
+            info["rel_diff_vs_fp64_plain"] = float(torch.linalg.vector_norm(x - xref) / torch.linalg.vector_norm(xref))
         out[name] = info
     # inner residuals on preconditioner inputs of the plain method (every 5th of 30)
     gains = [inner_gain(prob, cnn, v.contiguous(), p_inner, bufs)
-             for v in preconditioner_inputs(prob, b, p_inner, 30, bufs, restart=restart)[::5]]
+             for v in preconditioner_inputs(prob, bd, p_inner, 30, bufs, restart=restart)[::5]]
     out["inner"] = {k: np.mean([g[k] for g in gains], axis=0).tolist() for k in ("guess", "cold", "warm")}
+    out["x"] = xs
     return out
 
 
@@ -258,61 +270,3 @@ def load(ctx, path):
     cnn = api.ac_cnn_create(ctx)
     api.ac_cnn_set_params(cnn, np.asarray(d["params"], dtype=np.float32), d["c0"], d["c1"])
     return cnn, d
-
-
-def main():
-    from synth import lognormal_kappa
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--nx", type=int, default=1024)
-    ap.add_argument("--ell", type=int, default=10)
-    ap.add_argument("--alpha", type=float, default=1e-2)
-    ap.add_argument("--p", type=int, default=20, help="inner Chebyshev steps per shift")
-    ap.add_argument("--pairs", type=int, default=20000)
-    ap.add_argument("--crop", type=int, default=64)
-    ap.add_argument("--steps", type=int, default=3000)
-    ap.add_argument("--batch", type=int, default=64)
-    ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--border", type=int, default=3)
-    ap.add_argument("--restart", type=int, default=8, help="FGMRES restart length")
-    ap.add_argument("--rounds", type=int, default=1,
-                    help="extra rounds of pairs drawn from solves warm-started by the current network")
-    ap.add_argument("--out", default="")
-    a = ap.parse_args()
-    nx = ny = a.nx
-    ctx = api.ac_ctx_create(0)
-    kfn = lambda s: lognormal_kappa(nx, ny, 50.0, 10.0, 1.0, seed=1000 + s)  # noqa: E731
-    train_seeds, test_seed = list(range(9)), 9  # 90/10 split by coefficient field
-    lk = np.log(np.concatenate([kfn(s) for s in train_seeds[:2]]))
-    c0, c1 = float(lk.mean()), float(lk.std())
-    n_record, pick = 60, 4
-    b_seeds = (1, 2)
-    per_plane = max(1, a.pairs // (len(train_seeds) * len(b_seeds) * (n_record // pick) * (a.ell // 2 + 1)))
-    t0 = time.perf_counter()
-    train = generate_pairs(ctx, nx, ny, a.ell, a.alpha, kfn, train_seeds, b_seeds, n_record, pick, a.p, a.crop, per_plane,
-                           c0, c1, restart=a.restart)
-    held = generate_pairs(ctx, nx, ny, a.ell, a.alpha, kfn, [test_seed], b_seeds, n_record, pick, a.p, a.crop, per_plane,
-                          c0, c1, seed=1, restart=a.restart)
-    torch.cuda.synchronize()
-    t_gen = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    cnn, hist = train_network(ctx, train, a.steps, a.batch, a.lr, a.border, c0, c1)
-    for rnd in range(a.rounds):
-        more = generate_pairs(ctx, nx, ny, a.ell, a.alpha, kfn, train_seeds, b_seeds[:1], n_record, pick, a.p, a.crop,
-                              per_plane, c0, c1, seed=10 + rnd, net=cnn, restart=a.restart)
-        train = train.join(more)
-        cnn, hist2 = train_network(ctx, train, a.steps // 3, a.batch, a.lr / 2, a.border, c0, c1, cnn=cnn)
-        hist += hist2
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    res = compare_solves(ctx, cnn, nx, ny, a.ell, a.alpha, kfn(test_seed), 7, a.p, restart=a.restart)
-    record = {"grid": [nx, ny], "ell": a.ell, "alpha": a.alpha, "p": a.p, "restart": a.restart, "pairs": len(train),
-              "held_out_pairs": len(held), "crop": a.crop, "gen_s": t_gen, "train_s": t_train, "steps": a.steps,
-              "first_loss": float(np.mean(hist[:20])), "final_loss": float(np.mean(hist[-100:])),
-              "held_out_loss": eval_loss(ctx, cnn, held, a.border), "held_out_solve": res}
-    print(json.dumps(record))
-    if a.out:
-        save(a.out, cnn, record)
-
-
-if __name__ == "__main__":
-    main()

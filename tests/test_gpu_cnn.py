@@ -214,9 +214,11 @@ def test_cnn_inputs_layout():
     rhat = torch.zeros(off[-1], dtype=torch.float64, device="cuda:0")
     api.ac_tdft_forward(p, 0, G.dev(r), rhat)
     x = torch.zeros(p.ns * p.n * 16, dtype=torch.int16, device="cuda:0")
-    scales = api.ac_cnn_make_inputs(p, cnn, 0, rhat, x)
+    rs = torch.zeros((p.ns, p.n, 2), dtype=torch.float32, device="cuda:0")
+    scales = api.ac_cnn_make_inputs(p, cnn, 0, rhat, x, rs)
     bits = G.host(x).view(np.uint16).astype(np.uint32) << 16
     got = bits.view(np.float32).reshape(p.ns, 64, 96, 16)
+    got_rs = G.host(rs).reshape(p.ns, 64, 96, 2)
     R = pc.forward_transform(r, ell, 1e-2)
     lam = pc.shifts(ell, 1e-2)
     for s, m in enumerate(api.slot_order(p)):
@@ -225,6 +227,8 @@ def test_cnn_inputs_layout():
         ref = ocnn.make_inputs(R[m].reshape(64, 96), lam[m], kap, 3.0, 1.5, sc)
         assert G.max_rel(got[s, :, :, :5], to_bfloat16(ref)) < 1e-2
         assert not got[s, :, :, 5:].any()
+        # the float32 scaled right-hand side: channels 0 and 1 of the oracle's planes
+        assert G.max_rel(got_rs[s], ref[..., :2]) < 1e-6
 
 
 @pytest.mark.parametrize("precision", [L.AC_PREC_FP64, L.AC_PREC_MIXED_BF16K])
