@@ -126,7 +126,11 @@ def batch_mode(a):
         x.zero_()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    single = [api.ac_solve(p, opts, b, x, sws) for p, b, x in zip(probs, bs, xs)]
+    single, t_each = [], []
+    for p, b, x in zip(probs, bs, xs):
+        t1 = time.perf_counter()
+        single.append(api.ac_solve(p, opts, b, x, sws))
+        t_each.append(time.perf_counter() - t1)
     torch.cuda.synchronize()
     t_seq = time.perf_counter() - t0
     log(f"one by one: {t_seq:.3f} s")
@@ -169,6 +173,8 @@ def batch_mode(a):
         "iterations": {"batch_max": max(its_b), "batch_sum": sum(its_b), "single_sum": sum(its_s),
                        "all_converged": all(i["converged"] for i in infos)},
         "max_rel_diff_batch_vs_single": diff, "tune_seconds": t_tune,
+        "per_problem": [{"side": sp["nx"], "ell": sp["ell"], "iters": i["outer_iters"], "single_s": round(t, 5)}
+                        for sp, i, t in zip(specs, single, t_each)],
         "tilings": sorted({tuple(t) for t in tiles}),
     }))
 

@@ -175,7 +175,15 @@ struct BatchList {
     int wpb;            // waves per block, equal for every entry
 };
 
-enum BatchOp : int { BOP_FWD = 0, BOP_STEP = 1, BOP_FINAL = 2, BOP_CALA = 3, BOP_TRIPLE = 4 };
+enum BatchOp : int {
+    BOP_FWD = 0,
+    BOP_STEP = 1,
+    BOP_FINAL = 2,
+    BOP_CALA = 3,
+    BOP_TRIPLE = 4,
+    BOP_CALA_RES = 5,
+    BOP_PAIR = 6
+};
 
 // Grid of the forward transform for n points: vx points per thread, 256 threads.
 inline void fwd_geometry(long long n, int& vx, int& blocks) {
@@ -197,6 +205,7 @@ hipError_t launch_cheb_triple(int prec, const void* args, hipStream_t s);
 // Batched three-step sweeps (args TripleArgs per problem, L.wpb = their group count);
 // code = 2 * first.
 hipError_t launch_batch_triple(int prec, int code, int vx, const BatchList& L, hipStream_t s);
+hipError_t launch_batch_pair(int prec, int vx, const BatchList& L, hipStream_t s);
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);
@@ -371,6 +380,37 @@ struct SpProblem {
 // f32: float32 vectors and multigrid coefficients (inner products and scalars float64)
 size_t sp_ws_bytes(const MgHierarchy& h, long long n, int nc, int nr, bool f32);
 hipError_t sp_solve(const SpProblem& P, int iters, bool f32, void* ws, hipStream_t s);
+
+// ---- batched FGMRES with device-resident scalars (batch_krylov.hip) -----------------
+constexpr int kBKRed = 72;  // partial sums per block (2 * 32 dots + norm)
+struct BKProb {
+    const double* v0;   // basis V_i = v0 + i * vstride (i <= m)
+    const double* z0;   // preconditioned vectors Z_i = z0 + i * vstride
+    double* x;
+    long long vstride, len;
+    double* partial;    // nblk * kBKRed partial sums
+    const double* partial2;  // per-tile partials of the residual form
+    int ntiles;
+    int nblk;           // blocks of the problem in a batched Krylov launch (<= 1024)
+};
+struct BKState {
+    double H[(kMaxBasis) * (kMaxBasis - 1)];  // (m + 1) x m, row stride m
+    double cs[kMaxBasis - 1], sn[kMaxBasis - 1], g[kMaxBasis], scale[kMaxBasis];
+    double Lg[(kMaxBasis - 1) * (kMaxBasis - 1)], y[kMaxBasis - 1], coef[kMaxBasis];
+    double bnorm, beta, orth;
+    long long matvecs, ell, psum;
+    int total, restarts, kdone, status, finished;
+};
+// blocks: the sum of the problems' nblk; live / cyc: per-problem masks
+hipError_t launch_bk_mdot(const BKProb* P, int nprob, int blocks, const int* live, int nv, hipStream_t s);
+hipError_t launch_bk_arnoldi(const BKProb* P, BKState* S, int nprob, const int* live, int j, int m, hipStream_t s);
+hipError_t launch_bk_axpy_norm(const BKProb* P, const BKState* S, int nprob, int blocks, const int* live, int nv,
+                               hipStream_t s);
+hipError_t launch_bk_givens(const BKProb* P, BKState* S, int nprob, int* live, double* dscale, int j, int m,
+                            double tol, int max_outer, hipStream_t s);
+hipError_t launch_bk_update(const BKProb* P, BKState* S, int nprob, int blocks, const int* cyc, int m, hipStream_t s);
+hipError_t launch_bk_cycle(const BKProb* P, BKState* S, int nprob, int* live, int* cyc, double* dscale, int m,
+                           double tol, int max_outer, hipStream_t s);
 
 // ---- setup kernels (setup.hip) -----------------------------------------------
 hipError_t launch_kappa_setup(const Geom& g, const double* kappa, float* k32, uint16_t* k16, double* partial,

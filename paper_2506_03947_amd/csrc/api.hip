@@ -682,7 +682,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     const double spec_bytes = static_cast<double>(off[ns]) * sizeof(R);
     const bool fuse_ok = nb == 4 && p->ctx->pairs == 1 && !p->g.periodic && p->g.nx >= 3 &&
                          spec_bytes < 2147483648.0 && static_cast<double>(p->g.n) * ksz < 2147483648.0;
-    const bool can_pair = fuse_ok && !p->ctx->rec;
+    const bool can_pair = fuse_ok;
     auto steady_step = [&](int k) {
         if (k > k_last || (fuse && k == k_last)) return false;
         int ck, pk;
@@ -705,8 +705,10 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
         pa.out2 = reinterpret_cast<R*>(buf[bq[k + 2]]);
         pa.bytes = static_cast<unsigned>(spec_bytes);
         bytes = 0.0;
+        // recording for a batch: always kMaxGroups records, empty ones with no blocks
+        const bool rec = p->ctx->rec != nullptr;
         const int ngroups = std::max(p->nsr, (p->nsc + 1) / 2);
-        for (int grp = 0; grp < ngroups; ++grp) {
+        for (int grp = 0; grp < (rec ? kMaxGroups : ngroups); ++grp) {
             const int map[3] = {grp < p->nsr ? grp : -1, 2 * grp < p->nsc ? p->nsr + 2 * grp : -1,
                                 2 * grp + 1 < p->nsc ? p->nsr + 2 * grp + 1 : -1};
             bool anyc = false;
@@ -721,6 +723,10 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
                 fill_cf(pa.cf[1], j, cs[sl], k + 1);
                 bytes += 5.0 * (slot_is_real(p, sl) ? esz_r : esz_c);  // x_k, x_{k-1}, rhat in; two out
                 anyc = true;
+            }
+            if (rec) {
+                record_launch(p->ctx, ac::BOP_PAIR, 2, prec, 0, pa.t.vx, pa.t.wpb, anyc ? pa.t.blocks : 0, pa);
+                continue;
             }
             if (!anyc) continue;
             const hipError_t e = ac::launch_cheb_pair(prec, &pa, p->ctx->stream);
@@ -1350,9 +1356,8 @@ int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double
     a.ell = p->ell;
     if (p->kblocks) a.kappa = p->kblocks;
     if (p->ctx->rec) {
-        if (b) return fail(AC_ERR_UNSUPPORTED, "residual-mode calA is not recorded");
         if (p->kblocks) return fail(AC_ERR_UNSUPPORTED, "varying diagonal blocks are not batched");
-        record_launch(p->ctx, ac::BOP_CALA, p->ell, 0, 0, a.t.vx, a.t.wpb, a.t.blocks, a);
+        record_launch(p->ctx, b ? ac::BOP_CALA_RES : ac::BOP_CALA, p->ell, 0, 0, a.t.vx, a.t.wpb, a.t.blocks, a);
         return AC_OK;
     }
     const double kbytes = p->kblocks ? 8.0 * p->ell * p->g.n : 8.0 * p->g.n;
@@ -1871,6 +1876,10 @@ __global__ void zero_kernel(double* x, long long n) {
     if (i < n) x[i] = 0.0;
 }
 
+__global__ void zero_kernel_int(int* x, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
+}
+
 template <typename R>
 __global__ void scale_copy_kernel(R* dst, const R* src, long long n, int cplx_, R sr, R si) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
@@ -2274,12 +2283,12 @@ int ac_solve_record(ac_problem* p, const ac_solve_opts* o, const double* b, doub
 // ---------------------------------------------------------------------------
 // Batched solves: many independent problems (uneven grids and l) advance their
 // FGMRES iterations in lockstep.  Per Arnoldi index j the preconditioner and the
-// calA product of every problem are recorded once as launch records, aligned
-// records are grouped by kernel variant into work lists, and each j's sequence of
-// batched launches is captured into a hipGraph that every later cycle replays.  The
-// per-step input scales and the convergence mask live in device memory and are
-// updated before each replay.  Krylov kernels run per problem, but every problem's
-// reductions are fetched with one synchronisation per phase.
+// calA product of every problem are recorded once as launch records, and aligned
+// records are grouped by kernel variant into work lists; so is the residual
+// b - calA x.  The Arnoldi scalars of every problem (Gram-Schmidt coefficients,
+// Givens rotations, convergence and restart tests) live in device memory and are
+// updated by small kernels, so one whole FGMRES cycle of all problems is captured
+// once as a hipGraph and replayed; the host reads one counter per cycle.
 
 namespace {
 
@@ -2292,21 +2301,29 @@ struct BatchLaunch {
 };
 
 size_t max_args_bytes() {
-    return std::max(std::max(std::max(sizeof(ac::SweepArgs<double>), sizeof(ac::SweepArgs<float>)),
-                             std::max(sizeof(ac::FwdArgs), sizeof(ac::CalAArgs))),
-                    std::max(sizeof(ac::TripleArgs<double>), sizeof(ac::TripleArgs<float>)));
+    return std::max({sizeof(ac::SweepArgs<double>), sizeof(ac::SweepArgs<float>), sizeof(ac::FwdArgs),
+                     sizeof(ac::CalAArgs), sizeof(ac::TripleArgs<double>), sizeof(ac::TripleArgs<float>),
+                     sizeof(ac::PairArgs<double>), sizeof(ac::PairArgs<float>)});
 }
 
-// Device bytes for the work lists: per j at most 4p + 3 launch positions (a sweep step
-// records kMaxGroups shift groups), each with at most `count` groups.
+// Device bytes for the work lists: per j (and once more for the residual form) at most
+// kMaxGroups p + 3 launch positions (a sweep step records kMaxGroups shift groups),
+// each with at most `count` groups.
 size_t batch_list_bytes(int count, const ac_solve_opts* o) {
     const size_t per_pos = static_cast<size_t>(count) * (align_up(max_args_bytes(), 16) + 8) +
                            static_cast<size_t>(count) * (3 * 256 + 8);
-    return static_cast<size_t>(o->restart_m) * static_cast<size_t>(kMaxGroups * o->p_uniform + 3) * per_pos + 256;
+    return static_cast<size_t>(o->restart_m + 1) * static_cast<size_t>(kMaxGroups * o->p_uniform + 3) * per_pos + 256;
+}
+
+size_t batch_kry_bytes(int count) {
+    return align_up(static_cast<size_t>(count + 1) * sizeof(int), 256) +
+           align_up(static_cast<size_t>(count) * sizeof(ac::BKProb), 256) +
+           align_up(static_cast<size_t>(count) * sizeof(ac::BKState), 256);
 }
 
 size_t batch_ws_bytes(int count, ac_problem* const* probs, const ac_solve_opts* o) {
-    size_t b = batch_list_bytes(count, o) + align_up(static_cast<size_t>(count) * 12, 256) + 256;
+    size_t b = batch_list_bytes(count, o) + align_up(static_cast<size_t>(count) * 12, 256) + 256 +
+               batch_kry_bytes(count);
     for (int q = 0; q < count; ++q) b += align_up(solve_ws_bytes(probs[q], o), 256);
     return b;
 }
@@ -2335,11 +2352,7 @@ struct BatchState {
     ac_problem* p;
     SolveWs w;
     std::vector<int> pm;
-    long long len = 0, psum = 0, matvecs = 0;
-    double bnorm = 0, beta = 0, orth = 0;
-    int total = 0, restarts = 0, kdone = 0, status = AC_OK;
-    bool finished = false, in_cycle = false;
-    std::vector<double> H, cs, sn, g, scale, y, Lg, hcol;
+    long long len = 0, psum = 0;
 };
 
 // Restores the context and frees the graphs and the capture stream on every exit path.
@@ -2383,19 +2396,21 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
     const int m = o->restart_m;
     // The legacy default stream cannot be captured: work on a stream of our own.
     AC_HIP(hipStreamSynchronize(c->stream));
-    BatchGuard guard{c, c->stream, nullptr, c->profiling, std::vector<hipGraphExec_t>(m, nullptr)};
+    BatchGuard guard{c, c->stream, nullptr, c->profiling, std::vector<hipGraphExec_t>(1, nullptr)};
     AC_HIP(hipStreamCreateWithFlags(&guard.own, hipStreamNonBlocking));
     hipStream_t st = guard.own;
     c->stream = st;
     c->profiling = false;
 
-    // workspace: [lists][scale doubles | live ints][per-problem solve workspaces]
+    // workspace: [lists][scale doubles | live ints][cycle mask, active count | problem
+    // list | scalar states][per-problem solve workspaces]
     char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
     char* lists = base;
     const size_t list_cap = batch_list_bytes(count, o);
     double* dscale = reinterpret_cast<double*>(base + align_up(list_cap, 256));
     int* dlive = reinterpret_cast<int*>(dscale + count);
-    char* pw = base + align_up(list_cap, 256) + align_up(static_cast<size_t>(count) * 12, 256);
+    char* pw = base + align_up(list_cap, 256) + align_up(static_cast<size_t>(count) * 12, 256) +
+               batch_kry_bytes(count);
     std::vector<BatchState> S(count);
     for (int q = 0; q < count; ++q) {
         BatchState& s = S[q];
@@ -2405,18 +2420,11 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
         pw += align_up(solve_ws_bytes(s.p, o), 256);
         s.len = static_cast<long long>(s.p->ell) * s.p->g.n;
         for (int v : s.pm) s.psum += v;
-        s.H.assign((m + 1) * m, 0.0);
-        s.cs.assign(m, 0.0);
-        s.sn.assign(m, 0.0);
-        s.g.assign(m + 1, 0.0);
-        s.scale.assign(m + 1, 0.0);
-        s.y.assign(m, 0.0);
-        s.Lg.assign(m * m, 0.0);
-        s.hcol.assign(m + 1, 0.0);
     }
 
-    // record every problem's launches for each j and group aligned records
-    std::vector<std::vector<BatchLaunch>> plan(m);
+    // record every problem's launches for each j (and the residual form) and group
+    // aligned records into work lists
+    std::vector<std::vector<BatchLaunch>> plan(m + 1);  // plan[m]: the residual b - calA x
     std::vector<char> host(list_cap, 0);
     size_t used = 0;
     auto take = [&](size_t bytes, size_t align) -> size_t {
@@ -2429,18 +2437,10 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
         BatchLaunch l;
         size_t args_off, first_off, pid_off;
     };
-    std::vector<std::vector<Pending>> pend(m);
-    for (int j = 0; j < m; ++j) {
-        std::vector<std::vector<ac_launch_rec>> recs(count);
-        for (int q = 0; q < count; ++q) {
-            BatchState& s = S[q];
-            c->rec = &recs[q];
-            const int e1 = apply_prec_impl(s.p, o, s.pm, s.w.V[j], s.w.Z[j], s.w.prec, 1.0);
-            const int e2 = e1 < 0 ? e1 : calA_impl(s.p, s.w.Z[j], s.w.V[j + 1], nullptr, nullptr);
-            c->rec = nullptr;
-            if (e2 < 0) return e2;
+    std::vector<std::vector<Pending>> pend(m + 1);
+    auto group = [&](std::vector<std::vector<ac_launch_rec>>& recs, std::vector<Pending>& out) -> int {
+        for (int q = 0; q < count; ++q)
             if (recs[q].size() != recs[0].size()) return fail(AC_ERR_UNSUPPORTED, "batch launch sequences differ");
-        }
         const size_t npos = recs[0].size();
         for (size_t i = 0; i < npos; ++i) {
             std::vector<int> done(count, 0);
@@ -2482,25 +2482,66 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
                 pg.l.list.nprob = n;
                 pg.l.list.blocks = blocks;
                 pg.l.list.wpb = r0.wpb;
-                pend[j].push_back(pg);
+                out.push_back(pg);
             }
         }
+        return AC_OK;
+    };
+    for (int j = 0; j <= m; ++j) {
+        std::vector<std::vector<ac_launch_rec>> recs(count);
+        for (int q = 0; q < count; ++q) {
+            BatchState& s = S[q];
+            c->rec = &recs[q];
+            int e = AC_OK;
+            if (j < m) {
+                e = apply_prec_impl(s.p, o, s.pm, s.w.V[j], s.w.Z[j], s.w.prec, 1.0);
+                if (e >= 0) e = calA_impl(s.p, s.w.Z[j], s.w.V[j + 1], nullptr, nullptr);
+            } else {
+                e = calA_impl(s.p, x[q], s.w.V[0], b[q], s.w.partial2);
+            }
+            c->rec = nullptr;
+            if (e < 0) return e;
+        }
+        AC_TRY(group(recs, pend[j]));
     }
+
+    // device state of the batched FGMRES: problem list, scalar states, masks
+    char* kry = base + align_up(list_cap, 256) + align_up(static_cast<size_t>(count) * 12, 256);
+    int* dcyc = reinterpret_cast<int*>(kry);
+    ac::BKProb* dP = reinterpret_cast<ac::BKProb*>(kry + align_up(static_cast<size_t>(count + 1) * sizeof(int), 256));
+    ac::BKState* dS = reinterpret_cast<ac::BKState*>(reinterpret_cast<char*>(dP) +
+                                                     align_up(static_cast<size_t>(count) * sizeof(ac::BKProb), 256));
+    std::vector<ac::BKProb> hP(count);
+    int kblocks = 0;
+    for (int q = 0; q < count; ++q) {
+        BatchState& s = S[q];
+        ac::BKProb& bp = hP[q];
+        bp.v0 = s.w.V[0];
+        bp.z0 = s.w.Z[0];
+        bp.x = x[q];
+        bp.vstride = static_cast<long long>(vec_bytes(s.p) / sizeof(double));
+        bp.len = s.len;
+        bp.partial = s.w.partial;
+        bp.partial2 = s.w.partial2;
+        bp.ntiles = static_cast<int>(calA_partials(s.p));
+        // one block per 512 elements, at most the single solve's block count
+        const long long want = (s.len + 511) / 512;
+        bp.nblk = static_cast<int>(std::min<long long>(std::max<long long>(want, 1), ac::krylov_blocks()));
+        kblocks += bp.nblk;
+    }
+    AC_HIP(hipMemcpyAsync(dP, hP.data(), static_cast<size_t>(count) * sizeof(ac::BKProb), hipMemcpyHostToDevice, st));
     AC_HIP(hipMemcpyAsync(lists, host.data(), used, hipMemcpyHostToDevice, st));
-    for (int j = 0; j < m; ++j)
+    for (int j = 0; j <= m; ++j)
         for (auto& pg : pend[j]) {
             BatchLaunch l = pg.l;
             l.list.args = lists + pg.args_off;
             l.list.first = reinterpret_cast<const int*>(lists + pg.first_off);
             l.list.pid = reinterpret_cast<const int*>(lists + pg.pid_off);
-            l.list.live = dlive;
+            l.list.live = j < m ? dlive : dcyc;
             l.list.scale = l.op == ac::BOP_FWD ? dscale : nullptr;
             plan[j].push_back(l);
         }
 
-    // host staging for the scales and the mask (pinned, after the fetch area)
-    double* hscale = c->pinned + static_cast<size_t>(kMaxBatch) * kFetchStride;
-    int* hlive = reinterpret_cast<int*>(hscale + count);
     auto fetch = [&](const std::vector<int>& qs, int nq) -> int {
         for (int q : qs)
             AC_HIP(hipMemcpyAsync(c->pinned + static_cast<size_t>(q) * kFetchStride, S[q].w.red,
@@ -2509,20 +2550,9 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
         return AC_OK;
     };
     auto fetched = [&](int q) { return c->pinned + static_cast<size_t>(q) * kFetchStride; };
-    auto residuals = [&](const std::vector<int>& qs) -> int {
-        for (int q : qs) {
-            BatchState& s = S[q];
-            AC_TRY(calA_impl(s.p, x[q], s.w.V[0], b[q], s.w.partial2));
-            AC_HIP(ac::launch_reduce(s.w.partial2, static_cast<int>(calA_partials(s.p)), 1, 1, s.w.red, st));
-            s.matvecs += s.p->ell;
-        }
-        AC_TRY(fetch(qs, 1));
-        for (int q : qs) S[q].beta = std::sqrt(fetched(q)[0]);
-        return AC_OK;
-    };
     const int kb = ac::krylov_blocks();
 
-    // ||b|| and the first residuals
+    // ||b|| and the first residuals (once, on the host)
     std::vector<int> all(count);
     for (int q = 0; q < count; ++q) {
         all[q] = q;
@@ -2531,165 +2561,110 @@ int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solv
     }
     AC_TRY(fetch(all, 1));
     std::vector<int> live_q;
+    std::vector<ac::BKState> hS(count);
     for (int q = 0; q < count; ++q) {
-        S[q].bnorm = std::sqrt(fetched(q)[0]);
-        if (!std::isfinite(S[q].bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
-        if (S[q].bnorm == 0.0) {
+        ac::BKState& ks = hS[q];
+        std::memset(&ks, 0, sizeof(ks));
+        ks.ell = S[q].p->ell;
+        ks.psum = S[q].psum;
+        ks.bnorm = std::sqrt(fetched(q)[0]);
+        if (!std::isfinite(ks.bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
+        if (ks.bnorm == 0.0) {
             hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((S[q].len + 255) / 256)), dim3(256), 0, st, x[q],
                                S[q].len);
             AC_HIP(hipGetLastError());
-            S[q].finished = true;
+            ks.finished = 1;
         } else {
             live_q.push_back(q);
         }
     }
-    AC_TRY(residuals(live_q));
-
-    while (true) {
-        // cycle start
-        std::vector<int> cyc;
-        for (int q = 0; q < count; ++q) {
-            BatchState& s = S[q];
-            s.in_cycle = false;
-            if (s.finished) continue;
-            if (!std::isfinite(s.beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
-            if (s.beta / s.bnorm <= o->tol) {
-                s.finished = true;
-                continue;
-            }
-            if (s.total >= o->max_outer) {
-                s.finished = true;
-                s.status = AC_NOT_CONVERGED;
-                continue;
-            }
-            s.in_cycle = true;
-            std::fill(s.H.begin(), s.H.end(), 0.0);
-            std::fill(s.g.begin(), s.g.end(), 0.0);
-            s.g[0] = s.beta;
-            s.scale[0] = 1.0 / s.beta;
-            s.kdone = 0;
-            cyc.push_back(q);
-        }
-        if (cyc.empty()) break;
-        for (int j = 0; j < m; ++j) {
-            std::vector<int> act;
-            for (int q = 0; q < count; ++q) {
-                hlive[q] = S[q].in_cycle ? 1 : 0;
-                hscale[q] = S[q].in_cycle ? S[q].scale[j] : 0.0;
-                if (S[q].in_cycle) act.push_back(q);
-            }
-            if (act.empty()) break;
-            AC_HIP(hipMemcpyAsync(dscale, hscale, static_cast<size_t>(count) * 12, hipMemcpyHostToDevice, st));
-            if (!guard.execs[j]) {
-                AC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                hipError_t le = hipSuccess;
-                for (const BatchLaunch& l : plan[j]) {
-                    le = ac::launch_batch(l.op, l.ell, l.prec, l.curk, l.vx, l.list, st);
-                    if (le != hipSuccess) break;
-                }
-                hipGraph_t graph = nullptr;
-                const hipError_t ee = hipStreamEndCapture(st, &graph);
-                if (le != hipSuccess || ee != hipSuccess) {
-                    if (graph) (void)hipGraphDestroy(graph);
-                    return fail(AC_ERR_HIP, std::string("batch graph capture: ") +
-                                                hipGetErrorString(le != hipSuccess ? le : ee));
-                }
-                const hipError_t ie = hipGraphInstantiate(&guard.execs[j], graph, nullptr, nullptr, 0);
-                (void)hipGraphDestroy(graph);
-                if (ie != hipSuccess) return fail(AC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-            }
-            AC_HIP(hipGraphLaunch(guard.execs[j], st));
-            // Arnoldi: one-reduce modified Gram-Schmidt, as in ac_solve
-            const int nv = j + 1;
-            for (int q : act) {
-                BatchState& s = S[q];
-                s.matvecs += s.p->ell + s.psum;
-                AC_HIP(ac::launch_mdot_strided(s.w.V[0], static_cast<long long>(vec_bytes(s.p) / sizeof(double)), nv,
-                                               j >= 1, s.w.V[j + 1], s.len, s.w.partial, 72, st));
-                AC_HIP(ac::launch_reduce(s.w.partial, kb, j >= 1 ? 2 * nv : nv + 1, 72, s.w.red, st));
-            }
-            AC_TRY(fetch(act, 2 * nv + 1));
-            std::vector<ac::VecSet> vsets(count);
-            for (int q : act) {
-                BatchState& s = S[q];
-                const double* hd = fetched(q);
-                ac::VecSet& vs = vsets[q];
-                for (int i = 0; i <= j; ++i) vs.v[i] = s.w.V[i];
-                for (int i = 0; i < j; ++i) {
-                    s.Lg[j * m + i] = s.scale[i] * s.scale[j] * hd[nv + 1 + i];
-                    s.orth = std::max(s.orth, std::abs(s.Lg[j * m + i]));
-                }
-                for (int i = 0; i <= j; ++i) {
-                    double hi = s.scale[i] * hd[i];
-                    for (int k = 0; k < i; ++k) hi -= s.Lg[i * m + k] * s.hcol[k];
-                    s.hcol[i] = hi;
-                    s.H[i * m + j] = hi;
-                    vs.s2[i] = s.scale[i] * hi;
-                }
-                AC_HIP(ac::launch_axpy_norm(vs, nv, nullptr, s.w.V[j + 1], s.len, s.w.partial, 72, st));
-                AC_HIP(ac::launch_reduce(s.w.partial, kb, 1, 72, s.w.red, st));
-            }
-            AC_TRY(fetch(act, 1));
-            for (int q : act) {
-                BatchState& s = S[q];
-                const double hn = std::sqrt(fetched(q)[0]);
-                if (!std::isfinite(hn)) return fail(AC_ERR_NONFINITE, "Arnoldi produced a non-finite value");
-                double* H = s.H.data();
-                H[(j + 1) * m + j] = hn;
-                for (int i = 0; i < j; ++i) {
-                    const double t = s.cs[i] * H[i * m + j] + s.sn[i] * H[(i + 1) * m + j];
-                    H[(i + 1) * m + j] = -s.sn[i] * H[i * m + j] + s.cs[i] * H[(i + 1) * m + j];
-                    H[i * m + j] = t;
-                }
-                const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-                s.cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
-                s.sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
-                H[j * m + j] = den;
-                H[(j + 1) * m + j] = 0.0;
-                s.g[j + 1] = -s.sn[j] * s.g[j];
-                s.g[j] = s.cs[j] * s.g[j];
-                ++s.total;
-                s.kdone = j + 1;
-                if (std::abs(s.g[j + 1]) / s.bnorm <= o->tol || s.total >= o->max_outer || hn == 0.0)
-                    s.in_cycle = false;  // masked for the rest of this cycle
-                else
-                    s.scale[j + 1] = 1.0 / hn;
-            }
-        }
-        // x += Z y for every problem of the cycle, then the true residuals
-        for (int q : cyc) {
-            BatchState& s = S[q];
-            const int kd = s.kdone;
-            for (int i = kd - 1; i >= 0; --i) {
-                double t = s.g[i];
-                for (int k = i + 1; k < kd; ++k) t -= s.H[i * m + k] * s.y[k];
-                s.y[i] = s.H[i * m + i] != 0.0 ? t / s.H[i * m + i] : 0.0;
-            }
-            ac::VecSet zs{};
-            for (int i = 0; i < kd; ++i) {
-                zs.v[i] = s.w.Z[i];
-                zs.s2[i] = s.y[i];
-            }
-            AC_HIP(ac::launch_maxpy(zs, kd, nullptr, x[q], s.len, st));
-            ++s.restarts;
-        }
-        AC_TRY(residuals(cyc));
+    for (int q : live_q) {
+        BatchState& s = S[q];
+        AC_TRY(calA_impl(s.p, x[q], s.w.V[0], b[q], s.w.partial2));
+        AC_HIP(ac::launch_reduce(s.w.partial2, static_cast<int>(calA_partials(s.p)), 1, 1, s.w.red, st));
     }
+    AC_TRY(fetch(live_q, 1));
+    for (int q : live_q) {
+        hS[q].beta = std::sqrt(fetched(q)[0]);
+        hS[q].matvecs = S[q].p->ell;
+    }
+    AC_HIP(hipMemcpyAsync(dS, hS.data(), static_cast<size_t>(count) * sizeof(ac::BKState), hipMemcpyHostToDevice, st));
+    hipLaunchKernelGGL(zero_kernel_int, dim3(1), dim3(256), 0, st, dcyc, count);
+    AC_HIP(hipGetLastError());
+    AC_HIP(ac::launch_bk_cycle(dP, dS, count, dlive, dcyc, dscale, m, o->tol, o->max_outer, st));
+    // problems in the next cycle, read from the cycle mask
+    int* hcyc = reinterpret_cast<int*>(c->pinned);
+    auto active = [&]() -> int {
+        AC_HIP(hipMemcpyAsync(hcyc, dcyc, static_cast<size_t>(count) * sizeof(int), hipMemcpyDeviceToHost, st));
+        AC_HIP(hipStreamSynchronize(st));
+        int n = 0;
+        for (int q = 0; q < count; ++q) n += hcyc[q] != 0;
+        return n;
+    };
+    int nact = active();
+    if (nact < 0) return nact;
+
+    // One FGMRES cycle of every problem in it, captured once as a graph: per Arnoldi
+    // index the preconditioner and calA work lists, the batched multi-dot, the
+    // Gram-Schmidt coefficients, the multi-axpy with the new norm and the Givens update;
+    // then x += Z y, the residuals, and the restart test that sets the next cycle's
+    // masks.  The host reads one counter per cycle.
+    auto record_cycle = [&]() -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int j = 0; j < m && e == hipSuccess; ++j) {
+            for (const BatchLaunch& l : plan[j]) {
+                e = ac::launch_batch(l.op, l.ell, l.prec, l.curk, l.vx, l.list, st);
+                if (e != hipSuccess) return e;
+            }
+            const int nv = j + 1;
+            e = ac::launch_bk_mdot(dP, count, kblocks, dlive, nv, st);
+            if (e == hipSuccess) e = ac::launch_bk_arnoldi(dP, dS, count, dlive, j, m, st);
+            if (e == hipSuccess) e = ac::launch_bk_axpy_norm(dP, dS, count, kblocks, dlive, nv, st);
+            if (e == hipSuccess) e = ac::launch_bk_givens(dP, dS, count, dlive, dscale, j, m, o->tol, o->max_outer, st);
+        }
+        if (e == hipSuccess) e = ac::launch_bk_update(dP, dS, count, kblocks, dcyc, m, st);
+        for (const BatchLaunch& l : plan[m]) {
+            if (e != hipSuccess) break;
+            e = ac::launch_batch(l.op, l.ell, l.prec, l.curk, l.vx, l.list, st);
+        }
+        if (e == hipSuccess) e = ac::launch_bk_cycle(dP, dS, count, dlive, dcyc, dscale, m, o->tol, o->max_outer, st);
+        return e;
+    };
+    while (nact > 0) {
+        if (!guard.execs[0]) {
+            AC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const hipError_t le = record_cycle();
+            hipGraph_t graph = nullptr;
+            const hipError_t ee = hipStreamEndCapture(st, &graph);
+            if (le != hipSuccess || ee != hipSuccess) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return fail(AC_ERR_HIP, std::string("batch graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ee));
+            }
+            const hipError_t ie = hipGraphInstantiate(&guard.execs[0], graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (ie != hipSuccess) return fail(AC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+        }
+        AC_HIP(hipGraphLaunch(guard.execs[0], st));
+        nact = active();
+        if (nact < 0) return nact;
+    }
+    AC_HIP(hipMemcpyAsync(hS.data(), dS, static_cast<size_t>(count) * sizeof(ac::BKState), hipMemcpyDeviceToHost, st));
     AC_HIP(hipStreamSynchronize(st));
     const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     int worst = AC_OK;
     for (int q = 0; q < count; ++q) {
-        const BatchState& s = S[q];
-        if (s.status == AC_NOT_CONVERGED) worst = AC_NOT_CONVERGED;
+        const ac::BKState& ks = hS[q];
+        if (ks.status == AC_ERR_NONFINITE) return fail(AC_ERR_NONFINITE, "a batched solve produced a non-finite value");
+        if (ks.status == AC_NOT_CONVERGED) worst = AC_NOT_CONVERGED;
         if (!infos) continue;
         ac_solve_info& in = infos[q];
         in = ac_solve_info{};
-        in.outer_iters = s.total;
-        in.restarts = s.restarts;
-        in.matvecs_A = s.matvecs;
-        in.rel_residual_true = s.bnorm > 0 ? s.beta / s.bnorm : 0.0;
+        in.outer_iters = ks.total;
+        in.restarts = ks.restarts;
+        in.matvecs_A = ks.matvecs;
+        in.rel_residual_true = ks.bnorm > 0 ? ks.beta / ks.bnorm : 0.0;
         in.seconds = secs;
-        in.orth_loss = s.orth;
+        in.orth_loss = ks.orth;
     }
     return worst;
 }

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include "ac_internal.h"
+#include "worklist.h"
 
 namespace ac {
 
@@ -74,7 +75,9 @@ hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t
 }
 
 hipError_t launch_batch(int op, int ell, int prec, int curk, int vx, const BatchList& b, hipStream_t s) {
+    if (b.nprob > kListMax) return hipErrorInvalidValue;
     if (op == BOP_TRIPLE) return launch_batch_triple(prec, curk, vx, b, s);  // not specialised by l
+    if (op == BOP_PAIR) return launch_batch_pair(prec, vx, b, s);
 #define AC_X(L) batch_ell_##L(op, prec, curk, vx, b, s)
     AC_SWITCH(AC_X)
 #undef AC_X

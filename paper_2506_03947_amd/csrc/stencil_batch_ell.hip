@@ -12,7 +12,7 @@ namespace {
 
 template <typename R, typename KS, int VX, bool FINAL>
 hipError_t sweep_batch_t(int curk, const BatchList& L, hipStream_t s) {
-    const dim3 grid(L.blocks), block(L.wpb * kWave);
+    const dim3 grid(list_grid(L.blocks, L.nprob, L.wpb)), block(L.wpb * kWave);
     if (curk == SRC_RHAT)
         hipLaunchKernelGGL((cheb_sweep_batch_kernel<R, KS, AC_ELL, VX, true, FINAL>), grid, block, 0, s, L);
     else
@@ -47,7 +47,7 @@ hipError_t AC_CAT(batch_ell_, AC_ELL)(int op, int prec, int curk, int vx, const 
         case BOP_STEP: return sweep_batch_prec<false>(prec, vx, curk, L, s);
         case BOP_FINAL: return sweep_batch_prec<true>(prec, vx, curk, L, s);
         case BOP_FWD: {
-            const dim3 grid(L.blocks), block(256);
+            const dim3 grid(list_grid(L.blocks, L.nprob, 4)), block(256);
             if (prec == 0) {
                 if (vx == 2) hipLaunchKernelGGL((tdft_fwd_batch_kernel<double, AC_ELL, 2>), grid, block, 0, s, L);
                 else hipLaunchKernelGGL((tdft_fwd_batch_kernel<double, AC_ELL, 1>), grid, block, 0, s, L);
@@ -58,9 +58,15 @@ hipError_t AC_CAT(batch_ell_, AC_ELL)(int op, int prec, int curk, int vx, const 
             return hipGetLastError();
         }
         case BOP_CALA: {
-            const dim3 grid(L.blocks), block(L.wpb * kWave);
-            if (vx == 2) hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 2>), grid, block, 0, s, L);
-            else hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 1>), grid, block, 0, s, L);
+            const dim3 grid(list_grid(L.blocks, L.nprob, L.wpb)), block(L.wpb * kWave);
+            if (vx == 2) hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 2, false>), grid, block, 0, s, L);
+            else hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 1, false>), grid, block, 0, s, L);
+            return hipGetLastError();
+        }
+        case BOP_CALA_RES: {  // y = b - calA x with per-tile partial sums of y^2
+            const dim3 grid(list_grid(L.blocks, L.nprob, L.wpb)), block(L.wpb * kWave);
+            if (vx == 2) hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 2, true>), grid, block, 0, s, L);
+            else hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 1, true>), grid, block, 0, s, L);
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

@@ -19,6 +19,18 @@
 #include <type_traits>
 
 #include "ac_internal.h"
+#include "worklist.h"
+
+namespace ac {
+// Every operand pointer of these kernels addresses global memory.  Saying so lets the
+// compiler use global rather than flat memory instructions also when the pointer
+// comes from an argument record in memory (batched launches), not from the kernel
+// arguments.
+template <typename T>
+__device__ __forceinline__ T* gptr(T* p) {
+    return (T*)(__attribute__((address_space(1))) T*)p;
+}
+}  // namespace ac
 
 namespace ac {
 namespace {
@@ -326,7 +338,8 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
     const int x0 = sx * kWave * VX;
     const int y0 = cy * a.t.h;
     const int y1 = min(y0 + a.t.h, ny);
-    const KS* __restrict__ kap = static_cast<const KS*>(a.kappa);
+    const KS* __restrict__ kap = gptr(static_cast<const KS*>(a.kappa));
+    const R* __restrict__ rhat = gptr(a.rhat);
 
     bool comp[NS];
     bool any = false;
@@ -335,7 +348,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
         comp[s] = (a.src[s] == SRC_COMPUTE);
         any = any || comp[s];
     }
-    const R* __restrict__ wbase = CUR_RHAT ? a.rhat : a.cur;  // stencil operand buffer
+    const R* __restrict__ wbase = gptr(CUR_RHAT ? a.rhat : a.cur);  // stencil operand buffer
 
     // per-lane columns
     const int xb = x0 + lane * VX;
@@ -412,7 +425,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
     R hr[NSR][VX], hc[NSCA][2 * VX];  // rhat centre
     R pr[NSR][VX], pc[NSCA][2 * VX];  // x_{k-1} centre, or finished iterate
     const int prevk = a.prevk;
-    const R* __restrict__ pbase = a.prev;
+    const R* __restrict__ pbase = gptr(a.prev);
 
     auto load_centre = [&](int y) {
         const unsigned pt = static_cast<unsigned>(y) * static_cast<unsigned>(nx) + static_cast<unsigned>(xb);
@@ -423,11 +436,11 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
             for (int v = 0; v < VX; ++v) hr[s][v] = pr[s][v] = R(0);
             const unsigned o = a.soff[s] + pt;
             if (comp[s]) {
-                if (!CUR_RHAT && ok) ldc<R, VX>(a.rhat + o, hr[s]);
+                if (!CUR_RHAT && ok) ldc<R, VX>(rhat + o, hr[s]);
                 if (prevk == SRC_BUF && ok) ldc<R, VX>(pbase + o, pr[s]);
-                if (prevk == SRC_RHAT && ok) ldc<R, VX>(a.rhat + o, pr[s]);
+                if (prevk == SRC_RHAT && ok) ldc<R, VX>(rhat + o, pr[s]);
             } else if (FINAL && ok) {
-                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : a.bufs[a.fbuf[s]];
+                const R* f = gptr((a.src[s] == SRC_RHAT) ? a.rhat : a.bufs[a.fbuf[s]]);
                 ldc<R, VX>(f + o, pr[s]);
             }
         }
@@ -438,11 +451,11 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
             for (int v = 0; v < 2 * VX; ++v) hc[c][v] = pc[c][v] = R(0);
             const unsigned o = a.soff[s] + 2u * pt;
             if (comp[s]) {
-                if (!CUR_RHAT && ok) ldc<R, 2 * VX>(a.rhat + o, hc[c]);
+                if (!CUR_RHAT && ok) ldc<R, 2 * VX>(rhat + o, hc[c]);
                 if (prevk == SRC_BUF && ok) ldc<R, 2 * VX>(pbase + o, pc[c]);
-                if (prevk == SRC_RHAT && ok) ldc<R, 2 * VX>(a.rhat + o, pc[c]);
+                if (prevk == SRC_RHAT && ok) ldc<R, 2 * VX>(rhat + o, pc[c]);
             } else if (FINAL && ok) {
-                const R* f = (a.src[s] == SRC_RHAT) ? a.rhat : a.bufs[a.fbuf[s]];
+                const R* f = gptr((a.src[s] == SRC_RHAT) ? a.rhat : a.bufs[a.fbuf[s]]);
                 ldc<R, 2 * VX>(f + o, pc[c]);
             }
         }
@@ -487,7 +500,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
                     const R xp = (prevk == SRC_RHAT) ? a.cf.s_re[s] * pr[s][v] : pr[s][v];
                     yr[s][v] = xc + a.cf.a_re[s] * (xc - xp) + a.cf.c_re[s] * (rh - bx);
                 }
-                if (!FINAL && store_ok) stc<R, VX>(a.out + a.soff[s] + pt, yr[s]);
+                if (!FINAL && store_ok) stc<R, VX>(gptr(a.out) + a.soff[s] + pt, yr[s]);
             } else if (FINAL) {
                 const R sc = (a.src[s] == SRC_RHAT) ? a.cf.s_re[s] : R(1);
 #pragma unroll
@@ -538,7 +551,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
                     yc[c][2 * v] = xr + (ar * dr - ai * di) + (cr * qr - ci * qi);
                     yc[c][2 * v + 1] = xi + (ar * di + ai * dr) + (cr * qi + ci * qr);
                 }
-                if (!FINAL && store_ok) stc<R, 2 * VX>(a.out + a.soff[s] + 2u * pt, yc[c]);
+                if (!FINAL && store_ok) stc<R, 2 * VX>(gptr(a.out) + a.soff[s] + 2u * pt, yc[c]);
             } else if (FINAL) {
                 const bool rs = (a.src[s] == SRC_RHAT);
                 const R sr = rs ? a.cf.s_re[s] : R(1), si = rs ? a.cf.s_im[s] : R(0);
@@ -570,7 +583,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
                     }
                     zk[v] = a.ginv[k] * (acc + 2.0 * sum);
                 }
-                stv<double, VX>(a.z + static_cast<size_t>(k) * static_cast<size_t>(a.g.n) + pt, zk);
+                stv<double, VX>(gptr(a.z) + static_cast<size_t>(k) * static_cast<size_t>(a.g.n) + pt, zk);
             }
         }
     };
@@ -721,6 +734,8 @@ __device__ __forceinline__ void apply_calA_body(const CalAArgs& a, int bid, int 
     double ssq = 0.0;
     if (tile >= 0) {
         const Geom& g = a.g;
+        const double* __restrict__ kappa = gptr(a.kappa);
+        const double* __restrict__ ax = gptr(a.x);
         const int sx = static_cast<int>(tile % a.t.nsx);
         const int cy = static_cast<int>(tile / a.t.nsx);
         const int x0 = sx * kWave * VX;
@@ -729,18 +744,18 @@ __device__ __forceinline__ void apply_calA_body(const CalAArgs& a, int bid, int 
 
         double kp[VX], kc[VX], kn[VX], khc, khn, kd;
         double xp[ELL][VX], xc[ELL][VX], xn[ELL][VX], hc[ELL], hn[ELL], hd;
-        load_real_row<double, VX, double>(a.kappa, g, y0 - 1, x0, lane, kp, kd);
-        load_real_row<double, VX, double>(a.kappa, g, y0, x0, lane, kc, khc);
+        load_real_row<double, VX, double>(kappa, g, y0 - 1, x0, lane, kp, kd);
+        load_real_row<double, VX, double>(kappa, g, y0, x0, lane, kc, khc);
 #pragma unroll
         for (int k = 0; k < ELL; ++k) {
-            load_real_row<double, VX, double>(a.x + k * g.n, g, y0 - 1, x0, lane, xp[k], hd);
-            load_real_row<double, VX, double>(a.x + k * g.n, g, y0, x0, lane, xc[k], hc[k]);
+            load_real_row<double, VX, double>(ax + k * g.n, g, y0 - 1, x0, lane, xp[k], hd);
+            load_real_row<double, VX, double>(ax + k * g.n, g, y0, x0, lane, xc[k], hc[k]);
         }
         for (int y = y0; y < y1; ++y) {
-            load_real_row<double, VX, double>(a.kappa, g, y + 1, x0, lane, kn, khn);
+            load_real_row<double, VX, double>(kappa, g, y + 1, x0, lane, kn, khn);
 #pragma unroll
             for (int k = 0; k < ELL; ++k)
-                load_real_row<double, VX, double>(a.x + k * g.n, g, y + 1, x0, lane, xn[k], hn[k]);
+                load_real_row<double, VX, double>(ax + k * g.n, g, y + 1, x0, lane, xn[k], hn[k]);
 
             const long long rowoff = static_cast<long long>(y) * g.nx;
             const int xb = x0 + lane * VX;
@@ -771,14 +786,14 @@ __device__ __forceinline__ void apply_calA_body(const CalAArgs& a, int bid, int 
                 if (store_ok) {
                     if (RESID) {
                         double bb[VX];
-                        ldv<double, VX>(a.b + k * g.n + rowoff + xb, bb);
+                        ldv<double, VX>(gptr(a.b) + k * g.n + rowoff + xb, bb);
 #pragma unroll
                         for (int v = 0; v < VX; ++v) {
                             yo[v] = bb[v] - yo[v];
                             ssq += yo[v] * yo[v];
                         }
                     }
-                    stv<double, VX>(a.y + k * g.n + rowoff + xb, yo);
+                    stv<double, VX>(gptr(a.y) + k * g.n + rowoff + xb, yo);
                 }
             }
 #pragma unroll
@@ -802,7 +817,7 @@ __device__ __forceinline__ void apply_calA_body(const CalAArgs& a, int bid, int 
         // wave sum, lane 0 writes the tile partial
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) ssq += __shfl_down(ssq, off, kWave);
-        if (lane == 0 && tile >= 0) a.partial[tile] = ssq;
+        if (lane == 0 && tile >= 0) gptr(a.partial)[tile] = ssq;
     }
 }
 
@@ -893,43 +908,46 @@ __global__ __launch_bounds__(256) void apply_calA_var_kernel(const CalAArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// Batched launches over a work list of independent problems (uneven grids): problem
-// q owns blocks [first[q], first[q+1]) and its arguments are args[q]; a problem whose
-// live flag is zero returns at once (convergence mask).  The block-to-problem search
-// is uniform across the block.
-__device__ __forceinline__ int batch_problem(const BatchList& L, int bid) {
-    int lo = 0, hi = L.nprob - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (L.first[mid] <= bid) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
+// Batched launches over a work list of independent problems (uneven grids): member q
+// has its arguments in args[q] and first[q + 1] - first[q] blocks of its own launch;
+// members whose problem is not live (convergence mask) get no blocks (worklist.h).
+
+__device__ __forceinline__ LiveBlocks list_live_blocks(const BatchList& L) {
+    return live_blocks(
+        L.nprob, [&](int q) { return L.first[q + 1] - L.first[q]; }, [&](int q) { return L.live[L.pid[q]] != 0; });
 }
 
 template <typename R, typename KS, int ELL, int VX, bool CUR_RHAT, bool FINAL>
 __global__ __launch_bounds__(256) void cheb_sweep_batch_kernel(const BatchList L) {
-    const int q = batch_problem(L, blockIdx.x);
-    if (!L.live[L.pid[q]]) return;
-    const SweepArgs<R> a = static_cast<const SweepArgs<R>*>(L.args)[q];
-    cheb_sweep_body<R, KS, ELL, VX, CUR_RHAT, FINAL, false>(a, blockIdx.x - L.first[q], L.first[q + 1] - L.first[q]);
+    const LiveBlocks W = list_live_blocks(L);
+    for (int v = blockIdx.x; v < W.total; v += gridDim.x) {
+        int q, local, nb;
+        if (!live_block(W, v, q, local, nb)) continue;
+        const SweepArgs<R>& a = list_args<SweepArgs<R>>(L.args, q);
+        cheb_sweep_body<R, KS, ELL, VX, CUR_RHAT, FINAL, false>(a, local, nb);
+    }
 }
 
 template <typename R, int ELL, int VX>
 __global__ __launch_bounds__(256) void tdft_fwd_batch_kernel(const BatchList L) {
-    const int q = batch_problem(L, blockIdx.x);
-    const int pid = L.pid[q];
-    if (!L.live[pid]) return;
-    const FwdArgs a = static_cast<const FwdArgs*>(L.args)[q];
-    tdft_fwd_body<R, ELL, VX>(a, blockIdx.x - L.first[q], L.scale ? L.scale[pid] : 1.0);
+    const LiveBlocks W = list_live_blocks(L);
+    for (int v = blockIdx.x; v < W.total; v += gridDim.x) {
+        int q, local, nb;
+        if (!live_block(W, v, q, local, nb)) continue;
+        const FwdArgs& a = list_args<FwdArgs>(L.args, q);
+        tdft_fwd_body<R, ELL, VX>(a, local, L.scale ? L.scale[L.pid[q]] : 1.0);
+    }
 }
 
-template <int ELL, int VX>
+template <int ELL, int VX, bool RESID>
 __global__ __launch_bounds__(256) void apply_calA_batch_kernel(const BatchList L) {
-    const int q = batch_problem(L, blockIdx.x);
-    if (!L.live[L.pid[q]]) return;
-    const CalAArgs a = static_cast<const CalAArgs*>(L.args)[q];
-    apply_calA_body<ELL, VX, false>(a, blockIdx.x - L.first[q], L.first[q + 1] - L.first[q]);
+    const LiveBlocks W = list_live_blocks(L);
+    for (int v = blockIdx.x; v < W.total; v += gridDim.x) {
+        int q, local, nb;
+        if (!live_block(W, v, q, local, nb)) continue;
+        const CalAArgs& a = list_args<CalAArgs>(L.args, q);
+        apply_calA_body<ELL, VX, RESID>(a, local, nb);
+    }
 }
 
 }  // namespace

@@ -392,6 +392,27 @@ __global__ __launch_bounds__(256) void cheb_pair_kernel(const PairArgs<R> a) {
     cheb_pair_body<R, KS, VX>(a, blockIdx.x, gridDim.x);
 }
 
+// Batched: one pair sweep of one shift group for every live problem of a work list
+template <typename R, typename KS, int VX>
+__global__ __launch_bounds__(256) void cheb_pair_batch_kernel(const BatchList L) {
+    const LiveBlocks W = list_live_blocks(L);
+    for (int v = blockIdx.x; v < W.total; v += gridDim.x) {
+        int q, local, nb;
+        if (!live_block(W, v, q, local, nb)) continue;
+        const PairArgs<R>& a = list_args<PairArgs<R>>(L.args, q);
+        cheb_pair_body<R, KS, VX>(a, local, nb);
+    }
+}
+
+template <typename R, typename KS>
+hipError_t pair_batch_t(int vx, const BatchList& L, hipStream_t s) {
+    const dim3 grid(list_grid(L.blocks, L.nprob, L.wpb)), block(L.wpb * kWave);
+    if (vx == 2) hipLaunchKernelGGL((cheb_pair_batch_kernel<R, KS, 2>), grid, block, 0, s, L);
+    else if (vx == 1) hipLaunchKernelGGL((cheb_pair_batch_kernel<R, KS, 1>), grid, block, 0, s, L);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
 template <typename R, typename KS>
 hipError_t pair_launch_t(const void* args, hipStream_t s) {
     const PairArgs<R>& a = *static_cast<const PairArgs<R>*>(args);
@@ -411,6 +432,17 @@ hipError_t launch_cheb_pair(int prec, const void* args, hipStream_t s) {
         case 0: return pair_launch_t<double, double>(args, s);
         case 1: return pair_launch_t<float, uint16_t>(args, s);
         case 2: return pair_launch_t<float, float>(args, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_batch_pair(int prec, int vx, const BatchList& L, hipStream_t s) {
+    if (L.nprob < 1 || L.blocks < 1) return hipSuccess;
+    if (L.nprob > kListMax || L.wpb < 1 || L.wpb > 4) return hipErrorInvalidValue;
+    switch (prec) {
+        case 0: return pair_batch_t<double, double>(vx, L, s);
+        case 1: return pair_batch_t<float, uint16_t>(vx, L, s);
+        case 2: return pair_batch_t<float, float>(vx, L, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -453,12 +453,13 @@ __global__ __launch_bounds__(kWave * kMaxTripleGroups) void cheb_triple_kernel(c
 // mask: a problem whose live flag is zero returns at once).
 template <typename R, typename KS, int VX, bool FIRST>
 __global__ __launch_bounds__(kWave * kMaxTripleGroups) void cheb_triple_batch_kernel(const BatchList L) {
-    const int q = batch_problem(L, blockIdx.x);
-    if (!L.live[L.pid[q]]) return;
-    const TripleArgs<R>& a = static_cast<const TripleArgs<R>*>(L.args)[q];
-    const int tile = __builtin_amdgcn_readfirstlane(
-        tile_of_block(a.t, blockIdx.x - L.first[q], L.first[q + 1] - L.first[q]));
-    cheb_triple_tile<R, KS, VX, FIRST>(a, tile);
+    const LiveBlocks W = list_live_blocks(L);
+    for (int v = blockIdx.x; v < W.total; v += gridDim.x) {
+        int q, local, nb;
+        if (!live_block(W, v, q, local, nb)) continue;
+        const TripleArgs<R>& a = list_args<TripleArgs<R>>(L.args, q);
+        cheb_triple_tile<R, KS, VX, FIRST>(a, __builtin_amdgcn_readfirstlane(tile_of_block(a.t, local, nb)));
+    }
 }
 
 }  // namespace

@@ -9,7 +9,7 @@ namespace {
 template <typename R, typename KS>
 hipError_t batch_triple_t(int code, int vx, const BatchList& L, hipStream_t s) {
     const bool first = (code & 2) != 0;
-    const dim3 grid(L.blocks), block(L.wpb * kWave);
+    const dim3 grid(list_grid(L.blocks, L.nprob, L.wpb)), block(L.wpb * kWave);
     if (vx == 2) {
         if (first) hipLaunchKernelGGL((cheb_triple_batch_kernel<R, KS, 2, true>), grid, block, 0, s, L);
         else hipLaunchKernelGGL((cheb_triple_batch_kernel<R, KS, 2, false>), grid, block, 0, s, L);
