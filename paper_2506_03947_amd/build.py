@@ -86,7 +86,7 @@ def build(jobs: int | None = None, debug: bool = False, verbose: bool = True, in
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda j: compile_one(j, debug, incremental), work))
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), "-shared", "-o", tmp] + objs + ["--offload-arch=gfx950", "-fPIC", "-lrocblas"]
+    cmd = [hipcc(), "-shared", "-o", tmp] + objs + ["--offload-arch=gfx950", "-fPIC"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed\n{res.stdout}\n{res.stderr}")

@@ -325,6 +325,11 @@ hipError_t launch_exact_planes(int prec, bool split, const ExactArgs& a, void* p
 // carry: exact_carry_bytes(nx, ny, nslot) bytes of device scratch.
 size_t exact_carry_bytes(int nx, int ny, int nslot);
 hipError_t launch_exact_tridiag(int prec, const ExactArgs& a, void* t, void* u, void* carry, hipStream_t s);
+// C = op(S) B for the half sine matrices (exact_gemm.hip): S d x d column-major
+// (leading dimension d), B and C d x N with leading dimensions ldb, ldc; op(S) = S^T
+// when trans; prec 0 float64, otherwise float32.
+hipError_t launch_sine_gemm(int prec, bool trans, const void* S, int d, const void* B, int ldb, void* C, int ldc,
+                            int N, hipStream_t s);
 
 // ---- geometric multigrid for A - c I (mg.hip) --------------------------------
 // Vertex-centred V-cycle: coarse point J = fine point 2J + 1 per coarsened dimension,

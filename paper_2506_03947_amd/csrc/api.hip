@@ -2,7 +2,6 @@
 // flexible GMRES outer solve.  Host orchestration only; every vector operation
 // runs in the kernels of stencil.hip / krylov.hip / setup.hip.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <array>
@@ -41,13 +40,6 @@ int fail(int status, const std::string& msg) {
         hipError_t e_ = (call);                                                                      \
         if (e_ != hipSuccess)                                                                        \
             return fail(AC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));              \
-    } while (0)
-
-#define AC_BLAS(call)                                                                                \
-    do {                                                                                             \
-        rocblas_status b_ = (call);                                                                  \
-        if (b_ != rocblas_status_success)                                                            \
-            return fail(AC_ERR_HIP, std::string(#call) + ": " + rocblas_status_to_string(b_));       \
     } while (0)
 
 #define AC_TRY(call)              \
@@ -104,8 +96,6 @@ struct ac_ctx {
     int pairs = 1, pair_h = 0, pair_vx = 0, pair_wpb = 0;
     // three steady steps per sweep: 0 off, 1 on (where pairs are allowed); tiling as pairs
     int triples = 1, triple_h = 0, triple_vx = 0, triple_occ = 4;
-    // dense sine transforms of the exact inner solve (workspace set per call)
-    rocblas_handle blas = nullptr;
     // launch-bound inner solves (P_SP) are captured on this stream and replayed as graphs
     hipStream_t cap = nullptr;
     bool graphs = true;
@@ -420,14 +410,10 @@ size_t cnn_ws_bytes(const ac_problem* p) {
     return 3 * align_up(px * 32, 256) + align_up(px * 8, 256) + 256;
 }
 
-// rocBLAS workspace of the exact inner solve (plain GEMMs of these shapes need none;
-// the margin is for library kernels that split the reduction)
-constexpr size_t kBlasWs = 32u << 20;
-
-// exact inner solve: DST matrix, tridiagonal-scan carries, rocBLAS workspace
+// exact inner solve: DST matrix, tridiagonal-scan carries
 size_t exact_extra_bytes(const ac_problem* p, int prec) {
     return align_up(static_cast<size_t>(ac::dst_half_elems(p->g.nx)) * inner_elem(prec), 256) +
-           align_up(ac::exact_carry_bytes(p->g.nx, p->g.ny, p->ns), 256) + kBlasWs;
+           align_up(ac::exact_carry_bytes(p->g.nx, p->g.ny, p->ns), 256);
 }
 
 size_t sp_extra_bytes(const ac_problem* p, int prec) {
@@ -1200,7 +1186,6 @@ int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
     char* T = b.buf[1];
     char* S = b.cnn;
     char* carry = S + align_up(static_cast<size_t>(ac::dst_half_elems(nx)) * inner_elem(prec), 256);
-    char* bw = carry + align_up(ac::exact_carry_bytes(nx, ny, p->ns), 256);
     ac::ExactArgs a{};
     a.n = p->g.n;
     a.nx = nx;
@@ -1229,30 +1214,18 @@ int exact_inner(ac_problem* p, int prec, const PrecBufs& b, double* z) {
     ProfScope ps(c, AC_K_EXACT, bytes);
     AC_HIP(ac::launch_dst_half(prec, S, nx, st));
     AC_HIP(ac::launch_exact_planes(prec, true, a, P, st));
-    AC_BLAS(rocblas_set_stream(c->blas, st));
-    AC_BLAS(rocblas_set_workspace(c->blas, bw, kBlasWs));
-    const rocblas_int cols = static_cast<rocblas_int>(static_cast<long long>(ny) * planes);
+    const long long cols = static_cast<long long>(ny) * planes;
+    if (cols > 2147483647LL) return fail(AC_ERR_UNSUPPORTED, "too many plane columns for the sine transform");
     // Cm[off.., :] = op(half) * Bm[off.., :]; even block rows [0, h), odd block rows [h, nx)
     auto gemm = [&](bool inverse, const char* Bm, char* Cm) -> int {
-        const rocblas_operation op = inverse ? rocblas_operation_transpose : rocblas_operation_none;
+        const size_t esz_b = inner_elem(prec);
         for (int half = 0; half < 2; ++half) {
-            const rocblas_int d = half == 0 ? h : h2;
+            const int d = half == 0 ? h : h2;
             if (d == 0) continue;
             const size_t moff = half == 0 ? 0 : static_cast<size_t>(h) * h;  // matrix entries
             const size_t roff = half == 0 ? 0 : static_cast<size_t>(h);      // block row
-            if (prec == AC_PREC_FP64) {
-                const double one = 1.0, zero = 0.0;
-                const double* A = reinterpret_cast<const double*>(S) + moff;
-                AC_BLAS(rocblas_dgemm(c->blas, op, rocblas_operation_none, d, cols, d, &one, A, d,
-                                      reinterpret_cast<const double*>(Bm) + roff, nx, &zero,
-                                      reinterpret_cast<double*>(Cm) + roff, nx));
-            } else {
-                const float one = 1.0f, zero = 0.0f;
-                const float* A = reinterpret_cast<const float*>(S) + moff;
-                AC_BLAS(rocblas_sgemm(c->blas, op, rocblas_operation_none, d, cols, d, &one, A, d,
-                                      reinterpret_cast<const float*>(Bm) + roff, nx, &zero,
-                                      reinterpret_cast<float*>(Cm) + roff, nx));
-            }
+            AC_HIP(ac::launch_sine_gemm(prec == AC_PREC_FP64 ? 0 : 1, inverse, S + moff * esz_b, d,
+                                        Bm + roff * esz_b, nx, Cm + roff * esz_b, nx, static_cast<int>(cols), st));
         }
         return AC_OK;
     };
@@ -1407,15 +1380,8 @@ int ac_ctx_create(int device, void* stream, ac_ctx** out) {
         delete c;
         return fail(AC_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
-    const rocblas_status bs = rocblas_create_handle(&c->blas);
-    if (bs != rocblas_status_success) {
-        (void)hipHostFree(c->pinned);
-        delete c;
-        return fail(AC_ERR_HIP, std::string("rocblas_create_handle: ") + rocblas_status_to_string(bs));
-    }
     e = hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking);
     if (e != hipSuccess) {
-        (void)rocblas_destroy_handle(c->blas);
         (void)hipHostFree(c->pinned);
         delete c;
         return fail(AC_ERR_HIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
@@ -1423,7 +1389,6 @@ int ac_ctx_create(int device, void* stream, ac_ctx** out) {
     const int ns = ac::noalloc_scratch_init(device);
     if (ns < 0) {
         (void)hipStreamDestroy(c->cap);
-        (void)rocblas_destroy_handle(c->blas);
         (void)hipHostFree(c->pinned);
         delete c;
         return ns;
@@ -1444,7 +1409,6 @@ int ac_ctx_destroy(ac_ctx* c) {
         (void)hipEventDestroy(p.first);
         (void)hipEventDestroy(p.second);
     }
-    if (c->blas) (void)rocblas_destroy_handle(c->blas);
     if (c->cap) (void)hipStreamDestroy(c->cap);
     if (c->pinned) (void)hipHostFree(c->pinned);
     delete c;

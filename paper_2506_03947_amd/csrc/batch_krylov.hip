@@ -84,22 +84,34 @@ __global__ __launch_bounds__(kThreads) void bk_arnoldi_kernel(const BKProb* __re
                                                               const int* __restrict__ live, int j, int m) {
     const int q = blockIdx.x;
     if (!live[q]) return;
+    constexpr int NW = kThreads / kWave;
+    __shared__ double part[NW][2 * kMB];
     __shared__ double red[2 * kMB];
     __shared__ double Ls[kMB * kMB];
     const BKProb& p = list_args<BKProb>(P, q);
     BKState& s = S[q];
     const int nv = j + 1, nq = 2 * nv;
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
-    for (int t = wid; t < nq; t += kThreads / kWave) {
+    // wave w sums a contiguous quarter of the block partials, lane t output t (each
+    // wave reads whole partial rows); the quarters are added in order
+    {
+        const int per = (p.nblk + NW - 1) / NW;
+        const int b0 = wid * per, b1 = min(p.nblk, b0 + per);
         double a = 0.0;
-        for (int b = lane; b < p.nblk; b += kWave) a += p.partial[static_cast<long long>(b) * kBKRed + t];
-#pragma unroll
-        for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_down(a, off, kWave);
-        if (lane == 0) red[t] = a;
+        if (lane < nq)
+            for (int b = b0; b < b1; ++b) a += p.partial[static_cast<long long>(b) * kBKRed + lane];
+        if (lane < nq) part[wid][lane] = a;
     }
     for (int e = threadIdx.x; e < j * kMB; e += kThreads) {
         const int i = e / kMB, k = e % kMB;
         if (k < i) Ls[e] = s.Lg[i * m + k];
+    }
+    __syncthreads();
+    if (threadIdx.x < nq) {
+        double a = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) a += part[w][threadIdx.x];
+        red[threadIdx.x] = a;
     }
     __syncthreads();
     if (wid != 0) return;

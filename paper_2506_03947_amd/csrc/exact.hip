@@ -11,8 +11,9 @@
 // S_x has the reflection symmetry S[k][n-1-i] = (-1)^k S[k][i], so one butterfly level
 // halves each transform: the even modes k = 2m see only u_i = x_i + x_{n-1-i} (and the
 // middle point for odd n), the odd modes k = 2m+1 only v_i = x_i - x_{n-1-i}, each a
-// dense product with a half-size block of S_x (library GEMMs).  Spectral data are kept
-// in that order (h = ceil(n_x/2) even modes, then n_x - h odd modes); the inverse
+// dense product with a half-size block of S_x (matrix-core GEMMs, exact_gemm.hip).
+// Spectral data are kept in that order (h = ceil(n_x/2) even modes, then n_x - h odd
+// modes); the inverse
 // transform ends with x_i = E_i + O_i, x_{n-1-i} = E_i - O_i.  This file holds the half
 // matrices, the split into planes fused with the butterfly, the merge fused with its
 // inverse, and the tridiagonal solves, run as chunked scans over y so that every
