@@ -1,33 +1,15 @@
-// C ABI of alphacirc: contexts, problems, the preconditioner stages and the
-// flexible GMRES outer solve.  Host orchestration only; every vector operation
-// runs in the kernels of stencil.hip / krylov.hip / setup.hip.
-#include <hip/hip_runtime.h>
+// C ABI of alphacirc, first part: contexts, problems and the preconditioner stages
+// (the outer solves, batches, tuner and network are in solve.hip, batch.hip,
+// tuner.hip and cnn_api.hip).  Host orchestration only; every vector operation runs
+// in the kernels behind ac_internal.h.
+#include "host.h"
 
-#include <algorithm>
-#include <array>
-#include <chrono>
-#include <cmath>
-#include <complex>
-#include <cstdio>
-#include <cstring>
-#include <memory>
-#include <string>
-#include <vector>
-
-#include "alphacirc.h"
-#include "ac_internal.h"
-#include "tiling.h"
-
-using ac::Geom;
-using ac::kMaxEll;
-using ac::kMaxShift;
-using ac::Tiling;
-using cplx = std::complex<double>;
+using namespace ach;
 
 // ---------------------------------------------------------------------------
 // error plumbing
 
-namespace {
+namespace ach {
 thread_local std::string g_last_error;
 
 int fail(int status, const std::string& msg) {
@@ -35,154 +17,28 @@ int fail(int status, const std::string& msg) {
     return status;
 }
 
-#define AC_HIP(call)                                                                                 \
-    do {                                                                                             \
-        hipError_t e_ = (call);                                                                      \
-        if (e_ != hipSuccess)                                                                        \
-            return fail(AC_ERR_HIP, std::string(#call) + ": " + hipGetErrorString(e_));              \
-    } while (0)
+}  // namespace ach
 
-#define AC_TRY(call)              \
-    do {                          \
-        int s_ = (call);          \
-        if (s_ < 0) return s_;    \
-    } while (0)
+int ac::set_error(int status, const std::string& msg) { return ach::fail(status, msg); }
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
-}  // namespace
-
-int ac::set_error(int status, const std::string& msg) { return fail(status, msg); }
-
-namespace {
+namespace ach {
 
 constexpr double kPi = 3.14159265358979323846;
 
-}  // namespace
+}  // namespace ach
 
 // ---------------------------------------------------------------------------
-// opaque types
-
-// One stencil launch captured while a context records (batched driver): the op
-// (ac::BatchOp), its kernel variant, grid and argument bytes.
-struct ac_launch_rec {
-    int op, ell, prec, curk, vx, wpb, blocks;
-    std::vector<char> args;
-};
-
-struct ac_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    double* pinned = nullptr;  // host staging for reductions
-    bool profiling = false;
-    struct Pending {
-        hipEvent_t a, b;
-        int cls;
-        double bytes;
-        int launches;
-    };
-    std::vector<Pending> pending;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
-    double ms[AC_K_COUNT] = {};
-    long long launches[AC_K_COUNT] = {};
-    double bytes[AC_K_COUNT] = {};
-    // tiling overrides (0 = automatic): rows per wave, waves per block, points per lane
-    int tile_h = 0, tile_wpb = 0, tile_vx = 0;
-    // while set, stencil launch sites append records here instead of launching
-    std::vector<ac_launch_rec>* rec = nullptr;
-    // steady sweeps in shift groups: -1 automatic (5 or more unique shifts), 0 off, 1 on
-    int shift_groups = -1;
-    // two steady Chebyshev steps per sweep: 0 off, 1 on (Dirichlet grids); rows per
-    // wave, points per lane, waves per block of the paired sweep (0 = automatic)
-    int pairs = 1, pair_h = 0, pair_vx = 0, pair_wpb = 0;
-    // three steady steps per sweep: 0 off, 1 on (where pairs are allowed); tiling as pairs
-    int triples = 1, triple_h = 0, triple_vx = 0, triple_occ = 4;
-    // launch-bound inner solves (P_SP) are captured on this stream and replayed as graphs
-    hipStream_t cap = nullptr;
-    bool graphs = true;
-};
-
-constexpr int kResidBlocks = 512;  // blocks of the warm-start residual-statistics kernel
-// pinned host staging per context: reductions of up to 256 batched problems plus
-// their per-step scales and masks
-constexpr size_t kPinnedDoubles = 32768;
-
-struct ac_problem {
-    ac_ctx* ctx = nullptr;
-    Geom g{};
-    int ell = 0;
-    double alpha = 0;
-    int nsr = 0, nsc = 0, ns = 0;
-    double* k64 = nullptr;
-    float* k32 = nullptr;
-    uint16_t* k16 = nullptr;
-    double bounds[3][2] = {};  // per precision: mu_lo, mu_hi
-    double kmin64 = 0, kmax64 = 0;
-    double* rpart = nullptr;   // per-block partial sums of the warm-start residual test
-    double* kblocks = nullptr; // varying diagonal blocks: l coefficient fields for calA (k64 is their mean)
-    ac_cnn* cnn = nullptr;     // warm-start network (not owned)
-    // sweep tiling chosen for this problem (0 = the context's setting)
-    int tile_h = 0, tile_wpb = 0, tile_vx = 0;
-    // multigrid hierarchy of A (AC_INNER_SP), built by ac_problem_create_multigrid
-    ac::MgHierarchy mg{};
-    double* mgmem = nullptr;
-    // captured P_SP inner solve, valid for this workspace, step count and precision
-    struct SpGraph {
-        hipGraphExec_t exec = nullptr;
-        const void* ws = nullptr;
-        int iters = 0, prec = -1;
-    } spg;
-};
+// opaque-type accessors for the kernel units
 
 int ac::problem_device(const ac_problem* p) { return p->ctx->device; }
 int ac::ctx_device(const ac_ctx* c) { return c->device; }
 hipStream_t ac::ctx_stream(const ac_ctx* c) { return c->stream; }
 
-struct ac_cnn {
-    ac_ctx* ctx = nullptr;
-    char* mem = nullptr;       // one allocation for everything below
-    float* w = nullptr;        // float32 master parameters
-    float* g = nullptr;        // last gradient
-    float* m = nullptr;        // Adam moments
-    float* v = nullptr;
-    uint16_t* wf = nullptr;    // bf16 forward weights [3][9][16][16]
-    uint16_t* wb = nullptr;    // bf16 flipped/transposed weights for input gradients
-    float* bias = nullptr;     // [3][16]
-    double c0 = 0.0, c1 = 1.0; // ln kappa normalisation
-    int t = 0;                 // Adam steps taken
-    int fused = 1;             // inference by the fused (all layers in LDS) kernel
-    int scaled = 1;            // scale each guess by its residual-minimising factor
-    double accept = 1.0;       // keep a guess only if |rhat - B x0| < accept |rhat|
-};
-
 // ---------------------------------------------------------------------------
 // profiling helpers
 
-namespace {
+namespace ach {
 
-struct ProfScope {
-    ac_ctx* c;
-    hipEvent_t a = nullptr, b = nullptr;
-    int cls;
-    double bytes;
-    int launches = 1;
-    ProfScope(ac_ctx* ctx, int cls_, double bytes_) : c(ctx), cls(cls_), bytes(bytes_) {
-        if (!c->profiling) return;
-        if (!c->pool.empty()) {
-            a = c->pool.back().first;
-            b = c->pool.back().second;
-            c->pool.pop_back();
-        } else {
-            (void)hipEventCreate(&a);
-            (void)hipEventCreate(&b);
-        }
-        (void)hipEventRecord(a, c->stream);
-    }
-    ~ProfScope() {
-        if (!c->profiling || !a) return;
-        (void)hipEventRecord(b, c->stream);
-        c->pending.push_back({a, b, cls, bytes, launches});
-    }
-};
 
 int harvest(ac_ctx* c) {
     AC_HIP(hipStreamSynchronize(c->stream));
@@ -242,13 +98,6 @@ void spectral_offsets(const ac_problem* p, long long* off) {
     off[p->ns] = o;
 }
 
-// Steady Chebyshev sweeps of problems with many unique shifts run as several
-// launches of the (one real, two complex shifts) kernel variant over slot groups:
-// the all-shift variant needs more than 168 VGPRs at l = 10 (two waves per SIMD),
-// the group variant about 110 (four waves per SIMD), which hides more memory latency
-// at the price of reading kappa once per group.  Every shift is computed exactly as
-// in the all-shift variant.
-constexpr int kMaxGroups = 4;  // groups of (1 real, 2 complex) slots cover l <= 16
 
 bool use_shift_groups(const ac_problem* p) {
     const int mode = p->ctx->shift_groups;
@@ -426,7 +275,7 @@ size_t sp_extra_bytes(const ac_problem* p, int prec) {
 // reads), two for the exact and saddle-point solves.
 int iter_bufs(int inner) { return (inner == AC_INNER_EXACT || inner == AC_INNER_SP) ? 2 : 4; }
 
-size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
+size_t prec_ws_bytes(const ac_problem* p, int prec, int inner) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     size_t b = (1 + iter_bufs(inner)) * align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256) + 256;
@@ -436,13 +285,8 @@ size_t prec_ws_bytes(const ac_problem* p, int prec, int inner = AC_INNER_CHEB) {
     return b;
 }
 
-struct PrecBufs {
-    char* rhat;
-    char* buf[4];  // iterate buffers (the last two null for the exact and saddle-point solves)
-    char* cnn;     // start of the CNN buffers or of the exact / saddle-point solve's extra buffers
-};
 
-PrecBufs carve_prec(const ac_problem* p, int prec, void* ws, int inner = AC_INNER_CHEB) {
+PrecBufs carve_prec(const ac_problem* p, int prec, void* ws, int inner) {
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     const size_t sz = align_up(static_cast<size_t>(off[p->ns]) * inner_elem(prec), 256);
@@ -992,15 +836,6 @@ ac::CnnPrepArgs cnn_args(const ac_problem* p, int prec, const char* rhat) {
     return a;
 }
 
-// Per-slot sums over the grid for rhat and a guess x0 (B = A - lambda I):
-// rr = |rhat|^2, bb = |B x0|^2, (cr, ci) = sum conj(B x0) rhat (zero without x0).
-struct SlotStats {
-    std::vector<double> rr, bb, cr, ci;
-    // |rhat - c B x0|^2 for the complex factor c
-    double res(int s, double c_re = 1.0, double c_im = 0.0) const {
-        return rr[s] - 2.0 * (c_re * cr[s] - c_im * ci[s]) + (c_re * c_re + c_im * c_im) * bb[s];
-    }
-};
 
 int slot_residuals(ac_problem* p, int prec, const ac::CnnPrepArgs& a, const char* x0, SlotStats& out) {
     const void* kap = prec == AC_PREC_FP64 ? static_cast<const void*>(p->k64)
@@ -1301,7 +1136,7 @@ int sp_inner(ac_problem* p, int prec, int iters, const PrecBufs& b, double* z) {
 }
 
 int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* r, double* z,
-                    void* ws, double in_scale, int* fallbacks = nullptr) {
+                    void* ws, double in_scale, int* fallbacks) {
     const PrecBufs b = carve_prec(p, o->precision, ws, o->inner);
     AC_TRY(run_fwd(p, o->precision, r, b.rhat, in_scale));
     if (o->inner == AC_INNER_SP) {
@@ -1343,7 +1178,7 @@ int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double
 
 long long calA_partials(const ac_problem* p) { return calA_tiling(p).tiles * (p->kblocks ? p->ell : 1); }
 
-}  // namespace
+}  // namespace ach
 
 // ---------------------------------------------------------------------------
 // ABI (every definition below matches an extern "C" declaration of alphacirc.h)
@@ -1758,15 +1593,7 @@ int ac_prec_workspace_size(const ac_problem* p, const ac_solve_opts* o, size_t* 
     return AC_OK;
 }
 
-namespace {
-struct SolveWs {
-    double* V[ac::kMaxBasis];
-    double* Z[ac::kMaxBasis];
-    double* partial;   // krylov_blocks * 72
-    double* partial2;  // calA tiles
-    double* red;       // 128 reduced scalars
-    void* prec;
-};
+namespace ach {
 size_t vec_bytes(const ac_problem* p) { return align_up(static_cast<size_t>(p->ell) * p->g.n * sizeof(double), 256); }
 size_t solve_ws_bytes(const ac_problem* p, const ac_solve_opts* o) {
     const int m = o->restart_m;
@@ -1793,7 +1620,7 @@ SolveWs carve_solve(const ac_problem* p, const ac_solve_opts* o, void* ws) {
     w.prec = b;
     return w;
 }
-}  // namespace
+}  // namespace ach
 
 int ac_solve_workspace_size(const ac_problem* p, const ac_solve_opts* o, size_t* bytes) {
     if (!p || !o || !bytes) return fail(AC_ERR_ARG, "NULL argument");
@@ -1834,7 +1661,7 @@ int ac_tdft_forward(ac_problem* p, int prec, const double* r, void* rhat) {
     return run_fwd(p, prec, r, static_cast<char*>(rhat), 1.0);
 }
 
-namespace {
+namespace ach {
 __global__ void zero_kernel(double* x, long long n) {
     const long long i = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) x[i] = 0.0;
@@ -1842,6 +1669,17 @@ __global__ void zero_kernel(double* x, long long n) {
 
 __global__ void zero_kernel_int(int* x, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x) x[i] = 0;
+}
+
+hipError_t launch_zero(double* x, long long n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, x, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_int(int* x, int n, hipStream_t s) {
+    hipLaunchKernelGGL(zero_kernel_int, dim3(1), dim3(256), 0, s, x, n);
+    return hipGetLastError();
 }
 
 template <typename R>
@@ -1873,7 +1711,7 @@ int gather_t(ac_problem* p, int prec, const std::vector<std::pair<int, char*>>& 
     (void)rhat;
     return AC_OK;
 }
-}  // namespace
+}  // namespace ach
 
 int ac_shifted_cheb(ac_problem* p, const ac_solve_opts* o, const void* rhat, const void* x0hat, void* yhat, void* ws,
                     size_t ws_bytes) {
@@ -1907,1249 +1745,3 @@ int ac_tdft_inverse(ac_problem* p, int prec, const void* yhat, double* z) {
     return AC_OK;
 }
 
-// ---------------------------------------------------------------------------
-// FGMRES
-
-namespace {
-// Products with A per preconditioner application, counted over all l shifts as in
-// Table 1: p_m per Chebyshev solve; for P_SP two per MINRES step (complex shifts) and
-// one per CG step (real shifts); none for the exact solve.
-long long prec_products(const ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm) {
-    if (o->inner == AC_INNER_EXACT) return 0;
-    if (o->inner == AC_INNER_SP) return static_cast<long long>(pm[0]) * (2LL * (p->ell - p->nsr) + p->nsr);
-    long long s = 0;
-    for (int v : pm) s += v;
-    return s;
-}
-// The paper's outer solver (Section 5): Chebyshev semi-iteration on P^{-1} calA with
-// the Corollary 1 interval [1, mu^l/(mu^l - alpha)] and a zero-residual-norm stop.
-// Residual form: r = b - calA x, z = P^{-1} r, d_0 = z/theta, x_{k+1} = x_k + d_k,
-// rho_0 = delta/theta, rho_{k+1} = 1/(2 theta/delta - rho_k),
-// d_{k+1} = rho_{k+1} rho_k d_k + (2 rho_{k+1}/delta) z_{k+1}.
-int outer_cheb_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* b, double* x,
-                    void* ws, ac_solve_info* info, std::chrono::steady_clock::time_point t0) {
-    if (o->inner != AC_INNER_CHEB && o->inner != AC_INNER_EXACT && o->inner != AC_INNER_SP)
-        return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration takes the Chebyshev, exact or saddle-point "
-                                        "inner solves");
-    if (p->kblocks)
-        return fail(AC_ERR_UNSUPPORTED, "no eigenvalue interval is known for varying diagonal blocks (use FGMRES)");
-    // bf16 rounding of kappa (relative 2^-9) moves the eigenvalues of P^{-1} calA by more
-    // than the width of the Corollary 1 interval at small alpha, and the iteration diverges
-    if (o->precision == AC_PREC_MIXED_BF16K)
-        return fail(AC_ERR_UNSUPPORTED, "the outer Chebyshev iteration needs float32 or float64 kappa in the inner solve");
-    ac_ctx* c = p->ctx;
-    hipStream_t st = c->stream;
-    const long long len = static_cast<long long>(p->ell) * p->g.n;
-    SolveWs w = carve_solve(p, o, ws);
-    double* r = w.V[0];
-    double* d = w.V[1];
-    double* z = w.Z[0];
-    const int kb = ac::krylov_blocks();
-    const int ptiles = static_cast<int>(calA_partials(p));
-    const long long psum = prec_products(p, o, pm);
-    const double mul = std::pow(p->bounds[AC_PREC_FP64][0], p->ell);
-    const double lo = 1.0, hi = mul / (mul - p->alpha);
-    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo);
-    auto fetch1 = [&](double& v) -> int {
-        AC_HIP(hipMemcpyAsync(c->pinned, w.red, sizeof(double), hipMemcpyDeviceToHost, st));
-        AC_HIP(hipStreamSynchronize(st));
-        v = c->pinned[0];
-        return AC_OK;
-    };
-    double bb = 0.0;
-    {
-        ProfScope ps(c, AC_K_KRYLOV, 8.0 * len);
-        AC_HIP(ac::launch_norm2(b, len, w.partial, st));
-        AC_HIP(ac::launch_reduce(w.partial, kb, 1, 1, w.red, st));
-    }
-    AC_TRY(fetch1(bb));
-    const double bnorm = std::sqrt(bb);
-    if (!std::isfinite(bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
-    if (bnorm == 0.0) {  // the solution is x = 0, whatever the initial guess
-        hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((len + 255) / 256)), dim3(256), 0, st, x, len);
-        AC_HIP(hipGetLastError());
-        AC_HIP(hipStreamSynchronize(st));
-        if (info) *info = ac_solve_info{};
-        return AC_OK;
-    }
-    long long matvecs = 0;
-    int it = 0, status = AC_OK;
-    double beta = 0.0, rho = delta / theta;
-    while (true) {
-        AC_TRY(calA_impl(p, x, r, b, w.partial2));
-        AC_HIP(ac::launch_reduce(w.partial2, ptiles, 1, 1, w.red, st));
-        double rr = 0.0;
-        AC_TRY(fetch1(rr));
-        matvecs += p->ell;
-        beta = std::sqrt(rr);
-        if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
-        if (beta / bnorm <= o->tol) break;
-        if (it >= o->max_outer) {
-            status = AC_NOT_CONVERGED;
-            break;
-        }
-        AC_TRY(apply_prec_impl(p, o, pm, r, z, w.prec, 1.0));
-        matvecs += psum;
-        double a_k = 0.0, c_k = 1.0 / theta;
-        if (it > 0 && delta > 0.0) {
-            const double rn = 1.0 / (2.0 * theta / delta - rho);
-            a_k = rn * rho;
-            c_k = 2.0 * rn / delta;
-            rho = rn;
-        }
-        ProfScope ps(c, AC_K_KRYLOV, 40.0 * len);
-        AC_HIP(ac::launch_cheb_update(x, d, z, a_k, c_k, len, st));
-        ++it;
-    }
-    // the residual evaluations count l products each; the paper counts l per
-    // iteration, so drop the final check's product from the total
-    if (it > 0) matvecs -= p->ell;
-    if (info) {
-        *info = ac_solve_info{};
-        info->outer_iters = it;
-        info->matvecs_A = matvecs;
-        info->rel_residual_true = bnorm > 0 ? beta / bnorm : 0.0;
-        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    }
-    return status;
-}
-
-int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
-               ac_solve_info* info, double* rec, int rec_count, int* rec_done) {
-    const auto t0 = std::chrono::steady_clock::now();
-    if (!p || !b || !x) return fail(AC_ERR_ARG, "NULL argument");
-    if (ranges_overlap(b, x, block_bytes(p))) return fail(AC_ERR_ARG, "b and x overlap");
-    std::vector<int> pm;
-    AC_TRY(validate_opts(p, o, pm));
-    if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
-    if (!(o->tol > 0.0)) return fail(AC_ERR_ARG, "tol must be positive");
-    if (o->max_outer < 1) return fail(AC_ERR_ARG, "max_outer must be >= 1");
-    if (o->outer != AC_OUTER_FGMRES && o->outer != AC_OUTER_CHEBYSHEV) return fail(AC_ERR_ARG, "unknown outer solver");
-    if (!ws || ws_bytes < solve_ws_bytes(p, o)) return fail(AC_ERR_WORKSPACE, "workspace too small");
-    AC_HIP(hipSetDevice(p->ctx->device));
-    if (o->outer == AC_OUTER_CHEBYSHEV) {
-        if (rec) return fail(AC_ERR_UNSUPPORTED, "recording needs the FGMRES outer solver");
-        return outer_cheb_impl(p, o, pm, b, x, ws, info, t0);
-    }
-    ac_ctx* c = p->ctx;
-    hipStream_t st = c->stream;
-    const int m = o->restart_m;
-    const long long len = static_cast<long long>(p->ell) * p->g.n;
-    SolveWs w = carve_solve(p, o, ws);
-    const int kb = ac::krylov_blocks();
-    const int ptiles = static_cast<int>(calA_partials(p));
-    const long long psum = prec_products(p, o, pm);
-    long long matvecs = 0;
-
-    auto fetch = [&](int nq) -> int {
-        AC_HIP(hipMemcpyAsync(c->pinned, w.red, nq * sizeof(double), hipMemcpyDeviceToHost, st));
-        AC_HIP(hipStreamSynchronize(st));
-        return AC_OK;
-    };
-    // ||b||
-    {
-        ProfScope ps(c, AC_K_KRYLOV, 8.0 * len);
-        AC_HIP(ac::launch_norm2(b, len, w.partial, st));
-        AC_HIP(ac::launch_reduce(w.partial, kb, 1, 1, w.red, st));
-    }
-    AC_TRY(fetch(1));
-    const double bnorm = std::sqrt(c->pinned[0]);
-    if (!std::isfinite(bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
-    auto residual = [&](double& beta) -> int {
-        AC_TRY(calA_impl(p, x, w.V[0], b, w.partial2));
-        AC_HIP(ac::launch_reduce(w.partial2, ptiles, 1, 1, w.red, st));
-        AC_TRY(fetch(1));
-        beta = std::sqrt(c->pinned[0]);
-        matvecs += p->ell;
-        return AC_OK;
-    };
-    if (bnorm == 0.0) {
-        hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((len + 255) / 256)), dim3(256), 0, st, x, len);
-        AC_HIP(hipGetLastError());
-        AC_HIP(hipStreamSynchronize(st));
-        if (info) {
-            *info = ac_solve_info{};
-        }
-        return AC_OK;
-    }
-    double beta = 0;
-    AC_TRY(residual(beta));
-    int total = 0, restarts = 0, fallbacks = 0;
-    double orth_loss = 0.0;
-    std::vector<double> H((m + 1) * m), cs(m), sn(m), g(m + 1), scale(m + 1), y(m), Lg(m * m), hcol(m + 1);
-    int status = AC_OK;
-    while (true) {
-        if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
-        if (beta / bnorm <= o->tol) break;
-        if (total >= o->max_outer) {
-            status = AC_NOT_CONVERGED;
-            break;
-        }
-        if (o->inner == AC_INNER_CHEB_CNN_MR) {
-            // warm-started correction before the cycle: zw = P_warm(r) (the network's guesses
-            // corrected by the Chebyshev steps), then the one-dimensional minimal-residual
-            // step x += gamma zw, r -= gamma calA zw, gamma = <calA zw, r> / |calA zw|^2:
-            // the residual never grows, and the cycle that follows is the plain method's
-            ac_solve_opts ow = *o;
-            ow.inner = AC_INNER_CHEB_CNN;
-            AC_TRY(apply_prec_impl(p, &ow, pm, w.V[0], w.Z[0], w.prec, 1.0 / beta, &fallbacks));
-            AC_TRY(calA_impl(p, w.Z[0], w.V[1], nullptr, nullptr));
-            matvecs += p->ell + psum;
-            {
-                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * 2);
-                AC_HIP(ac::launch_mdot_strided(w.V[0], static_cast<long long>(vec_bytes(p) / sizeof(double)), 1,
-                                               false, w.V[1], len, w.partial, 72, st));
-                AC_HIP(ac::launch_reduce(w.partial, kb, 2, 72, w.red, st));
-            }
-            AC_TRY(fetch(2));
-            const double wr = c->pinned[0], ww = c->pinned[1];
-            if (ww > 0.0 && std::isfinite(wr) && std::isfinite(ww)) {
-                const double gam = wr / ww;
-                ac::VecSet zs{}, ws1{};
-                zs.v[0] = w.Z[0];
-                zs.s2[0] = gam;
-                ws1.v[0] = w.V[1];
-                ws1.s2[0] = gam;
-                {
-                    ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * 3);
-                    AC_HIP(ac::launch_maxpy(zs, 1, nullptr, x, len, st));
-                }
-                {
-                    ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * 3);
-                    AC_HIP(ac::launch_axpy_norm(ws1, 1, nullptr, w.V[0], len, w.partial, 72, st));
-                    AC_HIP(ac::launch_reduce(w.partial, kb, 1, 72, w.red, st));
-                }
-                AC_TRY(fetch(1));
-                beta = std::sqrt(c->pinned[0]);
-                if (!std::isfinite(beta)) return fail(AC_ERR_NONFINITE, "residual is not finite");
-                if (beta / bnorm <= o->tol) break;
-            }
-        }
-        std::fill(H.begin(), H.end(), 0.0);
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        scale[0] = 1.0 / beta;
-        int kdone = 0;
-        for (int j = 0; j < m; ++j) {
-            if (rec && *rec_done < rec_count) {
-                AC_HIP(hipMemcpyAsync(rec + static_cast<size_t>(*rec_done) * len, w.V[j], len * sizeof(double),
-                                      hipMemcpyDeviceToDevice, st));
-                ++*rec_done;
-            }
-            // z_j = P^{-1} v_j with v_j = scale_j * V_j (scale folded into the transform);
-            // AC_INNER_CHEB_CNN_CYCLE warm-starts only the cycle's first vector
-            ac_solve_opts oj = *o;
-            if ((o->inner == AC_INNER_CHEB_CNN_CYCLE && j > 0) || o->inner == AC_INNER_CHEB_CNN_MR)
-                oj.inner = AC_INNER_CHEB;
-            AC_TRY(apply_prec_impl(p, &oj, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
-            AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
-            matvecs += p->ell + psum;
-            ac::VecSet vs{};
-            for (int i = 0; i <= j; ++i) vs.v[i] = w.V[i];
-            const int nv = j + 1;
-            // Modified Gram-Schmidt in inverse compact WY form (one reduction per step):
-            // the projector (I - q_j q_j^T)...(I - q_0 q_0^T) equals I - Q (I + L)^{-1} Q^T with
-            // L the strictly lower part of Q^T Q.  One sweep gives r = Q^T w and the new row
-            // of L (dots of the newest basis vector with the older ones); the host solves
-            // (I + L) h = r; a second sweep forms w - Q h and its norm.
-            {
-                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 1));
-                AC_HIP(ac::launch_mdot_strided(w.V[0], static_cast<long long>(vec_bytes(p) / sizeof(double)), nv,
-                                               j >= 1, w.V[j + 1], len, w.partial, 72, st));
-                AC_HIP(ac::launch_reduce(w.partial, kb, j >= 1 ? 2 * nv : nv + 1, 72, w.red, st));
-            }
-            AC_TRY(fetch(2 * nv + 1));
-            {
-                const double* hd = c->pinned;
-                for (int i = 0; i < j; ++i) {
-                    Lg[j * m + i] = scale[i] * scale[j] * hd[nv + 1 + i];
-                    orth_loss = std::max(orth_loss, std::abs(Lg[j * m + i]));
-                }
-                for (int i = 0; i <= j; ++i) {
-                    double hi = scale[i] * hd[i];
-                    for (int k = 0; k < i; ++k) hi -= Lg[i * m + k] * hcol[k];
-                    hcol[i] = hi;
-                    H[i * m + j] = hi;
-                    vs.s2[i] = scale[i] * hi;  // coefficient of the raw basis vector
-                }
-            }
-            {
-                ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 2));
-                AC_HIP(ac::launch_axpy_norm(vs, nv, nullptr, w.V[j + 1], len, w.partial, 72, st));
-                AC_HIP(ac::launch_reduce(w.partial, kb, 1, 72, w.red, st));
-            }
-            AC_TRY(fetch(1));
-            const double hn = std::sqrt(c->pinned[0]);
-            if (!std::isfinite(hn)) return fail(AC_ERR_NONFINITE, "Arnoldi produced a non-finite value");
-            H[(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {
-                const double t = cs[i] * H[i * m + j] + sn[i] * H[(i + 1) * m + j];
-                H[(i + 1) * m + j] = -sn[i] * H[i * m + j] + cs[i] * H[(i + 1) * m + j];
-                H[i * m + j] = t;
-            }
-            const double den = std::hypot(H[j * m + j], H[(j + 1) * m + j]);
-            cs[j] = den > 0 ? H[j * m + j] / den : 1.0;
-            sn[j] = den > 0 ? H[(j + 1) * m + j] / den : 0.0;
-            H[j * m + j] = den;
-            H[(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            ++total;
-            kdone = j + 1;
-            if (std::abs(g[j + 1]) / bnorm <= o->tol || total >= o->max_outer || hn == 0.0) break;
-            scale[j + 1] = 1.0 / hn;
-        }
-        // back substitution and x += Z y
-        for (int i = kdone - 1; i >= 0; --i) {
-            double t = g[i];
-            for (int k = i + 1; k < kdone; ++k) t -= H[i * m + k] * y[k];
-            y[i] = H[i * m + i] != 0.0 ? t / H[i * m + i] : 0.0;
-        }
-        {
-            ac::VecSet zs{};
-            for (int i = 0; i < kdone; ++i) {
-                zs.v[i] = w.Z[i];
-                zs.s2[i] = y[i];
-            }
-            ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (kdone + 2));
-            AC_HIP(ac::launch_maxpy(zs, kdone, nullptr, x, len, st));
-        }
-        ++restarts;
-        AC_TRY(residual(beta));
-    }
-    if (info) {
-        info->outer_iters = total;
-        info->restarts = restarts;
-        info->matvecs_A = matvecs;
-        info->rel_residual_true = beta / bnorm;
-        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        info->cnn_fallbacks = fallbacks;
-        info->reserved = 0;
-        info->orth_loss = orth_loss;
-    }
-    if (rec) AC_HIP(hipStreamSynchronize(st));
-    return status;
-}
-}  // namespace
-
-int ac_solve(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
-             ac_solve_info* info) {
-    return solve_impl(p, o, b, x, ws, ws_bytes, info, nullptr, 0, nullptr);
-}
-
-int ac_solve_record(ac_problem* p, const ac_solve_opts* o, const double* b, double* x, void* ws, size_t ws_bytes,
-                    ac_solve_info* info, double* rec, int rec_count, int* recorded) {
-    if (!rec || rec_count < 1 || !recorded) return fail(AC_ERR_ARG, "record buffer, count and counter are required");
-    *recorded = 0;
-    return solve_impl(p, o, b, x, ws, ws_bytes, info, rec, rec_count, recorded);
-}
-
-// ---------------------------------------------------------------------------
-// Batched solves: many independent problems (uneven grids and l) advance their
-// FGMRES iterations in lockstep.  Per Arnoldi index j the preconditioner and the
-// calA product of every problem are recorded once as launch records, and aligned
-// records are grouped by kernel variant into work lists; so is the residual
-// b - calA x.  The Arnoldi scalars of every problem (Gram-Schmidt coefficients,
-// Givens rotations, convergence and restart tests) live in device memory and are
-// updated by small kernels, so one whole FGMRES cycle of all problems is captured
-// once as a hipGraph and replayed; the host reads one counter per cycle.
-
-namespace {
-
-constexpr int kMaxBatch = 256;
-constexpr int kFetchStride = 2 * ac::kMaxBasis + 2;  // pinned doubles per problem per fetch
-
-struct BatchLaunch {
-    int op, ell, prec, curk, vx;
-    ac::BatchList list;
-};
-
-size_t max_args_bytes() {
-    return std::max({sizeof(ac::SweepArgs<double>), sizeof(ac::SweepArgs<float>), sizeof(ac::FwdArgs),
-                     sizeof(ac::CalAArgs), sizeof(ac::TripleArgs<double>), sizeof(ac::TripleArgs<float>),
-                     sizeof(ac::PairArgs<double>), sizeof(ac::PairArgs<float>)});
-}
-
-// Device bytes for the work lists: per j (and once more for the residual form) at most
-// kMaxGroups p + 3 launch positions (a sweep step records kMaxGroups shift groups),
-// each with at most `count` groups.
-size_t batch_list_bytes(int count, const ac_solve_opts* o) {
-    const size_t per_pos = static_cast<size_t>(count) * (align_up(max_args_bytes(), 16) + 8) +
-                           static_cast<size_t>(count) * (3 * 256 + 8);
-    return static_cast<size_t>(o->restart_m + 1) * static_cast<size_t>(kMaxGroups * o->p_uniform + 3) * per_pos + 256;
-}
-
-size_t batch_kry_bytes(int count) {
-    return align_up(static_cast<size_t>(count + 1) * sizeof(int), 256) +
-           align_up(static_cast<size_t>(count) * sizeof(ac::BKProb), 256) +
-           align_up(static_cast<size_t>(count) * sizeof(ac::BKState), 256);
-}
-
-size_t batch_ws_bytes(int count, ac_problem* const* probs, const ac_solve_opts* o) {
-    size_t b = batch_list_bytes(count, o) + align_up(static_cast<size_t>(count) * 12, 256) + 256 +
-               batch_kry_bytes(count);
-    for (int q = 0; q < count; ++q) b += align_up(solve_ws_bytes(probs[q], o), 256);
-    return b;
-}
-
-int validate_batch(ac_ctx* c, int count, ac_problem* const* probs, const ac_solve_opts* o) {
-    if (!c || !probs || !o) return fail(AC_ERR_ARG, "NULL argument");
-    if (count < 1 || count > kMaxBatch) return fail(AC_ERR_UNSUPPORTED, "batch size must be in [1, 256]");
-    if (o->inner != AC_INNER_CHEB) return fail(AC_ERR_UNSUPPORTED, "batched solves use the plain inner solver");
-    if (o->outer != AC_OUTER_FGMRES) return fail(AC_ERR_UNSUPPORTED, "batched solves use the FGMRES outer solver");
-    if (o->p_per_shift) return fail(AC_ERR_UNSUPPORTED, "batched solves take a uniform inner count (p_uniform)");
-    if (o->restart_m < 1 || o->restart_m > 32) return fail(AC_ERR_UNSUPPORTED, "restart_m must be in [1, 32]");
-    if (!(o->tol > 0.0)) return fail(AC_ERR_ARG, "tol must be positive");
-    if (o->max_outer < 1) return fail(AC_ERR_ARG, "max_outer must be >= 1");
-    for (int q = 0; q < count; ++q) {
-        if (!probs[q]) return fail(AC_ERR_ARG, "NULL problem");
-        if (probs[q]->ctx != c) return fail(AC_ERR_ARG, "every problem must belong to the context");
-        if (probs[q]->g.periodic) return fail(AC_ERR_UNSUPPORTED, "batched solves take Dirichlet grids");
-        if (probs[q]->kblocks) return fail(AC_ERR_UNSUPPORTED, "batched solves take one block operator per problem");
-        std::vector<int> pm;
-        AC_TRY(validate_opts(probs[q], o, pm));
-    }
-    return AC_OK;
-}
-
-struct BatchState {
-    ac_problem* p;
-    SolveWs w;
-    std::vector<int> pm;
-    long long len = 0, psum = 0;
-};
-
-// Restores the context and frees the graphs and the capture stream on every exit path.
-struct BatchGuard {
-    ac_ctx* c;
-    hipStream_t user, own = nullptr;
-    bool prof;
-    std::vector<hipGraphExec_t> execs;
-    ~BatchGuard() {
-        c->rec = nullptr;
-        if (own) (void)hipStreamSynchronize(own);
-        for (auto e : execs)
-            if (e) (void)hipGraphExecDestroy(e);
-        if (own) (void)hipStreamDestroy(own);
-        c->stream = user;
-        c->profiling = prof;
-    }
-};
-
-}  // namespace
-
-int ac_batch_workspace_size(ac_ctx* c, int count, ac_problem* const* probs, const ac_solve_opts* o,
-                            size_t* bytes) {
-    if (!bytes) return fail(AC_ERR_ARG, "NULL argument");
-    AC_TRY(validate_batch(c, count, probs, o));
-    *bytes = batch_ws_bytes(count, probs, o);
-    return AC_OK;
-}
-
-int ac_batch_solve(ac_ctx* c, int count, ac_problem* const* probs, const ac_solve_opts* o, const double* const* b,
-                   double* const* x, void* ws, size_t ws_bytes, ac_solve_info* infos) {
-    const auto t0 = std::chrono::steady_clock::now();
-    AC_TRY(validate_batch(c, count, probs, o));
-    if (!b || !x) return fail(AC_ERR_ARG, "NULL argument");
-    for (int q = 0; q < count; ++q) {
-        if (!b[q] || !x[q]) return fail(AC_ERR_ARG, "NULL right-hand side or solution");
-        if (ranges_overlap(b[q], x[q], block_bytes(probs[q]))) return fail(AC_ERR_ARG, "b and x overlap");
-    }
-    if (!ws || ws_bytes < batch_ws_bytes(count, probs, o)) return fail(AC_ERR_WORKSPACE, "workspace too small");
-    AC_HIP(hipSetDevice(c->device));
-    const int m = o->restart_m;
-    // The legacy default stream cannot be captured: work on a stream of our own.
-    AC_HIP(hipStreamSynchronize(c->stream));
-    BatchGuard guard{c, c->stream, nullptr, c->profiling, std::vector<hipGraphExec_t>(1, nullptr)};
-    AC_HIP(hipStreamCreateWithFlags(&guard.own, hipStreamNonBlocking));
-    hipStream_t st = guard.own;
-    c->stream = st;
-    c->profiling = false;
-
-    // workspace: [lists][scale doubles | live ints][cycle mask, active count | problem
-    // list | scalar states][per-problem solve workspaces]
-    char* base = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
-    char* lists = base;
-    const size_t list_cap = batch_list_bytes(count, o);
-    double* dscale = reinterpret_cast<double*>(base + align_up(list_cap, 256));
-    int* dlive = reinterpret_cast<int*>(dscale + count);
-    char* pw = base + align_up(list_cap, 256) + align_up(static_cast<size_t>(count) * 12, 256) +
-               batch_kry_bytes(count);
-    std::vector<BatchState> S(count);
-    for (int q = 0; q < count; ++q) {
-        BatchState& s = S[q];
-        s.p = probs[q];
-        AC_TRY(validate_opts(s.p, o, s.pm));
-        s.w = carve_solve(s.p, o, pw);
-        pw += align_up(solve_ws_bytes(s.p, o), 256);
-        s.len = static_cast<long long>(s.p->ell) * s.p->g.n;
-        for (int v : s.pm) s.psum += v;
-    }
-
-    // record every problem's launches for each j (and the residual form) and group
-    // aligned records into work lists
-    std::vector<std::vector<BatchLaunch>> plan(m + 1);  // plan[m]: the residual b - calA x
-    std::vector<char> host(list_cap, 0);
-    size_t used = 0;
-    auto take = [&](size_t bytes, size_t align) -> size_t {
-        used = align_up(used, align);
-        const size_t off = used;
-        used += bytes;
-        return off;
-    };
-    struct Pending {
-        BatchLaunch l;
-        size_t args_off, first_off, pid_off;
-    };
-    std::vector<std::vector<Pending>> pend(m + 1);
-    auto group = [&](std::vector<std::vector<ac_launch_rec>>& recs, std::vector<Pending>& out) -> int {
-        for (int q = 0; q < count; ++q)
-            if (recs[q].size() != recs[0].size()) return fail(AC_ERR_UNSUPPORTED, "batch launch sequences differ");
-        const size_t npos = recs[0].size();
-        for (size_t i = 0; i < npos; ++i) {
-            std::vector<int> done(count, 0);
-            for (int q = 0; q < count; ++q) {
-                if (recs[q][i].op != recs[0][i].op) return fail(AC_ERR_UNSUPPORTED, "batch launch sequences differ");
-                if (recs[q][i].blocks == 0) done[q] = 1;  // an empty shift group
-            }
-            for (int q0 = 0; q0 < count; ++q0) {
-                if (done[q0]) continue;
-                const ac_launch_rec& r0 = recs[q0][i];
-                std::vector<int> members;
-                for (int q = q0; q < count; ++q) {
-                    const ac_launch_rec& r = recs[q][i];
-                    if (!done[q] && r.ell == r0.ell && r.prec == r0.prec && r.curk == r0.curk && r.vx == r0.vx &&
-                        r.wpb == r0.wpb) {
-                        members.push_back(q);
-                        done[q] = 1;
-                    }
-                }
-                const size_t asz = r0.args.size();
-                Pending pg{};
-                pg.l = BatchLaunch{r0.op, r0.ell, r0.prec, r0.curk, r0.vx, ac::BatchList{}};
-                const int n = static_cast<int>(members.size());
-                pg.args_off = take(asz * n, 256);
-                pg.first_off = take(sizeof(int) * (n + 1), 16);
-                pg.pid_off = take(sizeof(int) * n, 16);
-                if (used > list_cap) return fail(AC_ERR_WORKSPACE, "batch work lists exceed their bound");
-                int* first = reinterpret_cast<int*>(host.data() + pg.first_off);
-                int* pid = reinterpret_cast<int*>(host.data() + pg.pid_off);
-                int blocks = 0;
-                for (int k = 0; k < n; ++k) {
-                    const ac_launch_rec& r = recs[members[k]][i];
-                    std::memcpy(host.data() + pg.args_off + asz * k, r.args.data(), asz);
-                    first[k] = blocks;
-                    pid[k] = members[k];
-                    blocks += r.blocks;
-                }
-                first[n] = blocks;
-                pg.l.list.nprob = n;
-                pg.l.list.blocks = blocks;
-                pg.l.list.wpb = r0.wpb;
-                out.push_back(pg);
-            }
-        }
-        return AC_OK;
-    };
-    for (int j = 0; j <= m; ++j) {
-        std::vector<std::vector<ac_launch_rec>> recs(count);
-        for (int q = 0; q < count; ++q) {
-            BatchState& s = S[q];
-            c->rec = &recs[q];
-            int e = AC_OK;
-            if (j < m) {
-                e = apply_prec_impl(s.p, o, s.pm, s.w.V[j], s.w.Z[j], s.w.prec, 1.0);
-                if (e >= 0) e = calA_impl(s.p, s.w.Z[j], s.w.V[j + 1], nullptr, nullptr);
-            } else {
-                e = calA_impl(s.p, x[q], s.w.V[0], b[q], s.w.partial2);
-            }
-            c->rec = nullptr;
-            if (e < 0) return e;
-        }
-        AC_TRY(group(recs, pend[j]));
-    }
-
-    // device state of the batched FGMRES: problem list, scalar states, masks
-    char* kry = base + align_up(list_cap, 256) + align_up(static_cast<size_t>(count) * 12, 256);
-    int* dcyc = reinterpret_cast<int*>(kry);
-    ac::BKProb* dP = reinterpret_cast<ac::BKProb*>(kry + align_up(static_cast<size_t>(count + 1) * sizeof(int), 256));
-    ac::BKState* dS = reinterpret_cast<ac::BKState*>(reinterpret_cast<char*>(dP) +
-                                                     align_up(static_cast<size_t>(count) * sizeof(ac::BKProb), 256));
-    std::vector<ac::BKProb> hP(count);
-    int kblocks = 0;
-    for (int q = 0; q < count; ++q) {
-        BatchState& s = S[q];
-        ac::BKProb& bp = hP[q];
-        bp.v0 = s.w.V[0];
-        bp.z0 = s.w.Z[0];
-        bp.x = x[q];
-        bp.vstride = static_cast<long long>(vec_bytes(s.p) / sizeof(double));
-        bp.len = s.len;
-        bp.partial = s.w.partial;
-        bp.partial2 = s.w.partial2;
-        bp.ntiles = static_cast<int>(calA_partials(s.p));
-        // one block per 512 elements, at most the single solve's block count
-        const long long want = (s.len + 511) / 512;
-        bp.nblk = static_cast<int>(std::min<long long>(std::max<long long>(want, 1), ac::krylov_blocks()));
-        kblocks += bp.nblk;
-    }
-    AC_HIP(hipMemcpyAsync(dP, hP.data(), static_cast<size_t>(count) * sizeof(ac::BKProb), hipMemcpyHostToDevice, st));
-    AC_HIP(hipMemcpyAsync(lists, host.data(), used, hipMemcpyHostToDevice, st));
-    for (int j = 0; j <= m; ++j)
-        for (auto& pg : pend[j]) {
-            BatchLaunch l = pg.l;
-            l.list.args = lists + pg.args_off;
-            l.list.first = reinterpret_cast<const int*>(lists + pg.first_off);
-            l.list.pid = reinterpret_cast<const int*>(lists + pg.pid_off);
-            l.list.live = j < m ? dlive : dcyc;
-            l.list.scale = l.op == ac::BOP_FWD ? dscale : nullptr;
-            plan[j].push_back(l);
-        }
-
-    auto fetch = [&](const std::vector<int>& qs, int nq) -> int {
-        for (int q : qs)
-            AC_HIP(hipMemcpyAsync(c->pinned + static_cast<size_t>(q) * kFetchStride, S[q].w.red,
-                                  nq * sizeof(double), hipMemcpyDeviceToHost, st));
-        AC_HIP(hipStreamSynchronize(st));
-        return AC_OK;
-    };
-    auto fetched = [&](int q) { return c->pinned + static_cast<size_t>(q) * kFetchStride; };
-    const int kb = ac::krylov_blocks();
-
-    // ||b|| and the first residuals (once, on the host)
-    std::vector<int> all(count);
-    for (int q = 0; q < count; ++q) {
-        all[q] = q;
-        AC_HIP(ac::launch_norm2(b[q], S[q].len, S[q].w.partial, st));
-        AC_HIP(ac::launch_reduce(S[q].w.partial, kb, 1, 1, S[q].w.red, st));
-    }
-    AC_TRY(fetch(all, 1));
-    std::vector<int> live_q;
-    std::vector<ac::BKState> hS(count);
-    for (int q = 0; q < count; ++q) {
-        ac::BKState& ks = hS[q];
-        std::memset(&ks, 0, sizeof(ks));
-        ks.ell = S[q].p->ell;
-        ks.psum = S[q].psum;
-        ks.bnorm = std::sqrt(fetched(q)[0]);
-        if (!std::isfinite(ks.bnorm)) return fail(AC_ERR_NONFINITE, "b is not finite");
-        if (ks.bnorm == 0.0) {
-            hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((S[q].len + 255) / 256)), dim3(256), 0, st, x[q],
-                               S[q].len);
-            AC_HIP(hipGetLastError());
-            ks.finished = 1;
-        } else {
-            live_q.push_back(q);
-        }
-    }
-    for (int q : live_q) {
-        BatchState& s = S[q];
-        AC_TRY(calA_impl(s.p, x[q], s.w.V[0], b[q], s.w.partial2));
-        AC_HIP(ac::launch_reduce(s.w.partial2, static_cast<int>(calA_partials(s.p)), 1, 1, s.w.red, st));
-    }
-    AC_TRY(fetch(live_q, 1));
-    for (int q : live_q) {
-        hS[q].beta = std::sqrt(fetched(q)[0]);
-        hS[q].matvecs = S[q].p->ell;
-    }
-    AC_HIP(hipMemcpyAsync(dS, hS.data(), static_cast<size_t>(count) * sizeof(ac::BKState), hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(zero_kernel_int, dim3(1), dim3(256), 0, st, dcyc, count);
-    AC_HIP(hipGetLastError());
-    AC_HIP(ac::launch_bk_cycle(dP, dS, count, dlive, dcyc, dscale, m, o->tol, o->max_outer, st));
-    // problems in the next cycle, read from the cycle mask
-    int* hcyc = reinterpret_cast<int*>(c->pinned);
-    auto active = [&]() -> int {
-        AC_HIP(hipMemcpyAsync(hcyc, dcyc, static_cast<size_t>(count) * sizeof(int), hipMemcpyDeviceToHost, st));
-        AC_HIP(hipStreamSynchronize(st));
-        int n = 0;
-        for (int q = 0; q < count; ++q) n += hcyc[q] != 0;
-        return n;
-    };
-    int nact = active();
-    if (nact < 0) return nact;
-
-    // One FGMRES cycle of every problem in it, captured once as a graph: per Arnoldi
-    // index the preconditioner and calA work lists, the batched multi-dot, the
-    // Gram-Schmidt coefficients, the multi-axpy with the new norm and the Givens update;
-    // then x += Z y, the residuals, and the restart test that sets the next cycle's
-    // masks.  The host reads one counter per cycle.
-    auto record_cycle = [&]() -> hipError_t {
-        hipError_t e = hipSuccess;
-        for (int j = 0; j < m && e == hipSuccess; ++j) {
-            for (const BatchLaunch& l : plan[j]) {
-                e = ac::launch_batch(l.op, l.ell, l.prec, l.curk, l.vx, l.list, st);
-                if (e != hipSuccess) return e;
-            }
-            const int nv = j + 1;
-            e = ac::launch_bk_mdot(dP, count, kblocks, dlive, nv, st);
-            if (e == hipSuccess) e = ac::launch_bk_arnoldi(dP, dS, count, dlive, j, m, st);
-            if (e == hipSuccess) e = ac::launch_bk_axpy_norm(dP, dS, count, kblocks, dlive, nv, st);
-            if (e == hipSuccess) e = ac::launch_bk_givens(dP, dS, count, dlive, dscale, j, m, o->tol, o->max_outer, st);
-        }
-        if (e == hipSuccess) e = ac::launch_bk_update(dP, dS, count, kblocks, dcyc, m, st);
-        for (const BatchLaunch& l : plan[m]) {
-            if (e != hipSuccess) break;
-            e = ac::launch_batch(l.op, l.ell, l.prec, l.curk, l.vx, l.list, st);
-        }
-        if (e == hipSuccess) e = ac::launch_bk_cycle(dP, dS, count, dlive, dcyc, dscale, m, o->tol, o->max_outer, st);
-        return e;
-    };
-    while (nact > 0) {
-        if (!guard.execs[0]) {
-            AC_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-            const hipError_t le = record_cycle();
-            hipGraph_t graph = nullptr;
-            const hipError_t ee = hipStreamEndCapture(st, &graph);
-            if (le != hipSuccess || ee != hipSuccess) {
-                if (graph) (void)hipGraphDestroy(graph);
-                return fail(AC_ERR_HIP, std::string("batch graph capture: ") + hipGetErrorString(le != hipSuccess ? le : ee));
-            }
-            const hipError_t ie = hipGraphInstantiate(&guard.execs[0], graph, nullptr, nullptr, 0);
-            (void)hipGraphDestroy(graph);
-            if (ie != hipSuccess) return fail(AC_ERR_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
-        }
-        AC_HIP(hipGraphLaunch(guard.execs[0], st));
-        nact = active();
-        if (nact < 0) return nact;
-    }
-    AC_HIP(hipMemcpyAsync(hS.data(), dS, static_cast<size_t>(count) * sizeof(ac::BKState), hipMemcpyDeviceToHost, st));
-    AC_HIP(hipStreamSynchronize(st));
-    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-    int worst = AC_OK;
-    for (int q = 0; q < count; ++q) {
-        const ac::BKState& ks = hS[q];
-        if (ks.status == AC_ERR_NONFINITE) return fail(AC_ERR_NONFINITE, "a batched solve produced a non-finite value");
-        if (ks.status == AC_NOT_CONVERGED) worst = AC_NOT_CONVERGED;
-        if (!infos) continue;
-        ac_solve_info& in = infos[q];
-        in = ac_solve_info{};
-        in.outer_iters = ks.total;
-        in.restarts = ks.restarts;
-        in.matvecs_A = ks.matvecs;
-        in.rel_residual_true = ks.bnorm > 0 ? ks.beta / ks.bnorm : 0.0;
-        in.seconds = secs;
-        in.orth_loss = ks.orth;
-    }
-    return worst;
-}
-
-// ---------------------------------------------------------------------------
-// tiling control (used by the tile tuner)
-int ac_ctx_set_shift_groups(ac_ctx* c, int mode) {
-    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
-    if (mode < -1 || mode > 1) return fail(AC_ERR_ARG, "mode must be -1, 0 or 1");
-    c->shift_groups = mode;
-    return AC_OK;
-}
-
-int ac_ctx_set_step_triples(ac_ctx* c, int mode, int rows_per_wave, int waves_per_simd, int points_per_lane) {
-    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
-    if (mode < 0 || mode > 1) return fail(AC_ERR_ARG, "mode must be 0 or 1");
-    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
-    if (waves_per_simd < 0 || waves_per_simd > 8) return fail(AC_ERR_ARG, "waves_per_simd must be 0..8");
-    if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
-    c->triples = mode;
-    c->triple_h = rows_per_wave;
-    c->triple_occ = waves_per_simd > 0 ? waves_per_simd : 4;
-    c->triple_vx = points_per_lane;
-    return AC_OK;
-}
-
-int ac_ctx_set_step_pairs(ac_ctx* c, int mode, int rows_per_wave, int waves_per_block, int points_per_lane) {
-    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
-    if (mode < 0 || mode > 1) return fail(AC_ERR_ARG, "mode must be 0 or 1");
-    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
-    if (waves_per_block < 0 || waves_per_block > 4) return fail(AC_ERR_ARG, "waves_per_block must be 0..4");
-    if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
-    c->pairs = mode;
-    c->pair_h = rows_per_wave;
-    c->pair_wpb = waves_per_block;
-    c->pair_vx = points_per_lane;
-    return AC_OK;
-}
-
-int ac_ctx_set_tiling(ac_ctx* c, int rows_per_wave, int waves_per_block, int points_per_lane) {
-    if (!c) return fail(AC_ERR_ARG, "ctx is NULL");
-    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
-    if (waves_per_block < 0 || waves_per_block > 4) return fail(AC_ERR_ARG, "waves_per_block must be 0..4");
-    if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
-    c->tile_h = rows_per_wave;
-    c->tile_wpb = waves_per_block;
-    c->tile_vx = points_per_lane;
-    return AC_OK;
-}
-
-// ---------------------------------------------------------------------------
-// Tile tuner: times the Chebyshev sweeps of one problem for candidate tilings and
-// keeps the fastest; choices are cached in a small JSON file, one entry per line.
-
-namespace {
-
-struct TileEntry {
-    int nx, ny, ell, prec, h, wpb, vx;
-    double us;
-};
-
-const char* kTileFmt =
-    "{\"nx\": %d, \"ny\": %d, \"ell\": %d, \"prec\": %d, \"rows_per_wave\": %d, \"waves_per_block\": %d, "
-    "\"points_per_lane\": %d, \"us\": %lf}";
-
-std::vector<TileEntry> read_tile_cache(const char* path) {
-    std::vector<TileEntry> out;
-    FILE* f = std::fopen(path, "r");
-    if (!f) return out;
-    char line[512];
-    while (std::fgets(line, sizeof line, f)) {
-        const char* brace = std::strchr(line, '{');
-        if (!brace || std::strstr(line, "alphacirc_tiling")) continue;  // the header line
-        TileEntry e{};
-        if (std::sscanf(brace, kTileFmt, &e.nx, &e.ny, &e.ell, &e.prec, &e.h, &e.wpb, &e.vx, &e.us) == 8)
-            out.push_back(e);
-    }
-    std::fclose(f);
-    return out;
-}
-
-int write_tile_cache(const char* path, const std::vector<TileEntry>& es) {
-    const std::string tmp = std::string(path) + ".tmp";
-    FILE* f = std::fopen(tmp.c_str(), "w");
-    if (!f) return fail(AC_ERR_ARG, std::string("cannot write tiling cache ") + tmp);
-    std::fprintf(f, "{\"alphacirc_tiling\": [\n");
-    for (size_t i = 0; i < es.size(); ++i) {
-        std::fprintf(f, "  ");
-        std::fprintf(f, kTileFmt, es[i].nx, es[i].ny, es[i].ell, es[i].prec, es[i].h, es[i].wpb, es[i].vx, es[i].us);
-        std::fprintf(f, i + 1 < es.size() ? ",\n" : "\n");
-    }
-    std::fprintf(f, "]}\n");
-    std::fclose(f);
-    if (std::rename(tmp.c_str(), path) != 0) return fail(AC_ERR_ARG, std::string("cannot replace ") + path);
-    return AC_OK;
-}
-
-bool same_key(const TileEntry& e, const ac_problem* p, int prec) {
-    return e.nx == p->g.nx && e.ny == p->g.ny && e.ell == p->ell && e.prec == prec;
-}
-
-}  // namespace
-
-int ac_problem_set_tiling(ac_problem* p, int rows_per_wave, int waves_per_block, int points_per_lane) {
-    if (!p) return fail(AC_ERR_ARG, "problem is NULL");
-    if (rows_per_wave < 0 || rows_per_wave > 4096) return fail(AC_ERR_ARG, "rows_per_wave out of range");
-    if (waves_per_block < 0 || waves_per_block > 4) return fail(AC_ERR_ARG, "waves_per_block must be 0..4");
-    if (points_per_lane < 0 || points_per_lane > 2) return fail(AC_ERR_ARG, "points_per_lane must be 0..2");
-    p->tile_h = rows_per_wave;
-    p->tile_wpb = waves_per_block;
-    p->tile_vx = points_per_lane;
-    return AC_OK;
-}
-
-int ac_tune_tiling(ac_problem* p, int prec, const char* cache_path, void* ws, size_t ws_bytes, int* out,
-                   double* us_out) {
-    if (!p) return fail(AC_ERR_ARG, "problem is NULL");
-    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
-    auto report = [&](const Tiling& t, double us) {
-        if (out) {
-            out[0] = t.h;
-            out[1] = t.wpb;
-            out[2] = t.vx;
-        }
-        if (us_out) *us_out = us;
-    };
-    std::vector<TileEntry> cache;
-    if (cache_path) {
-        cache = read_tile_cache(cache_path);
-        for (const TileEntry& e : cache)
-            if (same_key(e, p, prec)) {
-                AC_TRY(ac_problem_set_tiling(p, e.h, e.wpb, e.vx));
-                report(sweep_tiling(p), 0.0);
-                return AC_OK;
-            }
-    }
-    if (!ws || ws_bytes < prec_ws_bytes(p, prec)) return fail(AC_ERR_WORKSPACE, "workspace too small");
-    AC_HIP(hipSetDevice(p->ctx->device));
-    ac_ctx* c = p->ctx;
-    const bool prof = c->profiling;
-    c->profiling = false;
-    const PrecBufs bufs = carve_prec(p, prec, ws);
-    {
-        const long long words = static_cast<long long>(prec_ws_bytes(p, prec) - 256) / 8;
-        hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((words + 255) / 256)), dim3(256), 0, c->stream,
-                           reinterpret_cast<double*>(bufs.rhat), words);
-        AC_HIP(hipGetLastError());
-    }
-    constexpr int kSteps = 8;  // one sweep from x_1 = rhat/theta, then steady sweeps
-    const std::vector<int> pm(p->ell, kSteps);
-    hipEvent_t e0, e1;
-    AC_HIP(hipEventCreate(&e0));
-    AC_HIP(hipEventCreate(&e1));
-    const int keep_h = p->tile_h, keep_wpb = p->tile_wpb, keep_vx = p->tile_vx;
-    double best = 1e300;
-    int bh = 0, bw = 0, bv = 0;
-    std::vector<std::array<int, 3>> seen;
-    int status = AC_OK;
-    for (int vx : {2, 1}) {
-        for (int h : {4, 8, 16, 32, 64}) {
-            for (int wpb : {1, 2, 4}) {
-                p->tile_h = h;
-                p->tile_wpb = wpb;
-                p->tile_vx = vx;
-                const Tiling t = sweep_tiling(p);
-                const std::array<int, 3> key{t.h, t.wpb, t.vx};
-                if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
-                seen.push_back(key);
-                double ms_best = 1e300;
-                for (int rep = 0; rep < 4 && status == AC_OK; ++rep) {
-                    if (hipEventRecord(e0, c->stream) != hipSuccess) {
-                        status = fail(AC_ERR_HIP, "tile tuner: hipEventRecord failed");
-                        break;
-                    }
-                    status = run_cheb(p, prec, pm, bufs.rhat, bufs.buf, false, nullptr, nullptr);
-                    if (status != AC_OK) break;
-                    if (hipEventRecord(e1, c->stream) != hipSuccess) {
-                        status = fail(AC_ERR_HIP, "tile tuner: hipEventRecord failed");
-                        break;
-                    }
-                    if (hipEventSynchronize(e1) != hipSuccess) {
-                        status = fail(AC_ERR_HIP, "tile tuner: event synchronisation failed");
-                        break;
-                    }
-                    float ms = 0.f;
-                    if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                        status = fail(AC_ERR_HIP, "tile tuner: hipEventElapsedTime failed");
-                        break;
-                    }
-                    if (rep > 0) ms_best = std::min(ms_best, static_cast<double>(ms));
-                }
-                if (status != AC_OK) break;
-                if (ms_best < best) {
-                    best = ms_best;
-                    bh = t.h;
-                    bw = t.wpb;
-                    bv = t.vx;
-                }
-            }
-            if (status != AC_OK) break;
-        }
-        if (status != AC_OK) break;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    c->profiling = prof;
-    if (status != AC_OK) {
-        p->tile_h = keep_h;
-        p->tile_wpb = keep_wpb;
-        p->tile_vx = keep_vx;
-        return status;
-    }
-    AC_TRY(ac_problem_set_tiling(p, bh, bw, bv));
-    const double us = 1000.0 * best / (kSteps - 1);
-    report(sweep_tiling(p), us);
-    if (cache_path) {
-        cache.push_back(TileEntry{p->g.nx, p->g.ny, p->ell, prec, bh, bw, bv, us});
-        AC_TRY(write_tile_cache(cache_path, cache));
-    }
-    return AC_OK;
-}
-
-// ---------------------------------------------------------------------------
-// warm-start network
-
-namespace {
-size_t cnn_train_ws_bytes(long long B, long long H, long long W) {
-    const size_t px = static_cast<size_t>(B * H * W);
-    const long long tiles = B * H * ((W + 15) / 16);
-    return 5 * align_up(px * 32, 256) + align_up(px * 8, 256) +
-           align_up(static_cast<size_t>(ac::cnn_wgrad_waves(tiles)) * (9 * 256 + 16) * sizeof(float), 256) +
-           align_up(static_cast<size_t>((px + 255) / 256) * sizeof(float), 256) + 256;
-}
-int cnn_check_shape(int B, int H, int W) {
-    if (B < 1 || H < 1 || W < 1) return fail(AC_ERR_ARG, "batch and image sizes must be positive");
-    if (static_cast<long long>(B) * H * W > (1LL << 31)) return fail(AC_ERR_UNSUPPORTED, "batch too large");
-    return AC_OK;
-}
-}  // namespace
-
-int ac_cnn_param_count(void) { return ac::kCnnParams; }
-
-int ac_cnn_create(ac_ctx* c, ac_cnn** out) {
-    if (!c || !out) return fail(AC_ERR_ARG, "NULL argument");
-    *out = nullptr;
-    AC_HIP(hipSetDevice(c->device));
-    auto* n = new ac_cnn();
-    n->ctx = c;
-    const size_t P = ac::kCnnParams;
-    const size_t bytes = 4 * align_up(P * 4, 256) + 2 * align_up(3 * 2304 * 2, 256) + 256;
-    hipError_t e = hipMalloc(&n->mem, bytes);
-    if (e != hipSuccess) {
-        delete n;
-        return fail(AC_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
-    }
-    char* b = n->mem;
-    n->w = reinterpret_cast<float*>(b);
-    b += align_up(P * 4, 256);
-    n->g = reinterpret_cast<float*>(b);
-    b += align_up(P * 4, 256);
-    n->m = reinterpret_cast<float*>(b);
-    b += align_up(P * 4, 256);
-    n->v = reinterpret_cast<float*>(b);
-    b += align_up(P * 4, 256);
-    n->wf = reinterpret_cast<uint16_t*>(b);
-    b += align_up(3 * 2304 * 2, 256);
-    n->wb = reinterpret_cast<uint16_t*>(b);
-    b += align_up(3 * 2304 * 2, 256);
-    n->bias = reinterpret_cast<float*>(b);
-    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((bytes / 8 + 255) / 256)), dim3(256), 0, c->stream,
-                       reinterpret_cast<double*>(n->mem), static_cast<long long>(bytes / 8));
-    e = hipStreamSynchronize(c->stream);
-    if (e != hipSuccess) {
-        (void)hipFree(n->mem);
-        delete n;
-        return fail(AC_ERR_HIP, std::string("cnn init: ") + hipGetErrorString(e));
-    }
-    *out = n;
-    return AC_OK;
-}
-
-int ac_cnn_destroy(ac_cnn* n) {
-    if (!n) return AC_OK;
-    (void)hipSetDevice(n->ctx->device);
-    (void)hipStreamSynchronize(n->ctx->stream);
-    (void)hipFree(n->mem);
-    delete n;
-    return AC_OK;
-}
-
-int ac_cnn_set_params(ac_cnn* n, const float* params, double c0, double c1) {
-    if (!n || !params) return fail(AC_ERR_ARG, "NULL argument");
-    if (!(c1 > 0.0) || !std::isfinite(c0) || !std::isfinite(c1)) return fail(AC_ERR_ARG, "need finite c0 and c1 > 0");
-    for (int q = 0; q < ac::kCnnParams; ++q)
-        if (!std::isfinite(params[q])) return fail(AC_ERR_NONFINITE, "parameters must be finite");
-    AC_HIP(hipSetDevice(n->ctx->device));
-    hipStream_t st = n->ctx->stream;
-    AC_HIP(hipMemcpyAsync(n->w, params, ac::kCnnParams * sizeof(float), hipMemcpyHostToDevice, st));
-    const size_t P = ac::kCnnParams;
-    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((P + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<double*>(n->m), static_cast<long long>(P / 2));
-    hipLaunchKernelGGL(zero_kernel, dim3(static_cast<int>((P + 255) / 256)), dim3(256), 0, st,
-                       reinterpret_cast<double*>(n->v), static_cast<long long>(P / 2));
-    // entries outside the network are forced to zero by an Adam step of size 0
-    AC_HIP(ac::launch_cnn_adam(n->w, n->g, n->m, n->v, 0.f, 0.9f, 0.999f, 1e-8f, 1.f, 1.f, st));
-    AC_HIP(ac::launch_cnn_weights(n->w, n->wf, n->wb, n->bias, st));
-    AC_HIP(hipStreamSynchronize(st));
-    n->c0 = c0;
-    n->c1 = c1;
-    n->t = 0;
-    return AC_OK;
-}
-
-int ac_cnn_get_params(const ac_cnn* n, float* params, double* c0, double* c1) {
-    if (!n) return fail(AC_ERR_ARG, "NULL argument");
-    AC_HIP(hipSetDevice(n->ctx->device));
-    if (params) {
-        AC_HIP(hipMemcpyAsync(params, n->w, ac::kCnnParams * sizeof(float), hipMemcpyDeviceToHost, n->ctx->stream));
-        AC_HIP(hipStreamSynchronize(n->ctx->stream));
-    }
-    if (c0) *c0 = n->c0;
-    if (c1) *c1 = n->c1;
-    return AC_OK;
-}
-
-int ac_cnn_workspace_size(int B, int H, int W, size_t* bytes) {
-    if (!bytes) return fail(AC_ERR_ARG, "NULL argument");
-    AC_TRY(cnn_check_shape(B, H, W));
-    *bytes = cnn_train_ws_bytes(B, H, W);
-    return AC_OK;
-}
-
-int ac_cnn_forward(ac_cnn* n, const uint16_t* x, int B, int H, int W, float* y, void* ws, size_t ws_bytes) {
-    if (!n || !x || !y) return fail(AC_ERR_ARG, "NULL argument");
-    AC_TRY(cnn_check_shape(B, H, W));
-    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
-    AC_HIP(hipSetDevice(n->ctx->device));
-    const size_t px = static_cast<size_t>(B) * H * W;
-    char* b = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
-    uint16_t* a1 = reinterpret_cast<uint16_t*>(b);
-    uint16_t* a2 = reinterpret_cast<uint16_t*>(b + align_up(px * 32, 256));
-    ProfScope ps(n->ctx, AC_K_CNN, static_cast<double>(px) * (32.0 * 5 + 8.0));
-    return cnn_forward_impl(n, x, B, H, W, y, a1, a2, n->ctx->stream);
-}
-
-namespace {
-// Forward pass, one loss kernel (which writes dL/dY as bf16) and the backward pass
-// into n->g.  The loss scratch (px float2) shares the dZ2 buffer, which is written
-// only after dY has been consumed.
-template <class LossFn>
-int cnn_train_pass(ac_cnn* n, const uint16_t* x, int B, int H, int W, void* ws, double* loss, float* grad_host,
-                   LossFn launch_loss) {
-    AC_HIP(hipSetDevice(n->ctx->device));
-    hipStream_t st = n->ctx->stream;
-    const size_t px = static_cast<size_t>(B) * H * W;
-    const long long tiles = static_cast<long long>(B) * H * ((W + 15) / 16);
-    char* b = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
-    const size_t a16 = align_up(px * 32, 256);
-    uint16_t* A1 = reinterpret_cast<uint16_t*>(b);
-    uint16_t* A2 = reinterpret_cast<uint16_t*>(b + a16);
-    uint16_t* dY = reinterpret_cast<uint16_t*>(b + 2 * a16);
-    uint16_t* dZ2 = reinterpret_cast<uint16_t*>(b + 3 * a16);
-    uint16_t* dZ1 = reinterpret_cast<uint16_t*>(b + 4 * a16);
-    float* Y = reinterpret_cast<float*>(b + 5 * a16);
-    float* wpart = reinterpret_cast<float*>(b + 5 * a16 + align_up(px * 8, 256));
-    float* lpart = reinterpret_cast<float*>(reinterpret_cast<char*>(wpart) +
-                                            align_up(static_cast<size_t>(ac::cnn_wgrad_waves(tiles)) * 2320 * 4, 256));
-    int nblk = 0;
-    {
-        ProfScope ps(n->ctx, AC_K_CNN, static_cast<double>(px) * (32.0 * 14 + 8.0 * 3));
-        AC_TRY(cnn_forward_impl(n, x, B, H, W, Y, A1, A2, st));
-        AC_HIP(launch_loss(Y, dY, reinterpret_cast<float*>(dZ2), lpart, &nblk, st));
-        ac::CnnWgradArgs wa{};
-        wa.B = B;
-        wa.H = H;
-        wa.W = W;
-        wa.partial = wpart;
-        wa.act = A2;
-        wa.dz = dY;
-        AC_HIP(ac::launch_cnn_wgrad(wa, n->g + 2 * 2320, st));
-        ac::CnnConvArgs ca{};
-        ca.B = B;
-        ca.H = H;
-        ca.W = W;
-        ca.in = dY;
-        ca.w = n->wb + 2 * 2304;
-        ca.mask = A2;
-        ca.out16 = dZ2;
-        AC_HIP(ac::launch_cnn_conv(ca, st));
-        wa.act = A1;
-        wa.dz = dZ2;
-        AC_HIP(ac::launch_cnn_wgrad(wa, n->g + 2320, st));
-        ca.in = dZ2;
-        ca.w = n->wb + 2304;
-        ca.mask = A1;
-        ca.out16 = dZ1;
-        AC_HIP(ac::launch_cnn_conv(ca, st));
-        wa.act = x;
-        wa.dz = dZ1;
-        AC_HIP(ac::launch_cnn_wgrad(wa, n->g, st));
-    }
-    std::vector<float> lp(nblk);
-    AC_HIP(hipMemcpyAsync(lp.data(), lpart, nblk * sizeof(float), hipMemcpyDeviceToHost, st));
-    if (grad_host) AC_HIP(hipMemcpyAsync(grad_host, n->g, ac::kCnnParams * sizeof(float), hipMemcpyDeviceToHost, st));
-    AC_HIP(hipStreamSynchronize(st));
-    double l = 0.0;
-    for (float v : lp) l += v;
-    if (loss) *loss = l / B;
-    return AC_OK;
-}
-}  // namespace
-
-int ac_cnn_grad(ac_cnn* n, const uint16_t* x, const float* t, const float* tnorm, int border, int B, int H, int W,
-                void* ws, size_t ws_bytes, double* loss, float* grad_host) {
-    if (!n || !x || !t || !tnorm) return fail(AC_ERR_ARG, "NULL argument");
-    AC_TRY(cnn_check_shape(B, H, W));
-    if (border < 0 || 2 * border >= H || 2 * border >= W) return fail(AC_ERR_ARG, "border too wide");
-    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
-    return cnn_train_pass(n, x, B, H, W, ws, loss, grad_host,
-                          [&](const float* Y, uint16_t* dY, float*, float* lpart, int* nblk, hipStream_t st) {
-                              return ac::launch_cnn_loss(Y, t, tnorm, B, H, W, border, dY, lpart, nblk, st);
-                          });
-}
-
-int ac_cnn_grad_residual(ac_cnn* n, const uint16_t* x, const float* rhat, const float* kappa, const float* lam,
-                         const float* rnorm, int border, int B, int H, int W, void* ws, size_t ws_bytes,
-                         double* loss, float* grad_host) {
-    if (!n || !x || !rhat || !kappa || !lam || !rnorm) return fail(AC_ERR_ARG, "NULL argument");
-    AC_TRY(cnn_check_shape(B, H, W));
-    if (border < 1 || 2 * border >= H || 2 * border >= W)
-        return fail(AC_ERR_ARG, "border must be at least 1 and leave an interior");
-    if (!ws || ws_bytes < cnn_train_ws_bytes(B, H, W)) return fail(AC_ERR_WORKSPACE, "workspace too small");
-    return cnn_train_pass(n, x, B, H, W, ws, loss, grad_host,
-                          [&](const float* Y, uint16_t* dY, float* e, float* lpart, int* nblk, hipStream_t st) {
-                              return ac::launch_cnn_resloss(Y, rhat, kappa, lam, rnorm, B, H, W, border, e, dY,
-                                                            lpart, nblk, st);
-                          });
-}
-
-int ac_cnn_adam_step(ac_cnn* n, double lr, double beta1, double beta2, double eps) {
-    if (!n) return fail(AC_ERR_ARG, "NULL argument");
-    if (!(lr >= 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps > 0))
-        return fail(AC_ERR_ARG, "invalid Adam hyper-parameters");
-    AC_HIP(hipSetDevice(n->ctx->device));
-    n->t += 1;
-    const float bc1 = static_cast<float>(1.0 - std::pow(beta1, n->t));
-    const float bc2 = static_cast<float>(1.0 - std::pow(beta2, n->t));
-    AC_HIP(ac::launch_cnn_adam(n->w, n->g, n->m, n->v, static_cast<float>(lr), static_cast<float>(beta1),
-                               static_cast<float>(beta2), static_cast<float>(eps), bc1, bc2, n->ctx->stream));
-    AC_HIP(ac::launch_cnn_weights(n->w, n->wf, n->wb, n->bias, n->ctx->stream));
-    return AC_OK;
-}
-
-int ac_cnn_make_inputs(ac_problem* p, const ac_cnn* n, int prec, const void* rhat, uint16_t* x, double* scales,
-                       float* rscaled) {
-    if (!p || !n || !rhat || !x) return fail(AC_ERR_ARG, "NULL argument");
-    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
-    AC_HIP(hipSetDevice(p->ctx->device));
-    ac::CnnPrepArgs a = cnn_args(p, prec, static_cast<const char*>(rhat));
-    a.c0 = n->c0;
-    a.c1 = n->c1;
-    SlotStats st;
-    AC_TRY(slot_residuals(p, prec, a, nullptr, st));
-    set_rms_scales(p, st, a, scales);
-    a.x = x;
-    a.rs = rscaled;
-    AC_HIP(ac::launch_cnn_prep(prec, a, p->ctx->stream));
-    return AC_OK;
-}
-
-int ac_problem_attach_cnn(ac_problem* p, ac_cnn* n) {
-    if (!p) return fail(AC_ERR_ARG, "problem is NULL");
-    if (n && n->ctx != p->ctx) return fail(AC_ERR_ARG, "network and problem belong to different contexts");
-    p->cnn = n;
-    return AC_OK;
-}
-
-int ac_shifted_residual(ac_problem* p, int prec, const void* rhat, const void* yhat, double* rel) {
-    if (!p || !rhat || !yhat || !rel) return fail(AC_ERR_ARG, "NULL argument");
-    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
-    AC_HIP(hipSetDevice(p->ctx->device));
-    ac::CnnPrepArgs a = cnn_args(p, prec, static_cast<const char*>(rhat));
-    SlotStats st;
-    AC_TRY(slot_residuals(p, prec, a, static_cast<const char*>(yhat), st));
-    for (int s = 0; s < p->ns; ++s) {
-        const double r = std::max(st.res(s), 0.0);
-        rel[slot_to_m(p, s)] = st.rr[s] > 0 ? std::sqrt(r / st.rr[s]) : 0.0;
-    }
-    return AC_OK;
-}
-
-int ac_cnn_guess_workspace_size(const ac_problem* p, size_t* bytes) {
-    if (!p || !bytes) return fail(AC_ERR_ARG, "NULL argument");
-    *bytes = cnn_ws_bytes(p) + 256;
-    return AC_OK;
-}
-
-int ac_cnn_guess(ac_problem* p, int prec, const void* rhat, void* x0hat, void* ws, size_t ws_bytes,
-                 int* rejected) {
-    if (!p || !rhat || !x0hat) return fail(AC_ERR_ARG, "NULL argument");
-    if (!p->cnn) return fail(AC_ERR_ARG, "no warm-start network attached");
-    if (prec < 0 || prec > 2) return fail(AC_ERR_ARG, "unknown precision");
-    if (!ws || ws_bytes < cnn_ws_bytes(p) + 256) return fail(AC_ERR_WORKSPACE, "workspace too small");
-    AC_HIP(hipSetDevice(p->ctx->device));
-    char* cws = reinterpret_cast<char*>(align_up(reinterpret_cast<size_t>(ws), 256));
-    int fb = 0;
-    AC_TRY(cnn_warm_start(p, prec, static_cast<const char*>(rhat), static_cast<char*>(x0hat), cws, &fb));
-    if (rejected) *rejected = fb;
-    return AC_OK;
-}
-
-int ac_cnn_set_inference(ac_cnn* n, int fused) {
-    if (!n) return fail(AC_ERR_ARG, "network is NULL");
-    n->fused = fused ? 1 : 0;
-    return AC_OK;
-}
-
-int ac_cnn_set_guess_policy(ac_cnn* n, int scaling, double accept_ratio) {
-    if (!n) return fail(AC_ERR_ARG, "network is NULL");
-    if (!(accept_ratio > 0.0 && accept_ratio <= 1.0)) return fail(AC_ERR_ARG, "accept_ratio must be in (0, 1]");
-    n->scaled = scaling ? 1 : 0;
-    n->accept = accept_ratio;
-    return AC_OK;
-}
