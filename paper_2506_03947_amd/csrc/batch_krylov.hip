@@ -97,10 +97,17 @@ __global__ __launch_bounds__(kThreads) void bk_arnoldi_kernel(const BKProb* __re
     {
         const int per = (p.nblk + NW - 1) / NW;
         const int b0 = wid * per, b1 = min(p.nblk, b0 + per);
-        double a = 0.0;
-        if (lane < nq)
-            for (int b = b0; b < b1; ++b) a += p.partial[static_cast<long long>(b) * kBKRed + lane];
-        if (lane < nq) part[wid][lane] = a;
+        // eight independent partial sums keep eight loads in flight per lane
+        double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (lane < nq) {
+            const double* src = p.partial + lane;
+            int b = b0;
+            for (; b + 8 <= b1; b += 8)
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += src[static_cast<long long>(b + u) * kBKRed];
+            for (; b < b1; ++b) a[0] += src[static_cast<long long>(b) * kBKRed];
+            part[wid][lane] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+        }
     }
     for (int e = threadIdx.x; e < j * kMB; e += kThreads) {
         const int i = e / kMB, k = e % kMB;
