@@ -3,11 +3,15 @@ warm-started solve.
 
 The oracle runs on the same bf16-representable inputs and bf16-rounded weights the
 matrix cores see; the remaining differences come from bf16 rounding (unit roundoff
-u = 2^-8 = 3.9e-3) of the two hidden activations (forward: bound 1e-2 ~ 2.5 u) and,
-for the first-layer gradient, of up to five tensors on the path (two activations,
-three back-propagated gradients) plus ReLU decisions on pre-activations within u of
-zero (gradients: bound 5e-2 ~ 13 u).
+u = 2^-8 = 3.9e-3) of the two hidden activations (forward: bound 1e-2 ~ 2.5 u) and, for
+the gradients, of the tensors on each parameter's path plus ReLU decisions on
+pre-activations within u of zero.  The bounds grow with the path: the last layer's
+gradient sees one rounded activation (bound 1e-2 ~ 2.5 u; measured <= 1.3e-3), the
+middle layer's also a back-propagated gradient and the first activation (3e-2 ~ 8 u;
+measured <= 1.5e-2), the first layer's up to five rounded tensors (5e-2 ~ 13 u;
+measured <= 3.8e-2).
 """
+
 
 import numpy as np
 import pytest
@@ -22,6 +26,9 @@ from tests import gpu_util as G
 
 L = api.L
 pytestmark = pytest.mark.gpu
+
+# relative gradient bound per parameter tensor (see the module docstring)
+GRAD_TOL = {"W1": 5e-2, "b1": 5e-2, "W2": 3e-2, "b2": 3e-2, "W3": 1e-2, "b3": 1e-2}
 
 
 def packed_from_oracle(params):
@@ -101,7 +108,7 @@ def test_gradient_parity_and_loss():
     assert abs(loss - L_ref) < 1e-2 * L_ref
     got = oracle_from_packed(g)
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
-        assert G.rel(got[k], g_ref[k]) < 5e-2, k
+        assert G.rel(got[k], g_ref[k]) < GRAD_TOL[k], k
     # parameters outside the network get no gradient
     assert np.all(g[0:2304].reshape(9, 16, 16)[:, :, 5:] == 0)
     assert np.all(g[2 * 2320:2 * 2320 + 2304].reshape(9, 16, 16)[:, 2:, :] == 0)
@@ -129,7 +136,7 @@ def test_residual_loss_gradient_parity():
     assert abs(loss - L_ref) < 1e-2 * L_ref
     got = oracle_from_packed(g)
     for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
-        assert G.rel(got[k], g_ref[k]) < 5e-2, k
+        assert G.rel(got[k], g_ref[k]) < GRAD_TOL[k], k
 
 
 def test_residual_loss_rejects_zero_border():

@@ -182,7 +182,9 @@ def test_apply_prec_fp64(case, pspec):
 @pytest.mark.parametrize("case", CASES, ids=lambda c: f"{c[0]}d_{c[1]}x{c[2]}_l{c[3]}_{c[5]}")
 def test_apply_prec_mixed(case, prec):
     """complex64 inner solve against the float64 oracle run on the same rounded
-    coefficients.  Bound: 64 u_32 cond(U^* Gamma) (p + 1), u_32 = 2^-24."""
+    coefficients.  Bound: u_32 cond(U^* Gamma) (p + 1), u_32 = 2^-24 -- one rounding per
+    step amplified by the transform's condition number (measured: at most 0.18 of it
+    norm-wise); element-wise against the largest entry, twice that."""
     dim, nx, ny, ell, alpha, bc, kind = case
     kap = _kappa(dim, nx, ny, kind)
     kq = to_float32(kap) if prec == L.AC_PREC_MIXED_FP32K else to_bfloat16(kap)
@@ -197,8 +199,11 @@ def test_apply_prec_mixed(case, prec):
     z = G.dev(np.zeros_like(r))
     api.ac_apply_prec(p, opts, G.dev(r), z, ws)
     ref = pc.apply_prec_nc(Aq, r, ell, alpha, lo, hi, pp)
-    tol = 64 * 2.0 ** -24 * alpha ** (-(ell - 1) / ell) * (pp + 1)
-    assert G.rel(G.host(z), ref) < tol
+    tol = 2.0 ** -24 * alpha ** (-(ell - 1) / ell) * (pp + 1)
+    zh = G.host(z)
+    assert G.rel(zh, ref) < tol
+    # element-wise against the largest entry (measured: at most 0.37 of 2 tol)
+    assert G.max_rel(zh, ref) < 2 * tol
 
 
 def test_prec_is_linear_and_deterministic():
