@@ -524,74 +524,78 @@ __global__ __launch_bounds__(256) void post_kernel(const CnnPrepArgs a, const fl
 // Per-slot partial sums, four per slot: |rhat|^2, and with a guess x0 (else zero)
 // |B x0|^2, Re and Im of sum conj(B x0) rhat, where B = A - lambda I.  The residual
 // of c x0 for any complex c follows: |rhat - c B x0|^2 = |rhat|^2 - 2 Re(c conj-dot)
-// + |c|^2 |B x0|^2.
+// + |c|^2 |B x0|^2.  One slot per blockIdx.y (its four sums stay in registers); the
+// points of a thread, and so every partial, do not depend on the slot count.
 template <typename R, typename KS>
 __global__ __launch_bounds__(256) void resid_kernel(const CnnPrepArgs a, const void* x0buf, const void* kap,
                                                     double* partial) {
     const Geom g = a.g;
-    double acc[4 * kMaxShift];
-#pragma unroll
-    for (int q = 0; q < 4 * kMaxShift; ++q) acc[q] = 0.0;
+    const int s = blockIdx.y;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     const long long step = static_cast<long long>(gridDim.x) * blockDim.x;
     const KS* k = static_cast<const KS*>(kap);
     auto kv = [&](long long i) -> double {
         if constexpr (sizeof(KS) == 2) return static_cast<double>(bf2f(k[i]));
         else return static_cast<double>(k[i]);
     };
+    const R* rh = static_cast<const R*>(a.rhat) + a.soff[s];
+    const R* x0 = x0buf ? static_cast<const R*>(x0buf) + a.soff[s] : nullptr;
+    const bool re = a.is_real[s];
+    const double lr = a.lam_re[s], li = a.lam_im[s];
+    constexpr int dxs[4] = {1, -1, 0, 0}, dys[4] = {0, 0, 1, -1};
+    const int nd = g.dim == 2 ? 4 : 2;
     for (long long p = static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x; p < a.n; p += step) {
+        const double rr = re ? rh[p] : rh[2 * p], ri = re ? 0.0 : rh[2 * p + 1];
+        acc[0] += rr * rr + ri * ri;
+        if (!x0) continue;
         const int ix = static_cast<int>(p % g.nx), iy = static_cast<int>(p / g.nx);
         const double kc = kv(p);
         long long nb[4];
         double f[4];
-        int nf = 0;
-        const int dxs[4] = {1, -1, 0, 0}, dys[4] = {0, 0, 1, -1};
+        bool ok[4];
         double diag = 1.0;
-        for (int d = 0; d < (g.dim == 2 ? 4 : 2); ++d) {
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            ok[d] = false;
+            nb[d] = p;
+            f[d] = 0.0;
+            if (d >= nd) continue;
             int jx = ix + dxs[d], jy = iy + dys[d];
             const bool inside = jx >= 0 && jx < g.nx && jy >= 0 && jy < g.ny;
             if (inside || g.periodic) {
                 jx = (jx + g.nx) % g.nx;
                 jy = (jy + g.ny) % g.ny;
-                const long long q = static_cast<long long>(jy) * g.nx + jx;
-                const double fq = 0.5 * (kc + kv(q));
-                diag += fq;
-                nb[nf] = q;
-                f[nf] = fq;
-                ++nf;
+                nb[d] = static_cast<long long>(jy) * g.nx + jx;
+                f[d] = 0.5 * (kc + kv(nb[d]));
+                diag += f[d];
+                ok[d] = true;
             } else {
                 diag += kc;
             }
         }
-        for (int s = 0; s < a.ns; ++s) {
-            const R* rh = static_cast<const R*>(a.rhat) + a.soff[s];
-            const R* x0 = x0buf ? static_cast<const R*>(x0buf) + a.soff[s] : nullptr;
-            const bool re = a.is_real[s];
-            const double rr = re ? rh[p] : rh[2 * p], ri = re ? 0.0 : rh[2 * p + 1];
-            acc[4 * s] += rr * rr + ri * ri;
-            if (x0) {
-                const double xr = re ? x0[p] : x0[2 * p], xi = re ? 0.0 : x0[2 * p + 1];
-                const double lr = a.lam_re[s], li = a.lam_im[s];
-                double br = (diag - lr) * xr + li * xi, bi = (diag - lr) * xi - li * xr;
-                for (int d = 0; d < nf; ++d) {
-                    br -= f[d] * (re ? x0[nb[d]] : x0[2 * nb[d]]);
-                    bi -= re ? 0.0 : f[d] * x0[2 * nb[d] + 1];
-                }
-                acc[4 * s + 1] += br * br + bi * bi;
-                acc[4 * s + 2] += br * rr + bi * ri;
-                acc[4 * s + 3] += br * ri - bi * rr;
-            }
+        const double xr = re ? x0[p] : x0[2 * p], xi = re ? 0.0 : x0[2 * p + 1];
+        double br = (diag - lr) * xr + li * xi, bi = (diag - lr) * xi - li * xr;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            if (!ok[d]) continue;
+            br -= f[d] * (re ? x0[nb[d]] : x0[2 * nb[d]]);
+            bi -= re ? 0.0 : f[d] * x0[2 * nb[d] + 1];
         }
+        acc[1] += br * br + bi * bi;
+        acc[2] += br * rr + bi * ri;
+        acc[3] += br * ri - bi * rr;
     }
-    __shared__ double red[4][4 * kMaxShift];
+    __shared__ double red[4][4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int q = 0; q < 4 * a.ns; ++q) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
         double v = acc[q];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
         if (lane == 0) red[wid][q] = v;
     }
     __syncthreads();
-    if (threadIdx.x < 4 * a.ns)
-        partial[blockIdx.x * 4 * kMaxShift + threadIdx.x] =
+    if (threadIdx.x < 4)
+        partial[blockIdx.x * 4 * kMaxShift + 4 * s + threadIdx.x] =
             red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
 }
 
@@ -683,9 +687,11 @@ hipError_t launch_cnn_post(int prec, const CnnPrepArgs& a, const float* y, void*
 
 hipError_t launch_cnn_resid(int prec, const CnnPrepArgs& a, const void* x0buf, const void* kap, double* partial,
                             int nblk, hipStream_t s) {
-    if (prec == 0) hipLaunchKernelGGL((resid_kernel<double, double>), dim3(nblk), dim3(256), 0, s, a, x0buf, kap, partial);
-    else if (prec == 1) hipLaunchKernelGGL((resid_kernel<float, uint16_t>), dim3(nblk), dim3(256), 0, s, a, x0buf, kap, partial);
-    else hipLaunchKernelGGL((resid_kernel<float, float>), dim3(nblk), dim3(256), 0, s, a, x0buf, kap, partial);
+    if (a.ns < 1 || a.ns > kMaxShift) return hipErrorInvalidValue;
+    const dim3 grid(nblk, a.ns);
+    if (prec == 0) hipLaunchKernelGGL((resid_kernel<double, double>), grid, dim3(256), 0, s, a, x0buf, kap, partial);
+    else if (prec == 1) hipLaunchKernelGGL((resid_kernel<float, uint16_t>), grid, dim3(256), 0, s, a, x0buf, kap, partial);
+    else hipLaunchKernelGGL((resid_kernel<float, float>), grid, dim3(256), 0, s, a, x0buf, kap, partial);
     return hipGetLastError();
 }
 
