@@ -22,9 +22,7 @@
  *          documented as "host" are host pointers.  The library allocates
  *          device memory only inside ac_ctx_create and ac_problem_create (and
  *          ac_cnn_create, ac_problem_create_multigrid) and frees it in the matching
- *          _destroy.  ac_ctx_create
- *          also creates the rocBLAS handle of AC_INNER_EXACT, whose GEMMs run in
- *          the caller's workspace (rocBLAS loads its kernels on first use).
+ *          _destroy.
  * Layout   Block vectors are float64, block-major: x[k*N + i], k in [0, l),
  *          grid index i = iy*nx + ix (x fastest).  Cell-centred coefficient
  *          kappa[i] > 0, float64, length N.
@@ -91,7 +89,8 @@ typedef enum { AC_PREC_FP64 = 0, AC_PREC_MIXED_BF16K = 1, AC_PREC_MIXED_FP32K = 
  * paper's reference preconditioner, Section 2 and Fig. 2): only for a constant
  * coefficient on a Dirichlet grid, where the sine transform of Appendix A diagonalises
  * A along x and every shifted solve reduces to tridiagonal systems along y (dense
- * transforms by rocBLAS GEMMs in the inner precision).  p_uniform and p_per_shift are
+ * transforms by the library's matrix-core products in the inner precision).  p_uniform
+ * and p_per_shift are
  * ignored and count no products with A.  AC_ERR_UNSUPPORTED for a varying coefficient
  * (or varying diagonal blocks whose mean is not constant) or periodic grids.
  * AC_INNER_SP is the saddle-point preconditioner P_SP (Section 4): each complex shift's
