@@ -149,6 +149,12 @@ struct InvArgs {
     double* z;
 };
 
+// calA runs on overlapping strips without halo loads (apply_calA_strip_body) on
+// Dirichlet grids whose blocks fit one buffer range (N * 8 < 2^31 bytes); periodic
+// grids and larger blocks use the halo-load form.  The tiling and the launch both
+// follow this test.
+inline bool calA_strips(const Geom& g) { return !g.periodic && g.n * 8 < (1ll << 31); }
+
 struct CalAArgs {
     Geom g;
     Tiling t;

@@ -171,8 +171,20 @@ void record_launch(ac_ctx* c, int op, int ell, int prec, int curk, int vx, int w
 }
 
 Tiling calA_tiling(const ac_problem* p) {
-    // float64 operand with l blocks per point: one point per lane past l = 8
-    return make_tiling(p, p->ell > 8 ? 1 : 2, 16, 4);
+    if (p->kblocks || !ac::calA_strips(p->g)) {
+        // halo-load form, float64 operand with l blocks per point: one point per lane
+        // past l = 8
+        return make_tiling(p, p->ell > 8 ? 1 : 2, 16, 4);
+    }
+    // overlapping strips: 64*vx - 2*vx owned columns per strip, 8-row chunks (measured
+    // best at 2048^2, l = 10 over a whole solve: 2 points per lane and 8 rows against
+    // 1 point and 16 rows, 8 or 32 rows)
+    Tiling t = make_tiling(p, p->ell > 12 ? 1 : 2, 8, 4);
+    const int owned = ac::kWave * t.vx - 2 * t.vx;
+    t.nsx = (p->g.nx + owned - 1) / owned;
+    t.tiles = static_cast<long long>(t.nsx) * t.ncy;
+    t.blocks = static_cast<int>((t.tiles + t.wpb - 1) / t.wpb);
+    return t;
 }
 
 // ---------------------------------------------------------------------------
@@ -1165,7 +1177,9 @@ int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double
     if (p->kblocks) a.kappa = p->kblocks;
     if (p->ctx->rec) {
         if (p->kblocks) return fail(AC_ERR_UNSUPPORTED, "varying diagonal blocks are not batched");
-        record_launch(p->ctx, b ? ac::BOP_CALA_RES : ac::BOP_CALA, p->ell, 0, 0, a.t.vx, a.t.wpb, a.t.blocks, a);
+        // curk carries the form (strips or halo loads), which a batched launch must share
+        record_launch(p->ctx, b ? ac::BOP_CALA_RES : ac::BOP_CALA, p->ell, 0, ac::calA_strips(p->g) ? 1 : 0, a.t.vx,
+                      a.t.wpb, a.t.blocks, a);
         return AC_OK;
     }
     const double kbytes = p->kblocks ? 8.0 * p->ell * p->g.n : 8.0 * p->g.n;

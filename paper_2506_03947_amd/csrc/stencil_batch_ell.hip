@@ -57,16 +57,20 @@ hipError_t AC_CAT(batch_ell_, AC_ELL)(int op, int prec, int curk, int vx, const 
             }
             return hipGetLastError();
         }
-        case BOP_CALA: {
+        case BOP_CALA:
+        case BOP_CALA_RES: {  // residual form: y = b - calA x with per-tile partial sums of y^2
+            // curk: 1 = overlapping strips, 0 = halo loads (the members' shared form)
             const dim3 grid(list_grid(L.blocks, L.nprob, L.wpb)), block(L.wpb * kWave);
-            if (vx == 2) hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 2, false>), grid, block, 0, s, L);
-            else hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 1, false>), grid, block, 0, s, L);
-            return hipGetLastError();
-        }
-        case BOP_CALA_RES: {  // y = b - calA x with per-tile partial sums of y^2
-            const dim3 grid(list_grid(L.blocks, L.nprob, L.wpb)), block(L.wpb * kWave);
-            if (vx == 2) hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 2, true>), grid, block, 0, s, L);
-            else hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, 1, true>), grid, block, 0, s, L);
+#define AC_CALA_B(VX, R, S) hipLaunchKernelGGL((apply_calA_batch_kernel<AC_ELL, VX, R, S>), grid, block, 0, s, L)
+            const bool res = op == BOP_CALA_RES;
+            if (curk == 1) {
+                if (vx == 2) { if (res) AC_CALA_B(2, true, true); else AC_CALA_B(2, false, true); }
+                else { if (res) AC_CALA_B(1, true, true); else AC_CALA_B(1, false, true); }
+            } else {
+                if (vx == 2) { if (res) AC_CALA_B(2, true, false); else AC_CALA_B(2, false, false); }
+                else { if (res) AC_CALA_B(1, true, false); else AC_CALA_B(1, false, false); }
+            }
+#undef AC_CALA_B
             return hipGetLastError();
         }
         default: return hipErrorInvalidValue;

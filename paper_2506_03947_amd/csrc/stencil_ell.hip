@@ -81,6 +81,16 @@ hipError_t AC_CAT(inv_ell_, AC_ELL)(int prec, const InvArgs& a, hipStream_t s) {
 hipError_t AC_CAT(calA_ell_, AC_ELL)(bool resid, const CalAArgs& a, hipStream_t s) {
     constexpr int ELL = AC_ELL;
     const dim3 grid(a.t.blocks), block(a.t.wpb * kWave);
+    if (calA_strips(a.g)) {
+        if (a.t.vx == 2) {
+            if (resid) hipLaunchKernelGGL((apply_calA_strip_kernel<ELL, 2, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((apply_calA_strip_kernel<ELL, 2, false>), grid, block, 0, s, a);
+        } else {
+            if (resid) hipLaunchKernelGGL((apply_calA_strip_kernel<ELL, 1, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((apply_calA_strip_kernel<ELL, 1, false>), grid, block, 0, s, a);
+        }
+        return hipGetLastError();
+    }
     if (a.t.vx == 2) {
         if (resid) hipLaunchKernelGGL((apply_calA_kernel<ELL, 2, true>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((apply_calA_kernel<ELL, 2, false>), grid, block, 0, s, a);

@@ -175,6 +175,51 @@ __device__ __forceinline__ float shfl_dn1(float v) { return __shfl_down(v, 1, kW
 __device__ __forceinline__ double shfl_up1(double v) { return __shfl_up(v, 1, kWave); }
 __device__ __forceinline__ double shfl_dn1(double v) { return __shfl_down(v, 1, kWave); }
 
+// Wavefront shifts by one lane (DPP): from_west(v, edge) gives lane i the value of lane
+// i-1 and lane 0 `edge`; from_east(v, edge) gives lane i the value of lane i+1 and lane
+// 63 `edge`.
+__device__ __forceinline__ float from_west(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float from_east(float v, float edge) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
+                                                                 __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
+}
+// The same with a zero edge value (bound_ctrl: the vacated lane reads zero)
+__device__ __forceinline__ float from_west0(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
+}
+__device__ __forceinline__ float from_east0(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
+}
+__device__ __forceinline__ double from_west0(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x138, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ double from_east0(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ double from_west(double v, double edge) {
+    const long long b = __builtin_bit_cast(long long, v), e = __builtin_bit_cast(long long, edge);
+    const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(e), static_cast<int>(b), 0x138, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(e >> 32), static_cast<int>(b >> 32), 0x138, 0xf, 0xf,
+                                               false);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+__device__ __forceinline__ double from_east(double v, double edge) {
+    const long long b = __builtin_bit_cast(long long, v), e = __builtin_bit_cast(long long, edge);
+    const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(e), static_cast<int>(b), 0x130, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(e >> 32), static_cast<int>(b >> 32), 0x130, 0xf, 0xf,
+                                               false);
+    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
+}
+
 // XCD-aware tile index of the calling wave (block bid of nb); -1 if the wave has no tile.
 __device__ __forceinline__ long long tile_of_wave(const Tiling& t, int bid, int nb) {
     const int per = nb >> 3;
@@ -583,7 +628,7 @@ __device__ __forceinline__ void cheb_sweep_body(const SweepArgs<R>& a, int bid, 
                     }
                     zk[v] = a.ginv[k] * (acc + 2.0 * sum);
                 }
-                stv<double, VX>(gptr(a.z) + static_cast<size_t>(k) * static_cast<size_t>(a.g.n) + pt, zk);
+                stv_nt<double, VX>(gptr(a.z) + static_cast<size_t>(k) * static_cast<size_t>(a.g.n) + pt, zk);
             }
         }
     };
@@ -631,7 +676,7 @@ __device__ __forceinline__ void tdft_fwd_body(const FwdArgs& a, int bid, double 
 #pragma unroll
     for (int k = 0; k < ELL; ++k) {
         double v[VX];
-        ldv<double, VX>(a.r + static_cast<long long>(k) * a.n + i0, v);
+        ldv_nt<double, VX>(a.r + static_cast<long long>(k) * a.n + i0, v);
         const double gk = a.gam[k] * mul;
 #pragma unroll
         for (int x = 0; x < VX; ++x) t[k][x] = gk * v[x];
@@ -650,8 +695,8 @@ __device__ __forceinline__ void tdft_fwd_body(const FwdArgs& a, int bid, double 
             o0[x] = static_cast<R>(s0);
             o1[x] = static_cast<R>(s1);
         }
-        stv<R, VX>(static_cast<R*>(a.rhat[0]) + i0, o0);
-        if (NSR == 2) stv<R, VX>(static_cast<R*>(a.rhat[1]) + i0, o1);
+        stv_nt<R, VX>(static_cast<R*>(a.rhat[0]) + i0, o0);
+        if (NSR == 2) stv_nt<R, VX>(static_cast<R*>(a.rhat[1]) + i0, o1);
     }
 #pragma unroll
     for (int c = 0; c < NSC; ++c) {
@@ -669,7 +714,7 @@ __device__ __forceinline__ void tdft_fwd_body(const FwdArgs& a, int bid, double 
             o[2 * x] = static_cast<R>(re);
             o[2 * x + 1] = static_cast<R>(im);
         }
-        stv<R, 2 * VX>(static_cast<R*>(a.rhat[NSR + c]) + 2 * i0, o);
+        stv_nt<R, 2 * VX>(static_cast<R*>(a.rhat[NSR + c]) + 2 * i0, o);
     }
 }
 
@@ -826,6 +871,111 @@ __global__ __launch_bounds__(256) void apply_calA_kernel(const CalAArgs a) {
     apply_calA_body<ELL, VX, RESID>(a, blockIdx.x, gridDim.x);
 }
 
+// The same operator on Dirichlet grids without halo loads: a wave loads 64*VX
+// consecutive columns starting VX columns left of the 64*VX - 2*VX columns it owns
+// (strips overlap by 2*VX columns), so lanes 1..62 own their points and the two edge
+// lanes only supply east / west neighbours, which cross lanes by DPP shifts.  Ghost
+// rows and columns read zeros through raw buffer loads (a block of N values must fit
+// a buffer range, N * 8 < 2^31 bytes).  Against the halo-load form this needs no
+// per-lane halo registers (84 against 176 VGPRs at l = 10, one point per lane) and no
+// single-lane halo loads.  The result is written with non-temporal stores: the next
+// kernel (the multi-dot that reads it, or the next preconditioner stage) then runs
+// without the write-back of this kernel's dirty lines, which measured faster over a
+// whole solve although this kernel alone is a little slower.
+template <int ELL, int VX, bool RESID>
+__device__ __forceinline__ void apply_calA_strip_body(const CalAArgs& a, long long tile) {
+    constexpr int W = kWave * VX;
+    constexpr int S = W - 2 * VX;  // owned columns per strip
+    const int lane = threadIdx.x & (kWave - 1);
+    double ssq = 0.0;
+    if (tile >= 0) {
+        const Geom& g = a.g;
+        const int nx = g.nx, ny = g.ny;
+        const int sx = static_cast<int>(tile % a.t.nsx);
+        const int cy = static_cast<int>(tile / a.t.nsx);
+        const int xb = sx * S - VX + lane * VX;  // first column of this lane
+        const bool colok = xb >= 0 && xb + VX <= nx;
+        const bool own = colok && lane > 0 && lane < kWave - 1;
+        const int y0 = cy * a.t.h;
+        const int y1 = min(y0 + a.t.h, ny);
+        const unsigned nb = static_cast<unsigned>(g.n) * 8u;
+        const __amdgpu_buffer_rsrc_t rk = buf_rsrc(a.kappa, nb);
+        auto load_row = [&](int y, double (&kr)[VX], double (&xr)[ELL][VX]) {
+            const unsigned off = (colok && y >= 0 && y < ny) ? static_cast<unsigned>(y * nx + xb) * 8u : kOob;
+            bld<0>(rk, off, kr);
+#pragma unroll
+            for (int k = 0; k < ELL; ++k) bld<0>(buf_rsrc(a.x + static_cast<long long>(k) * g.n, nb), off, xr[k]);
+        };
+        double kp[VX], kc[VX], kn[VX];
+        double xp[ELL][VX], xc[ELL][VX], xn[ELL][VX];
+        load_row(y0 - 1, kp, xp);
+        load_row(y0, kc, xc);
+        for (int y = y0; y < y1; ++y) {
+            load_row(y + 1, kn, xn);
+            const long long ro = static_cast<long long>(y) * nx + xb;
+            const double kwv = from_west0(kc[VX - 1]);
+            const double kev = from_east0(kc[0]);
+            Faces<double> fc[VX];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const double kw = (v > 0) ? kc[v - 1] : kwv;
+                const double ke = (v < VX - 1) ? kc[v + 1] : kev;
+                fc[v] = faces<double>(g, xb + v, y, kc[v], kw, ke, kp[v], kn[v]);
+            }
+#pragma unroll
+            for (int k = 0; k < ELL; ++k) {
+                const double wv = from_west0(xc[k][VX - 1]);
+                const double ev = from_east0(xc[k][0]);
+                double yo[VX];
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    const double xw = (v > 0) ? xc[k][v - 1] : wv;
+                    const double xe = (v < VX - 1) ? xc[k][v + 1] : ev;
+                    double ax = fc[v].diag * xc[k][v];
+                    ax -= fc[v].w * xw + fc[v].e * xe + fc[v].s * xp[k][v] + fc[v].n * xn[k][v];
+                    if (k > 0) ax -= xc[k - 1][v];
+                    yo[v] = ax;
+                }
+                if (own) {
+                    if (RESID) {
+                        double bb[VX];
+                        ldv_nt<double, VX>(gptr(a.b) + k * g.n + ro, bb);
+#pragma unroll
+                        for (int v = 0; v < VX; ++v) {
+                            yo[v] = bb[v] - yo[v];
+                            ssq += yo[v] * yo[v];
+                        }
+                    }
+                    stv_nt<double, VX>(gptr(a.y) + k * g.n + ro, yo);
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                kp[v] = kc[v];
+                kc[v] = kn[v];
+            }
+#pragma unroll
+            for (int k = 0; k < ELL; ++k) {
+#pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    xp[k][v] = xc[k][v];
+                    xc[k][v] = xn[k][v];
+                }
+            }
+        }
+    }
+    if (RESID) {
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) ssq += __shfl_down(ssq, off, kWave);
+        if (lane == 0 && tile >= 0) gptr(a.partial)[tile] = ssq;
+    }
+}
+
+template <int ELL, int VX, bool RESID>
+__global__ __launch_bounds__(256) void apply_calA_strip_kernel(const CalAArgs a) {
+    apply_calA_strip_body<ELL, VX, RESID>(a, tile_of_wave(a.t, blockIdx.x, gridDim.x));
+}
+
 // Varying diagonal blocks: y_k = A_k x_k - x_{k-1} with A_k built from the block's own
 // coefficient field kappa + k*N.  One wave per (tile, block k = blockIdx.y); x_{k-1}
 // enters only through its centre row.  Residual mode as above, partial index
@@ -939,14 +1089,15 @@ __global__ __launch_bounds__(256) void tdft_fwd_batch_kernel(const BatchList L) 
     }
 }
 
-template <int ELL, int VX, bool RESID>
+template <int ELL, int VX, bool RESID, bool STRIPS>
 __global__ __launch_bounds__(256) void apply_calA_batch_kernel(const BatchList L) {
     const LiveBlocks W = list_live_blocks(L);
     for (int v = blockIdx.x; v < W.total; v += gridDim.x) {
         int q, local, nb;
         if (!live_block(W, v, q, local, nb)) continue;
         const CalAArgs& a = list_args<CalAArgs>(L.args, q);
-        apply_calA_body<ELL, VX, RESID>(a, local, nb);
+        if (STRIPS) apply_calA_strip_body<ELL, VX, RESID>(a, tile_of_wave(a.t, local, nb));
+        else apply_calA_body<ELL, VX, RESID>(a, local, nb);
     }
 }
 

@@ -49,51 +49,6 @@ __device__ __forceinline__ int tile_of_block(const Tiling& t, int bid, int nb) {
     return b2 < t.tiles ? b2 : -1;
 }
 
-// Wavefront shifts by one lane (DPP): from_west(v, edge) gives lane i the value of lane
-// i-1 and lane 0 `edge`; from_east(v, edge) gives lane i the value of lane i+1 and lane
-// 63 `edge`.
-__device__ __forceinline__ float from_west(float v, float edge) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
-                                                                 __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, false));
-}
-__device__ __forceinline__ float from_east(float v, float edge) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, edge),
-                                                                 __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, false));
-}
-// The same with a zero edge value (bound_ctrl: the vacated lane reads zero)
-__device__ __forceinline__ float from_west0(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x138, 0xf, 0xf, true));
-}
-__device__ __forceinline__ float from_east0(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
-}
-__device__ __forceinline__ double from_west0(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x138, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x138, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-__device__ __forceinline__ double from_east0(double v) {
-    const long long b = __builtin_bit_cast(long long, v);
-    const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b), 0x130, 0xf, 0xf, true);
-    const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), 0x130, 0xf, 0xf, true);
-    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-__device__ __forceinline__ double from_west(double v, double edge) {
-    const long long b = __builtin_bit_cast(long long, v), e = __builtin_bit_cast(long long, edge);
-    const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(e), static_cast<int>(b), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(e >> 32), static_cast<int>(b >> 32), 0x138, 0xf, 0xf,
-                                               false);
-    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-__device__ __forceinline__ double from_east(double v, double edge) {
-    const long long b = __builtin_bit_cast(long long, v), e = __builtin_bit_cast(long long, edge);
-    const int lo = __builtin_amdgcn_update_dpp(static_cast<int>(e), static_cast<int>(b), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(static_cast<int>(e >> 32), static_cast<int>(b >> 32), 0x130, 0xf, 0xf,
-                                               false);
-    return __builtin_bit_cast(double, (static_cast<long long>(hi) << 32) | static_cast<unsigned>(lo));
-}
-
 // Face coefficients of one row for a lane's VX points: the diagonal 1 + w + e + s + n,
 // the east face of each point (the west face of point v > 0 is the east face of v - 1),
 // the west face of point 0, and the south / north faces.  All zero on lanes past the

@@ -1,7 +1,7 @@
 """GPU parity: every stage of the hot path through the C ABI against the oracle.
 
 Inputs come from synth (seeded); expected values from oracle/ only.  Sizes span
-several tiles (strips of 64 or 128 columns, chunks of 16 rows) and ragged tails
+several tiles (strips of 62 to 128 columns, chunks of 8 to 16 rows) and ragged tails
 in x and y.  Tolerances:
 * float64 paths: 1e-12 relative (norm-wise and max-element), the rounding of a
   few hundred float64 operations per output;
@@ -33,6 +33,12 @@ CASES = [
     (2, 20, 17, 4, 0.5, "periodic", "lognormal"),
     (2, 128, 20, 2, 1e-2, "periodic", "const"),
     (2, 64, 64, 16, 1e-2, "dirichlet", "lognormal"),
+    # calA on overlapping strips: 248 columns are exactly two strips of 124 owned
+    # columns at two points per lane (l <= 12) or four of 62 at one point (l = 13);
+    # an odd width (one point per lane) leaves a ragged last strip
+    (2, 248, 24, 6, 1e-2, "dirichlet", "lognormal"),
+    (2, 248, 19, 13, 1e-2, "dirichlet", "lognormal"),
+    (2, 251, 40, 8, 1e-2, "dirichlet", "lognormal"),
 ]
 
 
