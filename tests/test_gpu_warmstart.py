@@ -60,7 +60,7 @@ def test_warm_start_gain_on_the_1024_workload():
     to 1e-8.  Trained on about 20 000 crops from plain solves on nine fields, tested on a
     tenth.  As a minimal-residual correction before each cycle (AC_INNER_CHEB_CNN_MR) it
     must reach the tolerance with the oracle's solution to 1e-6 and fewer products with A
-    than the plain method (measured: 134 against 217 iterations, 1.25x faster)."""
+    than the plain method (measured: 137 against 217 iterations, 1.27x faster)."""
     from oracle import operators as ops
     nx = ny = 1024
     ell, alpha, p_in, m = 10, 1e-2, 20, 7
@@ -72,9 +72,6 @@ def test_warm_start_gain_on_the_1024_workload():
     train = W.generate_pairs(ctx, nx, ny, ell, alpha, kfn, list(range(9)), rfn, (1, 2), 60, 4, p_in, 64, 4, c0, c1,
                              restart=m, log=None)
     cnn, _ = W.train_network(ctx, train, 4000, 64, 2e-3, 3, c0, c1, log=None)
-    more = W.generate_pairs(ctx, nx, ny, ell, alpha, kfn, list(range(9)), rfn, (1,), 60, 4, p_in, 64, 4, c0, c1,
-                            seed=10, net=cnn, restart=m, log=None)
-    cnn, _ = W.train_network(ctx, train.join(more), 1333, 64, 1e-3, 3, c0, c1, cnn=cnn, log=None)
     res = W.compare_solves(ctx, cnn, nx, ny, ell, alpha, kfn(9), rfn(7), p_in, restart=m, modes=("plain", "cnn_mr"))
     plain, warm = res["plain"], res["cnn_mr"]
     print(json.dumps({"plain": plain, "cnn_mr": warm}))
