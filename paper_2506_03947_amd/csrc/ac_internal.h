@@ -141,6 +141,19 @@ struct FwdArgs {
     void* rhat[kMaxShift];            // slot order as ShiftCoef
 };
 
+// Gram-Schmidt update of the newest Krylov vector fused with the forward transform
+// (axpy_fwd_kernel): w -= sum_{q < nv} c[q] v[q], then f's transform of w into f.rhat
+// (f.r unused), per-block sums of w^2 at partial[block * stride].
+struct AxpyFwdArgs {
+    FwdArgs f;
+    const double* v[kMaxBasis];
+    double c[kMaxBasis];
+    int nv;
+    int stride;
+    double* w;
+    double* partial;
+};
+
 struct InvArgs {
     long long n;
     double ginv[kMaxEll];
@@ -215,6 +228,14 @@ hipError_t launch_batch_pair(int prec, int vx, const BatchList& L, hipStream_t s
 hipError_t launch_tdft_fwd(int ell, int prec, const FwdArgs& a, hipStream_t s);
 hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s);
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s);
+// At most kAxpyFwdBlocks blocks (partial sums), nv <= 32.
+constexpr int kAxpyFwdBlocks = 1024;
+inline int axpy_fwd_blocks(long long n) {
+    const int vx = (n % 2 == 0) ? 2 : 1;
+    const long long blocks = ((n + vx - 1) / vx + 255) / 256;
+    return static_cast<int>(blocks < kAxpyFwdBlocks ? blocks : kAxpyFwdBlocks);
+}
+hipError_t launch_axpy_fwd(int ell, int prec, const AxpyFwdArgs& a, hipStream_t s);
 // Varying diagonal blocks: a.kappa holds l coefficient fields (block-major); residual
 // mode writes l * tiles partials (index k * tiles + tile).
 hipError_t launch_apply_calA_var(int ell, bool resid, const CalAArgs& a, hipStream_t s);

@@ -326,13 +326,19 @@ void fill_twiddles(int ell, double* cw, double* sw) {
     }
 }
 
-int run_fwd(ac_problem* p, int prec, const double* r, char* rhat, double in_scale) {
+// Arguments of the forward transform of r (scaled by in_scale) into the slots of rhat.
+ac::FwdArgs fwd_args(ac_problem* p, int prec, const double* r, char* rhat, double in_scale) {
     ac::FwdArgs a{};
     a.n = p->g.n;
     for (int k = 0; k < p->ell; ++k) a.gam[k] = in_scale * std::pow(p->alpha, static_cast<double>(k) / p->ell);
     fill_twiddles(p->ell, a.cw, a.sw);
     a.r = r;
     for (int s = 0; s < p->ns; ++s) a.rhat[s] = slot_ptr(p, prec, rhat, s);
+    return a;
+}
+
+int run_fwd(ac_problem* p, int prec, const double* r, char* rhat, double in_scale) {
+    ac::FwdArgs a = fwd_args(p, prec, r, rhat, in_scale);
     long long off[kMaxShift + 1];
     spectral_offsets(p, off);
     if (p->ctx->rec) {
@@ -381,7 +387,7 @@ double sweep_bytes_per_point(int curk, int prevk, bool final, double esz) {
 // otherwise the finished iterates are left in place and `where` reports them.
 template <typename R>
 int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[4], bool warm,
-               double* z, std::vector<std::pair<int, char*>>* where) {
+               double* z, std::vector<std::pair<int, char*>>* where, double out_scale) {
     const int ns = p->ns;
     int pmax = 0;
     std::vector<int> ps(ns);
@@ -455,7 +461,7 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
     };
     auto fill_final = [&](ac::SweepArgs<R>& a) {
         for (int kk = 0; kk < p->ell; ++kk)
-            a.ginv[kk] = 1.0 / (p->ell * std::pow(p->alpha, static_cast<double>(kk) / p->ell));
+            a.ginv[kk] = out_scale / (p->ell * std::pow(p->alpha, static_cast<double>(kk) / p->ell));
         fill_twiddles(p->ell, a.cw, a.sw);
         a.z = z;
     };
@@ -816,9 +822,9 @@ int run_cheb_t(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, 
 }
 
 int run_cheb(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[4], bool warm, double* z,
-             std::vector<std::pair<int, char*>>* where) {
-    if (prec == AC_PREC_FP64) return run_cheb_t<double>(p, prec, pm, rhat, buf, warm, z, where);
-    return run_cheb_t<float>(p, prec, pm, rhat, buf, warm, z, where);
+             std::vector<std::pair<int, char*>>* where, double out_scale) {
+    if (prec == AC_PREC_FP64) return run_cheb_t<double>(p, prec, pm, rhat, buf, warm, z, where, out_scale);
+    return run_cheb_t<float>(p, prec, pm, rhat, buf, warm, z, where, out_scale);
 }
 
 // Builds the per-slot arguments shared by the CNN input/output/residual kernels.
@@ -1162,6 +1168,40 @@ int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int
         AC_TRY(run_cheb(p, o->precision, pm, b.rhat, b.buf, false, z, nullptr));
     }
     return AC_OK;
+}
+
+bool prec_from_rhat_ok(const ac_problem* p, const ac_solve_opts* o) {
+    (void)p;
+    return o->inner == AC_INNER_CHEB || o->inner == AC_INNER_CHEB_CNN_CYCLE || o->inner == AC_INNER_CHEB_CNN_MR;
+}
+
+int axpy_fwd_impl(ac_problem* p, const ac_solve_opts* o, const ac::VecSet& vs, int nv, double* w, void* ws,
+                  double* partial, int stride, int* blocks) {
+    if (p->ctx->rec) return fail(AC_ERR_UNSUPPORTED, "the fused Gram-Schmidt update is not batched");
+    const PrecBufs b = carve_prec(p, o->precision, ws, o->inner);
+    ac::AxpyFwdArgs a{};
+    a.f = fwd_args(p, o->precision, nullptr, b.rhat, 1.0);
+    for (int q = 0; q < nv; ++q) {
+        a.v[q] = vs.v[q];
+        a.c[q] = vs.s2[q];
+    }
+    a.nv = nv;
+    a.stride = stride;
+    a.w = w;
+    a.partial = partial;
+    *blocks = ac::axpy_fwd_blocks(p->g.n);
+    long long off[kMaxShift + 1];
+    spectral_offsets(p, off);
+    const double len = static_cast<double>(p->ell) * p->g.n;
+    ProfScope ps(p->ctx, AC_K_KRYLOV, 8.0 * len * (nv + 2) + static_cast<double>(off[p->ns]) * inner_elem(o->precision));
+    AC_HIP(ac::launch_axpy_fwd(p->ell, o->precision, a, p->ctx->stream));
+    return AC_OK;
+}
+
+int apply_prec_rhat(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, double* z, void* ws,
+                    double out_scale) {
+    const PrecBufs b = carve_prec(p, o->precision, ws, o->inner);
+    return run_cheb(p, o->precision, pm, b.rhat, b.buf, false, z, nullptr, out_scale);
 }
 
 int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double* partial) {

@@ -225,11 +225,24 @@ hipError_t launch_zero_int(int* x, int n, hipStream_t s);
 // Checks the options against the problem; pm receives the inner step count per slot.
 int validate_opts(const ac_problem* p, const ac_solve_opts* o, std::vector<int>& pm);
 // Nested-Chebyshev inner solves of every slot from rhat into z (inverse time-DFT fused).
+// z is scaled by out_scale (folded into the inverse transform).
 int run_cheb(ac_problem* p, int prec, const std::vector<int>& pm, char* rhat, char* const buf[4], bool warm, double* z,
-             std::vector<std::pair<int, char*>>* where);
+             std::vector<std::pair<int, char*>>* where, double out_scale = 1.0);
 // z = P^-1 (in_scale r) by the inner method of o (workspace carved by carve_prec).
 int apply_prec_impl(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, const double* r, double* z,
                     void* ws, double in_scale, int* fallbacks = nullptr);
+// Whether the inner method inside an FGMRES cycle is the plain nested Chebyshev (the
+// inner modes whose in-cycle applications can start from a transform made by
+// axpy_fwd_impl).
+bool prec_from_rhat_ok(const ac_problem* p, const ac_solve_opts* o);
+// The Gram-Schmidt update w -= sum_{q < nv} vs.s2[q] vs.v[q] fused with the forward
+// transform of the new w (no input scale) into the preconditioner workspace ws; the
+// per-block sums of w^2 go to partial[block * stride], *blocks of them.
+int axpy_fwd_impl(ac_problem* p, const ac_solve_opts* o, const ac::VecSet& vs, int nv, double* w, void* ws,
+                  double* partial, int stride, int* blocks);
+// z = out_scale P^-1 applied to the transform already in ws (plain nested Chebyshev).
+int apply_prec_rhat(ac_problem* p, const ac_solve_opts* o, const std::vector<int>& pm, double* z, void* ws,
+                    double out_scale);
 // y = calA x, or with b: y = b - calA x and per-tile partial sums of y^2.
 int calA_impl(ac_problem* p, const double* x, double* y, const double* b, double* partial);
 long long calA_partials(const ac_problem* p);

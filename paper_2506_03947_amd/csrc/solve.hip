@@ -225,6 +225,9 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
         g[0] = beta;
         scale[0] = 1.0 / beta;
         int kdone = 0;
+        // the transform of V_j is already in the preconditioner workspace (made by the
+        // previous step's fused Gram-Schmidt update, unscaled)
+        bool rhat_ready = false;
         for (int j = 0; j < m; ++j) {
             if (rec && *rec_done < rec_count) {
                 AC_HIP(hipMemcpyAsync(rec + static_cast<size_t>(*rec_done) * len, w.V[j], len * sizeof(double),
@@ -236,7 +239,9 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
             ac_solve_opts oj = *o;
             if ((o->inner == AC_INNER_CHEB_CNN_CYCLE && j > 0) || o->inner == AC_INNER_CHEB_CNN_MR)
                 oj.inner = AC_INNER_CHEB;
-            AC_TRY(apply_prec_impl(p, &oj, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
+            if (rhat_ready) AC_TRY(apply_prec_rhat(p, &oj, pm, w.Z[j], w.prec, scale[j]));
+            else AC_TRY(apply_prec_impl(p, &oj, pm, w.V[j], w.Z[j], w.prec, scale[j], &fallbacks));
+            rhat_ready = false;
             AC_TRY(calA_impl(p, w.Z[j], w.V[j + 1], nullptr, nullptr));
             matvecs += p->ell + psum;
             ac::VecSet vs{};
@@ -268,7 +273,15 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
                     vs.s2[i] = scale[i] * hi;  // coefficient of the raw basis vector
                 }
             }
-            {
+            // the next step's preconditioner input V_{j+1} is formed here; when that step
+            // applies the plain nested Chebyshev, its forward transform is computed in the
+            // same pass (the norm, known only afterwards, scales the result instead)
+            const bool fuse_fwd = j + 1 < m && prec_from_rhat_ok(p, o);
+            if (fuse_fwd) {
+                int nblk = 0;
+                AC_TRY(axpy_fwd_impl(p, o, vs, nv, w.V[j + 1], w.prec, w.partial, 72, &nblk));
+                AC_HIP(ac::launch_reduce(w.partial, nblk, 1, 72, w.red, st));
+            } else {
                 ProfScope ps(c, AC_K_KRYLOV, 8.0 * len * (nv + 2));
                 AC_HIP(ac::launch_axpy_norm(vs, nv, nullptr, w.V[j + 1], len, w.partial, 72, st));
                 AC_HIP(ac::launch_reduce(w.partial, kb, 1, 72, w.red, st));
@@ -293,6 +306,7 @@ int solve_impl(ac_problem* p, const ac_solve_opts* o, const double* b, double* x
             kdone = j + 1;
             if (std::abs(g[j + 1]) / bnorm <= o->tol || total >= o->max_outer || hn == 0.0) break;
             scale[j + 1] = 1.0 / hn;
+            rhat_ready = fuse_fwd;
         }
         // back substitution and x += Z y
         for (int i = kdone - 1; i >= 0; --i) {

@@ -12,6 +12,7 @@ namespace ac {
     hipError_t fwd_ell_##L(int prec, const FwdArgs& a, hipStream_t s);                                    \
     hipError_t inv_ell_##L(int prec, const InvArgs& a, hipStream_t s);                                    \
     hipError_t calA_ell_##L(bool resid, const CalAArgs& a, hipStream_t s);                                \
+    hipError_t axpy_fwd_ell_##L(int prec, const AxpyFwdArgs& a, hipStream_t s);                          \
     hipError_t batch_ell_##L(int op, int prec, int curk, int vx, const BatchList& b, hipStream_t s);
 AC_DECL(2) AC_DECL(3) AC_DECL(4) AC_DECL(5) AC_DECL(6) AC_DECL(7) AC_DECL(8) AC_DECL(9) AC_DECL(10)
 AC_DECL(11) AC_DECL(12) AC_DECL(13) AC_DECL(14) AC_DECL(15) AC_DECL(16)
@@ -70,6 +71,13 @@ hipError_t launch_tdft_inv(int ell, int prec, const InvArgs& a, hipStream_t s) {
 
 hipError_t launch_apply_calA(int ell, bool resid, const CalAArgs& a, hipStream_t s) {
 #define AC_X(L) calA_ell_##L(resid, a, s)
+    AC_SWITCH(AC_X)
+#undef AC_X
+}
+
+hipError_t launch_axpy_fwd(int ell, int prec, const AxpyFwdArgs& a, hipStream_t s) {
+    if (a.nv < 1 || a.nv > 32) return hipErrorInvalidValue;
+#define AC_X(L) axpy_fwd_ell_##L(prec, a, s)
     AC_SWITCH(AC_X)
 #undef AC_X
 }

@@ -78,6 +78,25 @@ hipError_t AC_CAT(inv_ell_, AC_ELL)(int prec, const InvArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// The Gram-Schmidt update fused with the forward transform: one point per lane on
+// odd grids, two otherwise; the basis bound NVB = 8 or 32.
+hipError_t AC_CAT(axpy_fwd_ell_, AC_ELL)(int prec, const AxpyFwdArgs& a, hipStream_t s) {
+    constexpr int ELL = AC_ELL;
+    const int vx = (a.f.n % 2 == 0) ? 2 : 1;
+    const int blocks = axpy_fwd_blocks(a.f.n);
+    const bool small = a.nv <= 8;
+#define AC_AF(R, VX, NVB) hipLaunchKernelGGL((axpy_fwd_kernel<R, ELL, VX, NVB>), dim3(blocks), dim3(256), 0, s, a)
+    if (prec == 0) {
+        if (vx == 2) { if (small) AC_AF(double, 2, 8); else AC_AF(double, 2, 32); }
+        else { if (small) AC_AF(double, 1, 8); else AC_AF(double, 1, 32); }
+    } else {
+        if (vx == 2) { if (small) AC_AF(float, 2, 8); else AC_AF(float, 2, 32); }
+        else { if (small) AC_AF(float, 1, 8); else AC_AF(float, 1, 32); }
+    }
+#undef AC_AF
+    return hipGetLastError();
+}
+
 hipError_t AC_CAT(calA_ell_, AC_ELL)(bool resid, const CalAArgs& a, hipStream_t s) {
     constexpr int ELL = AC_ELL;
     const dim3 grid(a.t.blocks), block(a.t.wpb * kWave);

@@ -664,23 +664,14 @@ __global__ __launch_bounds__(256) void cheb_sweep_kernel(const SweepArgs<R> a) {
 // ---------------------------------------------------------------------------
 // Forward scaled time-DFT: per grid point, t_k = gam_k r_k and
 // rhat_m = sum_k t_k exp(-2 pi i m k / l) for the l_s unique m, in float64,
-// stored in the inner real type.
+// stored in the inner real type.  The Krylov input is read and the transforms are
+// written with non-temporal accesses (each is touched once here).
 
+// The transform of one lane's VX points from their scaled values t[k][x].
 template <typename R, int ELL, int VX>
-__device__ __forceinline__ void tdft_fwd_body(const FwdArgs& a, int bid, double mul) {
+__device__ __forceinline__ void tdft_fwd_store(const FwdArgs& a, long long i0, const double (&t)[ELL][VX]) {
     constexpr int NSR = (ELL % 2 == 0) ? 2 : 1;
     constexpr int NSC = (ELL - NSR) / 2;
-    const long long i0 = (static_cast<long long>(bid) * blockDim.x + threadIdx.x) * VX;
-    if (i0 >= a.n) return;
-    double t[ELL][VX];
-#pragma unroll
-    for (int k = 0; k < ELL; ++k) {
-        double v[VX];
-        ldv_nt<double, VX>(a.r + static_cast<long long>(k) * a.n + i0, v);
-        const double gk = a.gam[k] * mul;
-#pragma unroll
-        for (int x = 0; x < VX; ++x) t[k][x] = gk * v[x];
-    }
     // real slots
     {
         R o0[VX], o1[VX];
@@ -716,6 +707,68 @@ __device__ __forceinline__ void tdft_fwd_body(const FwdArgs& a, int bid, double 
         }
         stv_nt<R, 2 * VX>(static_cast<R*>(a.rhat[NSR + c]) + 2 * i0, o);
     }
+}
+
+template <typename R, int ELL, int VX>
+__device__ __forceinline__ void tdft_fwd_body(const FwdArgs& a, int bid, double mul) {
+    const long long i0 = (static_cast<long long>(bid) * blockDim.x + threadIdx.x) * VX;
+    if (i0 >= a.n) return;
+    double t[ELL][VX];
+#pragma unroll
+    for (int k = 0; k < ELL; ++k) {
+        double v[VX];
+        ldv_nt<double, VX>(a.r + static_cast<long long>(k) * a.n + i0, v);
+        const double gk = a.gam[k] * mul;
+#pragma unroll
+        for (int x = 0; x < VX; ++x) t[k][x] = gk * v[x];
+    }
+    tdft_fwd_store<R, ELL, VX>(a, i0, t);
+}
+
+// The Gram-Schmidt update of the newest Krylov vector fused with the forward
+// transform that starts the next preconditioner application: per grid point and
+// block k, w_k <- w_k - sum_{q < nv} c_q V_q,k (written back), t_k = gam_k w_k, and
+// the l_s transforms of t; the block's sum of w^2 goes to partial[block * stride].
+// The transform is of the new vector as it stands (gam carries no input scale): the
+// caller scales the preconditioned result once the norm is known.  A grid-stride
+// loop over the points; blocks of 256 threads.
+template <typename R, int ELL, int VX, int NVB>
+__global__ __launch_bounds__(256) void axpy_fwd_kernel(const AxpyFwdArgs a) {
+    const FwdArgs& f = a.f;
+    double ssq = 0.0;
+    const long long step = static_cast<long long>(gridDim.x) * blockDim.x * VX;
+    for (long long i0 = (static_cast<long long>(blockIdx.x) * blockDim.x + threadIdx.x) * VX; i0 < f.n; i0 += step) {
+        double t[ELL][VX];
+#pragma unroll
+        for (int k = 0; k < ELL; ++k) {
+            double* wk = gptr(a.w) + static_cast<long long>(k) * f.n + i0;
+            double wv[VX];
+            ldv_nt<double, VX>(wk, wv);
+#pragma unroll
+            for (int q = 0; q < NVB; ++q) {
+                if (q < a.nv) {
+                    double v[VX];
+                    ldv_nt<double, VX>(gptr(a.v[q]) + static_cast<long long>(k) * f.n + i0, v);
+#pragma unroll
+                    for (int x = 0; x < VX; ++x) wv[x] -= a.c[q] * v[x];
+                }
+            }
+            stv_nt<double, VX>(wk, wv);
+#pragma unroll
+            for (int x = 0; x < VX; ++x) {
+                ssq += wv[x] * wv[x];
+                t[k][x] = f.gam[k] * wv[x];
+            }
+        }
+        tdft_fwd_store<R, ELL, VX>(f, i0, t);
+    }
+    __shared__ double red[4];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) ssq += __shfl_down(ssq, off, kWave);
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = ssq;
+    __syncthreads();
+    if (threadIdx.x == 0) gptr(a.partial)[static_cast<long long>(blockIdx.x) * a.stride] = red[0] + red[1] + red[2] + red[3];
 }
 
 template <typename R, int ELL, int VX>
