@@ -132,9 +132,28 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, const T
             bld<0>(r, (qok && comp[s]) ? (o + NV * hp) * nR : kOob, xh[s]);
         }
     };
+    // FIRST blocks read no centre rows, so a row's loads would be waited on at once: they
+    // are issued a row ahead into staging registers (rows are requested in order).
+    R XS[NS][E], XSH[NS][NV];
+    KS KWS[VX], KHS;
+    if constexpr (FIRST) fetch_row(y0 - 3, XS, XSH, KWS, KHS);
     auto load_row = [&](auto S_, int y) {
         constexpr int S = decltype(S_)::value;
-        fetch_row(y, X[S], XH[S], KW[S], KH[S]);
+        if constexpr (FIRST) {
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) X[S][s][e] = XS[s][e];
+#pragma unroll
+                for (int e = 0; e < NV; ++e) XH[S][s][e] = XSH[s][e];
+            }
+#pragma unroll
+            for (int v = 0; v < VX; ++v) KW[S][v] = KWS[v];
+            KH[S] = KHS;
+            fetch_row(y + 1, XS, XSH, KWS, KHS);
+        } else {
+            fetch_row(y, X[S], XH[S], KW[S], KH[S]);
+        }
     };
 
     // rhat of row y into h and x_{k-1} into p; non-temporal inside the chunk, plain on its
@@ -359,8 +378,11 @@ __device__ __forceinline__ void cheb_triple_body(const TripleArgs<R>& a, const T
     step2(I2{}, I0{}, I1{}, y0);      // x_{k+2}(y0) -> Z slot 0
 
     // Iteration at row y (i = y - y0): load row y+3 of x_k / kappa and row y+2 of rhat /
-    // x_{k-1}, then x_{k+1}(y+2), x_{k+2}(y+1), x_{k+3}(y).  (Loading a row ahead into
-    // staging registers was measured slower: 230-270 against 204 us per block at 2048^2.)
+    // x_{k-1}, then x_{k+1}(y+2), x_{k+2}(y+1), x_{k+3}(y).  (Loading the steady blocks'
+    // rows a row ahead into staging registers was measured slower: with the centre rows
+    // 230-270 against 204 us per block at 2048^2, with the x_k / kappa row alone 229
+    // against 206 us -- four waves per SIMD instead of five.  FIRST blocks stage their
+    // one row: 155 against 170 us.)
     int y = y0;
     while (y < y1) {
         // i = 0 mod 3: rows y-1 .. y+3 in slots 2, 0, 1, 2, 0
