@@ -65,6 +65,22 @@ def test_2d_lognormal_solve(alpha, precision):
     assert G.rel(x, x_seq) < (1e-10 if precision == L.AC_PREC_FP64 else 1e-6)
 
 
+@pytest.mark.parametrize("precision", [L.AC_PREC_FP64, L.AC_PREC_MIXED_BF16K])
+def test_odd_grid_short_restart_solve(precision):
+    """An odd number of points (one point per lane in the forward transforms, also the
+    one fused with the Gram-Schmidt update), odd l (a single real shift), FGMRES(7):
+    the solution of the sequential chain."""
+    nx, ny, ell, alpha = 37, 29, 5, 1e-2
+    kap = lognormal_kappa(nx, ny, 20.0, 5.0, 1.0, seed=2)
+    A = ops.build_A(2, nx, ny, kap)
+    b = first_block_rhs(nx * ny, ell, seed=3)
+    p = G.problem(2, nx, ny, kap, ell, alpha)
+    tol = 1e-12 if precision == L.AC_PREC_FP64 else 1e-10
+    x, info = _solve(p, b, precision, 10, tol, m=7)
+    assert info["converged"] and info["rel_residual_true"] <= tol, info
+    assert G.rel(x, ops.sequential_solve(A, b, ell)) < (1e-10 if precision == L.AC_PREC_FP64 else 1e-6)
+
+
 def test_restart_and_nc2_counts():
     nx, ny, ell, alpha = 64, 48, 6, 1e-2
     kap = lognormal_kappa(nx, ny, 10.0, 5.0, 0.5, seed=4)
