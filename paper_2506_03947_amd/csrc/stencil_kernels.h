@@ -935,8 +935,8 @@ __global__ __launch_bounds__(256) void apply_calA_kernel(const CalAArgs a) {
 // kernel (the multi-dot that reads it, or the next preconditioner stage) then runs
 // without the write-back of this kernel's dirty lines, which measured faster over a
 // whole solve although this kernel alone is a little slower.
-template <int ELL, int VX, bool RESID>
-__device__ __forceinline__ void apply_calA_strip_body(const CalAArgs& a, long long tile) {
+template <int ELL, int VX, bool RESID, bool UP>
+__device__ __forceinline__ void apply_calA_strip_rows(const CalAArgs& a, long long tile) {
     constexpr int W = kWave * VX;
     constexpr int S = W - 2 * VX;  // owned columns per strip
     const int lane = threadIdx.x & (kWave - 1);
@@ -959,12 +959,19 @@ __device__ __forceinline__ void apply_calA_strip_body(const CalAArgs& a, long lo
 #pragma unroll
             for (int k = 0; k < ELL; ++k) bld<0>(buf_rsrc(a.x + static_cast<long long>(k) * g.n, nb), off, xr[k]);
         };
+        // p: the row behind the march, n: the row ahead (UP: rows y + 1 and y - 1)
+        constexpr int dy = UP ? -1 : 1;
         double kp[VX], kc[VX], kn[VX];
         double xp[ELL][VX], xc[ELL][VX], xn[ELL][VX];
-        load_row(y0 - 1, kp, xp);
-        load_row(y0, kc, xc);
-        for (int y = y0; y < y1; ++y) {
-            load_row(y + 1, kn, xn);
+        const int ys = UP ? y1 - 1 : y0;
+        load_row(ys - dy, kp, xp);
+        load_row(ys, kc, xc);
+        for (int i = 0, y = ys; i < y1 - y0; ++i, y += dy) {
+            load_row(y + dy, kn, xn);
+            const double (&ks)[VX] = UP ? kn : kp;  // south (y - 1) and north (y + 1) rows
+            const double (&kq)[VX] = UP ? kp : kn;
+            const double (&xs)[ELL][VX] = UP ? xn : xp;
+            const double (&xq)[ELL][VX] = UP ? xp : xn;
             const long long ro = static_cast<long long>(y) * nx + xb;
             const double kwv = from_west0(kc[VX - 1]);
             const double kev = from_east0(kc[0]);
@@ -973,7 +980,7 @@ __device__ __forceinline__ void apply_calA_strip_body(const CalAArgs& a, long lo
             for (int v = 0; v < VX; ++v) {
                 const double kw = (v > 0) ? kc[v - 1] : kwv;
                 const double ke = (v < VX - 1) ? kc[v + 1] : kev;
-                fc[v] = faces<double>(g, xb + v, y, kc[v], kw, ke, kp[v], kn[v]);
+                fc[v] = faces<double>(g, xb + v, y, kc[v], kw, ke, ks[v], kq[v]);
             }
 #pragma unroll
             for (int k = 0; k < ELL; ++k) {
@@ -985,7 +992,7 @@ __device__ __forceinline__ void apply_calA_strip_body(const CalAArgs& a, long lo
                     const double xw = (v > 0) ? xc[k][v - 1] : wv;
                     const double xe = (v < VX - 1) ? xc[k][v + 1] : ev;
                     double ax = fc[v].diag * xc[k][v];
-                    ax -= fc[v].w * xw + fc[v].e * xe + fc[v].s * xp[k][v] + fc[v].n * xn[k][v];
+                    ax -= fc[v].w * xw + fc[v].e * xe + fc[v].s * xs[k][v] + fc[v].n * xq[k][v];
                     if (k > 0) ax -= xc[k - 1][v];
                     yo[v] = ax;
                 }
@@ -1022,6 +1029,15 @@ __device__ __forceinline__ void apply_calA_strip_body(const CalAArgs& a, long lo
         for (int off = kWave / 2; off > 0; off >>= 1) ssq += __shfl_down(ssq, off, kWave);
         if (lane == 0 && tile >= 0) gptr(a.partial)[tile] = ssq;
     }
+}
+
+// Chunks march down on even chunk rows and up on odd ones, so two neighbouring chunks
+// reach the rows they share (each one's halo row is the other's edge row) at about the
+// same time, and the second read of those rows can hit the cache.
+template <int ELL, int VX, bool RESID>
+__device__ __forceinline__ void apply_calA_strip_body(const CalAArgs& a, long long tile) {
+    if (tile >= 0 && ((tile / a.t.nsx) & 1)) apply_calA_strip_rows<ELL, VX, RESID, true>(a, tile);
+    else apply_calA_strip_rows<ELL, VX, RESID, false>(a, tile);
 }
 
 template <int ELL, int VX, bool RESID>
