@@ -516,8 +516,9 @@ def warmstart_mode(a):
 
 
 def kernels_only(a, api, prob, ell, n):
-    """A few P_NC^{-1} applications in the solve's precision and launch shape, then a
-    plain device copy of known size (reference for the FETCH_SIZE/WRITE_SIZE scale)."""
+    """A few P_NC^{-1} applications in the solve's precision and launch shape, as many
+    products with calA, then a plain device copy of known size (reference for the
+    FETCH_SIZE/WRITE_SIZE scale)."""
     import torch
     L = api.L
     dev = torch.device("cuda:0")
@@ -531,6 +532,8 @@ def kernels_only(a, api, prob, ell, n):
     api.ac_ctx_reset_stats(ctx)
     for _ in range(max(a.steps, 1)):
         api.ac_apply_prec(prob, opts, r, z, ws)
+    for _ in range(max(a.steps, 1)):
+        api.ac_apply_A(prob, r, z)
     stats = api.ac_ctx_kernel_stats(ctx)
     api.ac_ctx_set_profiling(ctx, False)
     out_ceil = stream_ceilings(api, ctx)
@@ -539,7 +542,7 @@ def kernels_only(a, api, prob, ell, n):
     dst.copy_(src)
     torch.cuda.synchronize()
     out = {"mode": "kernels", "copy_bytes_each_way": src.numel() * 8, "stream_ceilings_GBps": out_ceil}
-    for name in ("cheb_step", "cheb_pair", "cheb_triple"):
+    for name in ("cheb_step", "cheb_pair", "cheb_triple", "apply_calA"):
         st = stats[name]
         if st["launches"]:
             avg_ms = st["ms"] / st["launches"]
